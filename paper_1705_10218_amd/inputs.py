@@ -1,0 +1,225 @@
+"""Seeded synthetic inputs: block-CSR matrices shaped like the paper's workloads.
+
+This module is shared by the GPU path's tests and benchmark and by the CPU
+oracle's tests.  It only *draws* inputs (patterns, block sizes, values); it
+performs none of the multiply's arithmetic (no products, no norms, no
+filtering), so that the two sides stay independent.
+
+Workloads (arXiv:1705.10218, Section 4 and Table 1): the H2O-DFT-LS
+benchmark has matrices of 23x23 blocks, one per molecule, at liquid-water
+density and 7-15 % occupancy; block sizes in general follow the atomic
+kinds (Section 1).  The CP2K inputs are not available, so the generator
+places "atoms" uniformly in a periodic cube at 0.1 atoms per cubic
+Angstrom, gives each a block size, keeps block (i,j) when the
+minimum-image distance r_ij is below a cutoff, and fills the block with
+i.i.d. N(0,1) entries scaled by exp(-r_ij / decay).  Seeds come from
+``numpy.random.default_rng([config, matrix, request])``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+DENSITY = 0.1  # atoms per cubic Angstrom
+
+
+@dataclass
+class BlockCSR:
+    """Host block-CSR matrix.
+
+    rbs[i] / cbs[j]: row / column block sizes; row_ptr (int64, nbr+1) and
+    col_idx (int32, strictly increasing inside a row) index the stored
+    blocks; values (float64) holds the blocks contiguously in CSR order,
+    each block column-major with leading dimension rbs[i].
+    """
+    rbs: np.ndarray
+    cbs: np.ndarray
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    values: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nbr(self) -> int:
+        return int(self.rbs.shape[0])
+
+    @property
+    def nbc(self) -> int:
+        return int(self.cbs.shape[0])
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def block_rows(self) -> np.ndarray:
+        return np.repeat(np.arange(self.nbr, dtype=np.int32), np.diff(self.row_ptr))
+
+    def block_offsets(self) -> np.ndarray:
+        """Element offset of every block (nnzb+1 entries, int64)."""
+        sizes = self.rbs[self.block_rows()].astype(np.int64) * self.cbs[self.col_idx].astype(np.int64)
+        off = np.zeros(self.nnzb + 1, dtype=np.int64)
+        np.cumsum(sizes, out=off[1:])
+        return off
+
+    def n_values(self) -> int:
+        return int(self.block_offsets()[-1])
+
+
+def rng_for(config: int, matrix: int, request: int = 0) -> np.random.Generator:
+    return np.random.default_rng([config, matrix, request])
+
+
+def _csr_from_mask_rows(nbr: int, rows: np.ndarray, cols: np.ndarray):
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    row_ptr = np.zeros(nbr + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=nbr), out=row_ptr[1:])
+    return row_ptr, cols.astype(np.int32), order
+
+
+def from_pattern(rbs, cbs, rows, cols, rng, scale=None, dist="normal") -> BlockCSR:
+    """Block-CSR with the given (row, col) pattern and random values.
+
+    ``scale`` (one factor per pattern entry, in the order given) multiplies
+    every element of that block.  ``dist`` is 'normal' (N(0,1)) or
+    'uniform' (U[-1,1)).
+    """
+    rbs = np.asarray(rbs, dtype=np.int32)
+    cbs = np.asarray(cbs, dtype=np.int32)
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    row_ptr, col_idx, order = _csr_from_mask_rows(rbs.shape[0], rows, cols)
+    sizes = rbs[rows[order]].astype(np.int64) * cbs[col_idx].astype(np.int64)
+    total = int(sizes.sum())
+    if dist == "normal":
+        vals = rng.standard_normal(total)
+    elif dist == "uniform":
+        vals = rng.uniform(-1.0, 1.0, total)
+    else:
+        raise ValueError(dist)
+    if scale is not None:
+        s = np.asarray(scale, dtype=np.float64)[order]
+        vals *= np.repeat(s, sizes)
+    return BlockCSR(rbs, cbs, row_ptr, col_idx, vals)
+
+
+def bernoulli_pattern(nbr, nbc, p, rng, diag=True):
+    mask = rng.random((nbr, nbc)) < p
+    if diag:
+        d = np.arange(min(nbr, nbc))
+        mask[d, d] = True
+    r, c = np.nonzero(mask)
+    return r, c
+
+
+def config_tiny(matrix: int = 0, nb: int = 100, bs: int = 5, p: float = 0.2) -> BlockCSR:
+    """100x100 blocks of 5x5, diagonal always present, off-diagonal blocks
+    present with probability 0.2, N(0,1) entries."""
+    rng = rng_for(1, matrix)
+    r, c = bernoulli_pattern(nb, nb, p, rng, diag=True)
+    sizes = np.full(nb, bs, dtype=np.int32)
+    m = from_pattern(sizes, sizes, r, c, rng)
+    m.meta = dict(workload="tiny", nb=nb, bs=bs, p=p)
+    return m
+
+
+@dataclass
+class Atoms:
+    pos: np.ndarray      # (n, 3) Angstrom
+    box: float           # cube edge, Angstrom
+    sizes: np.ndarray    # (n,) block size per atom
+
+
+def make_atoms(n: int, rng: np.random.Generator, sizes=(5, 13), probs=None,
+               density: float = DENSITY) -> Atoms:
+    box = (n / density) ** (1.0 / 3.0)
+    pos = rng.random((n, 3)) * box
+    sz = rng.choice(np.asarray(sizes, dtype=np.int32), size=n, p=probs).astype(np.int32)
+    return Atoms(pos, box, sz)
+
+
+def neighbour_pairs(atoms: Atoms, cutoff: float, chunk: int = 512):
+    """All (i, j, r_ij) with minimum-image distance r_ij < cutoff (i == j
+    included, r = 0), sorted by (i, j)."""
+    n = atoms.pos.shape[0]
+    box = atoms.box
+    rows, cols, dist = [], [], []
+    c2 = cutoff * cutoff
+    for r0 in range(0, n, chunk):
+        r1 = min(n, r0 + chunk)
+        d = atoms.pos[r0:r1, None, :] - atoms.pos[None, :, :]
+        d -= box * np.round(d / box)
+        d2 = np.einsum("ijk,ijk->ij", d, d)
+        ii, jj = np.nonzero(d2 < c2)
+        rows.append(ii + r0)
+        cols.append(jj)
+        dist.append(np.sqrt(d2[ii, jj]))
+    rows = np.concatenate(rows).astype(np.int64)
+    cols = np.concatenate(cols).astype(np.int64)
+    dist = np.concatenate(dist)
+    return rows, cols, dist
+
+
+def cutoff_for_occupancy(n: int, occupancy: float, density: float = DENSITY) -> float:
+    """Cutoff radius whose expected blocks per row equal occupancy * n:
+    1 + density * 4/3 pi r^3 = occupancy * n."""
+    want = max(occupancy * n - 1.0, 0.0)
+    return (3.0 * want / (4.0 * math.pi * density)) ** (1.0 / 3.0)
+
+
+def dft_like_pair(n_atoms: int, config: int, sizes=(5, 13), probs=None, cutoff: float = 7.0,
+                  decay: float = 2.0, request: int = 0, dist: str = "normal"):
+    """Two matrices A, B on the same atoms (same pattern and block sizes),
+    with independent value streams."""
+    rng_atoms = rng_for(config, 0, request)
+    atoms = make_atoms(n_atoms, rng_atoms, sizes=sizes, probs=probs)
+    if cutoff >= atoms.box / 2:
+        raise ValueError("cutoff must stay below half the box edge for minimum-image distances")
+    r, c, d = neighbour_pairs(atoms, cutoff)
+    scale = np.exp(-d / decay)
+    mats = []
+    for mid in (1, 2):
+        m = from_pattern(atoms.sizes, atoms.sizes, r, c, rng_for(config, mid, request), scale=scale, dist=dist)
+        m.meta = dict(workload="dft_like", n_atoms=n_atoms, sizes=tuple(sizes), cutoff=cutoff,
+                      decay=decay, box=atoms.box, config=config, request=request)
+        mats.append(m)
+    return mats[0], mats[1], atoms
+
+
+def config_dft(n_atoms: int = 4000):
+    """4,000 atoms at 0.1 /A^3, block sizes 50/50 from {5,13}, cutoff 7 A,
+    values N(0,1) exp(-r/2 A).  Used with eps = 1e-10 for both filters."""
+    return dft_like_pair(n_atoms, config=2, sizes=(5, 13), cutoff=7.0, decay=2.0)
+
+
+def config_big23(n_atoms: int = 20000, occupancy: float = 0.03, sizes=(23,)):
+    """20,000 atoms, 23x23 blocks (or a mix), cutoff tuned to ~3 % occupancy."""
+    rc = cutoff_for_occupancy(n_atoms, occupancy)
+    return dft_like_pair(n_atoms, config=3, sizes=sizes, cutoff=rc, decay=2.0)
+
+
+def identity(sizes) -> BlockCSR:
+    sizes = np.asarray(sizes, dtype=np.int32)
+    n = sizes.shape[0]
+    row_ptr = np.arange(n + 1, dtype=np.int64)
+    col_idx = np.arange(n, dtype=np.int32)
+    vals = np.concatenate([np.eye(int(s)).reshape(-1, order="F") for s in sizes]) if n else np.zeros(0)
+    return BlockCSR(sizes.copy(), sizes.copy(), row_ptr, col_idx, vals)
+
+
+def to_dense(m: BlockCSR) -> np.ndarray:
+    """Dense copy (zeros outside stored blocks); a layout conversion only."""
+    ro = np.zeros(m.nbr + 1, dtype=np.int64)
+    np.cumsum(m.rbs, out=ro[1:])
+    co = np.zeros(m.nbc + 1, dtype=np.int64)
+    np.cumsum(m.cbs, out=co[1:])
+    d = np.zeros((int(ro[-1]), int(co[-1])))
+    off = m.block_offsets()
+    for i in range(m.nbr):
+        for p in range(int(m.row_ptr[i]), int(m.row_ptr[i + 1])):
+            j = int(m.col_idx[p])
+            mm, nn = int(m.rbs[i]), int(m.cbs[j])
+            d[ro[i]:ro[i] + mm, co[j]:co[j] + nn] = m.values[off[p]:off[p] + mm * nn].reshape((mm, nn), order="F")
+    return d
