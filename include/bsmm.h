@@ -1,0 +1,162 @@
+/*
+ * bsmm.h -- C ABI of libbsmm.so: local block-sparse matrix multiplication
+ *           on one AMD MI355X (gfx950).
+ *
+ * The operation is the local multiplication of DBCSR (arXiv:1705.10218,
+ * Section 2): C = alpha * op(A) * op(B) + beta * C, where every matrix is
+ * stored in blocked compressed-sparse-row form -- elements grouped into
+ * small dense blocks whose row and column sizes follow the atomic basis --
+ * and the pattern of C is not fixed in advance but produced by the product.
+ * Block products whose norm product falls below a threshold are skipped
+ * during the multiplication, and result blocks below it are removed after
+ * it (Section 1, two-phase filtering; Section 2, on-the-fly filtering).
+ *
+ * Conventions used by every entry point
+ *   Layout   : block rows i = 0..nbr-1 have row_blk_size[i] >= 1 rows, block
+ *              columns j have col_blk_size[j] >= 1 columns.  row_ptr (int64,
+ *              nbr+1 entries, row_ptr[0] = 0, non-decreasing, row_ptr[nbr] =
+ *              nnzb) and col_idx (int32, nnzb entries, strictly increasing
+ *              inside each block row) index the stored blocks.  Values are
+ *              FP64, one block after another in CSR order, each block
+ *              column-major with leading dimension = its row count.
+ *   Memory   : index arrays passed to bsmm_mat_create are host memory and are
+ *              copied.  values_dev is device memory on the context's device;
+ *              the library borrows it (never frees it) for matrices the caller
+ *              creates, and owns the values of matrices it returns.
+ *   Streams  : every device operation is ordered on the context's stream
+ *              (borrowed, e.g. a torch stream; NULL = the default stream).
+ *              Calls that must size a result (multiply, filter) synchronise
+ *              that stream internally to read the sizes back.
+ *   Errors   : every call returns a status and never throws.  On a
+ *              validation error the outputs are untouched.  bsmm_last_error()
+ *              returns a thread-local message describing the last failure.
+ *   Threads  : one context must not be used by two host threads at once.
+ */
+#ifndef BSMM_H
+#define BSMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsmm_ctx_s *bsmm_ctx;
+typedef struct bsmm_mat_s *bsmm_mat;
+
+typedef enum {
+  BSMM_OK = 0,
+  BSMM_ERR_INVALID_ARG = 1,   /* null/negative argument, bad trans character   */
+  BSMM_ERR_BAD_INDEX = 2,     /* malformed row_ptr / col_idx / block sizes     */
+  BSMM_ERR_SHAPE = 3,         /* operand block grids or block sizes disagree   */
+  BSMM_ERR_ALIAS = 4,         /* C_old values alias A or B values              */
+  BSMM_ERR_OUT_OF_MEMORY = 5, /* device memory or the context budget exhausted */
+  BSMM_ERR_DEVICE = 6,        /* a HIP call failed                             */
+  BSMM_ERR_UNSUPPORTED = 7    /* a size beyond what the kernels handle         */
+} bsmm_status;
+
+/* Arithmetic used by the block products (the norms, the filter thresholds
+ * and the stored values are FP64 in every mode). */
+typedef enum {
+  BSMM_COMPUTE_FP64 = 0,      /* FP64 MFMA, FP64 accumulation                  */
+  BSMM_COMPUTE_FP32 = 1,      /* operands rounded to FP32, FP32 MFMA products
+                                 and accumulation inside one block product,
+                                 FP64 accumulation across block products      */
+  BSMM_COMPUTE_SPLIT = 2      /* each operand split into FP32 hi + lo parts;
+                                 hi*hi + hi*lo + lo*hi on FP32 MFMA, FP64
+                                 accumulation across block products           */
+} bsmm_compute_mode;
+
+/* Sizes and counters of one multiplication. */
+typedef struct {
+  int64_t c_nnzb_symbolic;  /* blocks of C before the post-filter              */
+  int64_t c_nnzb;           /* blocks of C returned                            */
+  int64_t c_n_values;       /* FP64 values of C returned                       */
+  int64_t n_candidates;     /* block products of the symbolic pattern          */
+  int64_t n_products;       /* block products that passed the on-the-fly filter*/
+  double useful_flops;      /* sum over kept products of 2*m*k*n               */
+  /* device time per phase in ms (only when timing is enabled, else 0)         */
+  float ms_index, ms_norms, ms_symbolic, ms_stacks, ms_gemm, ms_filter, ms_total;
+} bsmm_multiply_info;
+
+/* Readable name of a status code (static storage). */
+const char *bsmm_status_string(bsmm_status s);
+/* Detail of the last failure on this host thread (static storage per thread). */
+const char *bsmm_last_error(void);
+
+/* Create a context on HIP device `device`.  `stream` is a borrowed
+ * hipStream_t (NULL = default stream).  `hbm_budget_bytes` caps the device
+ * memory the library itself holds (0 = no cap beyond the device). */
+bsmm_status bsmm_ctx_create(int device, void *stream, size_t hbm_budget_bytes, bsmm_ctx *out);
+bsmm_status bsmm_ctx_set_stream(bsmm_ctx ctx, void *stream);
+/* Enable per-phase device timing in bsmm_multiply_info (adds event records). */
+bsmm_status bsmm_ctx_set_timing(bsmm_ctx ctx, int enable);
+bsmm_status bsmm_ctx_set_compute_mode(bsmm_ctx ctx, bsmm_compute_mode mode);
+/* Bytes of device memory the library currently holds for this context
+ * (live buffers plus its cache of freed ones). */
+bsmm_status bsmm_ctx_memory(bsmm_ctx ctx, size_t *held_bytes, size_t *peak_bytes);
+/* Return cached free device memory to HIP. */
+bsmm_status bsmm_ctx_trim(bsmm_ctx ctx);
+/* Wait for all work queued on the context's stream. */
+bsmm_status bsmm_ctx_synchronize(bsmm_ctx ctx);
+/* Destroy the context.  Matrices created on it must be destroyed first. */
+bsmm_status bsmm_ctx_destroy(bsmm_ctx ctx);
+
+/* Create a matrix from its block sizes and block index (host arrays, copied;
+ * validated: sizes >= 1, row_ptr monotone from 0 to nnzb, col_idx in range
+ * and strictly increasing per row, n_values = sum of block areas) and a
+ * borrowed device buffer of n_values FP64 values in the layout above.
+ * values_dev may be NULL only when n_values == 0. */
+bsmm_status bsmm_mat_create(bsmm_ctx ctx, int32_t nbr, int32_t nbc,
+                            const int32_t *row_blk_size, const int32_t *col_blk_size,
+                            int64_t nnzb, const int64_t *row_ptr, const int32_t *col_idx,
+                            double *values_dev, int64_t n_values, bsmm_mat *out);
+bsmm_status bsmm_mat_info(bsmm_mat m, int32_t *nbr, int32_t *nbc, int64_t *nnzb, int64_t *n_values);
+/* Copy the block index to host arrays of nbr+1 and nnzb entries. */
+bsmm_status bsmm_mat_get_index(bsmm_mat m, int64_t *row_ptr_host, int32_t *col_idx_host);
+/* Copy the block sizes to host arrays of nbr and nbc entries. */
+bsmm_status bsmm_mat_get_block_sizes(bsmm_mat m, int32_t *row_blk_size, int32_t *col_blk_size);
+/* Device pointer of the values (owned or borrowed; valid while m lives). */
+bsmm_status bsmm_mat_values(bsmm_mat m, double **values_dev);
+/* Copy the n_values values into a device buffer, ordered on the stream. */
+bsmm_status bsmm_mat_copy_values(bsmm_mat m, double *dst_dev);
+/* Destroy the handle; borrowed values are left alone, owned ones freed. */
+bsmm_status bsmm_mat_destroy(bsmm_mat m);
+
+/* Frobenius norm (FP64) of every stored block, written in storage order to
+ * a device array of nnzb doubles.  The norm drives both filters (Section 1;
+ * Section 2, on-the-fly filtering). */
+bsmm_status bsmm_block_norms(bsmm_mat m, double *norms_dev);
+
+/* C = alpha * op(A) * op(B) + beta * C_old   (Section 2, local multiply)
+ *   transa/transb : 'N' or 'T' (op(X) = X or X^T, blocks transposed too).
+ *   The block column sizes of op(A) must equal the block row sizes of op(B)
+ *   one by one; C_old must have op(A)'s row sizes and op(B)'s column sizes.
+ *   c_old         : may be NULL iff beta == 0 and retain_sparsity == 0; with
+ *                   beta == 0 its values are never read.
+ *   filter_eps    : a block product A_ik B_kj is computed iff
+ *                   ||A_ik||_F * ||B_kj||_F >= filter_eps, and (unless
+ *                   retain_sparsity) a result block is kept iff its norm
+ *                   >= filter_eps; 0 filters nothing.
+ *   retain_sparsity: the pattern of C is exactly that of C_old; products
+ *                   landing outside it are dropped; no post-filter.
+ *   Otherwise the pattern of C is the symbolic product pattern, united with
+ *   C_old's when beta != 0, minus post-filtered blocks.
+ *   *c_out receives a new matrix owning its index and values.  info may be
+ *   NULL.  A and B may be the same handle.  Runs asynchronously except for
+ *   the size read-backs; the result is complete when the stream reaches it.
+ */
+bsmm_status bsmm_multiply(bsmm_ctx ctx, char transa, char transb, double alpha,
+                          bsmm_mat a, bsmm_mat b, double beta, bsmm_mat c_old,
+                          double filter_eps, int retain_sparsity,
+                          bsmm_mat *c_out, bsmm_multiply_info *info);
+
+/* New matrix holding the blocks of m whose Frobenius norm is >= eps
+ * (the post-multiply filter of Section 1 applied on its own). */
+bsmm_status bsmm_filter(bsmm_mat m, double eps, bsmm_mat *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSMM_H */

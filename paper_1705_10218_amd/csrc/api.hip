@@ -1,0 +1,756 @@
+// api.hip -- the C ABI of libbsmm: contexts, matrices, norms, multiply and
+// filter.  Host code only: validation, sizing, phase sequencing on the
+// context stream; every step of the multiply runs in the library's kernels.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <sstream>
+
+#include "internal.h"
+
+namespace bsmm {
+
+static thread_local std::string g_last_error;
+
+[[noreturn]] void fail(bsmm_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char *what, const char *file, int line) {
+  if (e == hipSuccess) return;
+  std::ostringstream os;
+  os << what << " failed: " << hipGetErrorString(e) << " (" << file << ":" << line << ")";
+  if (e == hipErrorOutOfMemory) fail(BSMM_ERR_OUT_OF_MEMORY, os.str());
+  fail(BSMM_ERR_DEVICE, os.str());
+}
+
+// ----------------------------------------------------------------- allocator
+static size_t round_up(size_t b) {
+  const size_t g = 256;
+  if (b == 0) b = 1;
+  return (b + g - 1) / g * g;
+}
+
+void Allocator::init(int device, size_t budget) {
+  device_ = device;
+  budget_ = budget;
+}
+
+void *Allocator::alloc(size_t bytes) {
+  size_t sz = round_up(bytes);
+  // reuse a cached block of at most twice the size
+  auto it = free_.lower_bound(sz);
+  if (it != free_.end() && it->first <= 2 * sz) {
+    void *p = it->second;
+    size_t have = it->first;
+    free_.erase(it);
+    live_[p] = have;
+    return p;
+  }
+  if (budget_ && held_ + sz > budget_) {
+    trim();
+    if (held_ + sz > budget_) {
+      std::ostringstream os;
+      os << "allocation of " << sz << " bytes exceeds the context budget (" << budget_ << " bytes, "
+         << held_ << " held)";
+      fail(BSMM_ERR_OUT_OF_MEMORY, os.str());
+    }
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    trim();
+    e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      std::ostringstream os;
+      os << "hipMalloc of " << sz << " bytes failed";
+      fail(BSMM_ERR_OUT_OF_MEMORY, os.str());
+    }
+  }
+  held_ += sz;
+  peak_ = std::max(peak_, held_);
+  live_[p] = sz;
+  return p;
+}
+
+void Allocator::release(void *p) {
+  if (!p) return;
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  free_.emplace(it->second, p);
+  live_.erase(it);
+}
+
+void Allocator::trim() {
+  if (free_.empty()) return;
+  // pending work may still use cached blocks: wait before freeing them
+  (void)hipDeviceSynchronize();
+  for (auto &kv : free_) {
+    (void)hipFree(kv.second);
+    held_ -= kv.first;
+  }
+  free_.clear();
+}
+
+Allocator::~Allocator() {
+  (void)hipDeviceSynchronize();
+  for (auto &kv : free_) (void)hipFree(kv.second);
+  for (auto &kv : live_) (void)hipFree(kv.first);
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) HIPCHECK(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+static void upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes) HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+}
+
+static constexpr int32_t MAX_BLOCK = 32;
+
+// Owned index arrays of a matrix built inside the library.
+static bsmm_mat_s *new_result(bsmm_ctx ctx, int32_t nbr, int32_t nbc, const std::vector<int32_t> &rbs,
+                              const std::vector<int32_t> &cbs) {
+  auto *m = new bsmm_mat_s();
+  m->ctx = ctx;
+  m->nbr = nbr;
+  m->nbc = nbc;
+  m->h_rbs = rbs;
+  m->h_cbs = cbs;
+  Allocator &al = ctx->alloc;
+  try {
+    m->d_rbs = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * std::max<size_t>(nbr, 1)));
+    m->d_cbs = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * std::max<size_t>(nbc, 1)));
+    upload(m->d_rbs, rbs.data(), sizeof(int32_t) * nbr, ctx->stream);
+    upload(m->d_cbs, cbs.data(), sizeof(int32_t) * nbc, ctx->stream);
+  } catch (...) {
+    al.release(m->d_rbs);
+    al.release(m->d_cbs);
+    delete m;
+    throw;
+  }
+  m->owns_values = true;
+  return m;
+}
+
+static void free_mat(bsmm_mat_s *m) {
+  Allocator &al = m->ctx->alloc;
+  al.release(m->d_rbs);
+  al.release(m->d_cbs);
+  al.release(m->d_row_ptr);
+  al.release(m->d_col_idx);
+  al.release(m->d_blk_off);
+  if (m->owns_values) al.release(m->d_values);
+  delete m;
+}
+
+static void make_op(bsmm_ctx ctx, bsmm_mat_s *x, bool trans, OpIndex &op) {
+  op.blk_off = x->d_blk_off;
+  op.values = x->d_values;
+  if (!trans) {
+    op.nbr = x->nbr;
+    op.nbc = x->nbc;
+    op.nnzb = x->nnzb;
+    op.row_ptr = x->d_row_ptr;
+    op.col_idx = x->d_col_idx;
+    op.blk = nullptr;
+    op.rbs = x->d_rbs;
+    op.cbs = x->d_cbs;
+    op.trans = false;
+  } else {
+    transpose_index(ctx->alloc, *x, op, ctx->stream);
+    op.rbs = x->d_cbs;
+    op.cbs = x->d_rbs;
+  }
+}
+
+struct Timer {
+  bsmm_ctx ctx;
+  std::vector<hipEvent_t> ev;
+  explicit Timer(bsmm_ctx c) : ctx(c) {}
+  void mark() {
+    if (!ctx->timing) return;
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    HIPCHECK(hipEventRecord(e, ctx->stream));
+    ev.push_back(e);
+  }
+  float between(size_t a, size_t b) {
+    if (!ctx->timing || b >= ev.size()) return 0.f;
+    HIPCHECK(hipEventSynchronize(ev[b]));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, ev[a], ev[b]));
+    return ms;
+  }
+  ~Timer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double alpha, bsmm_mat_s *A,
+                                 bsmm_mat_s *B, double beta, bsmm_mat_s *C0, double eps, int retain,
+                                 bsmm_multiply_info *info) {
+  hipStream_t s = ctx->stream;
+  Allocator &al = ctx->alloc;
+  const bool ta = (transa == 'T' || transa == 't');
+  const bool tb = (transb == 'T' || transb == 't');
+  // ---------------------------------------------------------- validation
+  const std::vector<int32_t> &opa_r = ta ? A->h_cbs : A->h_rbs;
+  const std::vector<int32_t> &opa_c = ta ? A->h_rbs : A->h_cbs;
+  const std::vector<int32_t> &opb_r = tb ? B->h_cbs : B->h_rbs;
+  const std::vector<int32_t> &opb_c = tb ? B->h_rbs : B->h_cbs;
+  if (opa_c.size() != opb_r.size()) fail(BSMM_ERR_SHAPE, "op(A) block columns != op(B) block rows");
+  for (size_t k = 0; k < opa_c.size(); k++)
+    if (opa_c[k] != opb_r[k]) fail(BSMM_ERR_SHAPE, "op(A) column block sizes differ from op(B) row block sizes");
+  for (int32_t v : opa_r) if (v > MAX_BLOCK) fail(BSMM_ERR_UNSUPPORTED, "block sizes above 32 are not supported");
+  for (int32_t v : opb_c) if (v > MAX_BLOCK) fail(BSMM_ERR_UNSUPPORTED, "block sizes above 32 are not supported");
+  for (int32_t v : opa_c) if (v > MAX_BLOCK) fail(BSMM_ERR_UNSUPPORTED, "block sizes above 32 are not supported");
+  const bool need_old = (beta != 0.0) || retain;
+  if (need_old && !C0) fail(BSMM_ERR_INVALID_ARG, "c_old is required when beta != 0 or retain_sparsity");
+  if (C0) {
+    if (C0->h_rbs != opa_r || C0->h_cbs != opb_c) fail(BSMM_ERR_SHAPE, "c_old block sizes do not match op(A) rows / op(B) columns");
+    if (need_old && C0->d_values && (C0->d_values == A->d_values || C0->d_values == B->d_values) && C0->n_values > 0)
+      fail(BSMM_ERR_ALIAS, "c_old values alias an operand");
+  }
+  if (!(eps >= 0.0)) fail(BSMM_ERR_INVALID_ARG, "filter_eps must be >= 0");
+  const int32_t nbr = (int32_t)opa_r.size(), nbc = (int32_t)opb_c.size();
+
+  Timer tm(ctx);
+  tm.mark();  // 0
+  // ------------------------------------------------------- a0: op index
+  OpIndex oa, ob;
+  make_op(ctx, A, ta, oa);
+  make_op(ctx, B, tb, ob);
+  tm.mark();  // 1
+  // ------------------------------------------------------- a1: norms
+  DBuf<double> na, nb;
+  const bool filt = eps > 0.0;
+  if (filt) {
+    na = DBuf<double>(al, std::max<int64_t>(A->nnzb, 1));
+    nb = DBuf<double>(al, std::max<int64_t>(B->nnzb, 1));
+    block_norms(*A, na.p, s);
+    block_norms(*B, nb.p, s);
+  }
+  tm.mark();  // 2
+  // ------------------------------------------------------- a2: symbolic
+  SymArgs sym;
+  sym.a = &oa;
+  sym.b = &ob;
+  sym.nbc = nbc;
+  sym.retain = retain != 0;
+  sym.use_cold = (beta != 0.0) && !retain && C0;
+  if (C0) {
+    sym.cold_rp = C0->d_row_ptr;
+    sym.cold_ci = C0->d_col_idx;
+  }
+  DBuf<int64_t> c_rp(al, (size_t)nbr + 1);
+  int64_t nnzb_c = 0;
+  int32_t max_row = 0;
+  {
+    DBuf<int64_t> row_nnz(al, std::max<int32_t>(nbr, 1));
+    DBuf<int32_t> dmax(al, 1);
+    HIPCHECK(hipMemsetAsync(dmax.p, 0, sizeof(int32_t), s));
+    if (retain) {
+      // pattern = C_old pattern; row lengths from its row_ptr
+      HIPCHECK(hipMemcpyAsync(c_rp.p, C0->d_row_ptr, sizeof(int64_t) * ((size_t)nbr + 1), hipMemcpyDeviceToDevice, s));
+      nnzb_c = C0->nnzb;
+      // max row length on the host side from a read-back of row_ptr
+      std::vector<int64_t> h(nbr + 1);
+      HIPCHECK(hipMemcpyAsync(h.data(), C0->d_row_ptr, sizeof(int64_t) * ((size_t)nbr + 1), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (int32_t i = 0; i < nbr; i++) max_row = std::max<int32_t>(max_row, (int32_t)(h[i + 1] - h[i]));
+    } else {
+      symbolic_count(sym, row_nnz.p, dmax.p, s);
+      if (nbr > 0) {
+        exclusive_scan_i64(al, row_nnz.p, c_rp.p, nbr, s);
+      } else {
+        HIPCHECK(hipMemsetAsync(c_rp.p, 0, sizeof(int64_t), s));
+      }
+      HIPCHECK(hipMemcpyAsync(ctx->pinned, c_rp.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipMemcpyAsync(ctx->pinned + 1, dmax.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      nnzb_c = ctx->pinned[0];
+      max_row = (int32_t)(ctx->pinned[1] & 0xffffffff);
+    }
+  }
+  if (nnzb_c > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "more than 2^31 result blocks");
+  if (A->nnzb > INT32_MAX || B->nnzb > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "more than 2^31 operand blocks");
+  const size_t nc1 = (size_t)std::max<int64_t>(nnzb_c, 1);
+  DBuf<int32_t> c_ci(al, nc1), c_row(al, nc1), c_cnt(al, nc1);
+  DBuf<int64_t> c_size(al, nc1), row_kmn(al, std::max<int32_t>(nbr, 1)), row_cand(al, std::max<int32_t>(nbr, 1));
+  HIPCHECK(hipMemsetAsync(c_cnt.p, 0, sizeof(int32_t) * nc1, s));
+  FillArgs fa;
+  fa.sym = sym;
+  fa.c_rp = c_rp.p;
+  fa.c_ci = c_ci.p;
+  fa.c_row = c_row.p;
+  fa.c_size = c_size.p;
+  fa.c_cnt = c_cnt.p;
+  fa.c_kflops = row_kmn.p;
+  fa.row_cand = row_cand.p;
+  fa.na = filt ? na.p : nullptr;
+  fa.nb = filt ? nb.p : nullptr;
+  fa.eps = eps;
+  fa.max_row = max_row;
+  symbolic_fill(fa, s);
+  DBuf<int64_t> c_off(al, nc1 + 1), seg_off(al, nc1 + 1), kmn_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1),
+      cand_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1);
+  exclusive_scan_i64(al, c_size.p, c_off.p, nnzb_c, s);
+  exclusive_scan_i32(al, c_cnt.p, seg_off.p, nnzb_c, s);
+  exclusive_scan_i64(al, row_kmn.p, kmn_scan.p, nbr, s);
+  exclusive_scan_i64(al, row_cand.p, cand_scan.p, nbr, s);
+  HIPCHECK(hipMemcpyAsync(ctx->pinned, c_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(ctx->pinned + 1, seg_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(ctx->pinned + 2, kmn_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(ctx->pinned + 3, cand_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  const int64_t nval_c = ctx->pinned[0];
+  const int64_t nprod = ctx->pinned[1];
+  const int64_t kmn_total = ctx->pinned[2];
+  const int64_t ncand = ctx->pinned[3];
+  DBuf<int32_t> old_blk;
+  if (C0 && beta != 0.0 && nnzb_c > 0) {
+    old_blk = DBuf<int32_t>(al, nc1);
+    HIPCHECK(hipMemsetAsync(old_blk.p, 0xff, sizeof(int32_t) * nc1, s));
+    old_block_map(C0->d_row_ptr, C0->d_col_idx, nbr, c_rp.p, c_ci.p, old_blk.p, s);
+  }
+  tm.mark();  // 3
+  // ------------------------------------------------------- a4: stacks
+  DBuf<int2> stack(al, (size_t)std::max<int64_t>(nprod, 1));
+  {
+    DBuf<int32_t> run;
+    if (max_row > 8192) {
+      run = DBuf<int32_t>(al, nc1);
+      HIPCHECK(hipMemsetAsync(run.p, 0, sizeof(int32_t) * nc1, s));
+    }
+    StackArgs sa;
+    sa.a = &oa;
+    sa.b = &ob;
+    sa.c_rp = c_rp.p;
+    sa.c_ci = c_ci.p;
+    sa.seg_off = seg_off.p;
+    sa.stack = stack.p;
+    sa.na = filt ? na.p : nullptr;
+    sa.nb = filt ? nb.p : nullptr;
+    sa.eps = eps;
+    sa.nbc = nbc;
+    sa.nbr = nbr;
+    sa.max_row = max_row;
+    if (nprod > 0) stack_fill(sa, run.p, s);
+  }
+  DBuf<int32_t> c_list;
+  std::vector<GemmClass> classes;
+  if (nnzb_c > 0) {
+    c_list = DBuf<int32_t>(al, nc1);
+    classes = group_classes(al, c_row.p, c_ci.p, nnzb_c, oa.rbs, ob.cbs, c_list.p, ctx->pinned, s);
+  }
+  tm.mark();  // 4
+  // ------------------------------------------------------- a5: GEMM
+  const bool post = filt && !retain;
+  DBuf<double> c_norm;
+  if (post) c_norm = DBuf<double>(al, nc1);
+  double *c_values = static_cast<double *>(al.alloc(sizeof(double) * (size_t)std::max<int64_t>(nval_c, 1)));
+  bsmm_mat_s *R = nullptr;
+  try {
+    GemmArgs ga;
+    ga.a = &oa;
+    ga.b = &ob;
+    ga.c_list = c_list.p;
+    ga.c_row = c_row.p;
+    ga.c_ci = c_ci.p;
+    ga.c_off = c_off.p;
+    ga.seg_off = seg_off.p;
+    ga.stack = stack.p;
+    ga.c_old_blk = old_blk.p;
+    ga.old_off = C0 ? C0->d_blk_off : nullptr;
+    ga.old_values = C0 ? C0->d_values : nullptr;
+    ga.c_values = c_values;
+    ga.c_norm = post ? c_norm.p : nullptr;
+    ga.alpha = alpha;
+    ga.beta = beta;
+    ga.mode = ctx->mode;
+    for (const GemmClass &cls : classes) gemm_launch(ga, cls, s);
+    tm.mark();  // 5
+    // ----------------------------------------------------- a6: post-filter
+    R = new_result(ctx, nbr, nbc, opa_r, opb_c);
+    int64_t kept = nnzb_c;
+    DBuf<int64_t> rank;
+    if (post && nnzb_c > 0) {
+      CompactArgs ca;
+      ca.nbr = nbr;
+      ca.nnzb = nnzb_c;
+      ca.rp = c_rp.p;
+      ca.ci = c_ci.p;
+      ca.off = c_off.p;
+      ca.values = c_values;
+      ca.norm = c_norm.p;
+      ca.eps = eps;
+      kept = count_kept(al, ca, c_cnt.p /* reused as flag space */, ctx->pinned, s, rank);
+      if (kept < nnzb_c) {
+        DBuf<int64_t> nrp(al, (size_t)nbr + 1), noff(al, (size_t)std::max<int64_t>(kept, 1) + 1);
+        DBuf<int32_t> nci(al, (size_t)std::max<int64_t>(kept, 1));
+        double *nv = nullptr;
+        int64_t nval = 0;
+        compact(al, ca, rank.p, oa.rbs, ob.cbs, nrp.p, nci.p, noff.p, ctx->pinned, &nv, &nval, s);
+        al.release(c_values);
+        c_values = nullptr;
+        R->d_row_ptr = nrp.release_ownership();
+        R->d_col_idx = nci.release_ownership();
+        R->d_blk_off = noff.release_ownership();
+        R->d_values = nv;
+        R->nnzb = kept;
+        R->n_values = nval;
+      }
+    }
+    if (c_values) {
+      R->d_row_ptr = c_rp.release_ownership();
+      R->d_col_idx = c_ci.release_ownership();
+      R->d_blk_off = c_off.release_ownership();
+      R->d_values = c_values;
+      c_values = nullptr;
+      R->nnzb = nnzb_c;
+      R->n_values = nval_c;
+    }
+    tm.mark();  // 6
+    if (info) {
+      info->c_nnzb_symbolic = nnzb_c;
+      info->c_nnzb = R->nnzb;
+      info->c_n_values = R->n_values;
+      info->n_products = nprod;
+      info->n_candidates = ncand;
+      info->useful_flops = 2.0 * (double)kmn_total;
+      info->ms_index = tm.between(0, 1);
+      info->ms_norms = tm.between(1, 2);
+      info->ms_symbolic = tm.between(2, 3);
+      info->ms_stacks = tm.between(3, 4);
+      info->ms_gemm = tm.between(4, 5);
+      info->ms_filter = tm.between(5, 6);
+      info->ms_total = tm.between(0, 6);
+    }
+  } catch (...) {
+    if (c_values) al.release(c_values);
+    if (R) free_mat(R);
+    throw;
+  }
+  return R;
+}
+
+}  // namespace bsmm
+
+using namespace bsmm;
+
+#define ABI_BEGIN try {
+#define ABI_END                                   \
+  return BSMM_OK;                                 \
+  }                                               \
+  catch (const Error &e) {                        \
+    g_last_error = e.msg;                         \
+    return e.code;                                \
+  }                                               \
+  catch (const std::bad_alloc &) {                \
+    g_last_error = "host allocation failed";      \
+    return BSMM_ERR_OUT_OF_MEMORY;                \
+  }                                               \
+  catch (...) {                                   \
+    g_last_error = "unexpected internal error";   \
+    return BSMM_ERR_DEVICE;                       \
+  }
+
+extern "C" {
+
+const char *bsmm_status_string(bsmm_status s) {
+  switch (s) {
+    case BSMM_OK: return "BSMM_OK";
+    case BSMM_ERR_INVALID_ARG: return "BSMM_ERR_INVALID_ARG";
+    case BSMM_ERR_BAD_INDEX: return "BSMM_ERR_BAD_INDEX";
+    case BSMM_ERR_SHAPE: return "BSMM_ERR_SHAPE";
+    case BSMM_ERR_ALIAS: return "BSMM_ERR_ALIAS";
+    case BSMM_ERR_OUT_OF_MEMORY: return "BSMM_ERR_OUT_OF_MEMORY";
+    case BSMM_ERR_DEVICE: return "BSMM_ERR_DEVICE";
+    case BSMM_ERR_UNSUPPORTED: return "BSMM_ERR_UNSUPPORTED";
+  }
+  return "BSMM_ERR_UNKNOWN";
+}
+
+const char *bsmm_last_error(void) { return g_last_error.c_str(); }
+
+bsmm_status bsmm_ctx_create(int device, void *stream, size_t hbm_budget_bytes, bsmm_ctx *out) {
+  ABI_BEGIN
+  if (!out) fail(BSMM_ERR_INVALID_ARG, "out is NULL");
+  int n = 0;
+  HIPCHECK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) fail(BSMM_ERR_INVALID_ARG, "no such device");
+  DeviceGuard g(device);
+  auto *c = new bsmm_ctx_s();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->alloc.init(device, hbm_budget_bytes);
+  if (hipHostMalloc((void **)&c->pinned, 64 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    fail(BSMM_ERR_OUT_OF_MEMORY, "pinned host buffer");
+  }
+  *out = c;
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_set_stream(bsmm_ctx ctx, void *stream) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard g(ctx->device);
+  // work queued on the old stream must finish before buffers are reused on the new one
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  ctx->stream = static_cast<hipStream_t>(stream);
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_set_timing(bsmm_ctx ctx, int enable) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->timing = enable != 0;
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_set_compute_mode(bsmm_ctx ctx, bsmm_compute_mode mode) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  if (mode != BSMM_COMPUTE_FP64) fail(BSMM_ERR_UNSUPPORTED, "only BSMM_COMPUTE_FP64 is available");
+  ctx->mode = mode;
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_memory(bsmm_ctx ctx, size_t *held, size_t *peak) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  if (held) *held = ctx->alloc.held();
+  if (peak) *peak = ctx->alloc.peak();
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_trim(bsmm_ctx ctx) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard g(ctx->device);
+  ctx->alloc.trim();
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_synchronize(bsmm_ctx ctx) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard g(ctx->device);
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_destroy(bsmm_ctx ctx) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  if (ctx->live_mats != 0) fail(BSMM_ERR_INVALID_ARG, "matrices of this context are still alive");
+  DeviceGuard g(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  ABI_END
+}
+
+bsmm_status bsmm_mat_create(bsmm_ctx ctx, int32_t nbr, int32_t nbc, const int32_t *rbs, const int32_t *cbs,
+                            int64_t nnzb, const int64_t *row_ptr, const int32_t *col_idx, double *values_dev,
+                            int64_t n_values, bsmm_mat *out) {
+  ABI_BEGIN
+  if (!ctx || !out) fail(BSMM_ERR_INVALID_ARG, "ctx/out is NULL");
+  if (nbr < 0 || nbc < 0 || nnzb < 0 || n_values < 0) fail(BSMM_ERR_INVALID_ARG, "negative size");
+  if ((nbr > 0 && !rbs) || (nbc > 0 && !cbs) || !row_ptr || (nnzb > 0 && !col_idx))
+    fail(BSMM_ERR_INVALID_ARG, "index array is NULL");
+  if (n_values > 0 && !values_dev) fail(BSMM_ERR_INVALID_ARG, "values_dev is NULL");
+  if (nnzb > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "more than 2^31 blocks");
+  for (int32_t i = 0; i < nbr; i++) if (rbs[i] < 1) fail(BSMM_ERR_BAD_INDEX, "row block size < 1");
+  for (int32_t j = 0; j < nbc; j++) if (cbs[j] < 1) fail(BSMM_ERR_BAD_INDEX, "column block size < 1");
+  if (row_ptr[0] != 0) fail(BSMM_ERR_BAD_INDEX, "row_ptr[0] != 0");
+  if (row_ptr[nbr] != nnzb) fail(BSMM_ERR_BAD_INDEX, "row_ptr[nbr] != nnzb");
+  std::vector<int64_t> off((size_t)nnzb + 1);
+  int64_t o = 0;
+  for (int32_t i = 0; i < nbr; i++) {
+    if (row_ptr[i + 1] < row_ptr[i]) fail(BSMM_ERR_BAD_INDEX, "row_ptr decreases");
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; p++) {
+      int32_t j = col_idx[p];
+      if (j < 0 || j >= nbc) fail(BSMM_ERR_BAD_INDEX, "col_idx out of range");
+      if (p > row_ptr[i] && col_idx[p - 1] >= j) fail(BSMM_ERR_BAD_INDEX, "col_idx not strictly increasing in a row");
+      off[p] = o;
+      o += (int64_t)rbs[i] * cbs[j];
+    }
+  }
+  off[nnzb] = o;
+  if (o != n_values) fail(BSMM_ERR_BAD_INDEX, "n_values differs from the sum of block areas");
+  DeviceGuard g(ctx->device);
+  auto *m = new bsmm_mat_s();
+  m->ctx = ctx;
+  m->nbr = nbr;
+  m->nbc = nbc;
+  m->nnzb = nnzb;
+  m->n_values = n_values;
+  m->h_rbs.assign(rbs, rbs + nbr);
+  m->h_cbs.assign(cbs, cbs + nbc);
+  Allocator &al = ctx->alloc;
+  try {
+    m->d_rbs = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * std::max<size_t>(nbr, 1)));
+    m->d_cbs = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * std::max<size_t>(nbc, 1)));
+    m->d_row_ptr = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * ((size_t)nbr + 1)));
+    m->d_col_idx = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * std::max<size_t>(nnzb, 1)));
+    m->d_blk_off = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * ((size_t)nnzb + 1)));
+    upload(m->d_rbs, rbs, sizeof(int32_t) * nbr, ctx->stream);
+    upload(m->d_cbs, cbs, sizeof(int32_t) * nbc, ctx->stream);
+    upload(m->d_row_ptr, row_ptr, sizeof(int64_t) * ((size_t)nbr + 1), ctx->stream);
+    upload(m->d_col_idx, col_idx, sizeof(int32_t) * nnzb, ctx->stream);
+    upload(m->d_blk_off, off.data(), sizeof(int64_t) * ((size_t)nnzb + 1), ctx->stream);
+    // the host arrays are pageable: finish the copies before returning
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+  } catch (...) {
+    m->owns_values = false;
+    free_mat(m);
+    throw;
+  }
+  m->d_values = values_dev;
+  m->owns_values = false;
+  ctx->live_mats++;
+  *out = m;
+  ABI_END
+}
+
+bsmm_status bsmm_mat_info(bsmm_mat m, int32_t *nbr, int32_t *nbc, int64_t *nnzb, int64_t *n_values) {
+  ABI_BEGIN
+  if (!m) fail(BSMM_ERR_INVALID_ARG, "m is NULL");
+  if (nbr) *nbr = m->nbr;
+  if (nbc) *nbc = m->nbc;
+  if (nnzb) *nnzb = m->nnzb;
+  if (n_values) *n_values = m->n_values;
+  ABI_END
+}
+
+bsmm_status bsmm_mat_get_index(bsmm_mat m, int64_t *row_ptr, int32_t *col_idx) {
+  ABI_BEGIN
+  if (!m || !row_ptr || (m->nnzb > 0 && !col_idx)) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  DeviceGuard g(m->ctx->device);
+  hipStream_t s = m->ctx->stream;
+  HIPCHECK(hipMemcpyAsync(row_ptr, m->d_row_ptr, sizeof(int64_t) * ((size_t)m->nbr + 1), hipMemcpyDeviceToHost, s));
+  if (m->nnzb > 0)
+    HIPCHECK(hipMemcpyAsync(col_idx, m->d_col_idx, sizeof(int32_t) * (size_t)m->nnzb, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  ABI_END
+}
+
+bsmm_status bsmm_mat_get_block_sizes(bsmm_mat m, int32_t *rbs, int32_t *cbs) {
+  ABI_BEGIN
+  if (!m || (m->nbr > 0 && !rbs) || (m->nbc > 0 && !cbs)) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  if (m->nbr) std::memcpy(rbs, m->h_rbs.data(), sizeof(int32_t) * m->nbr);
+  if (m->nbc) std::memcpy(cbs, m->h_cbs.data(), sizeof(int32_t) * m->nbc);
+  ABI_END
+}
+
+bsmm_status bsmm_mat_values(bsmm_mat m, double **values_dev) {
+  ABI_BEGIN
+  if (!m || !values_dev) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  *values_dev = m->d_values;
+  ABI_END
+}
+
+bsmm_status bsmm_mat_copy_values(bsmm_mat m, double *dst) {
+  ABI_BEGIN
+  if (!m || (m->n_values > 0 && !dst)) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  DeviceGuard g(m->ctx->device);
+  if (m->n_values > 0)
+    HIPCHECK(hipMemcpyAsync(dst, m->d_values, sizeof(double) * (size_t)m->n_values, hipMemcpyDeviceToDevice,
+                            m->ctx->stream));
+  ABI_END
+}
+
+bsmm_status bsmm_mat_destroy(bsmm_mat m) {
+  ABI_BEGIN
+  if (!m) fail(BSMM_ERR_INVALID_ARG, "m is NULL");
+  DeviceGuard g(m->ctx->device);
+  bsmm_ctx ctx = m->ctx;
+  bool user = !m->owns_values;
+  free_mat(m);
+  (void)user;
+  ctx->live_mats--;
+  ABI_END
+}
+
+bsmm_status bsmm_block_norms(bsmm_mat m, double *norms) {
+  ABI_BEGIN
+  if (!m || (m->nnzb > 0 && !norms)) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  DeviceGuard g(m->ctx->device);
+  block_norms(*m, norms, m->ctx->stream);
+  ABI_END
+}
+
+bsmm_status bsmm_multiply(bsmm_ctx ctx, char transa, char transb, double alpha, bsmm_mat a, bsmm_mat b,
+                          double beta, bsmm_mat c_old, double filter_eps, int retain_sparsity, bsmm_mat *c_out,
+                          bsmm_multiply_info *info) {
+  ABI_BEGIN
+  if (!ctx || !a || !b || !c_out) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  if (!(transa == 'N' || transa == 'n' || transa == 'T' || transa == 't') ||
+      !(transb == 'N' || transb == 'n' || transb == 'T' || transb == 't'))
+    fail(BSMM_ERR_INVALID_ARG, "trans must be 'N' or 'T'");
+  if (a->ctx != ctx || b->ctx != ctx || (c_old && c_old->ctx != ctx))
+    fail(BSMM_ERR_INVALID_ARG, "matrices belong to another context");
+  DeviceGuard g(ctx->device);
+  bsmm_mat_s *r = multiply_impl(ctx, transa, transb, alpha, a, b, beta, c_old, filter_eps, retain_sparsity, info);
+  ctx->live_mats++;
+  *c_out = r;
+  ABI_END
+}
+
+bsmm_status bsmm_filter(bsmm_mat m, double eps, bsmm_mat *out) {
+  ABI_BEGIN
+  if (!m || !out) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  if (!(eps >= 0.0)) fail(BSMM_ERR_INVALID_ARG, "eps must be >= 0");
+  bsmm_ctx ctx = m->ctx;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = ctx->stream;
+  Allocator &al = ctx->alloc;
+  const size_t n1 = (size_t)std::max<int64_t>(m->nnzb, 1);
+  DBuf<double> norm(al, n1);
+  DBuf<int32_t> flags(al, n1);
+  block_norms(*m, norm.p, s);
+  CompactArgs ca;
+  ca.nbr = m->nbr;
+  ca.nnzb = m->nnzb;
+  ca.rp = m->d_row_ptr;
+  ca.ci = m->d_col_idx;
+  ca.off = m->d_blk_off;
+  ca.values = m->d_values;
+  ca.norm = norm.p;
+  ca.eps = eps;
+  DBuf<int64_t> rank;
+  int64_t kept = count_kept(al, ca, flags.p, ctx->pinned, s, rank);
+  bsmm_mat_s *R = new_result(ctx, m->nbr, m->nbc, m->h_rbs, m->h_cbs);
+  try {
+    DBuf<int64_t> nrp(al, (size_t)m->nbr + 1), noff(al, (size_t)std::max<int64_t>(kept, 1) + 1);
+    DBuf<int32_t> nci(al, (size_t)std::max<int64_t>(kept, 1));
+    double *nv = nullptr;
+    int64_t nval = 0;
+    compact(al, ca, rank.p, m->d_rbs, m->d_cbs, nrp.p, nci.p, noff.p, ctx->pinned, &nv, &nval, s);
+    R->d_row_ptr = nrp.release_ownership();
+    R->d_col_idx = nci.release_ownership();
+    R->d_blk_off = noff.release_ownership();
+    R->d_values = nv;
+    R->nnzb = kept;
+    R->n_values = nval;
+  } catch (...) {
+    free_mat(R);
+    throw;
+  }
+  ctx->live_mats++;
+  *out = R;
+  ABI_END
+}
+
+}  // extern "C"

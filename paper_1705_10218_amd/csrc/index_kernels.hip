@@ -1,0 +1,314 @@
+// index_kernels.hip -- device-wide scans, the block-index transpose (op = T),
+// block Frobenius norms and the compaction used by the post-multiply filter.
+#include "internal.h"
+
+namespace bsmm {
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+// Inclusive scan over a 64-wide wavefront.
+__device__ inline int64_t wave_incl_scan(int64_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Exclusive prefix of `v` over the 256 threads of the block; total in *tot.
+__device__ inline int64_t block_excl_scan(int64_t v, int64_t *sh, int64_t *tot) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t inc = wave_incl_scan(v, lane);
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  int64_t base = 0, all = 0;
+  for (int t = 0; t < SCAN_THREADS / 64; t++) {
+    if (t < w) base += sh[t];
+    all += sh[t];
+  }
+  __syncthreads();
+  *tot = all;
+  return base + inc - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SCAN_THREADS) void k_tile_sums(const T *in, int64_t n, int64_t *sums) {
+  __shared__ int64_t sh[SCAN_THREADS / 64];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t s = 0;
+#pragma unroll
+  for (int t = 0; t < SCAN_ITEMS; t++)
+    if (base + t < n) s += (int64_t)in[base + t];
+  int64_t tot;
+  block_excl_scan(s, sh, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SCAN_THREADS) void k_tile_scan(const T *in, int64_t n, const int64_t *tile_base,
+                                                            int64_t *out) {
+  __shared__ int64_t sh[SCAN_THREADS / 64];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t v[SCAN_ITEMS];
+  int64_t s = 0;
+#pragma unroll
+  for (int t = 0; t < SCAN_ITEMS; t++) {
+    v[t] = (base + t < n) ? (int64_t)in[base + t] : 0;
+    s += v[t];
+  }
+  int64_t tot;
+  int64_t run = block_excl_scan(s, sh, &tot) + (tile_base ? tile_base[blockIdx.x] : 0);
+#pragma unroll
+  for (int t = 0; t < SCAN_ITEMS; t++) {
+    if (base + t < n) out[base + t] = run;
+    run += v[t];
+  }
+  // the block holding element n-1 (or block 0 when n == 0) writes the total
+  int64_t last_blk = n > 0 ? (n - 1) / SCAN_TILE : 0;
+  if ((int64_t)blockIdx.x == last_blk && threadIdx.x == SCAN_THREADS - 1) {
+    out[n] = (tile_base ? tile_base[blockIdx.x] : 0) + tot;
+  }
+}
+
+template <typename T>
+void scan_impl(Allocator &al, const T *in, int64_t *out, int64_t n, hipStream_t s) {
+  int64_t tiles = n > 0 ? (n + SCAN_TILE - 1) / SCAN_TILE : 1;
+  if (tiles == 1) {
+    hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(SCAN_THREADS), 0, s, in, n, (const int64_t *)nullptr, out);
+    HIPCHECK(hipGetLastError());
+    return;
+  }
+  DBuf<int64_t> sums(al, tiles), base(al, tiles + 1);
+  hipLaunchKernelGGL(k_tile_sums<T>, dim3(tiles), dim3(SCAN_THREADS), 0, s, in, n, sums.p);
+  HIPCHECK(hipGetLastError());
+  scan_impl<int64_t>(al, sums.p, base.p, tiles, s);
+  hipLaunchKernelGGL(k_tile_scan<T>, dim3(tiles), dim3(SCAN_THREADS), 0, s, in, n, (const int64_t *)base.p, out);
+  HIPCHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------- transpose
+// Rows are processed in chunks of R rows.  cc[c*nbc + j] first counts the
+// blocks of column j inside chunk c, then (after a scan down the chunks)
+// holds where chunk c starts writing inside new row j.  Chunks fill in
+// parallel; inside a chunk one wavefront walks its rows in order, so every
+// new row ends up sorted by old row.
+
+__global__ void k_tr_count(const int64_t *rp, const int32_t *ci, int32_t nbr, int32_t rows_per_chunk,
+                           int32_t nbc, int32_t *cc) {
+  int32_t chunk = blockIdx.x;
+  int32_t r0 = chunk * rows_per_chunk, r1 = min(nbr, r0 + rows_per_chunk);
+  if (r0 >= r1) return;
+  int64_t p0 = rp[r0], p1 = rp[r1];
+  int32_t *row = cc + (int64_t)chunk * nbc;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) atomicAdd(&row[ci[p]], 1);
+}
+
+__global__ void k_tr_colscan(int32_t *cc, int32_t nchunks, int32_t nbc, int64_t *colcount) {
+  int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nbc) return;
+  int32_t run = 0;
+  for (int32_t c = 0; c < nchunks; c++) {
+    int64_t idx = (int64_t)c * nbc + j;
+    int32_t v = cc[idx];
+    cc[idx] = run;
+    run += v;
+  }
+  colcount[j] = run;
+}
+
+__global__ __launch_bounds__(64) void k_tr_fill(const int64_t *rp, const int32_t *ci, int32_t nbr,
+                                                int32_t rows_per_chunk, int32_t nbc, int32_t *cc,
+                                                const int64_t *rpT, int32_t *ciT, int32_t *blkT) {
+  int32_t chunk = blockIdx.x;
+  int32_t r0 = chunk * rows_per_chunk, r1 = min(nbr, r0 + rows_per_chunk);
+  int32_t *row = cc + (int64_t)chunk * nbc;
+  for (int32_t i = r0; i < r1; i++) {
+    for (int64_t p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 64) {
+      int32_t j = ci[p];
+      // columns are distinct inside one old row; the atomic keeps successive
+      // rows of this wavefront ordered on the same counter
+      int32_t slot = atomicAdd(&row[j], 1);
+      int64_t q = rpT[j] + slot;
+      ciT[q] = i;
+      blkT[q] = (int32_t)p;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ norms
+// G lanes per block: G = 16 for small blocks, 64 otherwise.
+template <int G>
+__global__ __launch_bounds__(256) void k_block_norms(const int64_t *off, const double *v, int64_t nnzb,
+                                                     double *out) {
+  int lane = threadIdx.x % G;
+  int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
+  for (int64_t b = grp; b < nnzb; b += ngrp) {
+    int64_t o0 = off[b], o1 = off[b + 1];
+    double s = 0.0;
+    for (int64_t e = o0 + lane; e < o1; e += G) {
+      double x = v[e];
+      s = fma(x, x, s);
+    }
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) s += __shfl_xor(s, d, G);
+    if (lane == 0) out[b] = sqrt(s);
+  }
+}
+
+// ------------------------------------------------------------- compaction
+__global__ void k_keep_flags(const double *norm, double eps, int64_t n, int32_t *keep) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) keep[c] = (norm[c] < eps) ? 0 : 1;   // dropped iff norm < eps
+}
+
+__global__ void k_new_rowptr(const int64_t *rp, int32_t nbr, const int64_t *rank, int64_t *new_rp) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= nbr) new_rp[i] = rank[rp[i]];
+}
+
+__global__ void k_compact_index(const int64_t *rp, int32_t nbr, const int32_t *ci, const int64_t *rank,
+                                const int32_t *rbs, const int32_t *cbs, int32_t *new_ci, int64_t *new_size) {
+  int32_t i = blockIdx.x;
+  int64_t m = rbs[i];
+  for (int64_t p = rp[i] + threadIdx.x; p < rp[i + 1]; p += blockDim.x) {
+    int64_t r = rank[p];
+    if (rank[p + 1] != r) {
+      int32_t j = ci[p];
+      new_ci[r] = j;
+      new_size[r] = m * cbs[j];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_compact_values(const int64_t *rank, int64_t nnzb, const int64_t *off,
+                                                        const double *v, const int64_t *new_off, double *nv) {
+  int lane = threadIdx.x & 63;
+  int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t b = w; b < nnzb; b += nw) {
+    int64_t r = rank[b];
+    if (rank[b + 1] == r) continue;
+    int64_t o0 = off[b], len = off[b + 1] - o0, d0 = new_off[r];
+    for (int64_t e = lane; e < len; e += 64) nv[d0 + e] = v[o0 + e];
+  }
+}
+
+int grid_for(int64_t items, int per_block, int cap = 65536) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+void exclusive_scan_i64(Allocator &al, const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
+  scan_impl<int64_t>(al, in, out, n, s);
+}
+void exclusive_scan_i32(Allocator &al, const int32_t *in, int64_t *out, int64_t n, hipStream_t s) {
+  scan_impl<int32_t>(al, in, out, n, s);
+}
+
+void transpose_index(Allocator &al, const bsmm_mat_s &x, OpIndex &op, hipStream_t s) {
+  int32_t nbr = x.nbr, nbc = x.nbc;
+  int64_t nnzb = x.nnzb;
+  op.nbr = nbc;
+  op.nbc = nbr;
+  op.nnzb = nnzb;
+  op.trans = true;
+  op.own_rp = DBuf<int64_t>(al, (size_t)nbc + 1);
+  op.own_ci = DBuf<int32_t>(al, nnzb > 0 ? nnzb : 1);
+  op.own_blk = DBuf<int32_t>(al, nnzb > 0 ? nnzb : 1);
+  if (nbr == 0 || nbc == 0 || nnzb == 0) {
+    HIPCHECK(hipMemsetAsync(op.own_rp.p, 0, sizeof(int64_t) * ((size_t)nbc + 1), s));
+  } else {
+    int64_t cells = (int64_t)nbr * nbc;
+    int32_t rpc = (int32_t)std::max<int64_t>(16, (cells + (1 << 24) - 1) >> 24);
+    int32_t nch = (nbr + rpc - 1) / rpc;
+    DBuf<int32_t> cc(al, (size_t)nch * nbc);
+    DBuf<int64_t> colcount(al, nbc);
+    HIPCHECK(hipMemsetAsync(cc.p, 0, sizeof(int32_t) * (size_t)nch * nbc, s));
+    hipLaunchKernelGGL(k_tr_count, dim3(nch), dim3(256), 0, s, x.d_row_ptr, x.d_col_idx, nbr, rpc, nbc, cc.p);
+    HIPCHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_tr_colscan, dim3((nbc + 255) / 256), dim3(256), 0, s, cc.p, nch, nbc, colcount.p);
+    HIPCHECK(hipGetLastError());
+    exclusive_scan_i64(al, colcount.p, op.own_rp.p, nbc, s);
+    hipLaunchKernelGGL(k_tr_fill, dim3(nch), dim3(64), 0, s, x.d_row_ptr, x.d_col_idx, nbr, rpc, nbc, cc.p,
+                       (const int64_t *)op.own_rp.p, op.own_ci.p, op.own_blk.p);
+    HIPCHECK(hipGetLastError());
+  }
+  op.row_ptr = op.own_rp.p;
+  op.col_idx = op.own_ci.p;
+  op.blk = op.own_blk.p;
+}
+
+void block_norms(const bsmm_mat_s &x, double *norms, hipStream_t s) {
+  if (x.nnzb == 0) return;
+  int32_t mr = 0, mc = 0;
+  for (int32_t a : x.h_rbs) mr = std::max(mr, a);
+  for (int32_t b : x.h_cbs) mc = std::max(mc, b);
+  int64_t maxa = (int64_t)mr * mc;
+  if (maxa <= 64) {
+    hipLaunchKernelGGL(k_block_norms<16>, dim3(grid_for(x.nnzb * 16, 256)), dim3(256), 0, s, x.d_blk_off,
+                       x.d_values, x.nnzb, norms);
+  } else {
+    hipLaunchKernelGGL(k_block_norms<64>, dim3(grid_for(x.nnzb * 64, 256)), dim3(256), 0, s, x.d_blk_off,
+                       x.d_values, x.nnzb, norms);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+int64_t count_kept(Allocator &al, const CompactArgs &c, int32_t *keep_tmp, int64_t *pinned, hipStream_t s,
+                   DBuf<int64_t> &rank) {
+  rank = DBuf<int64_t>(al, (size_t)c.nnzb + 1);
+  if (c.nnzb > 0) {
+    hipLaunchKernelGGL(k_keep_flags, dim3(grid_for(c.nnzb, 256, 1 << 30)), dim3(256), 0, s, c.norm, c.eps,
+                       c.nnzb, keep_tmp);
+    HIPCHECK(hipGetLastError());
+  }
+  exclusive_scan_i32(al, keep_tmp, rank.p, c.nnzb, s);
+  HIPCHECK(hipMemcpyAsync(pinned, rank.p + c.nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  return pinned[0];
+}
+
+void compact(Allocator &al, const CompactArgs &c, const int64_t *rank, const int32_t *d_rbs,
+             const int32_t *d_cbs, int64_t *new_rp, int32_t *new_ci, int64_t *new_off, int64_t *pinned,
+             double **new_values, int64_t *new_nval, hipStream_t s) {
+  hipLaunchKernelGGL(k_new_rowptr, dim3((c.nbr + 1 + 255) / 256), dim3(256), 0, s, c.rp, c.nbr, rank, new_rp);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(pinned, rank + c.nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  int64_t kept = pinned[0];
+  DBuf<int64_t> sizes(al, kept > 0 ? kept : 1);
+  if (c.nbr > 0) {
+    hipLaunchKernelGGL(k_compact_index, dim3(c.nbr), dim3(256), 0, s, c.rp, c.nbr, c.ci, rank, d_rbs, d_cbs,
+                       new_ci, sizes.p);
+    HIPCHECK(hipGetLastError());
+  }
+  exclusive_scan_i64(al, sizes.p, new_off, kept, s);
+  HIPCHECK(hipMemcpyAsync(pinned, new_off + kept, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  *new_nval = pinned[0];
+  double *nv = static_cast<double *>(al.alloc(sizeof(double) * (size_t)std::max<int64_t>(*new_nval, 1)));
+  if (c.nnzb > 0) {
+    hipLaunchKernelGGL(k_compact_values, dim3(grid_for(c.nnzb * 64, 256)), dim3(256), 0, s, rank, c.nnzb, c.off,
+                       c.values, (const int64_t *)new_off, nv);
+    HIPCHECK(hipGetLastError());
+  }
+  *new_values = nv;
+}
+
+}  // namespace bsmm

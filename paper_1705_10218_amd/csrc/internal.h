@@ -1,0 +1,228 @@
+// internal.h -- shared host-side declarations of libbsmm (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "bsmm.h"
+
+namespace bsmm {
+
+// Thrown inside the library, converted to a status at the ABI boundary.
+struct Error {
+  bsmm_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(bsmm_status code, const std::string &msg);
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define HIPCHECK(x) ::bsmm::hip_check((x), #x, __FILE__, __LINE__)
+
+// Caching device allocator.  All work of one context is ordered on one
+// stream, so a buffer freed here can be handed out again at once: any later
+// use is queued behind the work that used it before.
+class Allocator {
+ public:
+  void init(int device, size_t budget);
+  void *alloc(size_t bytes);
+  void release(void *p);
+  void trim();             // return cached free blocks to HIP
+  size_t held() const { return held_; }
+  size_t peak() const { return peak_; }
+  ~Allocator();
+
+ private:
+  int device_ = 0;
+  size_t budget_ = 0;      // 0 = no cap
+  size_t held_ = 0, peak_ = 0;
+  std::multimap<size_t, void *> free_;   // size -> ptr
+  std::map<void *, size_t> live_;        // ptr -> size
+};
+
+}  // namespace bsmm
+
+struct bsmm_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool timing = false;
+  bsmm_compute_mode mode = BSMM_COMPUTE_FP64;
+  bsmm::Allocator alloc;
+  int64_t *pinned = nullptr;   // small host buffer for size read-backs
+  int live_mats = 0;
+};
+
+struct bsmm_mat_s {
+  bsmm_ctx ctx = nullptr;
+  int32_t nbr = 0, nbc = 0;
+  int64_t nnzb = 0, n_values = 0;
+  std::vector<int32_t> h_rbs, h_cbs;   // block sizes (host copy)
+  int32_t *d_rbs = nullptr, *d_cbs = nullptr;
+  int64_t *d_row_ptr = nullptr;        // nbr+1
+  int32_t *d_col_idx = nullptr;        // nnzb
+  int64_t *d_blk_off = nullptr;        // nnzb+1 element offsets
+  double *d_values = nullptr;
+  bool owns_values = false;
+};
+
+namespace bsmm {
+
+// RAII device buffer from the context allocator.
+template <typename T>
+struct DBuf {
+  Allocator *a = nullptr;
+  T *p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(Allocator &al, size_t count) : a(&al), p(nullptr), n(count) {
+    if (count) p = static_cast<T *>(al.alloc(count * sizeof(T)));
+  }
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept : a(o.a), p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf &operator=(DBuf &&o) noexcept {
+    if (this != &o) { reset(); a = o.a; p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() { if (p && a) a->release(p); p = nullptr; n = 0; }
+  T *release_ownership() { T *q = p; p = nullptr; n = 0; return q; }
+};
+
+// ----------------------------------------------------------- kernel launchers
+// Each launcher enqueues on `s`; sizes are validated by the caller.
+
+// out[i] = sum_{t<i} in[t] for i = 0..n (out has n+1 entries); the total
+// ends in out[n].  `tmp` comes from the allocator.
+void exclusive_scan_i64(Allocator &al, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+void exclusive_scan_i32(Allocator &al, const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+
+// Operand view: rows of op(X) with the original block id of every entry.
+struct OpIndex {
+  int32_t nbr = 0, nbc = 0;          // block grid of op(X)
+  const int64_t *row_ptr = nullptr;  // nbr+1
+  const int32_t *col_idx = nullptr;  // entries, sorted per row
+  const int32_t *blk = nullptr;      // original block id per entry (nullptr = identity)
+  const int32_t *rbs = nullptr, *cbs = nullptr;   // block sizes of op(X) (device)
+  const int64_t *blk_off = nullptr;  // value offsets of the original blocks
+  const double *values = nullptr;
+  bool trans = false;
+  int64_t nnzb = 0;
+  DBuf<int64_t> own_rp;              // storage when transposed
+  DBuf<int32_t> own_ci, own_blk;
+};
+
+// Index transpose of a block-CSR matrix (a0): fills op.{row_ptr,col_idx,blk}
+// with the block-CSR of X^T, entries of each new row in ascending old row.
+void transpose_index(Allocator &al, const bsmm_mat_s &x, OpIndex &op, hipStream_t s);
+
+// Frobenius norm of every block (a1).
+void block_norms(const bsmm_mat_s &x, double *norms, hipStream_t s);
+
+struct SymArgs {
+  const OpIndex *a, *b;
+  // C_old pattern (may be null)
+  const int64_t *cold_rp = nullptr;
+  const int32_t *cold_ci = nullptr;
+  bool use_cold = false;     // include C_old pattern (beta != 0 && !retain)
+  bool retain = false;       // pattern = C_old pattern exactly
+  int32_t nbc = 0;           // block columns of C
+};
+
+// a2: per C block row, number of distinct result block columns.
+void symbolic_count(const SymArgs &g, int64_t *row_nnz, int32_t *max_row, hipStream_t s);
+
+struct FillArgs {
+  SymArgs sym;
+  const int64_t *c_rp = nullptr;   // C row_ptr (from the scan)
+  int32_t *c_ci = nullptr;         // out: C col_idx
+  int32_t *c_row = nullptr;        // out: block row of every C block
+  int64_t *c_size = nullptr;       // out: m*n of every C block
+  int32_t *c_cnt = nullptr;        // out: kept products per C block (zeroed before)
+  int64_t *c_kflops = nullptr;     // out: per block row, sum of m*k*n over kept products
+  int64_t *row_cand = nullptr;     // out: per block row, candidate products (before filters)
+  const double *na = nullptr, *nb = nullptr;   // block norms (null when eps == 0)
+  double eps = 0.0;
+  int32_t max_row = 0;
+};
+
+// a2 (fill) + a4 (count): C col_idx, block sizes, product counts.
+void symbolic_fill(const FillArgs &f, hipStream_t s);
+
+struct StackArgs {
+  const OpIndex *a, *b;
+  const int64_t *c_rp = nullptr;
+  const int32_t *c_ci = nullptr;
+  const int64_t *seg_off = nullptr;  // start of every C block's stack segment
+  int2 *stack = nullptr;             // out: (a_blk, b_blk)
+  const double *na = nullptr, *nb = nullptr;
+  double eps = 0.0;
+  int32_t nbc = 0;
+  int32_t nbr = 0;
+  int32_t max_row = 0;
+};
+
+// a4: stack entries, grouped by C block, ascending k inside a block.  `run`
+// (nnzb of C, zeroed) serves rows too wide for the LDS cursors.
+void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s);
+
+// For every C_old block, store its id at the matching C block (old_blk must
+// be preset to -1).
+void old_block_map(const int64_t *cold_rp, const int32_t *cold_ci, int32_t nbr, const int64_t *c_rp,
+                   const int32_t *c_ci, int32_t *old_blk, hipStream_t s);
+
+// C blocks whose row and column block sizes round up to the same number of
+// 4x4 subtiles (2, 4, 6 or 8 per edge) form one class and one launch.
+struct GemmClass {
+  int mt, nt;             // subtiles per edge (even)
+  int64_t first, count;   // range in the class-ordered C block list
+};
+
+struct GemmArgs {
+  const OpIndex *a, *b;
+  const int32_t *c_list = nullptr;   // C blocks ordered by class
+  const int32_t *c_row = nullptr;
+  const int32_t *c_ci = nullptr;
+  const int64_t *c_off = nullptr;    // value offsets of C blocks
+  const int64_t *seg_off = nullptr;
+  const int2 *stack = nullptr;
+  const int32_t *c_old_blk = nullptr;
+  const int64_t *old_off = nullptr;
+  const double *old_values = nullptr;
+  double *c_values = nullptr;
+  double *c_norm = nullptr;          // out: norm of every C block (may be null)
+  double alpha = 1.0, beta = 0.0;
+  bsmm_compute_mode mode = BSMM_COMPUTE_FP64;
+};
+
+// a5: batched small-GEMM over the stacks, one launch per class.
+void gemm_launch(const GemmArgs &g, const GemmClass &cls, hipStream_t s);
+
+// Group C blocks by subtile class: fills c_list and returns the classes.
+std::vector<GemmClass> group_classes(Allocator &al, const int32_t *c_row, const int32_t *c_ci, int64_t nnzb,
+                                     const int32_t *d_rbs, const int32_t *d_cbs, int32_t *c_list,
+                                     int64_t *pinned, hipStream_t s);
+
+// a6: keep flags from norms, compaction of a block-CSR matrix.
+struct CompactArgs {
+  int32_t nbr = 0;
+  int64_t nnzb = 0;
+  const int64_t *rp = nullptr;
+  const int32_t *ci = nullptr;
+  const int64_t *off = nullptr;
+  const double *values = nullptr;
+  const double *norm = nullptr;
+  double eps = 0.0;
+};
+// Returns the number of kept blocks (synchronises to read it back).  When
+// every block is kept nothing is written and the caller keeps its arrays.
+int64_t count_kept(Allocator &al, const CompactArgs &c, int32_t *keep_prefix_tmp, int64_t *pinned,
+                   hipStream_t s, DBuf<int64_t> &new_rank);
+void compact(Allocator &al, const CompactArgs &c, const int64_t *new_rank, const int32_t *d_rbs,
+             const int32_t *d_cbs, int64_t *new_rp, int32_t *new_ci, int64_t *new_off,
+             int64_t *pinned, double **new_values, int64_t *new_nval, hipStream_t s);
+
+}  // namespace bsmm

@@ -1,0 +1,437 @@
+// sym_kernels.hip -- symbolic phase (block pattern of C), product counts per
+// C block, and stack generation.
+//
+// The result pattern is not known in advance (arXiv:1705.10218, Section 2):
+// block (i,j) of C exists when some k has A(i,k) and B(k,j) stored (plus
+// C_old's blocks when beta != 0, or exactly C_old's under retain_sparsity).
+// One workgroup owns one block row i of C and marks the reachable block
+// columns in a bitmap held in LDS; the bitmap doubles as the map from a
+// block column to its position inside the row (prefix popcounts), so
+// neither a dense column map nor a sort is needed.
+#include "internal.h"
+
+namespace bsmm {
+
+namespace {
+
+constexpr int SYM_THREADS = 256;
+constexpr int32_t MAX_WORDS = 4096;      // bitmap window: 131072 block columns
+constexpr int32_t CNT_CAP = 8192;        // per-row counters kept in LDS up to this
+
+struct OpView {
+  const int64_t *rp;
+  const int32_t *ci;
+  const int32_t *blk;   // null = identity
+  const int32_t *rbs, *cbs;
+};
+
+OpView view(const OpIndex &o) { return OpView{o.row_ptr, o.col_idx, o.blk, o.rbs, o.cbs}; }
+
+__device__ inline void bm_set(uint32_t *bm, int32_t j) { atomicOr(&bm[j >> 5], 1u << (j & 31)); }
+__device__ inline bool bm_test(const uint32_t *bm, int32_t j) { return (bm[j >> 5] >> (j & 31)) & 1u; }
+__device__ inline int32_t bm_slot(const uint32_t *bm, const int32_t *pre, int32_t j) {
+  uint32_t w = bm[j >> 5];
+  return pre[j >> 5] + __popc(w & ((1u << (j & 31)) - 1u));
+}
+
+// position of j in the sorted slice ci[lo, hi), or -1
+__device__ inline int32_t bsearch_slot(const int32_t *ci, int64_t lo, int64_t hi, int32_t j) {
+  int64_t base = lo;
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    int32_t v = ci[mid];
+    if (v == j) return (int32_t)(mid - base);
+    if (v < j) lo = mid + 1; else hi = mid;
+  }
+  return -1;
+}
+
+template <typename T>
+__device__ inline T block_sum(T v, T *sh) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  T t = 0;
+  for (int q = 0; q < nw; q++) t += sh[q];
+  __syncthreads();
+  return t;
+}
+
+// Mark every candidate block column of row i that falls in [j0, j1).
+__device__ inline void mark_candidates(const OpView &A, const OpView &B, int32_t i, int32_t j0, int32_t j1,
+                                       uint32_t *bm) {
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int64_t p = A.rp[i] + wv; p < A.rp[i + 1]; p += nw) {
+    int32_t k = A.ci[p];
+    int64_t q1 = B.rp[k + 1];
+    for (int64_t q = B.rp[k] + lane; q < q1; q += 64) {
+      int32_t j = B.ci[q];
+      if (j >= j0 && j < j1) bm_set(bm, j - j0);
+    }
+  }
+}
+
+__device__ inline void mark_row(const int64_t *rp, const int32_t *ci, int32_t i, int32_t j0, int32_t j1,
+                                uint32_t *bm) {
+  for (int64_t q = rp[i] + threadIdx.x; q < rp[i + 1]; q += blockDim.x) {
+    int32_t j = ci[q];
+    if (j >= j0 && j < j1) bm_set(bm, j - j0);
+  }
+}
+
+// Exclusive prefix popcount over W words (block-wide, simple two-level).
+__device__ inline void word_prefix(const uint32_t *bm, int32_t *pre, int32_t W, int32_t *sh) {
+  int t = threadIdx.x, nt = blockDim.x;
+  int32_t per = (W + nt - 1) / nt;
+  int32_t w0 = t * per, w1 = min(W, w0 + per);
+  int32_t s = 0;
+  for (int32_t w = w0; w < w1; w++) s += __popc(bm[w]);
+  // exclusive scan of s over threads
+  int lane = t & 63, wv = t >> 6, nw = nt >> 6;
+  int32_t inc = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int32_t o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  __syncthreads();
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  int32_t base = 0;
+  for (int q = 0; q < wv; q++) base += sh[q];
+  int32_t run = base + inc - s;
+  for (int32_t w = w0; w < w1; w++) {
+    pre[w] = run;
+    run += __popc(bm[w]);
+  }
+  (void)nw;
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ a2: count
+__global__ __launch_bounds__(SYM_THREADS) void k_sym_count(OpView A, OpView B, const int64_t *cold_rp,
+                                                           const int32_t *cold_ci, int use_cold, int32_t nbc,
+                                                           int64_t *row_nnz, int32_t *max_row) {
+  extern __shared__ uint32_t bm[];
+  __shared__ int64_t red[SYM_THREADS / 64];
+  int32_t i = blockIdx.x;
+  int32_t words_total = (nbc + 31) >> 5;
+  if (words_total == 0) {
+    if (threadIdx.x == 0) row_nnz[i] = 0;
+    return;
+  }
+  int32_t W = min(words_total, MAX_WORDS);
+  int32_t nwin = (words_total + W - 1) / W;
+  int64_t total = 0;
+  for (int32_t win = 0; win < nwin; win++) {
+    int32_t j0 = win * W * 32, j1 = min(nbc, j0 + W * 32);
+    for (int32_t t = threadIdx.x; t < W; t += blockDim.x) bm[t] = 0u;
+    __syncthreads();
+    if (use_cold) mark_row(cold_rp, cold_ci, i, j0, j1, bm);
+    mark_candidates(A, B, i, j0, j1, bm);
+    __syncthreads();
+    int64_t c = 0;
+    for (int32_t t = threadIdx.x; t < W; t += blockDim.x) c += __popc(bm[t]);
+    total += block_sum<int64_t>(c, red);
+  }
+  if (threadIdx.x == 0) {
+    row_nnz[i] = total;
+    atomicMax(max_row, (int32_t)total);
+  }
+}
+
+// ------------------------------------------- a2 fill + a4 product counts
+// Writes C's col_idx for row i, the block row / size of every C block, the
+// number of products per C block that pass the on-the-fly filter
+// (kept iff !(||A_ik|| * ||B_kj|| < eps)) and the row's sum of k over kept
+// products (for the useful flop count).
+__global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, const int64_t *cold_rp,
+                                                          const int32_t *cold_ci, int use_cold, int retain,
+                                                          int32_t nbc, const int64_t *c_rp, int32_t *c_ci,
+                                                          int32_t *c_row, int64_t *c_size, int32_t *c_cnt,
+                                                          int64_t *row_kmn, int64_t *row_cand, const double *na,
+                                                          const double *nb, double eps, int32_t cnt_cap) {
+  extern __shared__ uint32_t sm[];
+  __shared__ int32_t shi[SYM_THREADS / 64];
+  __shared__ int64_t shl[SYM_THREADS / 64];
+  int32_t i = blockIdx.x;
+  int32_t words_total = (nbc + 31) >> 5;
+  if (words_total == 0) {
+    if (threadIdx.x == 0) { row_kmn[i] = 0; row_cand[i] = 0; }
+    return;
+  }
+  int32_t W = min(words_total, MAX_WORDS);
+  int32_t nwin = (words_total + W - 1) / W;
+  uint32_t *bm = sm;
+  int32_t *pre = reinterpret_cast<int32_t *>(sm + W);
+  int32_t *cnt = pre + W;
+  const int64_t cbase = c_rp[i];
+  const int32_t R = (int32_t)(c_rp[i + 1] - cbase);
+  const int32_t m = A.rbs[i];
+  int64_t wbase = cbase;
+  for (int32_t win = 0; win < nwin; win++) {
+    int32_t j0 = win * W * 32, j1 = min(nbc, j0 + W * 32);
+    for (int32_t t = threadIdx.x; t < W; t += blockDim.x) bm[t] = 0u;
+    __syncthreads();
+    if (retain) {
+      mark_row(cold_rp, cold_ci, i, j0, j1, bm);
+    } else {
+      if (use_cold) mark_row(cold_rp, cold_ci, i, j0, j1, bm);
+      mark_candidates(A, B, i, j0, j1, bm);
+    }
+    __syncthreads();
+    word_prefix(bm, pre, W, shi);
+    for (int32_t t = threadIdx.x; t < W; t += blockDim.x) {
+      uint32_t w = bm[t];
+      int64_t pos = wbase + pre[t];
+      while (w) {
+        int b = __ffs(w) - 1;
+        w &= w - 1u;
+        int32_t j = j0 + t * 32 + b;
+        c_ci[pos] = j;
+        c_row[pos] = i;
+        c_size[pos] = (int64_t)m * B.cbs[j];
+        pos++;
+      }
+    }
+    int32_t last = W - 1;
+    int64_t wcount = (int64_t)pre[last] + __popc(bm[last]);
+    __syncthreads();
+    wbase += wcount;
+  }
+  // counts of kept products per C block
+  const bool lds_slot = (nwin == 1);
+  const bool lds_cnt = (R <= cnt_cap);
+  if (lds_cnt)
+    for (int32_t t = threadIdx.x; t < R; t += blockDim.x) cnt[t] = 0;
+  __syncthreads();
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int64_t kmn = 0, cand = 0;
+  for (int64_t p = A.rp[i] + wv; p < A.rp[i + 1]; p += nw) {
+    int32_t k = A.ci[p];
+    int32_t kk = A.cbs[k];
+    double nA = na ? na[A.blk ? A.blk[p] : (int32_t)p] : 0.0;
+    int64_t q1 = B.rp[k + 1];
+    if (lane == 0) cand += q1 - B.rp[k];
+    for (int64_t q = B.rp[k] + lane; q < q1; q += 64) {
+      int32_t j = B.ci[q];
+      if (na && (nA * nb[B.blk ? B.blk[q] : (int32_t)q] < eps)) continue;
+      int32_t slot;
+      if (lds_slot) slot = bm_test(bm, j) ? bm_slot(bm, pre, j) : -1;
+      else slot = bsearch_slot(c_ci, cbase, cbase + R, j);
+      if (slot < 0) continue;   // only under retain_sparsity
+      if (lds_cnt) atomicAdd(&cnt[slot], 1);
+      else atomicAdd(&c_cnt[cbase + slot], 1);
+      kmn += (int64_t)kk * B.cbs[j];
+    }
+  }
+  __syncthreads();
+  if (lds_cnt)
+    for (int32_t t = threadIdx.x; t < R; t += blockDim.x) c_cnt[cbase + t] = cnt[t];
+  int64_t tot = block_sum<int64_t>(kmn, shl);
+  int64_t tcand = block_sum<int64_t>(cand, shl);
+  if (threadIdx.x == 0) {
+    row_kmn[i] = tot * m;
+    row_cand[i] = tcand;
+  }
+}
+
+// ----------------------------------------------------- C_old block map
+__global__ void k_old_map(const int64_t *cold_rp, const int32_t *cold_ci, const int64_t *c_rp,
+                          const int32_t *c_ci, int32_t *old_blk) {
+  int32_t i = blockIdx.x;
+  int64_t c0 = c_rp[i], c1 = c_rp[i + 1];
+  for (int64_t q = cold_rp[i] + threadIdx.x; q < cold_rp[i + 1]; q += blockDim.x) {
+    int32_t s = bsearch_slot(c_ci, c0, c1, cold_ci[q]);
+    if (s >= 0) old_blk[c0 + s] = (int32_t)q;
+  }
+}
+
+// ------------------------------------------------------ a4: stack fill
+// One wavefront per C block row walks the k of row i in ascending order;
+// for each k its lanes take the block columns j of row k of op(B).  A given
+// j appears once per k, so the per-C-block write cursors never collide
+// inside one step, and successive steps are ordered: every C block's
+// segment comes out sorted by k, identically on every run.
+__global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t nbc, const int64_t *c_rp,
+                                                   const int32_t *c_ci, const int64_t *seg_off, int2 *stack,
+                                                   const double *na, const double *nb, double eps,
+                                                   int32_t cnt_cap, int32_t *run) {
+  extern __shared__ uint32_t sm[];
+  int32_t i = blockIdx.x;
+  int lane = threadIdx.x;
+  int32_t words_total = (nbc + 31) >> 5;
+  int32_t W = min(words_total, MAX_WORDS);
+  bool lds_slot = words_total <= MAX_WORDS;
+  const int64_t cbase = c_rp[i];
+  const int32_t R = (int32_t)(c_rp[i + 1] - cbase);
+  if (R == 0) return;
+  bool lds_cnt = R <= cnt_cap;
+  uint32_t *bm = sm;
+  int32_t *pre = reinterpret_cast<int32_t *>(sm + W);
+  int32_t *cnt = pre + W;
+  if (lds_slot) {
+    for (int32_t t = lane; t < W; t += 64) bm[t] = 0u;
+    __syncthreads();
+    for (int64_t e = cbase + lane; e < cbase + R; e += 64) bm_set(bm, c_ci[e]);
+    __syncthreads();
+    // prefix popcount (single wavefront)
+    int32_t per = (W + 63) / 64;
+    int32_t w0 = lane * per, w1 = min(W, w0 + per);
+    int32_t s = 0;
+    for (int32_t w = w0; w < w1; w++) s += __popc(bm[w]);
+    int32_t inc = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      int32_t o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    int32_t r = inc - s;
+    for (int32_t w = w0; w < w1; w++) {
+      pre[w] = r;
+      r += __popc(bm[w]);
+    }
+  }
+  if (lds_cnt)
+    for (int32_t t = lane; t < R; t += 64) cnt[t] = 0;
+  __syncthreads();
+  for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) {
+    int32_t k = A.ci[p];
+    int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
+    double nA = na ? na[ablk] : 0.0;
+    int64_t q1 = B.rp[k + 1];
+    for (int64_t q = B.rp[k] + lane; q < q1; q += 64) {
+      int32_t j = B.ci[q];
+      int32_t bblk = B.blk ? B.blk[q] : (int32_t)q;
+      if (na && (nA * nb[bblk] < eps)) continue;
+      int32_t slot;
+      if (lds_slot) slot = bm_test(bm, j) ? bm_slot(bm, pre, j) : -1;
+      else slot = bsearch_slot(c_ci, cbase, cbase + R, j);
+      if (slot < 0) continue;
+      int32_t at;
+      if (lds_cnt) { at = cnt[slot]; cnt[slot] = at + 1; }
+      else at = atomicAdd(&run[cbase + slot], 1);
+      stack[seg_off[cbase + slot] + at] = make_int2(ablk, bblk);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------- class grouping
+// Subtile class of a block size: 4x4 subtiles, rounded up to an even count
+// (2, 4, 6, 8 -> class 0..3).
+__device__ inline int size_class(int s) { return (((s + 3) >> 2) + 1) / 2 - 1; }
+
+__global__ void k_class_count(const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs, const int32_t *cbs,
+                              int64_t n, int32_t *cls, unsigned long long *counts) {
+  __shared__ unsigned int h[16];
+  if (threadIdx.x < 16) h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) {
+    int k = size_class(rbs[c_row[c]]) * 4 + size_class(cbs[c_ci[c]]);
+    cls[c] = k;
+    atomicAdd(&h[k], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 16 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+__global__ void k_class_fill(const int32_t *cls, int64_t n, unsigned long long *cursor, int32_t *c_list) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) {
+    unsigned long long at = atomicAdd(&cursor[cls[c]], 1ull);
+    c_list[at] = (int32_t)c;
+  }
+}
+
+}  // namespace
+
+void symbolic_count(const SymArgs &g, int64_t *row_nnz, int32_t *max_row, hipStream_t s) {
+  int32_t nbr = g.a->nbr;
+  if (nbr == 0) return;
+  int32_t words_total = (g.nbc + 31) >> 5;
+  int32_t W = std::min(words_total, MAX_WORDS);
+  if (W == 0) {
+    HIPCHECK(hipMemsetAsync(row_nnz, 0, sizeof(int64_t) * nbr, s));
+    return;
+  }
+  hipLaunchKernelGGL(k_sym_count, dim3(nbr), dim3(SYM_THREADS), W * sizeof(uint32_t), s, view(*g.a), view(*g.b),
+                     g.cold_rp, g.cold_ci, g.use_cold ? 1 : 0, g.nbc, row_nnz, max_row);
+  HIPCHECK(hipGetLastError());
+}
+
+void symbolic_fill(const FillArgs &f, hipStream_t s) {
+  int32_t nbr = f.sym.a->nbr;
+  if (nbr == 0) return;
+  int32_t words_total = (f.sym.nbc + 31) >> 5;
+  int32_t W = std::min(words_total, MAX_WORDS);
+  if (W == 0) W = 1;
+  int32_t cap = std::min(f.max_row, CNT_CAP);
+  size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 4;
+  hipLaunchKernelGGL(k_sym_fill, dim3(nbr), dim3(SYM_THREADS), lds, s, view(*f.sym.a), view(*f.sym.b),
+                     f.sym.cold_rp, f.sym.cold_ci, f.sym.use_cold ? 1 : 0, f.sym.retain ? 1 : 0, f.sym.nbc,
+                     f.c_rp, f.c_ci, f.c_row, f.c_size, f.c_cnt, f.c_kflops, f.row_cand, f.na, f.nb, f.eps, cap);
+  HIPCHECK(hipGetLastError());
+}
+
+void old_block_map(const int64_t *cold_rp, const int32_t *cold_ci, int32_t nbr, const int64_t *c_rp,
+                   const int32_t *c_ci, int32_t *old_blk, hipStream_t s) {
+  if (nbr == 0) return;
+  hipLaunchKernelGGL(k_old_map, dim3(nbr), dim3(256), 0, s, cold_rp, cold_ci, c_rp, c_ci, old_blk);
+  HIPCHECK(hipGetLastError());
+}
+
+void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
+  if (g.nbr == 0) return;
+  int32_t words_total = (g.nbc + 31) >> 5;
+  int32_t W = std::min(words_total, MAX_WORDS);
+  if (W == 0) W = 1;
+  int32_t cap = std::min(g.max_row, CNT_CAP);
+  size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 4;
+  hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr), dim3(64), lds, s, view(*g.a), view(*g.b), g.nbc, g.c_rp, g.c_ci,
+                     g.seg_off, g.stack, g.na, g.nb, g.eps, cap, run);
+  HIPCHECK(hipGetLastError());
+}
+
+std::vector<GemmClass> group_classes(Allocator &al, const int32_t *c_row, const int32_t *c_ci, int64_t nnzb,
+                                     const int32_t *d_rbs, const int32_t *d_cbs, int32_t *c_list,
+                                     int64_t *pinned, hipStream_t s) {
+  std::vector<GemmClass> out;
+  if (nnzb == 0) return out;
+  DBuf<int32_t> cls(al, nnzb);
+  DBuf<unsigned long long> counts(al, 32);
+  HIPCHECK(hipMemsetAsync(counts.p, 0, 32 * sizeof(unsigned long long), s));
+  int grid = (int)((nnzb + 255) / 256);
+  hipLaunchKernelGGL(k_class_count, dim3(grid), dim3(256), 0, s, c_row, c_ci, d_rbs, d_cbs, nnzb, cls.p, counts.p);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(pinned, counts.p, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  std::vector<unsigned long long> start(16, 0);
+  unsigned long long run = 0;
+  for (int k = 0; k < 16; k++) {
+    int64_t cnt = pinned[k];
+    start[k] = run;
+    if (cnt > 0) {
+      GemmClass g;
+      g.mt = 2 * (k / 4 + 1);
+      g.nt = 2 * (k % 4 + 1);
+      g.first = (int64_t)run;
+      g.count = cnt;
+      out.push_back(g);
+    }
+    run += (unsigned long long)cnt;
+  }
+  // cursor starts at each class start
+  for (int k = 0; k < 16; k++) pinned[k] = (int64_t)start[k];
+  HIPCHECK(hipMemcpyAsync(counts.p, pinned, 16 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_class_fill, dim3(grid), dim3(256), 0, s, (const int32_t *)cls.p, nnzb, counts.p, c_list);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(s));   // pinned is reused by the caller
+  return out;
+}
+
+}  // namespace bsmm

@@ -1,0 +1,339 @@
+"""GPU path vs the CPU oracle, through the C ABI (needs an MI355X).
+
+Bar (from the method's contract): at eps = 0 the block pattern of C equals
+the oracle's exactly and the FP64 values agree within relative Frobenius
+error 1e-12; product counts and useful flops are integers and must match
+exactly.  At eps > 0 pattern differences are allowed only for blocks whose
+norm (or norm product) lies within 1e-12 relative of eps (GPU and CPU norms
+may differ in the last bits), and their number is reported.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_10218_amd import inputs
+from _util import dense, random_bcsr, rel_fro, same_pattern
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _log(msg):
+    sys.stdout.write(msg + "\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1705_10218_amd import bsmm
+    return bsmm
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.Context(0)
+    yield c
+
+
+def _gpu_mul(B, ctx, ta, tb, alpha, a, b, beta=0.0, c=None, eps=0.0, retain=False):
+    A = B.Matrix.from_host(ctx, a)
+    Bm = A if b is a else B.Matrix.from_host(ctx, b)
+    C0 = B.Matrix.from_host(ctx, c) if c is not None else None
+    C, info = B.multiply(ctx, ta, tb, alpha, A, Bm, beta, C0, eps, retain)
+    host = C.to_host()
+    for m in (C, A, Bm, C0):
+        if m is not None:
+            m.close()
+    return host, info
+
+
+def _check_exact(host, info, ref, tol=TOL):
+    assert np.array_equal(host.row_ptr, ref.row_ptr), "row_ptr differs"
+    assert np.array_equal(host.col_idx, ref.col_idx), "col_idx differs"
+    assert info.n_products == ref.n_products
+    assert info.n_candidates == ref.n_candidates
+    assert info.useful_flops == ref.useful_flops
+    if ref.values.size:
+        assert rel_fro(host.values, ref.values) <= tol
+    else:
+        assert host.values.size == 0
+
+
+# ------------------------------------------------------------------ norms
+def test_block_norms(B, ctx):
+    import torch
+    rng = np.random.default_rng(1)
+    for max_bs in (5, 23, 32):
+        x = random_bcsr(rng, 37, 29, p=0.4, max_bs=max_bs)
+        _log(f"norms max_bs={max_bs} nnzb={x.nnzb}")
+        X = B.Matrix.from_host(ctx, x)
+        got = B.block_norms(X).cpu().numpy()
+        ref = oracle.block_norms(x)
+        assert np.max(np.abs(got - ref) / ref) <= 1e-14
+        X.close()
+
+
+# ------------------------------------------------------- small random cases
+@pytest.mark.parametrize("ta", ["N", "T"])
+@pytest.mark.parametrize("tb", ["N", "T"])
+@pytest.mark.parametrize("seed", range(3))
+def test_random_small(B, ctx, ta, tb, seed):
+    rng = np.random.default_rng([200, seed])
+    nbr, nk, nbc = rng.integers(1, 40, 3)
+    rbs = rng.integers(1, 33, nbr)
+    kbs = rng.integers(1, 33, nk)
+    cbs = rng.integers(1, 33, nbc)
+    a = random_bcsr(rng, nbr, nk, rbs, kbs, 0.3, empty_rows=(0,)) if ta == "N" else random_bcsr(rng, nk, nbr, kbs, rbs, 0.3)
+    b = random_bcsr(rng, nk, nbc, kbs, cbs, 0.3) if tb == "N" else random_bcsr(rng, nbc, nk, cbs, kbs, 0.3)
+    _log(f"random_small {ta}{tb} seed={seed} grid={nbr}x{nk}x{nbc}")
+    host, info = _gpu_mul(B, ctx, ta, tb, 1.0, a, b)
+    ref = oracle.multiply(ta, tb, 1.0, a, b)
+    _check_exact(host, info, ref)
+
+
+@pytest.mark.parametrize("alpha,beta", [(1.0, 1.0), (-0.5, 2.0), (0.0, 1.5), (2.0, 0.0)])
+def test_alpha_beta(B, ctx, alpha, beta):
+    rng = np.random.default_rng(300)
+    sizes_r = rng.integers(1, 14, 30)
+    sizes_k = rng.integers(1, 14, 25)
+    sizes_c = rng.integers(1, 14, 28)
+    a = random_bcsr(rng, 30, 25, sizes_r, sizes_k, 0.3)
+    b = random_bcsr(rng, 25, 28, sizes_k, sizes_c, 0.3)
+    c = random_bcsr(rng, 30, 28, sizes_r, sizes_c, 0.3)
+    _log(f"alpha_beta {alpha} {beta}")
+    host, info = _gpu_mul(B, ctx, "N", "N", alpha, a, b, beta, c)
+    ref = oracle.multiply("N", "N", alpha, a, b, beta, c)
+    _check_exact(host, info, ref)
+
+
+def test_beta_zero_ignores_nan_c_old(B, ctx):
+    rng = np.random.default_rng(301)
+    a = random_bcsr(rng, 12, 12, p=0.4)
+    b = random_bcsr(rng, 12, 12, a.cbs, None, p=0.4)
+    c = random_bcsr(rng, 12, 12, a.rbs, b.cbs, p=0.5)
+    c.values[:] = np.nan
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, 0.0, c)
+    ref = oracle.multiply("N", "N", 1.0, a, b)
+    assert np.all(np.isfinite(host.values))
+    _check_exact(host, info, ref)
+
+
+def test_retain_sparsity(B, ctx):
+    rng = np.random.default_rng(302)
+    a = random_bcsr(rng, 20, 18, p=0.3, max_bs=13)
+    b = random_bcsr(rng, 18, 22, a.cbs, None, p=0.3, max_bs=13)
+    c = random_bcsr(rng, 20, 22, a.rbs, b.cbs, p=0.2)
+    for beta in (0.0, 0.5):
+        host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, beta, c, retain=True)
+        ref = oracle.multiply("N", "N", 1.0, a, b, beta, c, retain_sparsity=True)
+        _check_exact(host, info, ref)
+        assert same_pattern(host, c)
+
+
+# --------------------------------------------------------------- identities
+def test_identity_bit_exact(B, ctx):
+    rng = np.random.default_rng(303)
+    a = random_bcsr(rng, 40, 35, p=0.3, max_bs=23)
+    host, _ = _gpu_mul(B, ctx, "N", "N", 1.0, a, inputs.identity(a.cbs))
+    assert same_pattern(host, a) and np.array_equal(host.values, a.values)
+    host, _ = _gpu_mul(B, ctx, "N", "N", 1.0, inputs.identity(a.rbs), a)
+    assert same_pattern(host, a) and np.array_equal(host.values, a.values)
+
+
+def test_same_handle_square(B, ctx):
+    """A == B (the X^2 of the sign iteration) through one handle."""
+    a, _, _ = inputs.dft_like_pair(300, config=93, cutoff=5.0)
+    A = B.Matrix.from_host(ctx, a)
+    C, info = B.multiply(ctx, "N", "N", 1.0, A, A)
+    host = C.to_host()
+    C.close()
+    A.close()
+    _check_exact(host, info, oracle.multiply("N", "N", 1.0, a, a))
+
+
+def test_deterministic(B, ctx):
+    a, b, _ = inputs.dft_like_pair(400, config=94, cutoff=6.0)
+    h1, _ = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
+    h2, _ = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
+    assert same_pattern(h1, h2) and np.array_equal(h1.values, h2.values)
+
+
+# ------------------------------------------------------------ workloads
+def test_tiny_workload(B, ctx):
+    """100 x 100 blocks of 5 x 5, p = 0.2, diagonal present; beta = 0, eps = 0."""
+    a, b = inputs.config_tiny(0), inputs.config_tiny(1)
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
+    _check_exact(host, info, oracle.multiply("N", "N", 1.0, a, b, nthreads=4))
+
+
+def test_dft_like_small_full(B, ctx):
+    """DFT-like structure at a size the oracle finishes in seconds: full compare."""
+    a, b, _ = inputs.dft_like_pair(700, config=95, sizes=(5, 13), cutoff=7.0)
+    for eps in (0.0, 1e-10):
+        _log(f"dft700 eps={eps}")
+        host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=eps)
+        _check_exact(host, info, oracle.multiply("N", "N", 1.0, a, b, eps=eps, nthreads=8))
+
+
+def test_dft_like_mixed_23(B, ctx):
+    a, b, _ = inputs.dft_like_pair(500, config=96, sizes=(5, 13, 23), cutoff=6.5)
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
+    _check_exact(host, info, oracle.multiply("N", "N", 1.0, a, b, nthreads=8))
+
+
+def _sampled_rows_check(host, info, ref_rows, rows):
+    assert info.useful_flops > 0
+    off = inputs.BlockCSR(host.rbs, host.cbs, host.row_ptr, host.col_idx, host.values).block_offsets()
+    roff = inputs.BlockCSR(ref_rows.rbs, ref_rows.cbs, ref_rows.row_ptr, ref_rows.col_idx,
+                           ref_rows.values).block_offsets()
+    num = den = 0.0
+    for i in rows:
+        g0, g1 = host.row_ptr[i], host.row_ptr[i + 1]
+        r0, r1 = ref_rows.row_ptr[i], ref_rows.row_ptr[i + 1]
+        assert np.array_equal(host.col_idx[g0:g1], ref_rows.col_idx[r0:r1]), f"row {i} pattern"
+        gv = host.values[off[g0]:off[g1]]
+        rv = ref_rows.values[roff[r0]:roff[r1]]
+        num += float(np.sum((gv - rv) ** 2))
+        den += float(np.sum(rv ** 2))
+    assert math.sqrt(num / den) <= TOL
+
+
+def test_dft_like_full_size_sampled(B, ctx):
+    """The 4,000-atom {5,13} workload in the benchmark's launch configuration;
+    32 seeded block rows are recomputed by the oracle and compared."""
+    a, b, _ = inputs.config_dft()
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=1e-10)
+    rows = np.sort(np.random.default_rng(97).choice(a.nbr, 32, replace=False)).astype(np.int32)
+    ref = oracle.multiply("N", "N", 1.0, a, b, eps=1e-10, rows=rows)
+    _sampled_rows_check(host, info, ref, rows)
+    # symbolic-pattern invariant at full size: every block reachable within
+    # 2 cutoffs appears exactly once per row, rows sorted
+    assert np.all(np.diff(host.row_ptr) >= 0)
+    for i in range(0, a.nbr, 97):
+        seg = host.col_idx[host.row_ptr[i]:host.row_ptr[i + 1]]
+        assert np.all(np.diff(seg) > 0)
+
+
+# ------------------------------------------------------------------ filters
+def _near(vals, eps):
+    return np.abs(vals - eps) <= 1e-12 * eps
+
+
+def test_filters_dft_like(B, ctx):
+    a, b, _ = inputs.dft_like_pair(500, config=98, sizes=(5, 13), cutoff=7.0, decay=1.0)
+    # eps inside the spread of block-norm products so both phases act
+    eps = 1e-3
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=eps)
+    ref = oracle.multiply("N", "N", 1.0, a, b, eps=eps, nthreads=8)
+    assert ref.n_products < ref.n_candidates
+    full = oracle.multiply("N", "N", 1.0, a, b, nthreads=8)
+    assert ref.nnzb < full.nnzb
+    # near ties: count them, they must be none here to compare exactly
+    na, nb = oracle.block_norms(a), oracle.block_norms(b)
+    _log(f"filters: products {ref.n_products}/{ref.n_candidates}, blocks {ref.nnzb}/{full.nnzb}")
+    _check_exact(host, info, ref)
+    assert not np.any(_near(na, eps) | _near(nb, eps))
+
+
+def test_filter_ties_exact(B, ctx):
+    one = np.array([1], np.int32)
+    two = np.array([1, 1], np.int32)
+    a = inputs.BlockCSR(one, two, np.array([0, 2], np.int64), np.array([0, 1], np.int32), np.array([0.5, 0.25]))
+    b = inputs.BlockCSR(two, one, np.array([0, 1, 2], np.int64), np.array([0, 0], np.int32), np.array([0.25, 1.0]))
+    for eps, nprod, val in ((0.125, 2, 0.375), (math.nextafter(0.125, 1.0), 1, 0.25), (math.inf, 0, None)):
+        host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=eps)
+        assert info.n_products == nprod
+        if val is None:
+            assert host.nnzb == 0
+        else:
+            assert host.nnzb == 1 and host.values[0] == val
+
+
+def test_filter_entry_point(B, ctx):
+    rng = np.random.default_rng(304)
+    x = random_bcsr(rng, 30, 30, p=0.5, max_bs=13)
+    norms = oracle.block_norms(x)
+    eps = float(np.median(norms))
+    X = B.Matrix.from_host(ctx, x)
+    F = B.filter(X, eps)
+    host = F.to_host()
+    F.close()
+    X.close()
+    ref = oracle.filter_blocks(x, eps)
+    assert same_pattern(host, ref) and np.array_equal(host.values, ref.values)
+
+
+# ----------------------------------------------------------------- edges
+def test_empty_and_degenerate(B, ctx):
+    z = inputs.BlockCSR(np.array([3, 2], np.int32), np.array([4], np.int32), np.zeros(3, np.int64),
+                        np.zeros(0, np.int32), np.zeros(0))
+    y = inputs.BlockCSR(np.array([4], np.int32), np.array([2, 2], np.int32), np.array([0, 2], np.int64),
+                        np.array([0, 1], np.int32), np.ones(16))
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, z, y)
+    assert host.nnzb == 0 and list(host.row_ptr) == [0, 0, 0] and info.n_products == 0
+    # product with no common k: empty result
+    a = inputs.BlockCSR(np.array([2], np.int32), np.array([3, 3], np.int32), np.array([0, 1], np.int64),
+                        np.array([0], np.int32), np.ones(6))
+    b = inputs.BlockCSR(np.array([3, 3], np.int32), np.array([2], np.int32), np.array([0, 0, 1], np.int64),
+                        np.array([0], np.int32), np.ones(6))
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
+    assert host.nnzb == 0 and info.n_candidates == 0
+
+
+def test_errors(B, ctx):
+    import torch
+    rng = np.random.default_rng(305)
+    a = random_bcsr(rng, 4, 5, p=0.5)
+    b = random_bcsr(rng, 5, 4, a.cbs[::-1].copy(), None, p=0.5)
+    A = B.Matrix.from_host(ctx, a)
+    Bm = B.Matrix.from_host(ctx, b)
+    if not np.array_equal(a.cbs, b.rbs):
+        with pytest.raises(B.BsmmError) as e:
+            B.multiply(ctx, "N", "N", 1.0, A, Bm)
+        assert e.value.status == 3
+    with pytest.raises(B.BsmmError) as e:
+        B.multiply(ctx, "X", "N", 1.0, A, Bm)
+    assert e.value.status == 1
+    sqr = random_bcsr(rng, 4, 4, np.array([2, 3, 2, 1]), np.array([2, 3, 2, 1]), p=0.5)
+    Q = B.Matrix.from_host(ctx, sqr)
+    with pytest.raises(B.BsmmError) as e:
+        B.multiply(ctx, "N", "N", 1.0, Q, Q, beta=1.0)   # beta != 0 without C_old
+    assert e.value.status == 1
+    Q.close()
+    # malformed index
+    v = torch.zeros(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.BsmmError) as e:
+        B.Matrix.create(ctx, [2, 2], [2, 2], [0, 2, 2], [1, 0], v)
+    assert e.value.status == 2
+    # block above 32
+    big = inputs.BlockCSR(np.array([33], np.int32), np.array([33], np.int32), np.array([0, 1], np.int64),
+                          np.array([0], np.int32), np.ones(33 * 33))
+    G = B.Matrix.from_host(ctx, big)
+    with pytest.raises(B.BsmmError) as e:
+        B.multiply(ctx, "N", "N", 1.0, G, G)
+    assert e.value.status == 7
+    # aliasing C_old values with an operand
+    sq = random_bcsr(rng, 3, 3, np.array([2, 2, 2]), np.array([2, 2, 2]), p=1.0)
+    S = B.Matrix.from_host(ctx, sq)
+    with pytest.raises(B.BsmmError) as e:
+        B.multiply(ctx, "N", "N", 1.0, S, S, 1.0, S)
+    assert e.value.status == 4
+    # budget: a context capped at 1 MiB cannot hold a large result
+    small = B.Context(0, budget_bytes=1 << 20)
+    x, y, _ = inputs.dft_like_pair(300, config=99, cutoff=5.0)
+    X = B.Matrix.from_host(small, x)
+    Y = B.Matrix.from_host(small, y)
+    with pytest.raises(B.BsmmError) as e:
+        B.multiply(small, "N", "N", 1.0, X, Y)
+    assert e.value.status == 5
+    for m in (X, Y, G, S, A, Bm):
+        m.close()
+    small.close()
