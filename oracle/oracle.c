@@ -179,7 +179,9 @@ typedef struct {
   int retain;
   int has_cold;        /* C_old is present (needed when beta != 0 or retain) */
   row_out *rows;
-  int32_t next_row;    /* shared work counter */
+  const int32_t *sel;  /* rows to compute (NULL = all rows)       */
+  int64_t n_sel;
+  int64_t next;        /* shared work counter over rows or sel   */
   pthread_mutex_t lock;
 } mul_job;
 
@@ -274,11 +276,13 @@ static void *worker(void *arg) {
   int32_t nbc = J->b->nbc;
   double **acc = (double **)calloc((size_t)(nbc ? nbc : 1), sizeof(double *));
   int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nbc ? nbc : 1));
+  int64_t total = J->sel ? J->n_sel : J->a->nbr;
   for (;;) {
     pthread_mutex_lock(&J->lock);
-    int32_t i = J->next_row++;
+    int64_t t = J->next++;
     pthread_mutex_unlock(&J->lock);
-    if (i >= J->a->nbr) break;
+    if (t >= total) break;
+    int32_t i = J->sel ? J->sel[t] : (int32_t)t;
     do_row(J, i, acc, touched);
   }
   free(acc); free(touched);
@@ -300,8 +304,9 @@ int oracle_block_norms(int32_t nbr, int32_t nbc, const int32_t *rbs, const int32
 /*
  * Full multiply.  transa/transb are 'N' or 'T'.  C_old may be absent
  * (c_nbr < 0) only when beta == 0 and retain == 0.  rows_sel, when not NULL,
- * restricts the computation to the listed block rows of the result (the
- * other rows come back empty) -- used to time or check a sample of rows.
+ * restricts the computation to the listed (distinct) block rows of the
+ * result (the other rows come back empty) -- used to time or check a sample
+ * of rows.  Rows are shared among nthreads threads either way.
  * Returns 0 on success, a negative code on bad arguments.
  */
 int oracle_multiply(char transa, char transb, double alpha,
@@ -345,20 +350,23 @@ int oracle_multiply(char transa, char transb, double alpha,
     J.alpha = alpha; J.beta = beta; J.eps = eps; J.retain = retain; J.has_cold = has_cold;
     J.rows = (row_out *)calloc((size_t)(A.nbr ? A.nbr : 1), sizeof(row_out));
     pthread_mutex_init(&J.lock, NULL);
+    J.sel = NULL;
+    J.n_sel = 0;
     if (rows_sel) {
-      /* only the selected rows; done serially in the order given */
-      int32_t nbc = B.nbc;
-      double **acc = (double **)calloc((size_t)(nbc ? nbc : 1), sizeof(double *));
-      int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nbc ? nbc : 1));
-      for (int64_t s = 0; s < n_rows_sel; s++) {
-        int32_t i = rows_sel[s];
-        if (i < 0 || i >= A.nbr) continue;
-        free(J.rows[i].cols); free(J.rows[i].val);
-        do_row(&J, i, acc, touched);
+      /* only the selected rows (distinct, in range) */
+      for (int64_t s = 0; s < n_rows_sel; s++)
+        if (rows_sel[s] < 0 || rows_sel[s] >= A.nbr) { rc = -6; break; }
+      char *seen = (char *)calloc((size_t)(A.nbr ? A.nbr : 1), 1);
+      for (int64_t s = 0; rc == 0 && s < n_rows_sel; s++) {
+        if (seen[rows_sel[s]]) rc = -7;
+        seen[rows_sel[s]] = 1;
       }
-      free(acc); free(touched);
-    } else {
-      J.next_row = 0;
+      free(seen);
+      J.sel = rows_sel;
+      J.n_sel = n_rows_sel;
+    }
+    if (rc == 0) {
+      J.next = 0;
       int nt = nthreads > 0 ? nthreads : 1;
       pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nt);
       for (int t = 0; t < nt; t++) pthread_create(&th[t], NULL, worker, &J);
@@ -366,6 +374,10 @@ int oracle_multiply(char transa, char transb, double alpha,
       free(th);
     }
     pthread_mutex_destroy(&J.lock);
+    if (rc != 0) {
+      free(J.rows); free(na); free(nb);
+      goto done;
+    }
     /* assemble block CSR */
     oracle_result *R = (oracle_result *)calloc(1, sizeof(oracle_result));
     R->nbr = A.nbr; R->nbc = B.nbc;

@@ -148,8 +148,29 @@ static void free_mat(bsmm_mat_s *m) {
   al.release(m->d_row_ptr);
   al.release(m->d_col_idx);
   al.release(m->d_blk_off);
+  al.release(m->d_order);
   if (m->owns_values) al.release(m->d_values);
   delete m;
+}
+
+// Locality order of x's block rows for the GEMM work list, computed once per
+// matrix from its (immutable) block pattern and cached on the device.
+static const int32_t *row_order(bsmm_ctx ctx, bsmm_mat_s *x) {
+  if (x->d_order) return x->d_order;
+  if (x->nbr != x->nbc || x->nbr < 64) return nullptr;
+  std::vector<int64_t> rp((size_t)x->nbr + 1);
+  std::vector<int32_t> ci((size_t)std::max<int64_t>(x->nnzb, 1));
+  HIPCHECK(hipMemcpyAsync(rp.data(), x->d_row_ptr, sizeof(int64_t) * rp.size(), hipMemcpyDeviceToHost, ctx->stream));
+  if (x->nnzb)
+    HIPCHECK(hipMemcpyAsync(ci.data(), x->d_col_idx, sizeof(int32_t) * (size_t)x->nnzb, hipMemcpyDeviceToHost,
+                            ctx->stream));
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  x->h_order = locality_order(x->nbr, rp, ci);
+  x->d_order = static_cast<int32_t *>(ctx->alloc.alloc(sizeof(int32_t) * (size_t)x->nbr));
+  HIPCHECK(hipMemcpyAsync(x->d_order, x->h_order.data(), sizeof(int32_t) * (size_t)x->nbr, hipMemcpyHostToDevice,
+                          ctx->stream));
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  return x->d_order;
 }
 
 static void make_op(bsmm_ctx ctx, bsmm_mat_s *x, bool trans, OpIndex &op) {
@@ -346,11 +367,14 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     sa.max_row = max_row;
     if (nprod > 0) stack_fill(sa, run.p, s);
   }
+  // GEMM work list: C blocks row by row in the planner's locality order
   DBuf<int32_t> c_list;
-  std::vector<GemmClass> classes;
   if (nnzb_c > 0) {
-    c_list = DBuf<int32_t>(al, nc1);
-    classes = group_classes(al, c_row.p, c_ci.p, nnzb_c, oa.rbs, ob.cbs, c_list.p, ctx->pinned, s);
+    const int32_t *ord = row_order(ctx, A);
+    if (ord) {
+      c_list = DBuf<int32_t>(al, nc1);
+      build_work_list(al, ord, c_rp.p, nbr, c_list.p, s);
+    }
   }
   tm.mark();  // 4
   // ------------------------------------------------------- a5: GEMM
@@ -377,7 +401,31 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     ga.alpha = alpha;
     ga.beta = beta;
     ga.mode = ctx->mode;
-    for (const GemmClass &cls : classes) gemm_launch(ga, cls, s);
+    // operand layouts for the matrix cores: op(A) column-major, op(B) row-major
+    DBuf<double> a_t, b_t;
+    if (ta && nprod > 0) {
+      a_t = DBuf<double>(al, (size_t)std::max<int64_t>(A->n_values, 1));
+      transpose_blocks(*A, a_t.p, s);
+    }
+    if (!tb && nprod > 0) {
+      b_t = DBuf<double>(al, (size_t)std::max<int64_t>(B->n_values, 1));
+      transpose_blocks(*B, b_t.p, s);
+    }
+    ga.a_cm = ta ? a_t.p : A->d_values;
+    ga.b_rm = tb ? B->d_values : b_t.p;
+    ga.a_bytes = (uint64_t)A->n_values * sizeof(double);
+    ga.b_bytes = (uint64_t)B->n_values * sizeof(double);
+    if (!ctx->zeros) {
+      ctx->zeros = static_cast<double *>(al.alloc(4096));
+      HIPCHECK(hipMemsetAsync(ctx->zeros, 0, 4096, s));
+    }
+    ga.zeros = ctx->zeros;
+    int max_edge = 1;
+    for (int32_t v : opa_r) max_edge = std::max(max_edge, v);
+    for (int32_t v : opb_c) max_edge = std::max(max_edge, v);
+    gemm_launch(ga, nnzb_c, max_edge, s);
+    a_t.reset();
+    b_t.reset();
     tm.mark();  // 5
     // ----------------------------------------------------- a6: post-filter
     R = new_result(ctx, nbr, nbc, opa_r, opb_c);

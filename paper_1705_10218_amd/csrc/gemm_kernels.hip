@@ -1,25 +1,36 @@
-// gemm_kernels.hip -- batched small-block GEMM on FP64 MFMA (gfx950).
+// gemm_kernels.hip -- batched small-block GEMM on FP64 matrix cores (gfx950).
 //
 // The local multiplication is a batch of small dense block products summed
-// into result blocks (arXiv:1705.10218, Section 2).  Here one wavefront owns
-// one C block for the whole of its stack segment: the accumulator lives in
-// registers, no other wavefront writes that block, and no atomics touch C.
+// into result blocks (arXiv:1705.10218, Section 2).  One wavefront owns one
+// C block for its whole stack segment: the accumulator stays in registers,
+// no other wavefront writes that block and no atomics touch C.
 //
-// Matrix core: V_MFMA_F64_4X4X4_4B (four independent 4x4x4 FP64 products per
-// instruction).  Lane layout on gfx950, checked on the device:
-//   A_b[i][k] in lane i + 4b + 16k,  B_b[k][j] in lane j + 4b + 16k,
-//   D_b[i][j] in lane j + 4b + 16i.
-// A C block of m x n is cut into 4x4 subtiles (MT x NT of them, both even).
-// The four MFMA blocks b = 2P + Q take the four quadrants of the subtile
-// grid; instruction (u, v) computes subtile (P*MT/2 + u, Q*NT/2 + v) in every
-// quadrant at once.  A lane therefore needs MT/2 values of op(A) and NT/2
-// values of op(B) per k-step, each reused by NT/2 or MT/2 instructions.
+// Contraction layout.  An MFMA instruction sums four k-slices; its four
+// 16-lane k-groups (kq = lane / 16) need not take those slices from the same
+// block product -- every product of the segment adds into the same C block.
+// So k-group kq walks its own quarter of the segment (products kq, kq+4,
+// kq+8, ...) one k at a time, and the MFMA adds the four groups' terms.
+// The k padding of a per-product formulation disappears (a 5x5x5 product
+// costs 5 k-steps, not 8), and all 16 lanes of a group read one k-column of
+// op(A) and one k-row of op(B): contiguous, coalesced loads.  To make both
+// contiguous, op(A) blocks are read column-major (m x K, ld m) and op(B)
+// blocks row-major (K x n, ld n); a prepass transposes the stored blocks
+// whose layout is the other one (A when transa = 'T', B when transb = 'N').
 //
-// The contraction index is permuted: in k-step kk, lane group kq uses
-// k = kq * ks + kk (ks = ceil(K/4)).  Any bijection of k gives the same
-// sum; this one makes every lane walk a contiguous run of k, so the
-// column-major op(B) operand is read sequentially.  Padded rows, columns and
-// k are zero-filled (never loaded), so padding adds no rounding.
+// Matrix cores (lane layouts on gfx950, checked on the device):
+//   V_MFMA_F64_16X16X4F64: A[i][k] lane i+16k, B[k][j] lane j+16k,
+//                          D[i][j] lane j+16(i%4), register i/4.
+//     Used when both C edges are in 9..16.
+//   V_MFMA_F64_4X4X4F64 (4 blocks b): A_b[i][k] lane i+4b+16k,
+//                          B_b[k][j] lane j+4b+16k, D_b[i][j] lane j+4b+16i.
+//     Used otherwise: the C block is cut into 4x4 subtiles (MT x NT, even),
+//     block b = 2P+Q takes quadrant (P,Q) of the subtile grid and
+//     instruction (u,v) subtile (P*MT/2+u, Q*NT/2+v).
+// Padded rows / columns are zero-filled, never loaded.
+//
+// Latency: product parameters (value offsets, k size) for up to 256
+// products are staged in LDS per round; operand loads run PF k-steps ahead
+// of the matrix core in a register ring.
 #include "internal.h"
 
 namespace bsmm {
@@ -28,12 +39,10 @@ namespace {
 
 struct GemmP {
   const int64_t *a_off;
-  const double *a_val;
+  const double *a_val;   // op(A) blocks column-major
   const int64_t *b_off;
-  const double *b_val;
-  int ta, tb;
+  const double *b_val;   // op(B) blocks row-major
   const int32_t *c_list;
-  int64_t first, count;
   const int32_t *c_row, *c_ci;
   const int32_t *rbs, *cbs;   // C block sizes (= op(A) rows, op(B) columns)
   const int64_t *c_off, *seg;
@@ -44,15 +53,239 @@ struct GemmP {
   double *c_val;
   double *c_norm;
   double alpha, beta;
+  uint32_t a_bytes, b_bytes;   // buffer extents (BUF path)
+  const double *zeros;         // zero page (pointer path)
 };
 
-template <int MT, int NT>
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmP P) {
+constexpr int ROUND = 256;   // products whose parameters sit in LDS at once
+constexpr int PF = 4;        // operand prefetch depth (k-steps)
+
+struct ParamLds {
+  int64_t ao[ROUND];
+  int64_t bo[ROUND];
+  int32_t K[ROUND];
+};
+
+// Stage the parameters of products [rb, rb + nr) of the segment in LDS.
+__device__ __forceinline__ void load_round(const GemmP &P, ParamLds &pl, int64_t rb, int nr, int m, int lane) {
+  for (int q = lane; q < nr; q += 64) {
+    const int2 ab = P.stack[rb + q];
+    const int64_t ao = P.a_off[ab.x];
+    pl.ao[q] = ao;
+    pl.K[q] = (int)((P.a_off[ab.x + 1] - ao) / m);
+    pl.bo[q] = P.b_off[ab.y];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Number of k-steps of this round: the longest group's sum of K.
+__device__ __forceinline__ int round_steps(const ParamLds &pl, int nr, int lane) {
+  int s = 0;
+  if (lane < 4)
+    for (int t = lane; t < nr; t += 4) s += pl.K[t];
+  s = max(s, __shfl_xor(s, 1, 64));
+  s = max(s, __shfl_xor(s, 2, 64));
+  return __builtin_amdgcn_readfirstlane(s);
+}
+
+// Read-after-round fence: the next round rewrites the parameter LDS.
+__device__ __forceinline__ void round_end() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------- operand streams
+// A lane reads one element per k-step from one row of op(A) (or one column
+// of op(B)) of its group's current product, stepping by the leading
+// dimension.  BUF: raw buffer loads with a 32-bit byte offset; an offset
+// past the buffer end reads 0, which serves padded rows / columns and
+// finished groups without any per-step test (arrays below 4 GB).  Otherwise
+// 64-bit pointers: finished groups read a zero page, padded rows / columns
+// read a clamped (valid) row whose products land only in discarded C
+// entries.
+constexpr uint32_t OOB = 0xFFFFFFF0u;
+
+template <bool BUF>
+struct Stream;
+
+template <>
+struct Stream<true> {
+  uint32_t off, step;
+  __device__ __forceinline__ void set(bool valid, int64_t elem, int ld, const double *, const double *) {
+    off = valid ? (uint32_t)(elem * 8) : OOB;
+    step = valid ? (uint32_t)(ld * 8) : 0u;
+  }
+  __device__ __forceinline__ void clear(const double *) {
+    off = OOB;
+    step = 0u;
+  }
+  __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, const double *) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  }
+  __device__ __forceinline__ void next() { off += step; }
+};
+
+template <>
+struct Stream<false> {
+  const double *p;
+  int step;
+  // elem is already clamped into the block by the caller
+  __device__ __forceinline__ void set(bool active, int64_t elem, int ld, const double *base, const double *zeros) {
+    p = active ? base + elem : zeros;
+    step = active ? ld : 0;
+  }
+  __device__ __forceinline__ void clear(const double *zeros) {
+    p = zeros;
+    step = 0;
+  }
+  __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t, const double *) const { return *p; }
+  __device__ __forceinline__ void next() { p += step; }
+};
+
+// Group walker: product t of the round, local k index lk; HA streams of
+// op(A) (one per A row the lane feeds) and HB streams of op(B).
+template <bool BUF, int HA, int HB>
+struct Walker {
+  int t, lk, K;
+  Stream<BUF> sa[HA], sb[HB];
+
+  __device__ __forceinline__ void open(const GemmP &P, const ParamLds &pl, int nr, int m, int n,
+                                       const int (&arow)[HA], const int (&bcol)[HB], const double *zeros) {
+    if (t < nr) {
+      const int64_t ao = pl.ao[t], bo = pl.bo[t];
+      K = pl.K[t];
+#pragma unroll
+      for (int u = 0; u < HA; u++) {
+        if (BUF) sa[u].set(arow[u] < m, ao + arow[u], m, P.a_val, zeros);
+        else sa[u].set(true, ao + min(arow[u], m - 1), m, P.a_val, zeros);
+      }
+#pragma unroll
+      for (int v = 0; v < HB; v++) {
+        if (BUF) sb[v].set(bcol[v] < n, bo + bcol[v], n, P.b_val, zeros);
+        else sb[v].set(true, bo + min(bcol[v], n - 1), n, P.b_val, zeros);
+      }
+    } else {
+      K = 0;
+#pragma unroll
+      for (int u = 0; u < HA; u++) sa[u].clear(zeros);
+#pragma unroll
+      for (int v = 0; v < HB; v++) sb[v].clear(zeros);
+    }
+  }
+
+  __device__ __forceinline__ void start(const GemmP &P, const ParamLds &pl, int kq, int nr, int m, int n,
+                                        const int (&arow)[HA], const int (&bcol)[HB], const double *zeros) {
+    t = kq;
+    lk = 0;
+    open(P, pl, nr, m, n, arow, bcol, zeros);
+  }
+
+  __device__ __forceinline__ void advance(const GemmP &P, const ParamLds &pl, int nr, int m, int n,
+                                          const int (&arow)[HA], const int (&bcol)[HB], const double *zeros) {
+    lk++;
+    if (lk >= K) {
+      if (t < nr) {
+        t += 4;
+        lk = 0;
+        open(P, pl, nr, m, n, arow, bcol, zeros);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < HA; u++) sa[u].next();
+#pragma unroll
+      for (int v = 0; v < HB; v++) sb[v].next();
+    }
+  }
+};
+
+// C = alpha * acc + beta * C_old for one element; sum of squares for the norm.
+__device__ __forceinline__ void store_c(const GemmP &P, const double *old, int64_t co, int m, int row, int col,
+                                        double v, double &ss) {
+  double x = P.alpha * v;
+  if (old) x += P.beta * old[row + col * m];
+  P.c_val[co + row + (int64_t)col * m] = x;
+  ss += x * x;
+}
+
+__device__ __forceinline__ const double *old_block(const GemmP &P, int32_t c) {
+  if (P.beta != 0.0 && P.old_blk) {
+    const int32_t ob = P.old_blk[c];
+    if (ob >= 0) return P.old_val + P.old_off[ob];
+  }
+  return nullptr;
+}
+
+__device__ __forceinline__ void store_norm(const GemmP &P, int32_t c, double ss, int lane) {
+  if (P.c_norm) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) ss += __shfl_xor(ss, d, 64);
+    if (lane == 0) P.c_norm[c] = sqrt(ss);
+  }
+}
+
+// ------------------------------------------------------------ 16x16x4 path
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <bool BUF>
+__device__ __forceinline__ void gemm_block_16(const GemmP &P, int32_t c, ParamLds &pl) {
+  const int lane = threadIdx.x & 63;
+  const int m = P.rbs[P.c_row[c]];
+  const int n = P.cbs[P.c_ci[c]];
+  const int i16 = lane & 15;
+  const int kq = lane >> 4;
+  const int arow[1] = {i16}, bcol[1] = {i16};
+  const __amdgpu_buffer_rsrc_t ra_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int64_t s0 = P.seg[c], s1 = P.seg[c + 1];
+  for (int64_t rb = s0; rb < s1; rb += ROUND) {
+    const int nr = (int)min<int64_t>(ROUND, s1 - rb);
+    load_round(P, pl, rb, nr, m, lane);
+    const int steps = round_steps(pl, nr, lane);
+    Walker<BUF, 1, 1> w;
+    w.start(P, pl, kq, nr, m, n, arow, bcol, P.zeros);
+    double qa[PF], qb[PF];
+#pragma unroll
+    for (int d = 0; d < PF; d++) {
+      qa[d] = w.sa[0].load(ra_, P.a_val);
+      qb[d] = w.sb[0].load(rb_, P.b_val);
+      w.advance(P, pl, nr, m, n, arow, bcol, P.zeros);
+    }
+    int s = 0;
+    for (; s + PF <= steps; s += PF) {
+#pragma unroll
+      for (int d = 0; d < PF; d++) {
+        const double a = qa[d], b = qb[d];
+        qa[d] = w.sa[0].load(ra_, P.a_val);
+        qb[d] = w.sb[0].load(rb_, P.b_val);
+        w.advance(P, pl, nr, m, n, arow, bcol, P.zeros);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < PF; d++)
+      if (s + d < steps) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[d], qb[d], acc, 0, 0, 0);
+    round_end();
+  }
+  const int64_t co = P.c_off[c];
+  const double *old = old_block(P, c);
+  double ss = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    const int row = 4 * r + kq;
+    if (row < m && i16 < n) store_c(P, old, co, m, row, i16, acc[r], ss);
+  }
+  store_norm(P, c, ss, lane);
+}
+
+// ------------------------------------------------------------- 4x4x4 path
+template <bool BUF, int MT, int NT>
+__device__ __forceinline__ void gemm_block_44(const GemmP &P, int32_t c, ParamLds &pl) {
   constexpr int HM = MT / 2, HN = NT / 2;
   const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= P.count) return;   // uniform per wavefront
-  const int32_t c = P.c_list ? P.c_list[P.first + w] : (int32_t)(P.first + w);
   const int m = P.rbs[P.c_row[c]];
   const int n = P.cbs[P.c_ci[c]];
   const int L4 = lane & 3;
@@ -64,99 +297,182 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmP P) {
   for (int u = 0; u < HM; u++) arow[u] = 4 * (Pq * HM + u) + L4;
 #pragma unroll
   for (int v = 0; v < HN; v++) bcol[v] = 4 * (Qq * HN + v) + L4;
+  const __amdgpu_buffer_rsrc_t ra_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
   double acc[HM * HN];
 #pragma unroll
   for (int t = 0; t < HM * HN; t++) acc[t] = 0.0;
 
   const int64_t s0 = P.seg[c], s1 = P.seg[c + 1];
-  for (int64_t e = s0; e < s1; e++) {
-    const int2 ab = P.stack[e];
-    const int64_t ao = P.a_off[ab.x];
-    const int K = (int)((P.a_off[ab.x + 1] - ao) / m);
-    const double *ap = P.a_val + ao;
-    const double *bp = P.b_val + P.b_off[ab.y];
-    const int ks = (K + 3) >> 2;
-    // op(A)[r][k] = ap[r*sar + k*sak], op(B)[k][c] = bp[k*sbk + c*sbc]
-    const int sar = P.ta ? K : 1, sak = P.ta ? 1 : m;
-    const int sbk = P.tb ? n : 1, sbc = P.tb ? 1 : K;
-    for (int kk = 0; kk < ks; kk++) {
-      const int k = kq * ks + kk;
-      const bool kv = k < K;
-      double av[HM], bv[HN];
+  for (int64_t rb = s0; rb < s1; rb += ROUND) {
+    const int nr = (int)min<int64_t>(ROUND, s1 - rb);
+    load_round(P, pl, rb, nr, m, lane);
+    const int steps = round_steps(pl, nr, lane);
+    Walker<BUF, HM, HN> w;
+    w.start(P, pl, kq, nr, m, n, arow, bcol, P.zeros);
+    double qa[PF][HM], qb[PF][HN];
 #pragma unroll
-      for (int u = 0; u < HM; u++) av[u] = (kv && arow[u] < m) ? ap[arow[u] * sar + k * sak] : 0.0;
+    for (int d = 0; d < PF; d++) {
 #pragma unroll
-      for (int v = 0; v < HN; v++) bv[v] = (kv && bcol[v] < n) ? bp[k * sbk + bcol[v] * sbc] : 0.0;
+      for (int u = 0; u < HM; u++) qa[d][u] = w.sa[u].load(ra_, P.a_val);
 #pragma unroll
-      for (int u = 0; u < HM; u++)
-#pragma unroll
-        for (int v = 0; v < HN; v++)
-          acc[u * HN + v] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[u], bv[v], acc[u * HN + v], 0, 0, 0);
+      for (int v = 0; v < HN; v++) qb[d][v] = w.sb[v].load(rb_, P.b_val);
+      w.advance(P, pl, nr, m, n, arow, bcol, P.zeros);
     }
+    int s = 0;
+    for (; s + PF <= steps; s += PF) {
+#pragma unroll
+      for (int d = 0; d < PF; d++) {
+        double a[HM], b[HN];
+#pragma unroll
+        for (int u = 0; u < HM; u++) a[u] = qa[d][u];
+#pragma unroll
+        for (int v = 0; v < HN; v++) b[v] = qb[d][v];
+#pragma unroll
+        for (int u = 0; u < HM; u++) qa[d][u] = w.sa[u].load(ra_, P.a_val);
+#pragma unroll
+        for (int v = 0; v < HN; v++) qb[d][v] = w.sb[v].load(rb_, P.b_val);
+        w.advance(P, pl, nr, m, n, arow, bcol, P.zeros);
+#pragma unroll
+        for (int u = 0; u < HM; u++)
+#pragma unroll
+          for (int v = 0; v < HN; v++)
+            acc[u * HN + v] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u], b[v], acc[u * HN + v], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < PF; d++) {
+      if (s + d < steps) {
+#pragma unroll
+        for (int u = 0; u < HM; u++)
+#pragma unroll
+          for (int v = 0; v < HN; v++)
+            acc[u * HN + v] = __builtin_amdgcn_mfma_f64_4x4x4f64(qa[d][u], qb[d][v], acc[u * HN + v], 0, 0, 0);
+      }
+    }
+    round_end();
   }
 
-  // epilogue: C = alpha * acc + beta * C_old, column-major, plus the block norm
   const int64_t co = P.c_off[c];
-  const double *old = nullptr;
-  if (P.beta != 0.0 && P.old_blk) {
-    const int32_t ob = P.old_blk[c];
-    if (ob >= 0) old = P.old_val + P.old_off[ob];
-  }
+  const double *old = old_block(P, c);
   double ss = 0.0;
 #pragma unroll
   for (int u = 0; u < HM; u++) {
     const int row = 4 * (Pq * HM + u) + kq;
 #pragma unroll
-    for (int v = 0; v < HN; v++) {
-      const int col = bcol[v];
-      if (row < m && col < n) {
-        double x = P.alpha * acc[u * HN + v];
-        if (old) x += P.beta * old[row + col * m];
-        P.c_val[co + row + (int64_t)col * m] = x;
-        ss += x * x;
+    for (int v = 0; v < HN; v++)
+      if (row < m && bcol[v] < n) store_c(P, old, co, m, row, bcol[v], acc[u * HN + v], ss);
+  }
+  store_norm(P, c, ss, lane);
+}
+
+// Size class of a block edge: 4x4 subtiles rounded up to an even count.
+__device__ __forceinline__ int edge_tiles(int e) { return ((((e + 3) >> 2) + 1) >> 1) << 1; }
+
+// One launch over all C blocks in the planner's order; every wavefront
+// dispatches on its own block's (m, n) class.  Workgroup ids are remapped so
+// that each of the 8 XCDs (ids are dealt to XCDs round-robin) walks one
+// contiguous stretch of the order, keeping its L2 on a compact region.
+// MAXT bounds the subtile counts compiled in (4: blocks up to 16).
+template <int MAXT, bool BUF>
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t per_xcd) {
+  __shared__ ParamLds lds[4];
+  ParamLds &pl = lds[threadIdx.x >> 6];
+  const int64_t b = blockIdx.x;
+  const int64_t lb = (b & 7) * per_xcd + (b >> 3);
+  const int64_t w = lb * 4 + (threadIdx.x >> 6);
+  if (w >= nblk) return;   // uniform per wavefront
+  const int32_t c = P.c_list ? P.c_list[w] : (int32_t)w;
+  const int mt = edge_tiles(P.rbs[P.c_row[c]]);
+  const int nt = edge_tiles(P.cbs[P.c_ci[c]]);
+  const int key = mt * 16 + nt;
+  switch (key) {
+    case 2 * 16 + 2: gemm_block_44<BUF, 2, 2>(P, c, pl); break;
+    case 2 * 16 + 4: gemm_block_44<BUF, 2, 4>(P, c, pl); break;
+    case 4 * 16 + 2: gemm_block_44<BUF, 4, 2>(P, c, pl); break;
+    case 4 * 16 + 4: gemm_block_16<BUF>(P, c, pl); break;
+    default:
+      if constexpr (MAXT > 4) {
+        switch (key) {
+          case 2 * 16 + 6: gemm_block_44<BUF, 2, 6>(P, c, pl); break;
+          case 2 * 16 + 8: gemm_block_44<BUF, 2, 8>(P, c, pl); break;
+          case 4 * 16 + 6: gemm_block_44<BUF, 4, 6>(P, c, pl); break;
+          case 4 * 16 + 8: gemm_block_44<BUF, 4, 8>(P, c, pl); break;
+          case 6 * 16 + 2: gemm_block_44<BUF, 6, 2>(P, c, pl); break;
+          case 6 * 16 + 4: gemm_block_44<BUF, 6, 4>(P, c, pl); break;
+          case 6 * 16 + 6: gemm_block_44<BUF, 6, 6>(P, c, pl); break;
+          case 6 * 16 + 8: gemm_block_44<BUF, 6, 8>(P, c, pl); break;
+          case 8 * 16 + 2: gemm_block_44<BUF, 8, 2>(P, c, pl); break;
+          case 8 * 16 + 4: gemm_block_44<BUF, 8, 4>(P, c, pl); break;
+          case 8 * 16 + 6: gemm_block_44<BUF, 8, 6>(P, c, pl); break;
+          case 8 * 16 + 8: gemm_block_44<BUF, 8, 8>(P, c, pl); break;
+          default: break;
+        }
       }
+      break;
+  }
+}
+
+// c_list = the C blocks of rows ord[0], ord[1], ... in order.
+__global__ void k_order_counts(const int32_t *ord, const int64_t *c_rp, int32_t nbr, int64_t *cnt) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nbr) cnt[r] = c_rp[ord[r] + 1] - c_rp[ord[r]];
+}
+
+__global__ void k_order_fill(const int32_t *ord, const int64_t *c_rp, const int64_t *start, int32_t *c_list) {
+  const int32_t r = blockIdx.x;
+  const int64_t c0 = c_rp[ord[r]], len = c_rp[ord[r] + 1] - c0, o = start[r];
+  for (int64_t t = threadIdx.x; t < len; t += blockDim.x) c_list[o + t] = (int32_t)(c0 + t);
+}
+
+// ---------------------------------------------------------------- prepass
+// Transpose every stored block of a matrix (column-major r x c becomes
+// column-major c x r, same offsets).  One workgroup per block row.
+__global__ __launch_bounds__(256) void k_transpose_blocks(const int64_t *rp, const int32_t *ci, const int32_t *rbs,
+                                                          const int32_t *cbs, const int64_t *off, const double *in,
+                                                          double *out) {
+  const int32_t i = blockIdx.x;
+  const int r = rbs[i];
+  for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+    const int cc = cbs[ci[p]];
+    const int64_t o = off[p];
+    const int len = r * cc;
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+      const int a = e % r, b = e / r;   // element (a, b) of the r x cc block
+      out[o + b + (int64_t)a * cc] = in[o + e];
     }
-  }
-  if (P.c_norm) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) ss += __shfl_xor(ss, d, 64);
-    if (lane == 0) P.c_norm[c] = sqrt(ss);
-  }
-}
-
-template <int MT, int NT>
-void launch_one(const GemmP &p, hipStream_t s) {
-  int64_t blocks = (p.count + 3) / 4;
-  hipLaunchKernelGGL((k_gemm_f64<MT, NT>), dim3((unsigned)blocks), dim3(256), 0, s, p);
-  HIPCHECK(hipGetLastError());
-}
-
-template <int MT>
-void launch_nt(const GemmP &p, int nt, hipStream_t s) {
-  switch (nt) {
-    case 2: launch_one<MT, 2>(p, s); break;
-    case 4: launch_one<MT, 4>(p, s); break;
-    case 6: launch_one<MT, 6>(p, s); break;
-    case 8: launch_one<MT, 8>(p, s); break;
-    default: fail(BSMM_ERR_UNSUPPORTED, "block size above 32");
   }
 }
 
 }  // namespace
 
-void gemm_launch(const GemmArgs &g, const GemmClass &cls, hipStream_t s) {
-  if (cls.count <= 0) return;
-  if (cls.count > (int64_t)INT32_MAX * 4) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks in one class");
+void transpose_blocks(const bsmm_mat_s &x, double *out, hipStream_t s) {
+  if (x.nbr == 0 || x.nnzb == 0) return;
+  hipLaunchKernelGGL(k_transpose_blocks, dim3(x.nbr), dim3(256), 0, s, x.d_row_ptr, x.d_col_idx, x.d_rbs, x.d_cbs,
+                     x.d_blk_off, x.d_values, out);
+  HIPCHECK(hipGetLastError());
+}
+
+void build_work_list(Allocator &al, const int32_t *d_ord, const int64_t *c_rp, int32_t nbr, int32_t *c_list,
+                     hipStream_t s) {
+  if (nbr == 0) return;
+  DBuf<int64_t> cnt(al, nbr), start(al, (size_t)nbr + 1);
+  hipLaunchKernelGGL(k_order_counts, dim3((nbr + 255) / 256), dim3(256), 0, s, d_ord, c_rp, nbr, cnt.p);
+  HIPCHECK(hipGetLastError());
+  exclusive_scan_i64(al, cnt.p, start.p, nbr, s);
+  hipLaunchKernelGGL(k_order_fill, dim3(nbr), dim3(256), 0, s, d_ord, c_rp, (const int64_t *)start.p, c_list);
+  HIPCHECK(hipGetLastError());
+}
+
+void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s) {
+  if (nnzb_c <= 0) return;
+  if (max_edge > 32) fail(BSMM_ERR_UNSUPPORTED, "block size above 32");
   GemmP p;
   p.a_off = g.a->blk_off;
-  p.a_val = g.a->values;
+  p.a_val = g.a_cm;
   p.b_off = g.b->blk_off;
-  p.b_val = g.b->values;
-  p.ta = g.a->trans ? 1 : 0;
-  p.tb = g.b->trans ? 1 : 0;
+  p.b_val = g.b_rm;
   p.c_list = g.c_list;
-  p.first = cls.first;
-  p.count = cls.count;
   p.c_row = g.c_row;
   p.c_ci = g.c_ci;
   p.rbs = g.a->rbs;
@@ -171,13 +487,23 @@ void gemm_launch(const GemmArgs &g, const GemmClass &cls, hipStream_t s) {
   p.c_norm = g.c_norm;
   p.alpha = g.alpha;
   p.beta = g.beta;
-  switch (cls.mt) {
-    case 2: launch_nt<2>(p, cls.nt, s); break;
-    case 4: launch_nt<4>(p, cls.nt, s); break;
-    case 6: launch_nt<6>(p, cls.nt, s); break;
-    case 8: launch_nt<8>(p, cls.nt, s); break;
-    default: fail(BSMM_ERR_UNSUPPORTED, "block size above 32");
-  }
+  const int64_t nwg = (nnzb_c + 3) / 4;
+  const int64_t per_xcd = (nwg + 7) / 8;
+  const int64_t grid = per_xcd * 8;
+  if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
+  const bool buf = g.a_bytes < (1ull << 32) - 64 && g.b_bytes < (1ull << 32) - 64;
+  p.a_bytes = buf ? (uint32_t)g.a_bytes : 0u;
+  p.b_bytes = buf ? (uint32_t)g.b_bytes : 0u;
+  p.zeros = g.zeros;
+  if (max_edge <= 16 && buf)
+    hipLaunchKernelGGL((k_gemm_f64<4, true>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+  else if (max_edge <= 16)
+    hipLaunchKernelGGL((k_gemm_f64<4, false>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+  else if (buf)
+    hipLaunchKernelGGL((k_gemm_f64<8, true>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+  else
+    hipLaunchKernelGGL((k_gemm_f64<8, false>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+  HIPCHECK(hipGetLastError());
 }
 
 }  // namespace bsmm

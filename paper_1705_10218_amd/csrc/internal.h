@@ -52,6 +52,7 @@ struct bsmm_ctx_s {
   bsmm_compute_mode mode = BSMM_COMPUTE_FP64;
   bsmm::Allocator alloc;
   int64_t *pinned = nullptr;   // small host buffer for size read-backs
+  double *zeros = nullptr;     // 4 KB zero page on the device
   int live_mats = 0;
 };
 
@@ -66,6 +67,9 @@ struct bsmm_mat_s {
   int64_t *d_blk_off = nullptr;        // nnzb+1 element offsets
   double *d_values = nullptr;
   bool owns_values = false;
+  // planner cache: locality order of the block rows (host and device copy)
+  std::vector<int32_t> h_order;
+  int32_t *d_order = nullptr;
 };
 
 namespace bsmm {
@@ -174,13 +178,6 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s);
 void old_block_map(const int64_t *cold_rp, const int32_t *cold_ci, int32_t nbr, const int64_t *c_rp,
                    const int32_t *c_ci, int32_t *old_blk, hipStream_t s);
 
-// C blocks whose row and column block sizes round up to the same number of
-// 4x4 subtiles (2, 4, 6 or 8 per edge) form one class and one launch.
-struct GemmClass {
-  int mt, nt;             // subtiles per edge (even)
-  int64_t first, count;   // range in the class-ordered C block list
-};
-
 struct GemmArgs {
   const OpIndex *a, *b;
   const int32_t *c_list = nullptr;   // C blocks ordered by class
@@ -196,15 +193,25 @@ struct GemmArgs {
   double *c_norm = nullptr;          // out: norm of every C block (may be null)
   double alpha = 1.0, beta = 0.0;
   bsmm_compute_mode mode = BSMM_COMPUTE_FP64;
+  const double *a_cm = nullptr;      // op(A) blocks, column-major (m x K)
+  const double *b_rm = nullptr;      // op(B) blocks, row-major (K x n)
+  uint64_t a_bytes = 0, b_bytes = 0; // sizes of the two value arrays
+  const double *zeros = nullptr;     // >= 4 KB of zeros
 };
 
-// a5: batched small-GEMM over the stacks, one launch per class.
-void gemm_launch(const GemmArgs &g, const GemmClass &cls, hipStream_t s);
+// Transpose every stored block of x into out (same offsets).
+void transpose_blocks(const bsmm_mat_s &x, double *out, hipStream_t s);
 
-// Group C blocks by subtile class: fills c_list and returns the classes.
-std::vector<GemmClass> group_classes(Allocator &al, const int32_t *c_row, const int32_t *c_ci, int64_t nnzb,
-                                     const int32_t *d_rbs, const int32_t *d_cbs, int32_t *c_list,
-                                     int64_t *pinned, hipStream_t s);
+// a5: batched small-GEMM over the stacks, one launch over all C blocks in
+// c_list order (max_edge: largest C block edge).
+void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s);
+
+// c_list = C blocks of block rows ord[0], ord[1], ... (ord on the device).
+void build_work_list(Allocator &al, const int32_t *d_ord, const int64_t *c_rp, int32_t nbr, int32_t *c_list,
+                     hipStream_t s);
+
+// Locality order of the rows of a square block pattern (host planner).
+std::vector<int32_t> locality_order(int32_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci);
 
 // a6: keep flags from norms, compaction of a block-CSR matrix.
 struct CompactArgs {

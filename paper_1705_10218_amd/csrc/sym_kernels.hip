@@ -320,34 +320,6 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
   }
 }
 
-// ---------------------------------------------------------- class grouping
-// Subtile class of a block size: 4x4 subtiles, rounded up to an even count
-// (2, 4, 6, 8 -> class 0..3).
-__device__ inline int size_class(int s) { return (((s + 3) >> 2) + 1) / 2 - 1; }
-
-__global__ void k_class_count(const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs, const int32_t *cbs,
-                              int64_t n, int32_t *cls, unsigned long long *counts) {
-  __shared__ unsigned int h[16];
-  if (threadIdx.x < 16) h[threadIdx.x] = 0;
-  __syncthreads();
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) {
-    int k = size_class(rbs[c_row[c]]) * 4 + size_class(cbs[c_ci[c]]);
-    cls[c] = k;
-    atomicAdd(&h[k], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x < 16 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], (unsigned long long)h[threadIdx.x]);
-}
-
-__global__ void k_class_fill(const int32_t *cls, int64_t n, unsigned long long *cursor, int32_t *c_list) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) {
-    unsigned long long at = atomicAdd(&cursor[cls[c]], 1ull);
-    c_list[at] = (int32_t)c;
-  }
-}
-
 }  // namespace
 
 void symbolic_count(const SymArgs &g, int64_t *row_nnz, int32_t *max_row, hipStream_t s) {
@@ -395,43 +367,6 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
   hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr), dim3(64), lds, s, view(*g.a), view(*g.b), g.nbc, g.c_rp, g.c_ci,
                      g.seg_off, g.stack, g.na, g.nb, g.eps, cap, run);
   HIPCHECK(hipGetLastError());
-}
-
-std::vector<GemmClass> group_classes(Allocator &al, const int32_t *c_row, const int32_t *c_ci, int64_t nnzb,
-                                     const int32_t *d_rbs, const int32_t *d_cbs, int32_t *c_list,
-                                     int64_t *pinned, hipStream_t s) {
-  std::vector<GemmClass> out;
-  if (nnzb == 0) return out;
-  DBuf<int32_t> cls(al, nnzb);
-  DBuf<unsigned long long> counts(al, 32);
-  HIPCHECK(hipMemsetAsync(counts.p, 0, 32 * sizeof(unsigned long long), s));
-  int grid = (int)((nnzb + 255) / 256);
-  hipLaunchKernelGGL(k_class_count, dim3(grid), dim3(256), 0, s, c_row, c_ci, d_rbs, d_cbs, nnzb, cls.p, counts.p);
-  HIPCHECK(hipGetLastError());
-  HIPCHECK(hipMemcpyAsync(pinned, counts.p, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  std::vector<unsigned long long> start(16, 0);
-  unsigned long long run = 0;
-  for (int k = 0; k < 16; k++) {
-    int64_t cnt = pinned[k];
-    start[k] = run;
-    if (cnt > 0) {
-      GemmClass g;
-      g.mt = 2 * (k / 4 + 1);
-      g.nt = 2 * (k % 4 + 1);
-      g.first = (int64_t)run;
-      g.count = cnt;
-      out.push_back(g);
-    }
-    run += (unsigned long long)cnt;
-  }
-  // cursor starts at each class start
-  for (int k = 0; k < 16; k++) pinned[k] = (int64_t)start[k];
-  HIPCHECK(hipMemcpyAsync(counts.p, pinned, 16 * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_class_fill, dim3(grid), dim3(256), 0, s, (const int32_t *)cls.p, nnzb, counts.p, c_list);
-  HIPCHECK(hipGetLastError());
-  HIPCHECK(hipStreamSynchronize(s));   // pinned is reused by the caller
-  return out;
 }
 
 }  // namespace bsmm
