@@ -306,7 +306,20 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   if (A->nnzb > INT32_MAX || B->nnzb > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "more than 2^31 operand blocks");
   const size_t nc1 = (size_t)std::max<int64_t>(nnzb_c, 1);
   DBuf<int32_t> c_ci(al, nc1), c_row(al, nc1), c_cnt(al, nc1);
-  DBuf<int64_t> c_size(al, nc1), row_kmn(al, std::max<int32_t>(nbr, 1)), row_cand(al, std::max<int32_t>(nbr, 1));
+  DBuf<int64_t> c_size(al, nc1), row_kmn(al, std::max<int32_t>(nbr, 1)), row_cand(al, std::max<int32_t>(nbr, 1)),
+      row_real(al, std::max<int32_t>(nbr, 1));
+  // quad path of the GEMM: value arrays below 2 GB and few distinct k sizes
+  std::vector<int32_t> ksizes(opa_c.begin(), opa_c.end());
+  std::sort(ksizes.begin(), ksizes.end());
+  ksizes.erase(std::unique(ksizes.begin(), ksizes.end()), ksizes.end());
+  const uint64_t two_gb = 1ull << 31;
+  const bool quads = (uint64_t)A->n_values * 8 < two_gb && (uint64_t)B->n_values * 8 < two_gb &&
+                     !ksizes.empty() && ksizes.size() <= 8;
+  DBuf<int32_t> cnt_g;
+  if (quads && (int64_t)max_row * (int64_t)ksizes.size() > 8192) {
+    cnt_g = DBuf<int32_t>(al, nc1 * ksizes.size());
+    HIPCHECK(hipMemsetAsync(cnt_g.p, 0, sizeof(int32_t) * nc1 * ksizes.size(), s));
+  }
   HIPCHECK(hipMemsetAsync(c_cnt.p, 0, sizeof(int32_t) * nc1, s));
   FillArgs fa;
   fa.sym = sym;
@@ -317,24 +330,31 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   fa.c_cnt = c_cnt.p;
   fa.c_kflops = row_kmn.p;
   fa.row_cand = row_cand.p;
+  fa.row_real = row_real.p;
+  fa.pad4 = quads;
+  fa.ksizes = ksizes;
+  fa.cnt_g = cnt_g.p;
   fa.na = filt ? na.p : nullptr;
   fa.nb = filt ? nb.p : nullptr;
   fa.eps = eps;
   fa.max_row = max_row;
   symbolic_fill(fa, s);
   DBuf<int64_t> c_off(al, nc1 + 1), seg_off(al, nc1 + 1), kmn_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1),
-      cand_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1);
+      cand_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1), real_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1);
   exclusive_scan_i64(al, c_size.p, c_off.p, nnzb_c, s);
   exclusive_scan_i32(al, c_cnt.p, seg_off.p, nnzb_c, s);
   exclusive_scan_i64(al, row_kmn.p, kmn_scan.p, nbr, s);
   exclusive_scan_i64(al, row_cand.p, cand_scan.p, nbr, s);
+  exclusive_scan_i64(al, row_real.p, real_scan.p, nbr, s);
   HIPCHECK(hipMemcpyAsync(ctx->pinned, c_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(ctx->pinned + 1, seg_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(ctx->pinned + 2, kmn_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(ctx->pinned + 3, cand_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(ctx->pinned + 4, real_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
   const int64_t nval_c = ctx->pinned[0];
-  const int64_t nprod = ctx->pinned[1];
+  const int64_t nstack = ctx->pinned[1];   // stack entries, padding included
+  const int64_t nprod = ctx->pinned[4];
   const int64_t kmn_total = ctx->pinned[2];
   const int64_t ncand = ctx->pinned[3];
   DBuf<int32_t> old_blk;
@@ -345,7 +365,7 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   }
   tm.mark();  // 3
   // ------------------------------------------------------- a4: stacks
-  DBuf<int2> stack(al, (size_t)std::max<int64_t>(nprod, 1));
+  DBuf<int2> stack(al, (size_t)std::max<int64_t>(nstack, 1));
   {
     DBuf<int32_t> run;
     if (max_row > 8192) {
@@ -365,6 +385,8 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     sa.nbc = nbc;
     sa.nbr = nbr;
     sa.max_row = max_row;
+    sa.ksizes = ksizes;
+    sa.pad4 = quads;
     if (nprod > 0) stack_fill(sa, run.p, s);
   }
   // GEMM work list: C blocks row by row in the planner's locality order
@@ -373,7 +395,12 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     const int32_t *ord = row_order(ctx, A);
     if (ord) {
       c_list = DBuf<int32_t>(al, nc1);
-      build_work_list(al, ord, c_rp.p, nbr, c_list.p, s);
+      if ((size_t)nbc * 4 > 160 * 1024) {
+        // columns too many for one LDS histogram: plain row order
+        build_work_list(al, ord, c_rp.p, c_ci.p, nbr, 0, c_list.p, s);
+      } else {
+        build_work_list(al, ord, c_rp.p, c_ci.p, nbr, nbc, c_list.p, s);
+      }
     }
   }
   tm.mark();  // 4
@@ -420,6 +447,7 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
       HIPCHECK(hipMemsetAsync(ctx->zeros, 0, 4096, s));
     }
     ga.zeros = ctx->zeros;
+    ga.quads = quads;
     int max_edge = 1;
     for (int32_t v : opa_r) max_edge = std::max(max_edge, v);
     for (int32_t v : opb_c) max_edge = std::max(max_edge, v);

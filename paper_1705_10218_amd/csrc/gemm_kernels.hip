@@ -366,6 +366,218 @@ __device__ __forceinline__ void gemm_block_44(const GemmP &P, int32_t c, ParamLd
   store_norm(P, c, ss, lane);
 }
 
+// ----------------------------------------------------------- quad path
+// With the stacks grouped by k size and every equal-k run padded to a
+// multiple of 4 entries (null entries), the segment splits into quads of
+// four products of one k size; the four k-groups run their quad in lockstep,
+// so the k index is uniform: it rides in the scalar offset of the buffer
+// loads (the range check covers voffset + soffset + immediate, so a lane
+// whose voffset is out of range -- padded row or column, null product --
+// reads zeros at every k).  Per k-step a lane issues HM + HN loads and the
+// MFMAs, nothing else; the next quad's lane offsets are read from LDS one
+// quad ahead.  Arrays below 2 GB (32-bit offsets with an out-of-range mark
+// that no k offset can wrap).
+constexpr uint32_t QOOB = 0x80000000u;
+
+struct QuadLds {
+  uint32_t oa[ROUND];   // byte offsets of op(A) / op(B) blocks (QOOB = null)
+  uint32_t ob[ROUND];
+  int32_t Kq[ROUND / 4];
+};
+
+__device__ __forceinline__ void load_quads(const GemmP &P, QuadLds &ql, int64_t rb, int nr, int m, int lane) {
+  for (int q = lane; q < nr; q += 64) {
+    const int2 ab = P.stack[rb + q];
+    if (ab.x >= 0) {
+      const int64_t ao = P.a_off[ab.x];
+      ql.oa[q] = (uint32_t)(ao * 8);
+      ql.ob[q] = (uint32_t)(P.b_off[ab.y] * 8);
+      if ((q & 3) == 0) ql.Kq[q >> 2] = (int)((P.a_off[ab.x + 1] - ao) / m);
+    } else {
+      ql.oa[q] = QOOB;
+      ql.ob[q] = QOOB;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool SIXTEEN, int MT, int NT>
+__device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadLds &ql) {
+  constexpr int HM = SIXTEEN ? 1 : MT / 2, HN = SIXTEEN ? 1 : NT / 2;
+  const int lane = threadIdx.x & 63;
+  // one C block per wavefront: its sizes are uniform (scalar registers)
+  const int m = __builtin_amdgcn_readfirstlane(P.rbs[P.c_row[c]]);
+  const int n = __builtin_amdgcn_readfirstlane(P.cbs[P.c_ci[c]]);
+  const int m8 = 8 * m, n8 = 8 * n;
+  const int kq = lane >> 4;
+  // lane's rows of op(A) / columns of op(B), as byte offsets (QOOB if padding)
+  uint32_t ra8[HM], cb8[HN];
+  if (SIXTEEN) {
+    ra8[0] = (lane & 15) < m ? 8u * (lane & 15) : QOOB;
+    cb8[0] = (lane & 15) < n ? 8u * (lane & 15) : QOOB;
+  } else {
+    const int L4 = lane & 3, bq = (lane >> 2) & 3;
+    const int Pq = bq >> 1, Qq = bq & 1;
+#pragma unroll
+    for (int u = 0; u < HM; u++) {
+      const int r = 4 * (Pq * HM + u) + L4;
+      ra8[u] = r < m ? 8u * r : QOOB;
+    }
+#pragma unroll
+    for (int v = 0; v < HN; v++) {
+      const int cc = 4 * (Qq * HN + v) + L4;
+      cb8[v] = cc < n ? 8u * cc : QOOB;
+    }
+  }
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
+  double acc[SIXTEEN ? 1 : HM * HN];
+  d4 acc16 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[t] = 0.0;
+
+  const int64_t s0 = P.seg[c], s1 = P.seg[c + 1];
+  for (int64_t rbase = s0; rbase < s1; rbase += ROUND) {
+    const int nr = (int)min<int64_t>(ROUND, s1 - rbase);   // multiple of 4
+    const int nq = nr >> 2;
+    load_quads(P, ql, rbase, nr, m, lane);
+    // total k-steps of the round
+    int steps = 0;
+    for (int q = lane; q < nq; q += 64) steps += ql.Kq[q];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) steps += __shfl_xor(steps, d, 64);
+    steps = __builtin_amdgcn_readfirstlane(steps);
+    // issue cursor: quad iq, k index ik (uniform), lane offsets of quad iq;
+    // the following quad's offsets and k size are already in flight
+    int iq = 0, ik = 0;
+    int iK = __builtin_amdgcn_readfirstlane(ql.Kq[0]);
+    uint32_t va[HM], vb[HN], nva[HM], nvb[HN];
+    int nK = 1 << 30;
+#pragma unroll
+    for (int u = 0; u < HM; u++) nva[u] = QOOB;
+#pragma unroll
+    for (int v = 0; v < HN; v++) nvb[v] = QOOB;
+    {
+      const uint32_t oa = ql.oa[kq], ob = ql.ob[kq];
+#pragma unroll
+      for (int u = 0; u < HM; u++) va[u] = (ra8[u] == QOOB || oa == QOOB) ? QOOB : oa + ra8[u];
+#pragma unroll
+      for (int v = 0; v < HN; v++) vb[v] = (cb8[v] == QOOB || ob == QOOB) ? QOOB : ob + cb8[v];
+      if (nq > 1) {
+        const uint32_t oa1 = ql.oa[4 + kq], ob1 = ql.ob[4 + kq];
+#pragma unroll
+        for (int u = 0; u < HM; u++) nva[u] = (ra8[u] == QOOB || oa1 == QOOB) ? QOOB : oa1 + ra8[u];
+#pragma unroll
+        for (int v = 0; v < HN; v++) nvb[v] = (cb8[v] == QOOB || ob1 == QOOB) ? QOOB : ob1 + cb8[v];
+        nK = ql.Kq[1];
+      }
+    }
+    double qa[PF][HM], qb[PF][HN];
+    auto issue = [&](double (&xa)[HM], double (&xb)[HN]) {
+      const int sa = ik * m8, sb = ik * n8;
+#pragma unroll
+      for (int u = 0; u < HM; u++)
+        xa[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ra, (int)va[u], sa, 0));
+#pragma unroll
+      for (int v = 0; v < HN; v++)
+        xb[v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, (int)vb[v], sb, 0));
+      if (++ik == iK) {   // uniform: next quad
+        ik = 0;
+        iq++;
+        iK = __builtin_amdgcn_readfirstlane(nK);
+#pragma unroll
+        for (int u = 0; u < HM; u++) va[u] = nva[u];
+#pragma unroll
+        for (int v = 0; v < HN; v++) vb[v] = nvb[v];
+        if (iq + 1 < nq) {
+          const int t = 4 * (iq + 1) + kq;
+          const uint32_t oa = ql.oa[t], ob = ql.ob[t];
+#pragma unroll
+          for (int u = 0; u < HM; u++) nva[u] = (ra8[u] == QOOB || oa == QOOB) ? QOOB : oa + ra8[u];
+#pragma unroll
+          for (int v = 0; v < HN; v++) nvb[v] = (cb8[v] == QOOB || ob == QOOB) ? QOOB : ob + cb8[v];
+          nK = ql.Kq[iq + 1];
+        } else {
+          // past the last quad: further issues read zeros (out of range)
+#pragma unroll
+          for (int u = 0; u < HM; u++) nva[u] = QOOB;
+#pragma unroll
+          for (int v = 0; v < HN; v++) nvb[v] = QOOB;
+          nK = 1 << 30;
+        }
+      }
+    };
+    auto mma = [&](const double (&xa)[HM], const double (&xb)[HN]) {
+      if (SIXTEEN) {
+        acc16 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[0], xb[0], acc16, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int u = 0; u < HM; u++)
+#pragma unroll
+          for (int v = 0; v < HN; v++)
+            acc[u * HN + v] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[u], xb[v], acc[u * HN + v], 0, 0, 0);
+      }
+    };
+    // prologue: always PF issues (beyond the round they read zeros), so the
+    // loop is entered with a fixed number of loads in flight
+#pragma unroll
+    for (int d = 0; d < PF; d++) {
+      issue(qa[d], qb[d]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // ring: the MFMA of step s reads slot s % PF, then the load of step
+    // s + PF lands in that same slot (no register copies, so no wait for
+    // younger loads)
+    int s = 0;
+    for (; s + 2 * PF <= steps; s += PF) {   // every issue in range
+#pragma unroll
+      for (int d = 0; d < PF; d++) {
+        mma(qa[d], qb[d]);
+        issue(qa[d], qb[d]);
+        __builtin_amdgcn_sched_barrier(0);   // keep the ring order: MFMA(s), load(s + PF)
+      }
+    }
+    // drain: remaining steps s .. steps-1, issuing while steps remain
+#pragma unroll
+    for (int d = 0; d < 2 * PF; d++) {
+      const int st = s + d;
+      if (st < steps) {
+        const int slot = d % PF;
+        mma(qa[slot], qb[slot]);
+        if (st + PF < steps) issue(qa[slot], qb[slot]);
+      }
+    }
+    round_end();
+  }
+
+  const int64_t co = P.c_off[c];
+  const double *old = old_block(P, c);
+  double ss = 0.0;
+  if (SIXTEEN) {
+    const int col = lane & 15;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = 4 * r + kq;
+      if (row < m && col < n) store_c(P, old, co, m, row, col, acc16[r], ss);
+    }
+  } else {
+    const int L4 = lane & 3, bq = (lane >> 2) & 3;
+    const int Pq = bq >> 1, Qq = bq & 1;
+#pragma unroll
+    for (int u = 0; u < HM; u++) {
+      const int row = 4 * (Pq * HM + u) + kq;
+#pragma unroll
+      for (int v = 0; v < HN; v++) {
+        const int col = 4 * (Qq * HN + v) + L4;
+        if (row < m && col < n) store_c(P, old, co, m, row, col, acc[u * HN + v], ss);
+      }
+    }
+  }
+  store_norm(P, c, ss, lane);
+}
+
 // Size class of a block edge: 4x4 subtiles rounded up to an even count.
 __device__ __forceinline__ int edge_tiles(int e) { return ((((e + 3) >> 2) + 1) >> 1) << 1; }
 
@@ -378,14 +590,42 @@ template <int MAXT, bool BUF>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t per_xcd) {
   __shared__ ParamLds lds[4];
   ParamLds &pl = lds[threadIdx.x >> 6];
+  QuadLds &ql = *reinterpret_cast<QuadLds *>(&pl);
   const int64_t b = blockIdx.x;
   const int64_t lb = (b & 7) * per_xcd + (b >> 3);
   const int64_t w = lb * 4 + (threadIdx.x >> 6);
   if (w >= nblk) return;   // uniform per wavefront
-  const int32_t c = P.c_list ? P.c_list[w] : (int32_t)w;
+  const int32_t c = __builtin_amdgcn_readfirstlane(P.c_list ? P.c_list[w] : (int32_t)w);
   const int mt = edge_tiles(P.rbs[P.c_row[c]]);
   const int nt = edge_tiles(P.cbs[P.c_ci[c]]);
   const int key = mt * 16 + nt;
+  if constexpr (BUF) {
+    switch (key) {
+      case 2 * 16 + 2: gemm_block_quad<false, 2, 2>(P, c, ql); return;
+      case 2 * 16 + 4: gemm_block_quad<false, 2, 4>(P, c, ql); return;
+      case 4 * 16 + 2: gemm_block_quad<false, 4, 2>(P, c, ql); return;
+      case 4 * 16 + 4: gemm_block_quad<true, 4, 4>(P, c, ql); return;
+      default: break;
+    }
+    if constexpr (MAXT > 4) {
+      switch (key) {
+        case 2 * 16 + 6: gemm_block_quad<false, 2, 6>(P, c, ql); return;
+        case 2 * 16 + 8: gemm_block_quad<false, 2, 8>(P, c, ql); return;
+        case 4 * 16 + 6: gemm_block_quad<false, 4, 6>(P, c, ql); return;
+        case 4 * 16 + 8: gemm_block_quad<false, 4, 8>(P, c, ql); return;
+        case 6 * 16 + 2: gemm_block_quad<false, 6, 2>(P, c, ql); return;
+        case 6 * 16 + 4: gemm_block_quad<false, 6, 4>(P, c, ql); return;
+        case 6 * 16 + 6: gemm_block_quad<false, 6, 6>(P, c, ql); return;
+        case 6 * 16 + 8: gemm_block_quad<false, 6, 8>(P, c, ql); return;
+        case 8 * 16 + 2: gemm_block_quad<false, 8, 2>(P, c, ql); return;
+        case 8 * 16 + 4: gemm_block_quad<false, 8, 4>(P, c, ql); return;
+        case 8 * 16 + 6: gemm_block_quad<false, 8, 6>(P, c, ql); return;
+        case 8 * 16 + 8: gemm_block_quad<false, 8, 8>(P, c, ql); return;
+        default: break;
+      }
+    }
+    return;
+  } else {
   switch (key) {
     case 2 * 16 + 2: gemm_block_44<BUF, 2, 2>(P, c, pl); break;
     case 2 * 16 + 4: gemm_block_44<BUF, 2, 4>(P, c, pl); break;
@@ -411,18 +651,79 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t
       }
       break;
   }
+  }
 }
 
-// c_list = the C blocks of rows ord[0], ord[1], ... in order.
+// Work list: tiles of TILE_ROWS consecutive rows of the locality order; inside
+// a tile, C blocks go column by column.  A block B(k,j) feeds only the C
+// blocks of column j, one per row i with A(i,k) stored, so running a
+// column's blocks of neighbouring rows back to back keeps B(k,j) in L2,
+// while the tile's A rows (a few MB) stay resident across its columns.
+constexpr int TILE_ROWS = 16;
+
 __global__ void k_order_counts(const int32_t *ord, const int64_t *c_rp, int32_t nbr, int64_t *cnt) {
-  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nbr) cnt[r] = c_rp[ord[r] + 1] - c_rp[ord[r]];
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;   // tile
+  const int32_t ntile = (nbr + TILE_ROWS - 1) / TILE_ROWS;
+  if (t >= ntile) return;
+  int64_t s = 0;
+  for (int32_t r = t * TILE_ROWS; r < min(nbr, (t + 1) * TILE_ROWS); r++) s += c_rp[ord[r] + 1] - c_rp[ord[r]];
+  cnt[t] = s;
 }
 
-__global__ void k_order_fill(const int32_t *ord, const int64_t *c_rp, const int64_t *start, int32_t *c_list) {
-  const int32_t r = blockIdx.x;
-  const int64_t c0 = c_rp[ord[r]], len = c_rp[ord[r] + 1] - c0, o = start[r];
-  for (int64_t t = threadIdx.x; t < len; t += blockDim.x) c_list[o + t] = (int32_t)(c0 + t);
+// One workgroup per tile: counting sort of the tile's C blocks by column
+// (LDS histogram over nbc columns); ties in a column fall in any order.
+__global__ __launch_bounds__(256) void k_order_fill(const int32_t *ord, const int64_t *c_rp, const int32_t *c_ci,
+                                                    int32_t nbr, int32_t nbc, const int64_t *start, int32_t *c_list) {
+  extern __shared__ int32_t hist[];   // nbc counters, then the scan
+  __shared__ int32_t wsum[4];
+  const int32_t t = blockIdx.x;
+  const int32_t r0 = t * TILE_ROWS, r1 = min(nbr, r0 + TILE_ROWS);
+  if (nbc == 0) {   // no column histogram: the tile's rows one after another
+    int64_t off = start[t];
+    for (int32_t r = r0; r < r1; r++) {
+      const int64_t c0 = c_rp[ord[r]], len = c_rp[ord[r] + 1] - c0;
+      for (int64_t q = threadIdx.x; q < len; q += blockDim.x) c_list[off + q] = (int32_t)(c0 + q);
+      off += len;
+    }
+    return;
+  }
+  for (int32_t j = threadIdx.x; j < nbc; j += blockDim.x) hist[j] = 0;
+  __syncthreads();
+  for (int32_t r = r0; r < r1; r++) {
+    const int64_t c0 = c_rp[ord[r]], c1 = c_rp[ord[r] + 1];
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) atomicAdd(&hist[c_ci[c]], 1);
+  }
+  __syncthreads();
+  // exclusive scan of hist over nbc entries (each thread a contiguous chunk)
+  const int32_t per = (nbc + blockDim.x - 1) / blockDim.x;
+  const int32_t j0 = threadIdx.x * per, j1 = min(nbc, j0 + per);
+  int32_t loc = 0;
+  for (int32_t j = j0; j < j1; j++) loc += hist[j];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t inc = loc;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int32_t run = inc - loc;
+  for (int w = 0; w < wv; w++) run += wsum[w];
+  for (int32_t j = j0; j < j1; j++) {
+    const int32_t h = hist[j];
+    hist[j] = run;
+    run += h;
+  }
+  __syncthreads();
+  const int64_t o = start[t];
+  for (int32_t r = r0; r < r1; r++) {
+    const int64_t c0 = c_rp[ord[r]], c1 = c_rp[ord[r] + 1];
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+      const int32_t at = atomicAdd(&hist[c_ci[c]], 1);
+      c_list[o + at] = (int32_t)c;
+    }
+  }
 }
 
 // ---------------------------------------------------------------- prepass
@@ -453,14 +754,19 @@ void transpose_blocks(const bsmm_mat_s &x, double *out, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
-void build_work_list(Allocator &al, const int32_t *d_ord, const int64_t *c_rp, int32_t nbr, int32_t *c_list,
-                     hipStream_t s) {
+void build_work_list(Allocator &al, const int32_t *d_ord, const int64_t *c_rp, const int32_t *c_ci, int32_t nbr,
+                     int32_t nbc, int32_t *c_list, hipStream_t s) {
   if (nbr == 0) return;
-  DBuf<int64_t> cnt(al, nbr), start(al, (size_t)nbr + 1);
-  hipLaunchKernelGGL(k_order_counts, dim3((nbr + 255) / 256), dim3(256), 0, s, d_ord, c_rp, nbr, cnt.p);
+  const int32_t ntile = (nbr + TILE_ROWS - 1) / TILE_ROWS;
+  DBuf<int64_t> cnt(al, ntile), start(al, (size_t)ntile + 1);
+  hipLaunchKernelGGL(k_order_counts, dim3((ntile + 255) / 256), dim3(256), 0, s, d_ord, c_rp, nbr, cnt.p);
   HIPCHECK(hipGetLastError());
-  exclusive_scan_i64(al, cnt.p, start.p, nbr, s);
-  hipLaunchKernelGGL(k_order_fill, dim3(nbr), dim3(256), 0, s, d_ord, c_rp, (const int64_t *)start.p, c_list);
+  exclusive_scan_i64(al, cnt.p, start.p, ntile, s);
+  const size_t lds = sizeof(int32_t) * (size_t)std::max(nbc, 1);
+  if (lds > 65536)
+    HIPCHECK(hipFuncSetAttribute((const void *)k_order_fill, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_order_fill, dim3(ntile), dim3(256), lds, s, d_ord, c_rp, c_ci, nbr, nbc,
+                     (const int64_t *)start.p, c_list);
   HIPCHECK(hipGetLastError());
 }
 
@@ -491,7 +797,7 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
   const int64_t per_xcd = (nwg + 7) / 8;
   const int64_t grid = per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
-  const bool buf = g.a_bytes < (1ull << 32) - 64 && g.b_bytes < (1ull << 32) - 64;
+  const bool buf = g.quads;
   p.a_bytes = buf ? (uint32_t)g.a_bytes : 0u;
   p.b_bytes = buf ? (uint32_t)g.b_bytes : 0u;
   p.zeros = g.zeros;

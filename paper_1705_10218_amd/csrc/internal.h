@@ -148,6 +148,10 @@ struct FillArgs {
   int32_t *c_cnt = nullptr;        // out: kept products per C block (zeroed before)
   int64_t *c_kflops = nullptr;     // out: per block row, sum of m*k*n over kept products
   int64_t *row_cand = nullptr;     // out: per block row, candidate products (before filters)
+  int64_t *row_real = nullptr;     // out: per block row, kept products (without padding)
+  bool pad4 = false;               // pad every equal-k-size run of a segment to 4 entries
+  std::vector<int32_t> ksizes;     // distinct k block sizes, ascending (when pad4)
+  int32_t *cnt_g = nullptr;        // nnzb_C * |ksizes| zeroed counters for wide rows
   const double *na = nullptr, *nb = nullptr;   // block norms (null when eps == 0)
   double eps = 0.0;
   int32_t max_row = 0;
@@ -167,6 +171,8 @@ struct StackArgs {
   int32_t nbc = 0;
   int32_t nbr = 0;
   int32_t max_row = 0;
+  std::vector<int32_t> ksizes;       // distinct k block sizes, ascending
+  bool pad4 = false;                 // pad every equal-k-size run to 4 entries (null = -1)
 };
 
 // a4: stack entries, grouped by C block, ascending k inside a block.  `run`
@@ -196,6 +202,7 @@ struct GemmArgs {
   const double *a_cm = nullptr;      // op(A) blocks, column-major (m x K)
   const double *b_rm = nullptr;      // op(B) blocks, row-major (K x n)
   uint64_t a_bytes = 0, b_bytes = 0; // sizes of the two value arrays
+  bool quads = false;                // stacks padded to k-homogeneous quads (quad path)
   const double *zeros = nullptr;     // >= 4 KB of zeros
 };
 
@@ -206,9 +213,10 @@ void transpose_blocks(const bsmm_mat_s &x, double *out, hipStream_t s);
 // c_list order (max_edge: largest C block edge).
 void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s);
 
-// c_list = C blocks of block rows ord[0], ord[1], ... (ord on the device).
-void build_work_list(Allocator &al, const int32_t *d_ord, const int64_t *c_rp, int32_t nbr, int32_t *c_list,
-                     hipStream_t s);
+// c_list = C blocks in tiles of consecutive rows of ord (device), column by
+// column inside a tile.
+void build_work_list(Allocator &al, const int32_t *d_ord, const int64_t *c_rp, const int32_t *c_ci, int32_t nbr,
+                     int32_t nbc, int32_t *c_list, hipStream_t s);
 
 // Locality order of the rows of a square block pattern (host planner).
 std::vector<int32_t> locality_order(int32_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci);

@@ -17,6 +17,12 @@ namespace {
 constexpr int SYM_THREADS = 256;
 constexpr int32_t MAX_WORDS = 4096;      // bitmap window: 131072 block columns
 constexpr int32_t CNT_CAP = 8192;        // per-row counters kept in LDS up to this
+constexpr int MAX_KSIZES = 8;            // k-size grouping of the stacks up to this many sizes
+
+// Distinct k block sizes, ascending (nks == 0: no grouping by size).
+struct KSizes {
+  int32_t v[MAX_KSIZES];
+};
 
 struct OpView {
   const int64_t *rp;
@@ -152,15 +158,16 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
                                                           const int32_t *cold_ci, int use_cold, int retain,
                                                           int32_t nbc, const int64_t *c_rp, int32_t *c_ci,
                                                           int32_t *c_row, int64_t *c_size, int32_t *c_cnt,
-                                                          int64_t *row_kmn, int64_t *row_cand, const double *na,
-                                                          const double *nb, double eps, int32_t cnt_cap) {
+                                                          int64_t *row_kmn, int64_t *row_cand, int64_t *row_real,
+                                                          const double *na, const double *nb, double eps,
+                                                          int32_t cnt_cap, KSizes ksz, int nkp, int32_t *cnt_g) {
   extern __shared__ uint32_t sm[];
   __shared__ int32_t shi[SYM_THREADS / 64];
   __shared__ int64_t shl[SYM_THREADS / 64];
   int32_t i = blockIdx.x;
   int32_t words_total = (nbc + 31) >> 5;
   if (words_total == 0) {
-    if (threadIdx.x == 0) { row_kmn[i] = 0; row_cand[i] = 0; }
+    if (threadIdx.x == 0) { row_kmn[i] = 0; row_cand[i] = 0; row_real[i] = 0; }
     return;
   }
   int32_t W = min(words_total, MAX_WORDS);
@@ -202,11 +209,14 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
     __syncthreads();
     wbase += wcount;
   }
-  // counts of kept products per C block
+  // counts of kept products per C block, per k size when padding (nkp > 0):
+  // every run of equal k size is padded to a multiple of 4 entries
   const bool lds_slot = (nwin == 1);
-  const bool lds_cnt = (R <= cnt_cap);
+  const int nk1 = nkp > 0 ? nkp : 1;
+  const bool lds_cnt = ((int64_t)R * nk1 <= cnt_cap);
+  int32_t *gcnt = nkp > 0 ? cnt_g + cbase * nk1 : c_cnt + cbase;
   if (lds_cnt)
-    for (int32_t t = threadIdx.x; t < R; t += blockDim.x) cnt[t] = 0;
+    for (int32_t t = threadIdx.x; t < R * nk1; t += blockDim.x) cnt[t] = 0;
   __syncthreads();
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int64_t kmn = 0, cand = 0;
@@ -223,19 +233,33 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
       if (lds_slot) slot = bm_test(bm, j) ? bm_slot(bm, pre, j) : -1;
       else slot = bsearch_slot(c_ci, cbase, cbase + R, j);
       if (slot < 0) continue;   // only under retain_sparsity
-      if (lds_cnt) atomicAdd(&cnt[slot], 1);
-      else atomicAdd(&c_cnt[cbase + slot], 1);
+      int kx = 0;
+      if (nkp > 0)
+        while (kx + 1 < nkp && ksz.v[kx] != kk) kx++;
+      if (lds_cnt) atomicAdd(&cnt[slot * nk1 + kx], 1);
+      else atomicAdd(&gcnt[slot * nk1 + kx], 1);
       kmn += (int64_t)kk * B.cbs[j];
     }
   }
   __syncthreads();
-  if (lds_cnt)
-    for (int32_t t = threadIdx.x; t < R; t += blockDim.x) c_cnt[cbase + t] = cnt[t];
+  int64_t real = 0;
+  for (int32_t t = threadIdx.x; t < R; t += blockDim.x) {
+    int32_t tot_real = 0, tot_pad = 0;
+    for (int kx = 0; kx < nk1; kx++) {
+      const int32_t v = lds_cnt ? cnt[t * nk1 + kx] : gcnt[t * nk1 + kx];
+      tot_real += v;
+      tot_pad += nkp > 0 ? (v + 3) & ~3 : v;
+    }
+    c_cnt[cbase + t] = tot_pad;
+    real += tot_real;
+  }
   int64_t tot = block_sum<int64_t>(kmn, shl);
   int64_t tcand = block_sum<int64_t>(cand, shl);
+  int64_t treal = block_sum<int64_t>(real, shl);
   if (threadIdx.x == 0) {
     row_kmn[i] = tot * m;
     row_cand[i] = tcand;
+    row_real[i] = treal;
   }
 }
 
@@ -259,7 +283,7 @@ __global__ void k_old_map(const int64_t *cold_rp, const int32_t *cold_ci, const 
 __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t nbc, const int64_t *c_rp,
                                                    const int32_t *c_ci, const int64_t *seg_off, int2 *stack,
                                                    const double *na, const double *nb, double eps,
-                                                   int32_t cnt_cap, int32_t *run) {
+                                                   int32_t cnt_cap, int32_t *run, KSizes ksz, int nks, int pad4) {
   extern __shared__ uint32_t sm[];
   int32_t i = blockIdx.x;
   int lane = threadIdx.x;
@@ -298,8 +322,14 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
   if (lds_cnt)
     for (int32_t t = lane; t < R; t += 64) cnt[t] = 0;
   __syncthreads();
+  // one pass per distinct k block size (ascending): every C block's segment
+  // is grouped by k size, ascending k inside a group, so the GEMM can run
+  // products of equal k size in lockstep
+  const int npass = nks > 0 ? nks : 1;
+  for (int pass = 0; pass < npass; pass++) {
   for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) {
     int32_t k = A.ci[p];
+    if (nks > 0 && A.cbs[k] != ksz.v[pass]) continue;
     int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
     double nA = na ? na[ablk] : 0.0;
     int64_t q1 = B.rp[k + 1];
@@ -317,6 +347,18 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
       stack[seg_off[cbase + slot] + at] = make_int2(ablk, bblk);
     }
     __syncthreads();
+  }
+  if (pad4) {
+    // close this k size: pad every C block's run to a multiple of 4 entries
+    for (int32_t t = lane; t < R; t += 64) {
+      int32_t at = lds_cnt ? cnt[t] : atomicAdd(&run[cbase + t], 0);
+      const int32_t end = (at + 3) & ~3;
+      for (; at < end; at++) stack[seg_off[cbase + t] + at] = make_int2(-1, -1);
+      if (lds_cnt) cnt[t] = end;
+      else atomicExch(&run[cbase + t], end);
+    }
+    __syncthreads();
+  }
   }
 }
 
@@ -342,11 +384,15 @@ void symbolic_fill(const FillArgs &f, hipStream_t s) {
   int32_t words_total = (f.sym.nbc + 31) >> 5;
   int32_t W = std::min(words_total, MAX_WORDS);
   if (W == 0) W = 1;
-  int32_t cap = std::min(f.max_row, CNT_CAP);
+  KSizes ks;
+  const int nkp = f.pad4 ? (int)f.ksizes.size() : 0;
+  for (int t = 0; t < nkp; t++) ks.v[t] = f.ksizes[t];
+  int32_t cap = (int32_t)std::min<int64_t>((int64_t)f.max_row * std::max(nkp, 1), CNT_CAP);
   size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 4;
   hipLaunchKernelGGL(k_sym_fill, dim3(nbr), dim3(SYM_THREADS), lds, s, view(*f.sym.a), view(*f.sym.b),
                      f.sym.cold_rp, f.sym.cold_ci, f.sym.use_cold ? 1 : 0, f.sym.retain ? 1 : 0, f.sym.nbc,
-                     f.c_rp, f.c_ci, f.c_row, f.c_size, f.c_cnt, f.c_kflops, f.row_cand, f.na, f.nb, f.eps, cap);
+                     f.c_rp, f.c_ci, f.c_row, f.c_size, f.c_cnt, f.c_kflops, f.row_cand, f.row_real, f.na, f.nb,
+                     f.eps, cap, ks, nkp, f.cnt_g);
   HIPCHECK(hipGetLastError());
 }
 
@@ -364,8 +410,12 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
   if (W == 0) W = 1;
   int32_t cap = std::min(g.max_row, CNT_CAP);
   size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 4;
+  KSizes ks;
+  int nks = (int)g.ksizes.size();
+  if (nks > MAX_KSIZES) nks = 0;
+  for (int t = 0; t < nks; t++) ks.v[t] = g.ksizes[t];
   hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr), dim3(64), lds, s, view(*g.a), view(*g.b), g.nbc, g.c_rp, g.c_ci,
-                     g.seg_off, g.stack, g.na, g.nb, g.eps, cap, run);
+                     g.seg_off, g.stack, g.na, g.nb, g.eps, cap, run, ks, nks, g.pad4 ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
 
