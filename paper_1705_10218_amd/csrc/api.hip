@@ -313,6 +313,8 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   std::sort(ksizes.begin(), ksizes.end());
   ksizes.erase(std::unique(ksizes.begin(), ksizes.end()), ksizes.end());
   const uint64_t two_gb = 1ull << 31;
+  // quad path of the GEMM: value arrays below 2 GB (32-bit byte offsets in
+  // the stack entries), at most 8 distinct k sizes
   const bool quads = (uint64_t)A->n_values * 8 < two_gb && (uint64_t)B->n_values * 8 < two_gb &&
                      !ksizes.empty() && ksizes.size() <= 8;
   DBuf<int32_t> cnt_g;
@@ -387,6 +389,7 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     sa.max_row = max_row;
     sa.ksizes = ksizes;
     sa.pad4 = quads;
+    sa.encode = quads;
     if (nprod > 0) stack_fill(sa, run.p, s);
   }
   // GEMM work list: C blocks row by row in the planner's locality order

@@ -385,18 +385,15 @@ struct QuadLds {
   int32_t Kq[ROUND / 4];
 };
 
-__device__ __forceinline__ void load_quads(const GemmP &P, QuadLds &ql, int64_t rb, int nr, int m, int lane) {
+__device__ __forceinline__ void load_quads(const GemmP &P, QuadLds &ql, int64_t rb, int nr, int lane) {
+  // entries: byte offsets of the two blocks with (k - 1) in their low 3 + 2
+  // bits; nulls are QOOB (a quad's first entry is never null)
   for (int q = lane; q < nr; q += 64) {
-    const int2 ab = P.stack[rb + q];
-    if (ab.x >= 0) {
-      const int64_t ao = P.a_off[ab.x];
-      ql.oa[q] = (uint32_t)(ao * 8);
-      ql.ob[q] = (uint32_t)(P.b_off[ab.y] * 8);
-      if ((q & 3) == 0) ql.Kq[q >> 2] = (int)((P.a_off[ab.x + 1] - ao) / m);
-    } else {
-      ql.oa[q] = QOOB;
-      ql.ob[q] = QOOB;
-    }
+    const int2 e = P.stack[rb + q];
+    const uint32_t oa = (uint32_t)e.x, ob = (uint32_t)e.y;
+    ql.oa[q] = oa & ~7u;
+    ql.ob[q] = ob & ~7u;
+    if ((q & 3) == 0) ql.Kq[q >> 2] = (int)((oa & 7u) | ((ob & 7u) << 3)) + 1;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -442,7 +439,7 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
   for (int64_t rbase = s0; rbase < s1; rbase += ROUND) {
     const int nr = (int)min<int64_t>(ROUND, s1 - rbase);   // multiple of 4
     const int nq = nr >> 2;
-    load_quads(P, ql, rbase, nr, m, lane);
+    load_quads(P, ql, rbase, nr, lane);
     // total k-steps of the round
     int steps = 0;
     for (int q = lane; q < nq; q += 64) steps += ql.Kq[q];
@@ -453,12 +450,11 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
     // the following quad's offsets and k size are already in flight
     int iq = 0, ik = 0;
     int iK = __builtin_amdgcn_readfirstlane(ql.Kq[0]);
-    uint32_t va[HM], vb[HN], nva[HM], nvb[HN];
+    uint32_t va[HM], vb[HN];
+    // next quad: raw LDS values, turned into lane offsets only at the switch
+    // (a quad later), so the LDS read never stalls the issue
+    uint32_t noa = QOOB, nob = QOOB;
     int nK = 1 << 30;
-#pragma unroll
-    for (int u = 0; u < HM; u++) nva[u] = QOOB;
-#pragma unroll
-    for (int v = 0; v < HN; v++) nvb[v] = QOOB;
     {
       const uint32_t oa = ql.oa[kq], ob = ql.ob[kq];
 #pragma unroll
@@ -466,11 +462,8 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
 #pragma unroll
       for (int v = 0; v < HN; v++) vb[v] = (cb8[v] == QOOB || ob == QOOB) ? QOOB : ob + cb8[v];
       if (nq > 1) {
-        const uint32_t oa1 = ql.oa[4 + kq], ob1 = ql.ob[4 + kq];
-#pragma unroll
-        for (int u = 0; u < HM; u++) nva[u] = (ra8[u] == QOOB || oa1 == QOOB) ? QOOB : oa1 + ra8[u];
-#pragma unroll
-        for (int v = 0; v < HN; v++) nvb[v] = (cb8[v] == QOOB || ob1 == QOOB) ? QOOB : ob1 + cb8[v];
+        noa = ql.oa[4 + kq];
+        nob = ql.ob[4 + kq];
         nK = ql.Kq[1];
       }
     }
@@ -488,23 +481,18 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
         iq++;
         iK = __builtin_amdgcn_readfirstlane(nK);
 #pragma unroll
-        for (int u = 0; u < HM; u++) va[u] = nva[u];
+        for (int u = 0; u < HM; u++) va[u] = (ra8[u] == QOOB || noa == QOOB) ? QOOB : noa + ra8[u];
 #pragma unroll
-        for (int v = 0; v < HN; v++) vb[v] = nvb[v];
+        for (int v = 0; v < HN; v++) vb[v] = (cb8[v] == QOOB || nob == QOOB) ? QOOB : nob + cb8[v];
         if (iq + 1 < nq) {
           const int t = 4 * (iq + 1) + kq;
-          const uint32_t oa = ql.oa[t], ob = ql.ob[t];
-#pragma unroll
-          for (int u = 0; u < HM; u++) nva[u] = (ra8[u] == QOOB || oa == QOOB) ? QOOB : oa + ra8[u];
-#pragma unroll
-          for (int v = 0; v < HN; v++) nvb[v] = (cb8[v] == QOOB || ob == QOOB) ? QOOB : ob + cb8[v];
+          noa = ql.oa[t];
+          nob = ql.ob[t];
           nK = ql.Kq[iq + 1];
         } else {
           // past the last quad: further issues read zeros (out of range)
-#pragma unroll
-          for (int u = 0; u < HM; u++) nva[u] = QOOB;
-#pragma unroll
-          for (int v = 0; v < HN; v++) nvb[v] = QOOB;
+          noa = QOOB;
+          nob = QOOB;
           nK = 1 << 30;
         }
       }

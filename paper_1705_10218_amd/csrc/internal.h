@@ -173,6 +173,7 @@ struct StackArgs {
   int32_t max_row = 0;
   std::vector<int32_t> ksizes;       // distinct k block sizes, ascending
   bool pad4 = false;                 // pad every equal-k-size run to 4 entries (null = -1)
+  bool encode = false;               // entries = byte offsets | (k-1) bits (quad path), null = 0x80000000
 };
 
 // a4: stack entries, grouped by C block, ascending k inside a block.  `run`

@@ -29,9 +29,10 @@ struct OpView {
   const int32_t *ci;
   const int32_t *blk;   // null = identity
   const int32_t *rbs, *cbs;
+  const int64_t *off;   // value offsets of the original blocks
 };
 
-OpView view(const OpIndex &o) { return OpView{o.row_ptr, o.col_idx, o.blk, o.rbs, o.cbs}; }
+OpView view(const OpIndex &o) { return OpView{o.row_ptr, o.col_idx, o.blk, o.rbs, o.cbs, o.blk_off}; }
 
 __device__ inline void bm_set(uint32_t *bm, int32_t j) { atomicOr(&bm[j >> 5], 1u << (j & 31)); }
 __device__ inline bool bm_test(const uint32_t *bm, int32_t j) { return (bm[j >> 5] >> (j & 31)) & 1u; }
@@ -283,7 +284,8 @@ __global__ void k_old_map(const int64_t *cold_rp, const int32_t *cold_ci, const 
 __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t nbc, const int64_t *c_rp,
                                                    const int32_t *c_ci, const int64_t *seg_off, int2 *stack,
                                                    const double *na, const double *nb, double eps,
-                                                   int32_t cnt_cap, int32_t *run, KSizes ksz, int nks, int pad4) {
+                                                   int32_t cnt_cap, int32_t *run, KSizes ksz, int nks, int pad4,
+                                                   int enc) {
   extern __shared__ uint32_t sm[];
   int32_t i = blockIdx.x;
   int lane = threadIdx.x;
@@ -344,7 +346,12 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
       int32_t at;
       if (lds_cnt) { at = cnt[slot]; cnt[slot] = at + 1; }
       else at = atomicAdd(&run[cbase + slot], 1);
-      stack[seg_off[cbase + slot] + at] = make_int2(ablk, bblk);
+      if (enc)   // byte offsets of the two blocks, k size - 1 in their low 3 + 2 bits
+        stack[seg_off[cbase + slot] + at] =
+            make_int2((int)((uint32_t)(A.off[ablk] * 8) | (uint32_t)((A.cbs[k] - 1) & 7)),
+                      (int)((uint32_t)(B.off[bblk] * 8) | (uint32_t)((A.cbs[k] - 1) >> 3)));
+      else
+        stack[seg_off[cbase + slot] + at] = make_int2(ablk, bblk);
     }
     __syncthreads();
   }
@@ -353,7 +360,8 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
     for (int32_t t = lane; t < R; t += 64) {
       int32_t at = lds_cnt ? cnt[t] : atomicAdd(&run[cbase + t], 0);
       const int32_t end = (at + 3) & ~3;
-      for (; at < end; at++) stack[seg_off[cbase + t] + at] = make_int2(-1, -1);
+      for (; at < end; at++)
+        stack[seg_off[cbase + t] + at] = enc ? make_int2((int)0x80000000u, (int)0x80000000u) : make_int2(-1, -1);
       if (lds_cnt) cnt[t] = end;
       else atomicExch(&run[cbase + t], end);
     }
@@ -415,7 +423,7 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
   if (nks > MAX_KSIZES) nks = 0;
   for (int t = 0; t < nks; t++) ks.v[t] = g.ksizes[t];
   hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr), dim3(64), lds, s, view(*g.a), view(*g.b), g.nbc, g.c_rp, g.c_ci,
-                     g.seg_off, g.stack, g.na, g.nb, g.eps, cap, run, ks, nks, g.pad4 ? 1 : 0);
+                     g.seg_off, g.stack, g.na, g.nb, g.eps, cap, run, ks, nks, g.pad4 ? 1 : 0, g.encode ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
 
