@@ -16,9 +16,11 @@ CPU oracle on a seeded sample of block rows.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -46,6 +48,50 @@ def workload(name: str):
         a, b = inputs.config_tiny(0), inputs.config_tiny(1)
         return a, b, 0.0, {"workload": "tiny_100x100_blocks_5", "filter_eps": 0.0}
     raise SystemExit(f"unknown workload {name}")
+
+
+GEMM_SOURCE = os.path.join(ROOT, "paper_1705_10218_amd", "csrc", "gemm_kernels.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_gemm_f64_dft4000_traffic.md")
+
+
+def gemm_source_digest() -> str:
+    with open(GEMM_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per GEMM launch from the committed counter summary.
+
+    The summary holds FETCH_SIZE and WRITE_SIZE of the block-GEMM kernel on
+    this workload, each divided by the factor the same counter reads for a
+    plain copy of known size.  It is used only while the kernel source is the
+    one the counters were taken on (digest match); otherwise None.
+    """
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^- ([a-z_0-9]+): `([^`]*)`", text, re.M))
+    if kv.get("gemm_source_sha256_16") != gemm_source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib: int, reps: int):
+    """Plain device-to-device copies of a known size (counter calibration)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.randn(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
+                      "copies": reps}))
 
 
 def cpu_baseline(a, b, eps, gpu_host, target_s: float, threads: int):
@@ -101,6 +147,8 @@ def main():
     ap.add_argument("--workload", default="dft4000", choices=["dft4000", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run plain device copies of this size (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -113,6 +161,9 @@ def main():
     from paper_1705_10218_amd import bsmm
     if not torch.cuda.is_available():
         raise SystemExit("no HIP device visible")
+    if args.calibrate_copy_mib > 0:
+        copy_calibration(args.calibrate_copy_mib, 3)
+        return
 
     _log("generating workload")
     a, b, eps, cfg = workload(args.workload)
@@ -156,6 +207,9 @@ def main():
     gemm_tflops = flops / (gemm_ms * 1e-3) / 1e12
     gpu_host = last.to_host()
     last.close()
+    # compulsory HBM bytes of the GEMM launch: A and B values once, C values once
+    compulsory = int(8 * (a.n_values() + b.n_values() + infos[-1].c_n_values))
+    traffic = measured_traffic()
 
     out = {
         "metric": METRIC,
@@ -183,7 +237,10 @@ def main():
             "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(gemm_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
+            "compulsory_bytes": compulsory,
+            "ms_per_launch": round(gemm_ms, 4),
         },
     }
     if not args.no_cpu_baseline:

@@ -154,7 +154,9 @@ static void free_mat(bsmm_mat_s *m) {
 }
 
 // Locality order of x's block rows for the GEMM work list, computed once per
-// matrix from its (immutable) block pattern and cached on the device.
+// matrix from its (immutable) block pattern and cached on the device: nbr
+// entries of the order, then nbr entries of its inverse (the rank of a row,
+// also used for the columns of a square product).
 static const int32_t *row_order(bsmm_ctx ctx, bsmm_mat_s *x) {
   if (x->d_order) return x->d_order;
   if (x->nbr != x->nbc || x->nbr < 64) return nullptr;
@@ -166,8 +168,10 @@ static const int32_t *row_order(bsmm_ctx ctx, bsmm_mat_s *x) {
                             ctx->stream));
   HIPCHECK(hipStreamSynchronize(ctx->stream));
   x->h_order = locality_order(x->nbr, rp, ci);
-  x->d_order = static_cast<int32_t *>(ctx->alloc.alloc(sizeof(int32_t) * (size_t)x->nbr));
-  HIPCHECK(hipMemcpyAsync(x->d_order, x->h_order.data(), sizeof(int32_t) * (size_t)x->nbr, hipMemcpyHostToDevice,
+  x->h_order.resize(2 * (size_t)x->nbr);
+  for (int32_t r = 0; r < x->nbr; r++) x->h_order[(size_t)x->nbr + x->h_order[r]] = r;
+  x->d_order = static_cast<int32_t *>(ctx->alloc.alloc(sizeof(int32_t) * 2 * (size_t)x->nbr));
+  HIPCHECK(hipMemcpyAsync(x->d_order, x->h_order.data(), sizeof(int32_t) * 2 * (size_t)x->nbr, hipMemcpyHostToDevice,
                           ctx->stream));
   HIPCHECK(hipStreamSynchronize(ctx->stream));
   return x->d_order;
@@ -313,9 +317,10 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   std::sort(ksizes.begin(), ksizes.end());
   ksizes.erase(std::unique(ksizes.begin(), ksizes.end()), ksizes.end());
   const uint64_t two_gb = 1ull << 31;
-  // quad path of the GEMM: value arrays below 2 GB (32-bit byte offsets in
-  // the stack entries), at most 8 distinct k sizes
-  const bool quads = (uint64_t)A->n_values * 8 < two_gb && (uint64_t)B->n_values * 8 < two_gb &&
+  // quad path of the GEMM: packed operand copies below 2 GB (32-bit byte
+  // offsets in the stack entries; a packed block holds at most twice the
+  // values of the stored one), at most 8 distinct k sizes
+  const bool quads = (uint64_t)A->n_values * 16 < two_gb && (uint64_t)B->n_values * 16 < two_gb &&
                      !ksizes.empty() && ksizes.size() <= 8;
   DBuf<int32_t> cnt_g;
   if (quads && (int64_t)max_row * (int64_t)ksizes.size() > 8192) {
@@ -348,6 +353,16 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   exclusive_scan_i64(al, row_kmn.p, kmn_scan.p, nbr, s);
   exclusive_scan_i64(al, row_cand.p, cand_scan.p, nbr, s);
   exclusive_scan_i64(al, row_real.p, real_scan.p, nbr, s);
+  // packed operand offsets for the quad path (op(A) row-major, op(B) column-major)
+  DBuf<int64_t> a_poff, b_poff;
+  if (quads) {
+    a_poff = DBuf<int64_t>(al, (size_t)A->nnzb + 1);
+    b_poff = DBuf<int64_t>(al, (size_t)B->nnzb + 1);
+    pack_offsets(al, *A, ta, a_poff.p, s);
+    pack_offsets(al, *B, !tb, b_poff.p, s);
+    HIPCHECK(hipMemcpyAsync(ctx->pinned + 5, a_poff.p + A->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(ctx->pinned + 6, b_poff.p + B->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  }
   HIPCHECK(hipMemcpyAsync(ctx->pinned, c_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(ctx->pinned + 1, seg_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(ctx->pinned + 2, kmn_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -359,6 +374,7 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   const int64_t nprod = ctx->pinned[4];
   const int64_t kmn_total = ctx->pinned[2];
   const int64_t ncand = ctx->pinned[3];
+  const int64_t a_pack_n = quads ? ctx->pinned[5] : 0, b_pack_n = quads ? ctx->pinned[6] : 0;
   DBuf<int32_t> old_blk;
   if (C0 && beta != 0.0 && nnzb_c > 0) {
     old_blk = DBuf<int32_t>(al, nc1);
@@ -367,6 +383,13 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   }
   tm.mark();  // 3
   // ------------------------------------------------------- a4: stacks
+  DBuf<double> a_pack, b_pack;
+  if (quads && nprod > 0) {
+    a_pack = DBuf<double>(al, (size_t)std::max<int64_t>(a_pack_n, 2));
+    b_pack = DBuf<double>(al, (size_t)std::max<int64_t>(b_pack_n, 2));
+    pack_values(*A, ta, a_poff.p, a_pack.p, s);
+    pack_values(*B, !tb, b_poff.p, b_pack.p, s);
+  }
   DBuf<int2> stack(al, (size_t)std::max<int64_t>(nstack, 1));
   {
     DBuf<int32_t> run;
@@ -390,19 +413,24 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     sa.ksizes = ksizes;
     sa.pad4 = quads;
     sa.encode = quads;
+    sa.a_poff = a_poff.p;
+    sa.b_poff = b_poff.p;
     if (nprod > 0) stack_fill(sa, run.p, s);
   }
-  // GEMM work list: C blocks row by row in the planner's locality order
+  // GEMM work list: tiles of rows in the planner's locality order, columns
+  // inside a tile in the same order when C is square over the same blocks
   DBuf<int32_t> c_list;
   if (nnzb_c > 0) {
     const int32_t *ord = row_order(ctx, A);
     if (ord) {
       c_list = DBuf<int32_t>(al, nc1);
+      const int32_t *rank = (nbc == nbr) ? ord + nbr : nullptr;
+      const int32_t tile_rows = 16;
       if ((size_t)nbc * 4 > 160 * 1024) {
         // columns too many for one LDS histogram: plain row order
-        build_work_list(al, ord, c_rp.p, c_ci.p, nbr, 0, c_list.p, s);
+        build_work_list(al, ord, nullptr, c_rp.p, c_ci.p, nbr, 0, tile_rows, c_list.p, s);
       } else {
-        build_work_list(al, ord, c_rp.p, c_ci.p, nbr, nbc, c_list.p, s);
+        build_work_list(al, ord, rank, c_rp.p, c_ci.p, nbr, nbc, tile_rows, c_list.p, s);
       }
     }
   }
@@ -431,20 +459,23 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     ga.alpha = alpha;
     ga.beta = beta;
     ga.mode = ctx->mode;
-    // operand layouts for the matrix cores: op(A) column-major, op(B) row-major
+    // operand layouts for the matrix cores.  Quad path: the packed copies.
+    // Walker path: op(A) column-major, op(B) row-major.
     DBuf<double> a_t, b_t;
-    if (ta && nprod > 0) {
+    if (!quads && ta && nprod > 0) {
       a_t = DBuf<double>(al, (size_t)std::max<int64_t>(A->n_values, 1));
       transpose_blocks(*A, a_t.p, s);
     }
-    if (!tb && nprod > 0) {
+    if (!quads && !tb && nprod > 0) {
       b_t = DBuf<double>(al, (size_t)std::max<int64_t>(B->n_values, 1));
       transpose_blocks(*B, b_t.p, s);
     }
     ga.a_cm = ta ? a_t.p : A->d_values;
     ga.b_rm = tb ? B->d_values : b_t.p;
-    ga.a_bytes = (uint64_t)A->n_values * sizeof(double);
-    ga.b_bytes = (uint64_t)B->n_values * sizeof(double);
+    ga.a_pack = a_pack.p;
+    ga.b_pack = b_pack.p;
+    ga.a_bytes = (uint64_t)(quads ? a_pack_n : A->n_values) * sizeof(double);
+    ga.b_bytes = (uint64_t)(quads ? b_pack_n : B->n_values) * sizeof(double);
     if (!ctx->zeros) {
       ctx->zeros = static_cast<double *>(al.alloc(4096));
       HIPCHECK(hipMemsetAsync(ctx->zeros, 0, 4096, s));
@@ -457,6 +488,8 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     gemm_launch(ga, nnzb_c, max_edge, s);
     a_t.reset();
     b_t.reset();
+    a_pack.reset();
+    b_pack.reset();
     tm.mark();  // 5
     // ----------------------------------------------------- a6: post-filter
     R = new_result(ctx, nbr, nbc, opa_r, opb_c);

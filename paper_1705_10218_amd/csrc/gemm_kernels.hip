@@ -370,24 +370,31 @@ __device__ __forceinline__ void gemm_block_44(const GemmP &P, int32_t c, ParamLd
 // With the stacks grouped by k size and every equal-k run padded to a
 // multiple of 4 entries (null entries), the segment splits into quads of
 // four products of one k size; the four k-groups run their quad in lockstep,
-// so the k index is uniform: it rides in the scalar offset of the buffer
-// loads (the range check covers voffset + soffset + immediate, so a lane
-// whose voffset is out of range -- padded row or column, null product --
-// reads zeros at every k).  Per k-step a lane issues HM + HN loads and the
-// MFMAs, nothing else; the next quad's lane offsets are read from LDS one
-// quad ahead.  Arrays below 2 GB (32-bit offsets with an out-of-range mark
-// that no k offset can wrap).
+// so the k index is uniform.
+//
+// Operands come from packed copies in k-pair slabs (two consecutive k of
+// every row of op(A), or column of op(B), side by side; K padded to even
+// with a zero; blocks 16-byte aligned).  One 128-bit load brings a lane two
+// k-steps, and the 16 lanes of a k-group read one contiguous run: a buffer
+// load costs the address unit about the same for 64 and 128 bits per lane,
+// so pairs halve the load-issue time that bounds this kernel.  The slab
+// offset rides in the scalar offset (the range check
+// covers voffset + soffset + immediate, so a lane whose voffset is out of
+// range -- padded row or column, null product -- reads zeros at every k).
+// The pad's zero times zero adds an exact 0 when K is odd.  Arrays below
+// 2 GB (32-bit offsets with an out-of-range mark that no k offset can wrap).
 constexpr uint32_t QOOB = 0x80000000u;
+constexpr int PF2 = 3;   // pairs of k-steps in flight
 
 struct QuadLds {
-  uint32_t oa[ROUND];   // byte offsets of op(A) / op(B) blocks (QOOB = null)
+  uint32_t oa[ROUND];   // byte offsets of packed op(A) / op(B) blocks (QOOB = null)
   uint32_t ob[ROUND];
   int32_t Kq[ROUND / 4];
 };
 
 __device__ __forceinline__ void load_quads(const GemmP &P, QuadLds &ql, int64_t rb, int nr, int lane) {
-  // entries: byte offsets of the two blocks with (k - 1) in their low 3 + 2
-  // bits; nulls are QOOB (a quad's first entry is never null)
+  // entries: byte offsets of the two packed blocks with (k - 1) in their low
+  // 3 + 2 bits; nulls are QOOB (a quad's first entry is never null)
   for (int q = lane; q < nr; q += 64) {
     const int2 e = P.stack[rb + q];
     const uint32_t oa = (uint32_t)e.x, ob = (uint32_t)e.y;
@@ -400,90 +407,103 @@ __device__ __forceinline__ void load_quads(const GemmP &P, QuadLds &ql, int64_t 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ d2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff, int soff) {
+  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, soff, 0));
+}
+
 template <bool SIXTEEN, int MT, int NT>
 __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadLds &ql) {
   constexpr int HM = SIXTEEN ? 1 : MT / 2, HN = SIXTEEN ? 1 : NT / 2;
+  // two accumulator sets (the two k-steps of a pair) when a step has a single
+  // MFMA chain: a dependent FP64 MFMA waits for the previous result
+  constexpr int NC = (SIXTEEN || HM * HN == 1) ? 2 : 1;
   const int lane = threadIdx.x & 63;
   // one C block per wavefront: its sizes are uniform (scalar registers)
   const int m = __builtin_amdgcn_readfirstlane(P.rbs[P.c_row[c]]);
   const int n = __builtin_amdgcn_readfirstlane(P.cbs[P.c_ci[c]]);
-  const int m8 = 8 * m, n8 = 8 * n;
+  const int m16 = 16 * m, n16 = 16 * n;   // bytes of one k-pair slab of op(A) / op(B)
   const int kq = lane >> 4;
-  // lane's rows of op(A) / columns of op(B), as byte offsets (QOOB if padding)
-  uint32_t ra8[HM], cb8[HN];
+  // lane's rows of op(A) / columns of op(B) (-1 if padding)
+  int ra[HM], cb[HN];
   if (SIXTEEN) {
-    ra8[0] = (lane & 15) < m ? 8u * (lane & 15) : QOOB;
-    cb8[0] = (lane & 15) < n ? 8u * (lane & 15) : QOOB;
+    ra[0] = (lane & 15) < m ? (lane & 15) : -1;
+    cb[0] = (lane & 15) < n ? (lane & 15) : -1;
   } else {
     const int L4 = lane & 3, bq = (lane >> 2) & 3;
     const int Pq = bq >> 1, Qq = bq & 1;
 #pragma unroll
     for (int u = 0; u < HM; u++) {
       const int r = 4 * (Pq * HM + u) + L4;
-      ra8[u] = r < m ? 8u * r : QOOB;
+      ra[u] = r < m ? r : -1;
     }
 #pragma unroll
     for (int v = 0; v < HN; v++) {
       const int cc = 4 * (Qq * HN + v) + L4;
-      cb8[v] = cc < n ? 8u * cc : QOOB;
+      cb[v] = cc < n ? cc : -1;
     }
   }
-  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
-  double acc[SIXTEEN ? 1 : HM * HN];
-  d4 acc16 = {0.0, 0.0, 0.0, 0.0};
+  const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
+  double acc[NC][SIXTEEN ? 1 : HM * HN];
+  d4 acc16[NC];
 #pragma unroll
-  for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[t] = 0.0;
+  for (int h = 0; h < NC; h++) {
+    acc16[h] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[h][t] = 0.0;
+  }
 
   const int64_t s0 = P.seg[c], s1 = P.seg[c + 1];
   for (int64_t rbase = s0; rbase < s1; rbase += ROUND) {
     const int nr = (int)min<int64_t>(ROUND, s1 - rbase);   // multiple of 4
     const int nq = nr >> 2;
     load_quads(P, ql, rbase, nr, lane);
-    // total k-steps of the round
+    // total pairs of the round
     int steps = 0;
-    for (int q = lane; q < nq; q += 64) steps += ql.Kq[q];
+    for (int q = lane; q < nq; q += 64) steps += (ql.Kq[q] + 1) >> 1;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) steps += __shfl_xor(steps, d, 64);
     steps = __builtin_amdgcn_readfirstlane(steps);
-    // issue cursor: quad iq, k index ik (uniform), lane offsets of quad iq;
-    // the following quad's offsets and k size are already in flight
-    int iq = 0, ik = 0;
-    int iK = __builtin_amdgcn_readfirstlane(ql.Kq[0]);
+    // issue cursor: quad iq, pair ip (uniform), lane offsets of quad iq;
+    // the following quad's block offsets and k size are read a quad ahead
+    int iq = 0, ip = 0;
     uint32_t va[HM], vb[HN];
-    // next quad: raw LDS values, turned into lane offsets only at the switch
-    // (a quad later), so the LDS read never stalls the issue
     uint32_t noa = QOOB, nob = QOOB;
-    int nK = 1 << 30;
+    int nK = 1 << 20;
+    // lane offsets of a quad with block offsets (oa, ob): row r of a slab at
+    // 16 r bytes; slab p at p * 16 * (rows) bytes rides in the scalar offset
+    auto lane_offsets = [&](uint32_t oa, uint32_t ob, int) {
+#pragma unroll
+      for (int u = 0; u < HM; u++) va[u] = (ra[u] < 0 || oa == QOOB) ? QOOB : oa + 16u * (uint32_t)ra[u];
+#pragma unroll
+      for (int v = 0; v < HN; v++) vb[v] = (cb[v] < 0 || ob == QOOB) ? QOOB : ob + 16u * (uint32_t)cb[v];
+    };
+    int iP;
     {
-      const uint32_t oa = ql.oa[kq], ob = ql.ob[kq];
-#pragma unroll
-      for (int u = 0; u < HM; u++) va[u] = (ra8[u] == QOOB || oa == QOOB) ? QOOB : oa + ra8[u];
-#pragma unroll
-      for (int v = 0; v < HN; v++) vb[v] = (cb8[v] == QOOB || ob == QOOB) ? QOOB : ob + cb8[v];
+      const int K0 = __builtin_amdgcn_readfirstlane(ql.Kq[0]);
+      iP = (K0 + 1) >> 1;
+      lane_offsets(ql.oa[kq], ql.ob[kq], K0);
       if (nq > 1) {
         noa = ql.oa[4 + kq];
         nob = ql.ob[4 + kq];
         nK = ql.Kq[1];
       }
     }
-    double qa[PF][HM], qb[PF][HN];
-    auto issue = [&](double (&xa)[HM], double (&xb)[HN]) {
-      const int sa = ik * m8, sb = ik * n8;
+    d2 qa[PF2][HM], qb[PF2][HN];
+    auto issue = [&](d2 (&xa)[HM], d2 (&xb)[HN]) {
+      const int sa = ip * m16, sb = ip * n16;
 #pragma unroll
-      for (int u = 0; u < HM; u++)
-        xa[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ra, (int)va[u], sa, 0));
+      for (int u = 0; u < HM; u++) xa[u] = load_pair(rsa, va[u], sa);
 #pragma unroll
-      for (int v = 0; v < HN; v++)
-        xb[v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, (int)vb[v], sb, 0));
-      if (++ik == iK) {   // uniform: next quad
-        ik = 0;
+      for (int v = 0; v < HN; v++) xb[v] = load_pair(rsb, vb[v], sb);
+      if (++ip == iP) {   // uniform: next quad
+        ip = 0;
         iq++;
-        iK = __builtin_amdgcn_readfirstlane(nK);
-#pragma unroll
-        for (int u = 0; u < HM; u++) va[u] = (ra8[u] == QOOB || noa == QOOB) ? QOOB : noa + ra8[u];
-#pragma unroll
-        for (int v = 0; v < HN; v++) vb[v] = (cb8[v] == QOOB || nob == QOOB) ? QOOB : nob + cb8[v];
+        const int K = __builtin_amdgcn_readfirstlane(nK);
+        iP = (K + 1) >> 1;
+        lane_offsets(noa, nob, K);
         if (iq + 1 < nq) {
           const int t = 4 * (iq + 1) + kq;
           noa = ql.oa[t];
@@ -493,53 +513,63 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
           // past the last quad: further issues read zeros (out of range)
           noa = QOOB;
           nob = QOOB;
-          nK = 1 << 30;
+          nK = 1 << 20;
         }
       }
     };
-    auto mma = [&](const double (&xa)[HM], const double (&xb)[HN]) {
-      if (SIXTEEN) {
-        acc16 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[0], xb[0], acc16, 0, 0, 0);
-      } else {
+    auto mma = [&](const d2 (&xa)[HM], const d2 (&xb)[HN]) {
 #pragma unroll
-        for (int u = 0; u < HM; u++)
+      for (int e = 0; e < 2; e++) {
+        const int h = e % NC;
+        if (SIXTEEN) {
+          acc16[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[0][e], xb[0][e], acc16[h], 0, 0, 0);
+        } else {
 #pragma unroll
-          for (int v = 0; v < HN; v++)
-            acc[u * HN + v] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[u], xb[v], acc[u * HN + v], 0, 0, 0);
+          for (int u = 0; u < HM; u++)
+#pragma unroll
+            for (int v = 0; v < HN; v++)
+              acc[h][u * HN + v] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[u][e], xb[v][e], acc[h][u * HN + v], 0, 0, 0);
+        }
       }
     };
-    // prologue: always PF issues (beyond the round they read zeros), so the
+    // prologue: always PF2 issues (beyond the round they read zeros), so the
     // loop is entered with a fixed number of loads in flight
 #pragma unroll
-    for (int d = 0; d < PF; d++) {
+    for (int d = 0; d < PF2; d++) {
       issue(qa[d], qb[d]);
       __builtin_amdgcn_sched_barrier(0);
     }
-    // ring: the MFMA of step s reads slot s % PF, then the load of step
-    // s + PF lands in that same slot (no register copies, so no wait for
+    // ring: the MFMAs of pair s read slot s % PF2, then the load of pair
+    // s + PF2 lands in that same slot (no register copies, so no wait for
     // younger loads)
     int s = 0;
-    for (; s + 2 * PF <= steps; s += PF) {   // every issue in range
+    for (; s + 2 * PF2 <= steps; s += PF2) {   // every issue in range
 #pragma unroll
-      for (int d = 0; d < PF; d++) {
+      for (int d = 0; d < PF2; d++) {
         mma(qa[d], qb[d]);
         issue(qa[d], qb[d]);
-        __builtin_amdgcn_sched_barrier(0);   // keep the ring order: MFMA(s), load(s + PF)
+        __builtin_amdgcn_sched_barrier(0);   // keep the ring order: MFMA(s), load(s + PF2)
       }
     }
-    // drain: remaining steps s .. steps-1, issuing while steps remain
+    // drain: remaining pairs s .. steps-1, issuing while pairs remain
 #pragma unroll
-    for (int d = 0; d < 2 * PF; d++) {
+    for (int d = 0; d < 2 * PF2; d++) {
       const int st = s + d;
       if (st < steps) {
-        const int slot = d % PF;
+        const int slot = d % PF2;
         mma(qa[slot], qb[slot]);
-        if (st + PF < steps) issue(qa[slot], qb[slot]);
+        if (st + PF2 < steps) issue(qa[slot], qb[slot]);
       }
     }
     round_end();
   }
 
+  // fold the accumulator sets in a fixed order
+  if constexpr (NC == 2) {
+    acc16[0] += acc16[NC - 1];
+#pragma unroll
+    for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[0][t] += acc[NC - 1][t];
+  }
   const int64_t co = P.c_off[c];
   const double *old = old_block(P, c);
   double ss = 0.0;
@@ -548,7 +578,7 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
 #pragma unroll
     for (int r = 0; r < 4; r++) {
       const int row = 4 * r + kq;
-      if (row < m && col < n) store_c(P, old, co, m, row, col, acc16[r], ss);
+      if (row < m && col < n) store_c(P, old, co, m, row, col, acc16[0][r], ss);
     }
   } else {
     const int L4 = lane & 3, bq = (lane >> 2) & 3;
@@ -559,7 +589,7 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
 #pragma unroll
       for (int v = 0; v < HN; v++) {
         const int col = 4 * (Qq * HN + v) + L4;
-        if (row < m && col < n) store_c(P, old, co, m, row, col, acc[u * HN + v], ss);
+        if (row < m && col < n) store_c(P, old, co, m, row, col, acc[0][u * HN + v], ss);
       }
     }
   }
@@ -642,30 +672,31 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t
   }
 }
 
-// Work list: tiles of TILE_ROWS consecutive rows of the locality order; inside
-// a tile, C blocks go column by column.  A block B(k,j) feeds only the C
+// Work list: tiles of `tr` consecutive rows of the locality order; inside a
+// tile, C blocks go column by column, the columns in the same locality order
+// (rank[j] = position of column j in it).  A block B(k,j) feeds only the C
 // blocks of column j, one per row i with A(i,k) stored, so running a
-// column's blocks of neighbouring rows back to back keeps B(k,j) in L2,
-// while the tile's A rows (a few MB) stay resident across its columns.
-constexpr int TILE_ROWS = 16;
-
-__global__ void k_order_counts(const int32_t *ord, const int64_t *c_rp, int32_t nbr, int64_t *cnt) {
+// column's blocks of neighbouring rows back to back keeps B(k,j) in L2;
+// neighbouring columns need neighbouring k, so the tile's A(i,k) in use at
+// any time are a compact subset as well.
+__global__ void k_order_counts(const int32_t *ord, const int64_t *c_rp, int32_t nbr, int32_t tr, int64_t *cnt) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;   // tile
-  const int32_t ntile = (nbr + TILE_ROWS - 1) / TILE_ROWS;
+  const int32_t ntile = (nbr + tr - 1) / tr;
   if (t >= ntile) return;
   int64_t s = 0;
-  for (int32_t r = t * TILE_ROWS; r < min(nbr, (t + 1) * TILE_ROWS); r++) s += c_rp[ord[r] + 1] - c_rp[ord[r]];
+  for (int32_t r = t * tr; r < min(nbr, (t + 1) * tr); r++) s += c_rp[ord[r] + 1] - c_rp[ord[r]];
   cnt[t] = s;
 }
 
 // One workgroup per tile: counting sort of the tile's C blocks by column
 // (LDS histogram over nbc columns); ties in a column fall in any order.
-__global__ __launch_bounds__(256) void k_order_fill(const int32_t *ord, const int64_t *c_rp, const int32_t *c_ci,
-                                                    int32_t nbr, int32_t nbc, const int64_t *start, int32_t *c_list) {
+__global__ __launch_bounds__(256) void k_order_fill(const int32_t *ord, const int32_t *rank, const int64_t *c_rp,
+                                                    const int32_t *c_ci, int32_t nbr, int32_t nbc, int32_t tr,
+                                                    const int64_t *start, int32_t *c_list) {
   extern __shared__ int32_t hist[];   // nbc counters, then the scan
   __shared__ int32_t wsum[4];
   const int32_t t = blockIdx.x;
-  const int32_t r0 = t * TILE_ROWS, r1 = min(nbr, r0 + TILE_ROWS);
+  const int32_t r0 = t * tr, r1 = min(nbr, r0 + tr);
   if (nbc == 0) {   // no column histogram: the tile's rows one after another
     int64_t off = start[t];
     for (int32_t r = r0; r < r1; r++) {
@@ -679,7 +710,7 @@ __global__ __launch_bounds__(256) void k_order_fill(const int32_t *ord, const in
   __syncthreads();
   for (int32_t r = r0; r < r1; r++) {
     const int64_t c0 = c_rp[ord[r]], c1 = c_rp[ord[r] + 1];
-    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) atomicAdd(&hist[c_ci[c]], 1);
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) atomicAdd(&hist[rank ? rank[c_ci[c]] : c_ci[c]], 1);
   }
   __syncthreads();
   // exclusive scan of hist over nbc entries (each thread a contiguous chunk)
@@ -708,7 +739,7 @@ __global__ __launch_bounds__(256) void k_order_fill(const int32_t *ord, const in
   for (int32_t r = r0; r < r1; r++) {
     const int64_t c0 = c_rp[ord[r]], c1 = c_rp[ord[r] + 1];
     for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-      const int32_t at = atomicAdd(&hist[c_ci[c]], 1);
+      const int32_t at = atomicAdd(&hist[rank ? rank[c_ci[c]] : c_ci[c]], 1);
       c_list[o + at] = (int32_t)c;
     }
   }
@@ -733,7 +764,67 @@ __global__ __launch_bounds__(256) void k_transpose_blocks(const int64_t *rp, con
   }
 }
 
+// Packed operand copies for the quad path.  Stored block b (R x C,
+// column-major) of X is viewed as nr rows r by K contraction indices k:
+//   k_is_row = 1 (op(A) = A^T, op(B) = B):  K = R, nr = C, x(r,k) = in[k + r R]
+//   k_is_row = 0 (op(A) = A,   op(B) = B^T): K = C, nr = R, x(r,k) = in[r + k R]
+// (for op(A) the rows r are the rows of op(A), for op(B) its columns) and
+// stored pair-major: Kp/2 slabs, Kp = K + (K & 1), slab p holding for each
+// r the two values x(r, 2p), x(r, 2p+1) (the pad zero).  A lane's 16 bytes
+// of slab p are then one 128-bit load giving two k-steps, and the lanes of
+// consecutive r read one contiguous run.  Every packed block holds an even
+// number of values, so all start 16-byte aligned.
+__global__ __launch_bounds__(64) void k_pack_sizes(const int64_t *rp, const int32_t *ci, const int32_t *rbs,
+                                                  const int32_t *cbs, int k_is_row, int64_t *sizes) {
+  const int32_t i = blockIdx.x;
+  const int R = rbs[i];
+  for (int64_t p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 64) {
+    const int C = cbs[ci[p]];
+    const int K = k_is_row ? R : C, nr = k_is_row ? C : R;
+    sizes[p] = (int64_t)nr * (K + (K & 1));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pack_blocks(const int64_t *rp, const int32_t *ci, const int32_t *rbs,
+                                                     const int32_t *cbs, const int64_t *off, const double *in,
+                                                     int k_is_row, const int64_t *poff, double *out) {
+  const int32_t i = blockIdx.x;
+  const int R = rbs[i];
+  for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+    const int C = cbs[ci[p]];
+    const int K = k_is_row ? R : C, nr = k_is_row ? C : R;
+    const int Kp = K + (K & 1);
+    const int64_t o = off[p], po = poff[p];
+    for (int e = threadIdx.x; e < nr * Kp; e += blockDim.x) {
+      const int slab = e / (2 * nr), w = e - slab * 2 * nr;
+      const int r = w >> 1, k = 2 * slab + (w & 1);
+      double x = 0.0;
+      if (k < K) x = k_is_row ? in[o + k + (int64_t)r * R] : in[o + r + (int64_t)k * R];
+      out[po + e] = x;
+    }
+  }
+}
+
 }  // namespace
+
+void pack_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_poff, hipStream_t s) {
+  if (x.nnzb == 0) {
+    HIPCHECK(hipMemsetAsync(d_poff, 0, sizeof(int64_t), s));
+    return;
+  }
+  DBuf<int64_t> sizes(al, (size_t)x.nnzb);
+  hipLaunchKernelGGL(k_pack_sizes, dim3(x.nbr), dim3(64), 0, s, x.d_row_ptr, x.d_col_idx, x.d_rbs, x.d_cbs,
+                     k_is_row ? 1 : 0, sizes.p);
+  HIPCHECK(hipGetLastError());
+  exclusive_scan_i64(al, sizes.p, d_poff, x.nnzb, s);
+}
+
+void pack_values(const bsmm_mat_s &x, bool k_is_row, const int64_t *d_poff, double *out, hipStream_t s) {
+  if (x.nbr == 0 || x.nnzb == 0) return;
+  hipLaunchKernelGGL(k_pack_blocks, dim3(x.nbr), dim3(256), 0, s, x.d_row_ptr, x.d_col_idx, x.d_rbs, x.d_cbs,
+                     x.d_blk_off, x.d_values, k_is_row ? 1 : 0, d_poff, out);
+  HIPCHECK(hipGetLastError());
+}
 
 void transpose_blocks(const bsmm_mat_s &x, double *out, hipStream_t s) {
   if (x.nbr == 0 || x.nnzb == 0) return;
@@ -742,18 +833,19 @@ void transpose_blocks(const bsmm_mat_s &x, double *out, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
-void build_work_list(Allocator &al, const int32_t *d_ord, const int64_t *c_rp, const int32_t *c_ci, int32_t nbr,
-                     int32_t nbc, int32_t *c_list, hipStream_t s) {
+void build_work_list(Allocator &al, const int32_t *d_ord, const int32_t *d_rank, const int64_t *c_rp,
+                     const int32_t *c_ci, int32_t nbr, int32_t nbc, int32_t tile_rows, int32_t *c_list, hipStream_t s) {
   if (nbr == 0) return;
-  const int32_t ntile = (nbr + TILE_ROWS - 1) / TILE_ROWS;
+  const int32_t tr = std::max(tile_rows, 1);
+  const int32_t ntile = (nbr + tr - 1) / tr;
   DBuf<int64_t> cnt(al, ntile), start(al, (size_t)ntile + 1);
-  hipLaunchKernelGGL(k_order_counts, dim3((ntile + 255) / 256), dim3(256), 0, s, d_ord, c_rp, nbr, cnt.p);
+  hipLaunchKernelGGL(k_order_counts, dim3((ntile + 255) / 256), dim3(256), 0, s, d_ord, c_rp, nbr, tr, cnt.p);
   HIPCHECK(hipGetLastError());
   exclusive_scan_i64(al, cnt.p, start.p, ntile, s);
   const size_t lds = sizeof(int32_t) * (size_t)std::max(nbc, 1);
   if (lds > 65536)
     HIPCHECK(hipFuncSetAttribute((const void *)k_order_fill, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_order_fill, dim3(ntile), dim3(256), lds, s, d_ord, c_rp, c_ci, nbr, nbc,
+  hipLaunchKernelGGL(k_order_fill, dim3(ntile), dim3(256), lds, s, d_ord, d_rank, c_rp, c_ci, nbr, nbc, tr,
                      (const int64_t *)start.p, c_list);
   HIPCHECK(hipGetLastError());
 }
@@ -786,6 +878,10 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
   const int64_t grid = per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   const bool buf = g.quads;
+  if (buf) {   // quad path: packed copies (op(A) row-major, op(B) column-major, k padded to even)
+    p.a_val = g.a_pack;
+    p.b_val = g.b_pack;
+  }
   p.a_bytes = buf ? (uint32_t)g.a_bytes : 0u;
   p.b_bytes = buf ? (uint32_t)g.b_bytes : 0u;
   p.zeros = g.zeros;

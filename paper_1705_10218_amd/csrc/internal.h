@@ -174,6 +174,8 @@ struct StackArgs {
   std::vector<int32_t> ksizes;       // distinct k block sizes, ascending
   bool pad4 = false;                 // pad every equal-k-size run to 4 entries (null = -1)
   bool encode = false;               // entries = byte offsets | (k-1) bits (quad path), null = 0x80000000
+  const int64_t *a_poff = nullptr;   // packed block offsets used by the encoded entries
+  const int64_t *b_poff = nullptr;
 };
 
 // a4: stack entries, grouped by C block, ascending k inside a block.  `run`
@@ -200,12 +202,21 @@ struct GemmArgs {
   double *c_norm = nullptr;          // out: norm of every C block (may be null)
   double alpha = 1.0, beta = 0.0;
   bsmm_compute_mode mode = BSMM_COMPUTE_FP64;
-  const double *a_cm = nullptr;      // op(A) blocks, column-major (m x K)
-  const double *b_rm = nullptr;      // op(B) blocks, row-major (K x n)
-  uint64_t a_bytes = 0, b_bytes = 0; // sizes of the two value arrays
+  const double *a_cm = nullptr;      // op(A) blocks, column-major (m x K) (walker path)
+  const double *b_rm = nullptr;      // op(B) blocks, row-major (K x n) (walker path)
+  const double *a_pack = nullptr;    // packed op(A): row-major, k padded to even (quad path)
+  const double *b_pack = nullptr;    // packed op(B): column-major, k padded to even (quad path)
+  uint64_t a_bytes = 0, b_bytes = 0; // sizes of the two value arrays the kernel reads
   bool quads = false;                // stacks padded to k-homogeneous quads (quad path)
   const double *zeros = nullptr;     // >= 4 KB of zeros
 };
+
+// Packed operand copies (quad path): per stored block, nr rows of
+// Kp = K + (K & 1) values contiguous in k (pad zero).  k_is_row: the block's
+// row count is the contraction extent (op(A) = A^T or op(B) = B).
+// pack_offsets writes nnzb + 1 offsets (exclusive scan, total last).
+void pack_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_poff, hipStream_t s);
+void pack_values(const bsmm_mat_s &x, bool k_is_row, const int64_t *d_poff, double *out, hipStream_t s);
 
 // Transpose every stored block of x into out (same offsets).
 void transpose_blocks(const bsmm_mat_s &x, double *out, hipStream_t s);
@@ -216,8 +227,8 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
 
 // c_list = C blocks in tiles of consecutive rows of ord (device), column by
 // column inside a tile.
-void build_work_list(Allocator &al, const int32_t *d_ord, const int64_t *c_rp, const int32_t *c_ci, int32_t nbr,
-                     int32_t nbc, int32_t *c_list, hipStream_t s);
+void build_work_list(Allocator &al, const int32_t *d_ord, const int32_t *d_rank, const int64_t *c_rp,
+                     const int32_t *c_ci, int32_t nbr, int32_t nbc, int32_t tile_rows, int32_t *c_list, hipStream_t s);
 
 // Locality order of the rows of a square block pattern (host planner).
 std::vector<int32_t> locality_order(int32_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci);

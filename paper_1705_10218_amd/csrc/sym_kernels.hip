@@ -422,7 +422,12 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
   int nks = (int)g.ksizes.size();
   if (nks > MAX_KSIZES) nks = 0;
   for (int t = 0; t < nks; t++) ks.v[t] = g.ksizes[t];
-  hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr), dim3(64), lds, s, view(*g.a), view(*g.b), g.nbc, g.c_rp, g.c_ci,
+  OpView va = view(*g.a), vb = view(*g.b);
+  if (g.encode) {   // entries carry offsets into the packed operand copies
+    va.off = g.a_poff;
+    vb.off = g.b_poff;
+  }
+  hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr), dim3(64), lds, s, va, vb, g.nbc, g.c_rp, g.c_ci,
                      g.seg_off, g.stack, g.na, g.nb, g.eps, cap, run, ks, nks, g.pad4 ? 1 : 0, g.encode ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
