@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
 METRIC = "useful FP64 GFLOP/s of block-sparse C+=A·B, % MFMA peak; p99 serve latency"
 
@@ -94,8 +95,8 @@ def copy_calibration(mib: int, reps: int):
                       "copies": reps}))
 
 
-def cpu_baseline(a, b, eps, gpu_host, target_s: float, threads: int):
-    """Time the oracle on a seeded sample of block rows; also compare those rows."""
+def oracle_sample(a, b, eps, target_s: float, threads: int):
+    """Time the oracle on a seeded sample of block rows (about target_s seconds)."""
     import numpy as np
 
     import oracle
@@ -104,7 +105,7 @@ def cpu_baseline(a, b, eps, gpu_host, target_s: float, threads: int):
     # calibrate on a few rows, then size the sample to about target_s seconds
     probe = np.sort(order[: max(threads, 8)])
     t0 = time.perf_counter()
-    r = oracle.multiply("N", "N", 1.0, a, b, eps=eps, nthreads=threads, rows=probe)
+    oracle.multiply("N", "N", 1.0, a, b, eps=eps, nthreads=threads, rows=probe)
     dt = time.perf_counter() - t0
     per_row = dt / len(probe)
     n = int(min(a.nbr, max(len(probe), target_s / max(per_row, 1e-9))))
@@ -112,7 +113,13 @@ def cpu_baseline(a, b, eps, gpu_host, target_s: float, threads: int):
     t0 = time.perf_counter()
     r = oracle.multiply("N", "N", 1.0, a, b, eps=eps, nthreads=threads, rows=rows)
     dt = time.perf_counter() - t0
-    # parity of the sampled rows against the GPU result
+    return r, rows, dt
+
+
+def sample_parity(gpu_host, r, rows):
+    """Pattern equality and relative Frobenius error of the sampled rows."""
+    import numpy as np
+
     from paper_1705_10218_amd.inputs import BlockCSR
     go = BlockCSR(gpu_host.rbs, gpu_host.cbs, gpu_host.row_ptr, gpu_host.col_idx, gpu_host.values).block_offsets()
     ro = BlockCSR(r.rbs, r.cbs, r.row_ptr, r.col_idx, r.values).block_offsets()
@@ -128,15 +135,30 @@ def cpu_baseline(a, b, eps, gpu_host, target_s: float, threads: int):
         num += float(d @ d)
         den += float(r.values[ro[r0]:ro[r1]] @ r.values[ro[r0]:ro[r1]])
     rel = math.sqrt(num / den) if den > 0 else 0.0
-    return {
-        "value": round(r.useful_flops / dt / 1e9, 3),
-        "unit": "GFLOP/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": (f"{n} of {a.nbr} seeded block rows of C ({r.useful_flops:.3e} useful flops, "
-                   f"{100.0 * n / a.nbr:.1f}% of rows), {dt:.2f} s wall"),
-        "sample_parity": {"rows": int(n), "pattern_equal": bool(pattern_ok), "rel_fro_err": rel},
-    }
+    return {"rows": int(len(rows)), "pattern_equal": bool(pattern_ok), "rel_fro_err": rel}
+
+
+def time_mode(bsmm, ctx, A, Bm, eps, steps, warmup):
+    """Warm-up, then `steps` whole multiplies timed with events on the stream."""
+    import torch
+    for _ in range(warmup):
+        C, info = bsmm.multiply(ctx, "N", "N", 1.0, A, Bm, filter_eps=eps)
+        C.close()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    last = None
+    for _ in range(steps):
+        C, info = bsmm.multiply(ctx, "N", "N", 1.0, A, Bm, filter_eps=eps)
+        infos.append(info)
+        if last is not None:
+            last.close()
+        last = C
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, infos, last
 
 
 def main():
@@ -146,6 +168,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="dft4000", choices=["dft4000", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--fp64-only", action="store_true", help="skip the FP32 / split-FP32 measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run plain device copies of this size (HBM counter calibration)")
@@ -173,31 +196,11 @@ def main():
     torch.cuda.synchronize()
     ctx.set_timing(True)
 
-    _log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        C, info = bsmm.multiply(ctx, "N", "N", 1.0, A, Bm, filter_eps=eps)
-        C.close()
-    torch.cuda.synchronize()
-
-    _log(f"timing {args.steps} steps")
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    infos = []
-    torch.cuda.synchronize()
+    _log(f"warmup {args.warmup}, timing {args.steps} steps")
     t0 = time.perf_counter()
-    ev0.record(stream)
-    last = None
-    for s in range(args.steps):
-        C, info = bsmm.multiply(ctx, "N", "N", 1.0, A, Bm, filter_eps=eps)
-        infos.append(info)
-        if last is not None:
-            last.close()
-        last = C
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    ms_step, infos, last = time_mode(bsmm, ctx, A, Bm, eps, args.steps, args.warmup)
     wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    _log(f"{ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f})")
+    _log(f"{ms_step:.3f} ms/step")
 
     flops = infos[-1].useful_flops
     value = flops / (ms_step * 1e-3) / 1e9
@@ -243,10 +246,40 @@ def main():
             "ms_per_launch": round(gemm_ms, 4),
         },
     }
+    # FP32 and split-FP32 modes on the same matrices (norms and filters FP64)
+    lowp_hosts = {}
+    if not args.fp64_only:
+        prec = {}
+        for name, mode in (("fp32", 1), ("split", 2)):
+            ctx.set_compute_mode(mode)
+            ms_m, inf_m, last_m = time_mode(bsmm, ctx, A, Bm, eps, args.steps, 1)
+            ctx.set_compute_mode(0)
+            g_m = sum(i.ms_gemm for i in inf_m) / len(inf_m)
+            prec[name] = {"value": round(inf_m[-1].useful_flops / (ms_m * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                          "ms_per_step": round(ms_m, 4), "gemm_ms": round(g_m, 4),
+                          "speedup_vs_fp64": round(ms_step / ms_m, 3),
+                          "gemm_tflops": round(inf_m[-1].useful_flops / (g_m * 1e-3) / 1e12, 3),
+                          "frac_of_fp32_mfma_peak": round(inf_m[-1].useful_flops / (g_m * 1e-3) / 1e12
+                                                          / FP32_MFMA_PEAK_TFLOPS, 4)}
+            _log(f"{name}: {ms_m:.3f} ms/step")
+            lowp_hosts[name] = last_m.to_host()
+            last_m.close()
+        out["precision"] = prec
     if not args.no_cpu_baseline:
         threads = min(len(os.sched_getaffinity(0)), 16)
         _log(f"cpu baseline on {threads} threads")
-        out["cpu_baseline"] = cpu_baseline(a, b, eps, gpu_host, args.cpu_seconds, threads)
+        r, rows, dt = oracle_sample(a, b, eps, args.cpu_seconds, threads)
+        out["cpu_baseline"] = {
+            "value": round(r.useful_flops / dt / 1e9, 3),
+            "unit": "GFLOP/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": (f"{len(rows)} of {a.nbr} seeded block rows of C ({r.useful_flops:.3e} useful flops, "
+                       f"{100.0 * len(rows) / a.nbr:.1f}% of rows), {dt:.2f} s wall"),
+            "sample_parity": sample_parity(gpu_host, r, rows),
+        }
+        for name, h in lowp_hosts.items():
+            out["precision"][name]["sample_parity"] = sample_parity(h, r, rows)
     A.close()
     Bm.close()
     print(json.dumps(out))

@@ -57,15 +57,17 @@ typedef enum {
 } bsmm_status;
 
 /* Arithmetic used by the block products (the norms, the filter thresholds
- * and the stored values are FP64 in every mode). */
+ * and the stored values are FP64 in every mode).  FP32 and SPLIT need packed
+ * operand copies below 1 GB and at most 8 distinct k block sizes; otherwise
+ * bsmm_multiply returns BSMM_ERR_UNSUPPORTED. */
 typedef enum {
   BSMM_COMPUTE_FP64 = 0,      /* FP64 MFMA, FP64 accumulation                  */
-  BSMM_COMPUTE_FP32 = 1,      /* operands rounded to FP32, FP32 MFMA products
-                                 and accumulation inside one block product,
-                                 FP64 accumulation across block products      */
+  BSMM_COMPUTE_FP32 = 1,      /* operands rounded to FP32, FP32 MFMA products,
+                                 FP32 accumulation over a result block, then
+                                 FP64 for alpha/beta, C and its norm          */
   BSMM_COMPUTE_SPLIT = 2      /* each operand split into FP32 hi + lo parts;
-                                 hi*hi + hi*lo + lo*hi on FP32 MFMA, FP64
-                                 accumulation across block products           */
+                                 per k-step lo*hi + hi*lo + hi*hi on FP32
+                                 MFMA, accumulated across k in FP64           */
 } bsmm_compute_mode;
 
 /* Sizes and counters of one multiplication. */

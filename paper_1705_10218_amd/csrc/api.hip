@@ -355,11 +355,19 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   exclusive_scan_i64(al, row_real.p, real_scan.p, nbr, s);
   // packed operand offsets for the quad path (op(A) row-major, op(B) column-major)
   DBuf<int64_t> a_poff, b_poff;
+  const bool lowp = ctx->mode != BSMM_COMPUTE_FP64;
+  if (lowp && !quads && nnzb_c > 0)
+    fail(BSMM_ERR_UNSUPPORTED, "FP32 / split modes need operands below 1 GB and at most 8 distinct k block sizes");
   if (quads) {
     a_poff = DBuf<int64_t>(al, (size_t)A->nnzb + 1);
     b_poff = DBuf<int64_t>(al, (size_t)B->nnzb + 1);
-    pack_offsets(al, *A, ta, a_poff.p, s);
-    pack_offsets(al, *B, !tb, b_poff.p, s);
+    if (lowp) {   // FP32 k-quad slabs
+      pack32_offsets(al, *A, ta, a_poff.p, s);
+      pack32_offsets(al, *B, !tb, b_poff.p, s);
+    } else {      // FP64 k-pair slabs
+      pack_offsets(al, *A, ta, a_poff.p, s);
+      pack_offsets(al, *B, !tb, b_poff.p, s);
+    }
     HIPCHECK(hipMemcpyAsync(ctx->pinned + 5, a_poff.p + A->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(ctx->pinned + 6, b_poff.p + B->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   }
@@ -383,12 +391,23 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   }
   tm.mark();  // 3
   // ------------------------------------------------------- a4: stacks
-  DBuf<double> a_pack, b_pack;
+  // packed operand copies (a_pack_n / b_pack_n are in units of 8 bytes)
+  DBuf<double> a_pack, b_pack, a_lo, b_lo;
   if (quads && nprod > 0) {
     a_pack = DBuf<double>(al, (size_t)std::max<int64_t>(a_pack_n, 2));
     b_pack = DBuf<double>(al, (size_t)std::max<int64_t>(b_pack_n, 2));
-    pack_values(*A, ta, a_poff.p, a_pack.p, s);
-    pack_values(*B, !tb, b_poff.p, b_pack.p, s);
+    if (lowp) {
+      const bool split = ctx->mode == BSMM_COMPUTE_SPLIT;
+      if (split) {
+        a_lo = DBuf<double>(al, (size_t)std::max<int64_t>(a_pack_n, 2));
+        b_lo = DBuf<double>(al, (size_t)std::max<int64_t>(b_pack_n, 2));
+      }
+      pack32_values(*A, ta, a_poff.p, reinterpret_cast<float *>(a_pack.p), reinterpret_cast<float *>(a_lo.p), s);
+      pack32_values(*B, !tb, b_poff.p, reinterpret_cast<float *>(b_pack.p), reinterpret_cast<float *>(b_lo.p), s);
+    } else {
+      pack_values(*A, ta, a_poff.p, a_pack.p, s);
+      pack_values(*B, !tb, b_poff.p, b_pack.p, s);
+    }
   }
   DBuf<int2> stack(al, (size_t)std::max<int64_t>(nstack, 1));
   {
@@ -474,6 +493,10 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     ga.b_rm = tb ? B->d_values : b_t.p;
     ga.a_pack = a_pack.p;
     ga.b_pack = b_pack.p;
+    ga.a_hi = reinterpret_cast<const float *>(a_pack.p);
+    ga.b_hi = reinterpret_cast<const float *>(b_pack.p);
+    ga.a_lo = reinterpret_cast<const float *>(a_lo.p);
+    ga.b_lo = reinterpret_cast<const float *>(b_lo.p);
     ga.a_bytes = (uint64_t)(quads ? a_pack_n : A->n_values) * sizeof(double);
     ga.b_bytes = (uint64_t)(quads ? b_pack_n : B->n_values) * sizeof(double);
     if (!ctx->zeros) {
@@ -485,11 +508,16 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     int max_edge = 1;
     for (int32_t v : opa_r) max_edge = std::max(max_edge, v);
     for (int32_t v : opb_c) max_edge = std::max(max_edge, v);
-    gemm_launch(ga, nnzb_c, max_edge, s);
+    if (lowp)
+      gemm_launch_lowp(ga, nnzb_c, max_edge, s);
+    else
+      gemm_launch(ga, nnzb_c, max_edge, s);
     a_t.reset();
     b_t.reset();
     a_pack.reset();
     b_pack.reset();
+    a_lo.reset();
+    b_lo.reset();
     tm.mark();  // 5
     // ----------------------------------------------------- a6: post-filter
     R = new_result(ctx, nbr, nbc, opa_r, opb_c);
@@ -633,7 +661,8 @@ bsmm_status bsmm_ctx_set_timing(bsmm_ctx ctx, int enable) {
 bsmm_status bsmm_ctx_set_compute_mode(bsmm_ctx ctx, bsmm_compute_mode mode) {
   ABI_BEGIN
   if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
-  if (mode != BSMM_COMPUTE_FP64) fail(BSMM_ERR_UNSUPPORTED, "only BSMM_COMPUTE_FP64 is available");
+  if (mode != BSMM_COMPUTE_FP64 && mode != BSMM_COMPUTE_FP32 && mode != BSMM_COMPUTE_SPLIT)
+    fail(BSMM_ERR_INVALID_ARG, "unknown compute mode");
   ctx->mode = mode;
   ABI_END
 }

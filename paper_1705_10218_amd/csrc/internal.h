@@ -206,6 +206,8 @@ struct GemmArgs {
   const double *b_rm = nullptr;      // op(B) blocks, row-major (K x n) (walker path)
   const double *a_pack = nullptr;    // packed op(A): row-major, k padded to even (quad path)
   const double *b_pack = nullptr;    // packed op(B): column-major, k padded to even (quad path)
+  const float *a_hi = nullptr, *a_lo = nullptr;   // packed FP32 k-quad slabs (FP32 / split modes)
+  const float *b_hi = nullptr, *b_lo = nullptr;
   uint64_t a_bytes = 0, b_bytes = 0; // sizes of the two value arrays the kernel reads
   bool quads = false;                // stacks padded to k-homogeneous quads (quad path)
   const double *zeros = nullptr;     // >= 4 KB of zeros
@@ -217,6 +219,12 @@ struct GemmArgs {
 // pack_offsets writes nnzb + 1 offsets (exclusive scan, total last).
 void pack_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_poff, hipStream_t s);
 void pack_values(const bsmm_mat_s &x, bool k_is_row, const int64_t *d_poff, double *out, hipStream_t s);
+// FP32 k-quad slabs (FP32 / split modes): offsets in units of 8 bytes; lo
+// (the rounding remainder x - fp32(x)) is written only when non-null.
+void pack32_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_poff, hipStream_t s);
+void pack32_values(const bsmm_mat_s &x, bool k_is_row, const int64_t *d_poff, float *hi, float *lo, hipStream_t s);
+// a5 in FP32 or split-FP32 arithmetic (g.mode), quad path only.
+void gemm_launch_lowp(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s);
 
 // Transpose every stored block of x into out (same offsets).
 void transpose_blocks(const bsmm_mat_s &x, double *out, hipStream_t s);
