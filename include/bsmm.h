@@ -158,6 +158,41 @@ bsmm_status bsmm_multiply(bsmm_ctx ctx, char transa, char transb, double alpha,
  * (the post-multiply filter of Section 1 applied on its own). */
 bsmm_status bsmm_filter(bsmm_mat m, double eps, bsmm_mat *out);
 
+/* Statistics of a sign iteration. */
+typedef struct {
+  int32_t iterations;     /* iterations run (each forms X^2)                  */
+  int32_t converged;      /* 1 if the residual fell below tol                 */
+  double residual;        /* ||X^2 - I||_F / sqrt(N) of the last iterate whose
+                             square was formed (N = matrix dimension)         */
+  int64_t nnzb;           /* blocks of the returned matrix                    */
+  int64_t nnzb_max;       /* most blocks held by any iterate or 3I - X^2      */
+  double useful_flops;    /* sum over all multiplications (2*m*k*n per kept
+                             block product)                                   */
+  float ms_total;         /* device time when timing is enabled, else 0      */
+} bsmm_sign_info;
+
+/* Newton-Schulz iteration for the matrix sign function (Section 1, eq. (3)
+ * and the iteration that follows it): X_{n+1} = 1/2 X_n (3I - X_n^2),
+ * starting from x0.  x0 must be square with equal row and column block
+ * sizes; the iteration converges to sign(x0) when the spectral radius of x0
+ * is below 1 and no eigenvalue is 0.
+ * Each iteration is two filtered multiplications on the device: T = 3I - X X
+ * (beta = 3 with the block-diagonal identity as C_old, so the pattern is the
+ * union) and X = 0.5 X T, both with filter_eps for the on-the-fly and post
+ * filters, so the pattern of X evolves from iteration to iteration.
+ * The residual ||X_n^2 - I||_F / sqrt(N) comes from T.  The loop stops after
+ * max_iter iterations, or as soon as the residual of the current iterate is
+ * below tol (tol <= 0: never); the current iterate is then returned as is.
+ * trace_residual and trace_nnzb (each max_iter entries, or NULL) receive the
+ * residual of X_n and the block count of the matrix returned after step n.
+ * x0 is not modified; *x_out is a new matrix (also when max_iter = 0: a copy).
+ * Errors: BSMM_ERR_SHAPE for a non-square grid or unequal row and column
+ * block sizes, BSMM_ERR_INVALID_ARG for max_iter < 0 or filter_eps < 0, and
+ * every error of bsmm_multiply. */
+bsmm_status bsmm_sign_newton_schulz(bsmm_ctx ctx, bsmm_mat x0, int32_t max_iter, double filter_eps, double tol,
+                                    bsmm_mat *x_out, bsmm_sign_info *info, double *trace_residual,
+                                    int64_t *trace_nnzb);
+
 #ifdef __cplusplus
 }
 #endif

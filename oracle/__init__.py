@@ -14,6 +14,7 @@ readings taken where the paper is silent are listed at the top of
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -188,3 +189,64 @@ def filter_blocks(m, eps: float) -> Mat:
     del keep
     assert rc == 0
     return _take(res)
+
+
+# ------------------------------------------------------------------ sign
+def _identity(sizes) -> Mat:
+    """Block-diagonal identity with the given block sizes."""
+    sizes = np.asarray(sizes, dtype=np.int32)
+    n = sizes.shape[0]
+    vals = np.concatenate([np.eye(int(s)).reshape(-1, order="F") for s in sizes]) if n else np.zeros(0)
+    return Mat(sizes.copy(), sizes.copy(), np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), vals)
+
+
+def _shift_dist(t: Mat, shift: float) -> float:
+    """||T - shift * I||_F for a square block matrix T (block rows in order)."""
+    sizes = t.rbs.astype(np.int64)
+    ss = 0.0
+    off = 0
+    for i in range(t.nbr):
+        has_diag = False
+        for p in range(int(t.row_ptr[i]), int(t.row_ptr[i + 1])):
+            j = int(t.col_idx[p])
+            n = int(sizes[i] * t.cbs[j])
+            blk = t.values[off:off + n].reshape((int(sizes[i]), int(t.cbs[j])), order="F").copy()
+            off += n
+            if j == i:
+                has_diag = True
+                blk[np.diag_indices(int(sizes[i]))] -= shift
+            ss += float(np.sum(blk * blk))
+        if not has_diag:
+            ss += shift * shift * float(sizes[i])
+    return math.sqrt(ss)
+
+
+def newton_schulz(x0, max_iter: int, eps: float = 0.0, tol: float = 0.0, nthreads: int = 1):
+    """Newton-Schulz iteration for the matrix sign function, X <- X (3I - X^2) / 2
+    (arXiv:1705.10218, Section 1, eq. (3) and the iteration after it), each
+    product a filtered block-sparse multiplication of this oracle:
+    T = 3I - X X (C_old = I, beta = 3), residual ||T - 2I||_F / sqrt(N) =
+    ||X^2 - I||_F / sqrt(N), stop if it is below tol (> 0), else
+    X = 0.5 X T.  Returns (X, residuals, nnzb after each step, converged,
+    useful flops)."""
+    ident = _identity(x0.rbs)
+    ndim = float(np.sum(np.asarray(x0.rbs, dtype=np.int64)))
+    x = x0
+    res, nnz = [], []
+    flops = 0.0
+    converged = False
+    for _ in range(max_iter):
+        t = multiply("N", "N", -1.0, x, x, beta=3.0, c=ident, eps=eps, nthreads=nthreads)
+        flops += t.useful_flops
+        r = _shift_dist(t, 2.0) / math.sqrt(ndim) if ndim > 0 else 0.0
+        res.append(r)
+        if tol > 0.0 and r < tol:
+            nnz.append(int(x.row_ptr[-1]))
+            converged = True
+            break
+        x = multiply("N", "N", 0.5, x, t, eps=eps, nthreads=nthreads)
+        flops += x.useful_flops
+        nnz.append(int(x.row_ptr[-1]))
+    if x is x0:
+        x = multiply("N", "N", 1.0, x0, ident, nthreads=nthreads)
+    return x, np.array(res), np.array(nnz, dtype=np.int64), converged, flops

@@ -32,7 +32,7 @@ SYMBOLS = (
     "bsmm_ctx_set_timing", "bsmm_ctx_set_compute_mode", "bsmm_ctx_memory", "bsmm_ctx_trim",
     "bsmm_ctx_synchronize", "bsmm_ctx_destroy", "bsmm_mat_create", "bsmm_mat_info",
     "bsmm_mat_get_index", "bsmm_mat_get_block_sizes", "bsmm_mat_values", "bsmm_mat_copy_values",
-    "bsmm_mat_destroy", "bsmm_block_norms", "bsmm_multiply", "bsmm_filter",
+    "bsmm_mat_destroy", "bsmm_block_norms", "bsmm_multiply", "bsmm_filter", "bsmm_sign_newton_schulz",
 )
 
 
@@ -48,6 +48,17 @@ class MultiplyInfo(ctypes.Structure):
         ("n_candidates", ctypes.c_int64), ("n_products", ctypes.c_int64), ("useful_flops", ctypes.c_double),
         ("ms_index", ctypes.c_float), ("ms_norms", ctypes.c_float), ("ms_symbolic", ctypes.c_float),
         ("ms_stacks", ctypes.c_float), ("ms_gemm", ctypes.c_float), ("ms_filter", ctypes.c_float),
+        ("ms_total", ctypes.c_float),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SignInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("residual", ctypes.c_double),
+        ("nnzb", ctypes.c_int64), ("nnzb_max", ctypes.c_int64), ("useful_flops", ctypes.c_double),
         ("ms_total", ctypes.c_float),
     ]
 
@@ -96,6 +107,9 @@ def lib() -> ctypes.CDLL:
                                     _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_vp),
                                     ctypes.POINTER(MultiplyInfo)]
         L.bsmm_filter.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_vp)]
+        L.bsmm_sign_newton_schulz.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                              ctypes.POINTER(_vp), ctypes.POINTER(SignInfo),
+                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         _lib = L
     return _lib
 
@@ -282,6 +296,24 @@ def filter(m: Matrix, eps: float) -> Matrix:  # noqa: A001 - mirrors bsmm_filter
     out = _vp()
     _check(lib().bsmm_filter(m.handle, float(eps), ctypes.byref(out)))
     return Matrix(m.ctx, out)
+
+
+def sign_newton_schulz(ctx: Context, x0: Matrix, max_iter: int, filter_eps: float = 0.0, tol: float = 0.0):
+    """bsmm_sign_newton_schulz: returns (X matrix, SignInfo, residual per
+    iteration, blocks after each iteration) -- the two traces cut to the
+    iterations run."""
+    import numpy as np
+    out = _vp()
+    info = SignInfo()
+    n = max(int(max_iter), 1)
+    res = np.zeros(n, dtype=np.float64)
+    nnz = np.zeros(n, dtype=np.int64)
+    _check(lib().bsmm_sign_newton_schulz(ctx.handle, x0.handle, int(max_iter), float(filter_eps), float(tol),
+                                         ctypes.byref(out), ctypes.byref(info),
+                                         res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         nnz.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    k = info.iterations
+    return Matrix(ctx, out), info, res[:k].copy(), nnz[:k].copy()
 
 
 def status_string(s: int) -> str:

@@ -583,6 +583,134 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   return R;
 }
 
+// Block-diagonal identity with the given block sizes (owned values).
+static bsmm_mat_s *make_identity(bsmm_ctx ctx, const std::vector<int32_t> &sizes) {
+  const int32_t n = (int32_t)sizes.size();
+  bsmm_mat_s *I = new_result(ctx, n, n, sizes, sizes);
+  Allocator &al = ctx->alloc;
+  try {
+    std::vector<int64_t> rp((size_t)n + 1), off((size_t)n + 1);
+    std::vector<int32_t> ci((size_t)std::max(n, 1));
+    off[0] = 0;
+    for (int32_t i = 0; i < n; i++) {
+      rp[i] = i;
+      ci[i] = i;
+      off[i + 1] = off[i] + (int64_t)sizes[i] * sizes[i];
+    }
+    rp[n] = n;
+    I->nnzb = n;
+    I->n_values = off[n];
+    I->d_row_ptr = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * ((size_t)n + 1)));
+    I->d_col_idx = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * (size_t)std::max(n, 1)));
+    I->d_blk_off = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * ((size_t)n + 1)));
+    I->d_values = static_cast<double *>(al.alloc(sizeof(double) * (size_t)std::max<int64_t>(off[n], 1)));
+    upload(I->d_row_ptr, rp.data(), sizeof(int64_t) * rp.size(), ctx->stream);
+    upload(I->d_col_idx, ci.data(), sizeof(int32_t) * (size_t)n, ctx->stream);
+    upload(I->d_blk_off, off.data(), sizeof(int64_t) * off.size(), ctx->stream);
+    identity_values(I->d_rbs, I->d_blk_off, n, I->d_values, ctx->stream);
+    HIPCHECK(hipStreamSynchronize(ctx->stream));   // host vectors go out of scope
+  } catch (...) {
+    free_mat(I);
+    throw;
+  }
+  return I;
+}
+
+// ||X^2 - I||_F from T = 3I - X^2 (= ||T - 2I||_F), summed per block row.
+static double sign_residual(bsmm_ctx ctx, const bsmm_mat_s &T) {
+  Allocator &al = ctx->alloc;
+  DBuf<double> rows(al, (size_t)std::max(T.nbr, 1));
+  shift_dist_rows(T, 2.0, rows.p, ctx->stream);
+  std::vector<double> h((size_t)T.nbr);
+  if (T.nbr) HIPCHECK(hipMemcpyAsync(h.data(), rows.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  double ss = 0.0;
+  for (double v : h) ss += v;   // fixed order: deterministic
+  return std::sqrt(ss);
+}
+
+// Newton-Schulz sign iteration, X <- 1/2 X (3I - X^2): two filtered
+// multiplications per iteration.
+static bsmm_mat_s *sign_impl(bsmm_ctx ctx, bsmm_mat_s *X0, int32_t max_iter, double eps, double tol,
+                             bsmm_sign_info *info, double *trace_res, int64_t *trace_nnzb) {
+  if (X0->nbr != X0->nbc) fail(BSMM_ERR_SHAPE, "the sign iteration needs a square block grid");
+  if (X0->h_rbs != X0->h_cbs) fail(BSMM_ERR_SHAPE, "row and column block sizes differ");
+  if (max_iter < 0) fail(BSMM_ERR_INVALID_ARG, "max_iter < 0");
+  if (!(eps >= 0.0)) fail(BSMM_ERR_INVALID_ARG, "filter_eps must be >= 0");
+  double ndim = 0.0;
+  for (int32_t v : X0->h_rbs) ndim += v;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    HIPCHECK(hipEventRecord(e0, ctx->stream));
+  }
+  bsmm_mat_s *I = make_identity(ctx, X0->h_rbs);
+  bsmm_mat_s *X = X0;   // borrowed until the first update
+  bsmm_sign_info st{};
+  st.nnzb_max = X0->nnzb;
+  st.residual = -1.0;
+  try {
+    for (int32_t it = 0; it < max_iter; it++) {
+      bsmm_multiply_info mi{};
+      // T = 3I - X X  (beta = 3, C_old = I: the pattern is the union)
+      bsmm_mat_s *T = multiply_impl(ctx, 'N', 'N', -1.0, X, X, 3.0, I, eps, 0, &mi);
+      st.useful_flops += mi.useful_flops;
+      st.nnzb_max = std::max(st.nnzb_max, T->nnzb);
+      double res;
+      try {
+        res = (ndim > 0 ? sign_residual(ctx, *T) / std::sqrt(ndim) : 0.0);
+      } catch (...) {
+        free_mat(T);
+        throw;
+      }
+      st.residual = res;
+      st.iterations = it + 1;
+      if (trace_res) trace_res[it] = res;
+      if (tol > 0.0 && res < tol) {
+        free_mat(T);
+        st.converged = 1;
+        if (trace_nnzb) trace_nnzb[it] = X->nnzb;
+        break;
+      }
+      bsmm_mat_s *Xn;
+      try {
+        Xn = multiply_impl(ctx, 'N', 'N', 0.5, X, T, 0.0, nullptr, eps, 0, &mi);
+      } catch (...) {
+        free_mat(T);
+        throw;
+      }
+      st.useful_flops += mi.useful_flops;
+      free_mat(T);
+      if (X != X0) free_mat(X);
+      X = Xn;
+      st.nnzb_max = std::max(st.nnzb_max, X->nnzb);
+      if (trace_nnzb) trace_nnzb[it] = X->nnzb;
+    }
+    if (X == X0) {   // no update ran: return a copy of X0's blocks
+      bsmm_multiply_info mi{};
+      X = multiply_impl(ctx, 'N', 'N', 1.0, X0, I, 0.0, nullptr, 0.0, 0, &mi);
+    }
+  } catch (...) {
+    if (X != X0) free_mat(X);
+    free_mat(I);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    throw;
+  }
+  free_mat(I);
+  st.nnzb = X->nnzb;
+  if (ctx->timing) {
+    HIPCHECK(hipEventRecord(e1, ctx->stream));
+    HIPCHECK(hipEventSynchronize(e1));
+    HIPCHECK(hipEventElapsedTime(&st.ms_total, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  if (info) *info = st;
+  return X;
+}
+
 }  // namespace bsmm
 
 using namespace bsmm;
@@ -846,6 +974,19 @@ bsmm_status bsmm_multiply(bsmm_ctx ctx, char transa, char transb, double alpha, 
   bsmm_mat_s *r = multiply_impl(ctx, transa, transb, alpha, a, b, beta, c_old, filter_eps, retain_sparsity, info);
   ctx->live_mats++;
   *c_out = r;
+  ABI_END
+}
+
+bsmm_status bsmm_sign_newton_schulz(bsmm_ctx ctx, bsmm_mat x0, int32_t max_iter, double filter_eps, double tol,
+                                    bsmm_mat *x_out, bsmm_sign_info *info, double *trace_residual,
+                                    int64_t *trace_nnzb) {
+  ABI_BEGIN
+  if (!ctx || !x0 || !x_out) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  if (x0->ctx != ctx) fail(BSMM_ERR_INVALID_ARG, "matrix belongs to another context");
+  DeviceGuard g(ctx->device);
+  bsmm_mat_s *r = sign_impl(ctx, x0, max_iter, filter_eps, tol, info, trace_residual, trace_nnzb);
+  ctx->live_mats++;
+  *x_out = r;
   ABI_END
 }
 

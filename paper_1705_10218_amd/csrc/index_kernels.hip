@@ -270,6 +270,58 @@ void block_norms(const bsmm_mat_s &x, double *norms, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
+// ---------------------------------------------------- identity / residual
+namespace {
+
+// Values of the block-diagonal identity: block i (s_i x s_i) at off[i].
+__global__ void k_identity_values(const int32_t *sizes, const int64_t *off, int32_t n, double *v) {
+  const int32_t i = blockIdx.x;
+  if (i >= n) return;
+  const int sz = sizes[i];
+  for (int e = threadIdx.x; e < sz * sz; e += blockDim.x) v[off[i] + e] = (e % sz == e / sz) ? 1.0 : 0.0;
+}
+
+// Per block row i: sum over its stored blocks of ||X_ij - shift * delta_ij I||_F^2
+// (a block row with no diagonal block contributes shift^2 * s_i for it).
+__global__ __launch_bounds__(64) void k_shift_dist_rows(const int64_t *rp, const int32_t *ci, const int32_t *rbs,
+                                                       const int64_t *off, const double *v, double shift,
+                                                       double *row_out) {
+  const int32_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int sz = rbs[i];
+  double acc = 0.0;
+  bool has_diag = false;
+  for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+    const bool diag = ci[p] == i;
+    has_diag |= diag;
+    const int64_t o0 = off[p], o1 = off[p + 1];
+    for (int64_t e = o0 + lane; e < o1; e += 64) {
+      double x = v[e];
+      const int64_t t = e - o0;
+      if (diag && (t % sz) == (t / sz)) x -= shift;
+      acc = fma(x, x, acc);
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if (lane == 0) row_out[i] = acc + (has_diag ? 0.0 : shift * shift * (double)sz);
+}
+
+}  // namespace
+
+void identity_values(const int32_t *d_sizes, const int64_t *d_off, int32_t n, double *values, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_identity_values, dim3(n), dim3(256), 0, s, d_sizes, d_off, n, values);
+  HIPCHECK(hipGetLastError());
+}
+
+void shift_dist_rows(const bsmm_mat_s &x, double shift, double *row_out, hipStream_t s) {
+  if (x.nbr == 0) return;
+  hipLaunchKernelGGL(k_shift_dist_rows, dim3(x.nbr), dim3(64), 0, s, x.d_row_ptr, x.d_col_idx, x.d_rbs, x.d_blk_off,
+                     x.d_values, shift, row_out);
+  HIPCHECK(hipGetLastError());
+}
+
 int64_t count_kept(Allocator &al, const CompactArgs &c, int32_t *keep_tmp, int64_t *pinned, hipStream_t s,
                    DBuf<int64_t> &rank) {
   rank = DBuf<int64_t>(al, (size_t)c.nnzb + 1);

@@ -213,6 +213,11 @@ struct GemmArgs {
   const double *zeros = nullptr;     // >= 4 KB of zeros
 };
 
+// Block-diagonal identity values (block i of size sizes[i] at off[i]).
+void identity_values(const int32_t *d_sizes, const int64_t *d_off, int32_t n, double *values, hipStream_t s);
+// row_out[i] = sum over block row i of ||X_ij - shift * delta_ij I||_F^2 (square x).
+void shift_dist_rows(const bsmm_mat_s &x, double shift, double *row_out, hipStream_t s);
+
 // Packed operand copies (quad path): per stored block, nr rows of
 // Kp = K + (K & 1) values contiguous in k (pad zero).  k_is_row: the block's
 // row count is the contraction extent (op(A) = A^T or op(B) = B).

@@ -200,6 +200,50 @@ def config_big23(n_atoms: int = 20000, occupancy: float = 0.03, sizes=(23,)):
     return dft_like_pair(n_atoms, config=3, sizes=sizes, cutoff=rc, decay=2.0)
 
 
+def symmetric_dft_like(n_atoms: int, config: int = 4, sizes=(5, 13), cutoff: float = 7.0, decay: float = 2.0,
+                       gap: float = 10.0, request: int = 0) -> BlockCSR:
+    """Symmetric DFT-like start matrix for the sign iteration (Section 1,
+    eq. (3)): the DFT-like pattern, off-diagonal blocks N(0,1) exp(-r/decay)
+    with block (j,i) the transpose of block (i,j), diagonal blocks symmetric
+    N(0,1) plus +-gap on the diagonal (a random sign per orbital, so the
+    spectrum has eigenvalues on both sides of 0, away from it), the whole
+    matrix divided by its largest absolute row sum (a Gershgorin bound), so
+    every eigenvalue lies in (-1, 1).  Input preparation only."""
+    rng = rng_for(config, 0, request)
+    atoms = make_atoms(n_atoms, rng, sizes=sizes)
+    if cutoff >= atoms.box / 2:
+        raise ValueError("cutoff must stay below half the box edge for minimum-image distances")
+    r, c, d = neighbour_pairs(atoms, cutoff)
+    vrng = rng_for(config, 1, request)
+    sz = atoms.sizes
+    blocks = {}
+    for i, j, dist in zip(r.tolist(), c.tolist(), d.tolist()):
+        if i < j:
+            blocks[(i, j)] = vrng.standard_normal((sz[i], sz[j])) * math.exp(-dist / decay)
+        elif i == j:
+            g = vrng.standard_normal((sz[i], sz[i]))
+            g = 0.5 * (g + g.T)
+            g[np.diag_indices(sz[i])] += gap * vrng.choice([-1.0, 1.0], size=sz[i])
+            blocks[(i, i)] = g
+    for (i, j) in list(blocks):
+        if i < j:
+            blocks[(j, i)] = blocks[(i, j)].T
+    keys = sorted(blocks)
+    rows = np.array([k[0] for k in keys], dtype=np.int64)
+    cols = np.array([k[1] for k in keys], dtype=np.int64)
+    row_ptr = np.zeros(n_atoms + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n_atoms), out=row_ptr[1:])
+    rowsum = np.zeros(int(sz.sum()))
+    first = np.concatenate([[0], np.cumsum(sz)[:-1]])
+    for (i, j) in keys:
+        rowsum[first[i]:first[i] + sz[i]] += np.abs(blocks[(i, j)]).sum(axis=1)
+    scale = 1.0 / float(rowsum.max()) if rowsum.size else 1.0
+    vals = np.concatenate([(blocks[k] * scale).reshape(-1, order="F") for k in keys]) if keys else np.zeros(0)
+    m = BlockCSR(sz.copy(), sz.copy(), row_ptr, cols.astype(np.int32), vals)
+    m.meta = dict(workload="sign_start", atoms=n_atoms, sizes=list(sizes), cutoff=cutoff, gap=gap, scale=scale)
+    return m
+
+
 def identity(sizes) -> BlockCSR:
     sizes = np.asarray(sizes, dtype=np.int32)
     n = sizes.shape[0]
