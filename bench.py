@@ -29,6 +29,8 @@ sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+SIGN_ATOMS, SIGN_EPS, SIGN_TOL, SIGN_MAX_ITER = 1000, 1e-6, 1e-4, 20
+BATCH_ATOMS = 3500   # 23x23 blocks at 3 % occupancy: the packed operands just fit 32-bit offsets
 HBM_PEAK_GBS = 8000.0
 METRIC = "useful FP64 GFLOP/s of block-sparse C+=A·B, % MFMA peak; p99 serve latency"
 
@@ -168,7 +170,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="dft4000", choices=["dft4000", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
-    ap.add_argument("--fp64-only", action="store_true", help="skip the FP32 / split-FP32 measurements")
+    ap.add_argument("--fp64-only", action="store_true",
+                    help="only the headline FP64 workload (no precision, batching or sign-iteration legs)")
+    ap.add_argument("--no-tuning", action="store_true", help="default GEMM kernel variants instead of the tuned table")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run plain device copies of this size (HBM counter calibration)")
@@ -181,7 +185,7 @@ def main():
 
     import torch
 
-    from paper_1705_10218_amd import bsmm
+    from paper_1705_10218_amd import bsmm, inputs
     if not torch.cuda.is_available():
         raise SystemExit("no HIP device visible")
     if args.calibrate_copy_mib > 0:
@@ -191,6 +195,19 @@ def main():
     _log("generating workload")
     a, b, eps, cfg = workload(args.workload)
     ctx = bsmm.Context(0)
+    from paper_1705_10218_amd import autotune
+    def tune_for(sizes):
+        """Tuned GEMM variants of this block-size set, if the table has them."""
+        for m in (5, 13, 23, 32):
+            for n in (5, 13, 23, 32):
+                ctx.set_gemm_variant(m, n, 0)
+        if args.no_tuning or not os.path.exists(autotune.DEFAULT_TABLE):
+            return "default"
+        if autotune.apply(ctx, autotune.DEFAULT_TABLE, sizes) == 0:
+            return "default (no tuned table for these block sizes)"
+        return "autotuned per size class (" + os.path.relpath(autotune.DEFAULT_TABLE, ROOT) + ")"
+
+    cfg["gemm_variants"] = tune_for(cfg.get("block_sizes", [5]))
     A = bsmm.Matrix.from_host(ctx, a)
     Bm = bsmm.Matrix.from_host(ctx, b)
     torch.cuda.synchronize()
@@ -265,6 +282,48 @@ def main():
             lowp_hosts[name] = last_m.to_host()
             last_m.close()
         out["precision"] = prec
+    # batching workloads: 23x23 blocks at 3 % occupancy, and sizes {5, 13, 23}
+    if not args.fp64_only:
+        batching = {}
+        for name, sizes in (("blocks_23", (23,)), ("blocks_5_13_23", (5, 13, 23))):
+            ab, bb, atb = inputs.config_big23(BATCH_ATOMS, 0.03, sizes=sizes)
+            variants = tune_for(sizes)
+            Ab, Bb = bsmm.Matrix.from_host(ctx, ab), bsmm.Matrix.from_host(ctx, bb)
+            ms_b, inf_b, last_b = time_mode(bsmm, ctx, Ab, Bb, 1e-10, 3, 1)
+            last_b.close()
+            g_b = sum(i.ms_gemm for i in inf_b) / len(inf_b)
+            fl = inf_b[-1].useful_flops
+            batching[name] = {"atoms": BATCH_ATOMS, "occupancy": round(ab.nnzb / ab.nbr ** 2, 4),
+                              "c_nnzb": int(inf_b[-1].c_nnzb), "n_products": int(inf_b[-1].n_products),
+                              "useful_flops": fl, "ms_per_step": round(ms_b, 3), "gemm_ms": round(g_b, 3),
+                              "value": round(fl / (ms_b * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                              "gemm_tflops": round(fl / (g_b * 1e-3) / 1e12, 3),
+                              "gemm_frac_of_fp64_mfma_peak": round(fl / (g_b * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+                              "gemm_variants": variants}
+            _log(f"batching {name}: {ms_b:.3f} ms/step, GEMM {g_b:.3f} ms")
+            Ab.close()
+            Bb.close()
+        out["batching"] = batching
+    # second workload: Newton-Schulz sign iteration (two filtered multiplies
+    # per step, pattern evolving then stabilising)
+    if not args.fp64_only:
+        tune_for((5, 13))
+        x0 = inputs.symmetric_dft_like(SIGN_ATOMS, config=4, sizes=(5, 13), cutoff=7.0)
+        X0 = bsmm.Matrix.from_host(ctx, x0)
+        torch.cuda.synchronize()
+        Y, sinfo, sres, snnz = bsmm.sign_newton_schulz(ctx, X0, SIGN_MAX_ITER, SIGN_EPS, SIGN_TOL)
+        torch.cuda.synchronize()
+        out["sign_iteration"] = {
+            "workload": f"symmetric_dft_like_{SIGN_ATOMS}_atoms_blocks_5_13", "filter_eps": SIGN_EPS, "tol": SIGN_TOL,
+            "iterations": sinfo.iterations, "converged": bool(sinfo.converged), "residual": sinfo.residual,
+            "ms_total": round(sinfo.ms_total, 3), "ms_per_iteration": round(sinfo.ms_total / max(sinfo.iterations, 1), 3),
+            "value": round(sinfo.useful_flops / (sinfo.ms_total * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+            "x0_nnzb": int(x0.nnzb), "nnzb_trace": [int(v) for v in snnz],
+            "residual_trace": [float(f"{v:.4g}") for v in sres],
+        }
+        _log(f"sign iteration: {sinfo.iterations} steps, {sinfo.ms_total:.1f} ms")
+        Y.close()
+        X0.close()
     if not args.no_cpu_baseline:
         threads = min(len(os.sched_getaffinity(0)), 16)
         _log(f"cpu baseline on {threads} threads")

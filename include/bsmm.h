@@ -58,8 +58,9 @@ typedef enum {
 
 /* Arithmetic used by the block products (the norms, the filter thresholds
  * and the stored values are FP64 in every mode).  FP32 and SPLIT need packed
- * operand copies below 1 GB and at most 8 distinct k block sizes; otherwise
- * bsmm_multiply returns BSMM_ERR_UNSUPPORTED. */
+ * operand copies below 2 GB (about half the FP64 values of A and of B) and
+ * at most 8 distinct k block sizes; otherwise bsmm_multiply returns
+ * BSMM_ERR_UNSUPPORTED. */
 typedef enum {
   BSMM_COMPUTE_FP64 = 0,      /* FP64 MFMA, FP64 accumulation                  */
   BSMM_COMPUTE_FP32 = 1,      /* operands rounded to FP32, FP32 MFMA products,
@@ -95,6 +96,17 @@ bsmm_status bsmm_ctx_set_stream(bsmm_ctx ctx, void *stream);
 /* Enable per-phase device timing in bsmm_multiply_info (adds event records). */
 bsmm_status bsmm_ctx_set_timing(bsmm_ctx ctx, int enable);
 bsmm_status bsmm_ctx_set_compute_mode(bsmm_ctx ctx, bsmm_compute_mode mode);
+/* Kernel variant of the FP64 block GEMM for result blocks whose edges fall
+ * in the size classes of m and n (classes: edges 1-8, 9-16, 17-24, 25-32):
+ *   0 = default (one 16x16x4 MFMA tile when both edges are in 9..16, 4x4x4
+ *       MFMA subtiles otherwise), 1 = 16x16x4 MFMA tiles, 2 = 4x4x4 MFMA
+ *       subtiles.
+ * All variants give results within FP64 rounding of each other; the choice
+ * only changes speed (an autotuner picks it per size class).  Applies to the
+ * packed-operand path (packed copies of op(A) and op(B) below 2 GB each, at
+ * most 8 distinct k sizes).
+ * Errors: BSMM_ERR_INVALID_ARG for edges outside 1..32 or another variant. */
+bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_t variant);
 /* Bytes of device memory the library currently holds for this context
  * (live buffers plus its cache of freed ones). */
 bsmm_status bsmm_ctx_memory(bsmm_ctx ctx, size_t *held_bytes, size_t *peak_bytes);

@@ -1,0 +1,145 @@
+"""Autotuner for the block GEMM's kernel variant per (m, n) size class.
+
+The FP64 block GEMM has two ways to cover a result block on the matrix
+cores: 16x16x4 MFMA tiles (few loads per k-step, padding to 16) or 4x4x4
+MFMA subtiles (padding to 4, more loads).  Which is faster depends on the
+block edges, so it is chosen per size class (edges 1-8, 9-16, 17-24, 25-32)
+by timing: for every (m, n) pair of a block-size set, a synthetic DFT-like
+workload whose result blocks all have that shape (contraction sizes drawn
+from the same set) is multiplied with each variant, and the fastest GEMM
+time wins.  The best variant depends on the contraction-size mix as well,
+so the JSON file holds one table per block-size set and :func:`apply` picks
+the table of the workload's set.
+
+Usage::
+
+    python -m paper_1705_10218_amd.autotune --size-sets 5,13 23 5,13,23 --out tuning.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+
+import numpy as np
+
+VARIANTS = {1: "mfma16x16x4_tiles", 2: "mfma4x4x4_subtiles"}
+DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.json")
+
+
+def size_class(edge: int) -> int:
+    """0: 1-8, 1: 9-16, 2: 17-24, 3: 25-32."""
+    if not 1 <= edge <= 32:
+        raise ValueError("block edge outside 1..32")
+    return (edge + 7) // 8 - 1
+
+
+def class_workload(m: int, n: int, ks, atoms: int = 1500, cutoff: float = 7.0, seed: int = 0):
+    """A (rows of size m) and B (columns of size n) on a DFT-like pattern;
+    contraction sizes drawn from ks.  Every result block is m x n."""
+    from . import inputs
+    rng = inputs.rng_for(70, 0, seed)
+    at = inputs.make_atoms(atoms, rng, sizes=tuple(ks))
+    r, c, d = inputs.neighbour_pairs(at, cutoff)
+    scale = np.exp(-d / 2.0)
+    ms = np.full(atoms, m, dtype=np.int32)
+    ns = np.full(atoms, n, dtype=np.int32)
+    a = inputs.from_pattern(ms, at.sizes, r, c, inputs.rng_for(70, 1, seed), scale=scale)
+    b = inputs.from_pattern(at.sizes, ns, r, c, inputs.rng_for(70, 2, seed), scale=scale)
+    return a, b
+
+
+def time_gemm(bsmm, ctx, A, B, reps: int = 3) -> float:
+    """Median GEMM time (ms) over reps multiplies after one warm-up."""
+    C, _ = bsmm.multiply(ctx, "N", "N", 1.0, A, B)
+    C.close()
+    ts = []
+    for _ in range(reps):
+        C, info = bsmm.multiply(ctx, "N", "N", 1.0, A, B)
+        ts.append(info.ms_gemm)
+        C.close()
+    return statistics.median(ts)
+
+
+def tune(sizes=(5, 13, 23), atoms: int = 1500, reps: int = 3, log=None) -> dict:
+    """Time every variant for every (m, n) in sizes x sizes; returns the table."""
+    import torch
+
+    from . import bsmm
+    ctx = bsmm.Context(0)
+    ctx.set_timing(True)
+    entries = {}
+    for m in sizes:
+        for n in sizes:
+            key = (size_class(m), size_class(n))
+            a, b = class_workload(m, n, sizes, atoms=atoms)
+            A = bsmm.Matrix.from_host(ctx, a)
+            B = bsmm.Matrix.from_host(ctx, b)
+            times = {}
+            for v in VARIANTS:
+                ctx.set_gemm_variant(m, n, v)
+                times[v] = time_gemm(bsmm, ctx, A, B, reps)
+            ctx.set_gemm_variant(m, n, 0)
+            best = min(times, key=times.get)
+            entries[key] = {"m_class": key[0], "n_class": key[1], "m": m, "n": n, "variant": best,
+                            "variant_name": VARIANTS[best], "gemm_ms": {VARIANTS[v]: round(t, 4) for v, t in times.items()}}
+            if log:
+                log(f"m={m} n={n}: " + ", ".join(f"{VARIANTS[v]} {t:.3f} ms" for v, t in times.items())
+                    + f" -> {VARIANTS[best]}")
+            A.close()
+            B.close()
+            torch.cuda.synchronize()
+    ctx.close()
+    return {"device": torch.cuda.get_device_name(0), "sizes": sorted(set(sizes)),
+            "workload": f"dft-like {atoms} atoms, block sizes {list(sizes)}",
+            "classes": sorted(entries.values(), key=lambda e: (e["m_class"], e["n_class"]))}
+
+
+def pick(doc: dict, sizes) -> dict | None:
+    """The table of doc tuned on exactly this block-size set, if any."""
+    want = sorted(set(int(x) for x in sizes))
+    for t in doc.get("tables", []):
+        if sorted(t["sizes"]) == want:
+            return t
+    return None
+
+
+def apply(ctx, table, sizes=None) -> int:
+    """Set the tuned variant of every class on ctx.  table: a table dict, or a
+    JSON document (dict or path) holding several; with a document, the table
+    of `sizes` is used (none applied if there is no such table)."""
+    if isinstance(table, (str, os.PathLike)):
+        with open(table) as f:
+            table = json.load(f)
+    if "tables" in table:
+        table = pick(table, sizes or ())
+        if table is None:
+            return 0
+    for e in table["classes"]:
+        edge = lambda cls: 8 * cls + 1   # noqa: E731 - any edge of the class
+        ctx.set_gemm_variant(edge(e["m_class"]), edge(e["n_class"]), int(e["variant"]))
+    return len(table["classes"])
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--size-sets", nargs="+", default=["5,13", "23", "5,13,23"])
+    ap.add_argument("--atoms", type=int, default=1500)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    args = ap.parse_args(argv)
+    doc = {"tables": []}
+    for spec in args.size_sets:
+        sizes = tuple(int(x) for x in spec.split(","))
+        print(f"block sizes {sizes}", flush=True)
+        doc["tables"].append(tune(sizes, args.atoms, args.reps, log=lambda s: print("  " + s, flush=True)))
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -29,7 +29,8 @@ COMPUTE_FP64, COMPUTE_FP32, COMPUTE_SPLIT = 0, 1, 2
 # every symbol include/bsmm.h declares
 SYMBOLS = (
     "bsmm_status_string", "bsmm_last_error", "bsmm_ctx_create", "bsmm_ctx_set_stream",
-    "bsmm_ctx_set_timing", "bsmm_ctx_set_compute_mode", "bsmm_ctx_memory", "bsmm_ctx_trim",
+    "bsmm_ctx_set_timing", "bsmm_ctx_set_compute_mode", "bsmm_ctx_set_gemm_variant", "bsmm_ctx_memory",
+    "bsmm_ctx_trim",
     "bsmm_ctx_synchronize", "bsmm_ctx_destroy", "bsmm_mat_create", "bsmm_mat_info",
     "bsmm_mat_get_index", "bsmm_mat_get_block_sizes", "bsmm_mat_values", "bsmm_mat_copy_values",
     "bsmm_mat_destroy", "bsmm_block_norms", "bsmm_multiply", "bsmm_filter", "bsmm_sign_newton_schulz",
@@ -90,6 +91,7 @@ def lib() -> ctypes.CDLL:
         L.bsmm_ctx_set_stream.argtypes = [_vp, _vp]
         L.bsmm_ctx_set_timing.argtypes = [_vp, ctypes.c_int]
         L.bsmm_ctx_set_compute_mode.argtypes = [_vp, ctypes.c_int]
+        L.bsmm_ctx_set_gemm_variant.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.bsmm_ctx_memory.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
         L.bsmm_ctx_trim.argtypes = [_vp]
         L.bsmm_ctx_synchronize.argtypes = [_vp]
@@ -150,6 +152,9 @@ class Context:
 
     def set_compute_mode(self, mode: int):
         _check(lib().bsmm_ctx_set_compute_mode(self.handle, mode))
+
+    def set_gemm_variant(self, m: int, n: int, variant: int):
+        _check(lib().bsmm_ctx_set_gemm_variant(self.handle, int(m), int(n), int(variant)))
 
     def memory(self):
         held, peak = ctypes.c_size_t(), ctypes.c_size_t()

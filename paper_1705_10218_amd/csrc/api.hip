@@ -318,10 +318,16 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   ksizes.erase(std::unique(ksizes.begin(), ksizes.end()), ksizes.end());
   const uint64_t two_gb = 1ull << 31;
   // quad path of the GEMM: packed operand copies below 2 GB (32-bit byte
-  // offsets in the stack entries; a packed block holds at most twice the
-  // values of the stored one), at most 8 distinct k sizes
-  const bool quads = (uint64_t)A->n_values * 16 < two_gb && (uint64_t)B->n_values * 16 < two_gb &&
-                     !ksizes.empty() && ksizes.size() <= 8;
+  // offsets in the stack entries), at most 8 distinct k sizes.  A packed
+  // block pads its contraction extent k to a multiple of 2 (FP64) or 4
+  // (FP32 / split, half the bytes), so it holds at most (k + 1) / k or
+  // (k + 3) / k times the values of the stored block; kmin bounds both.
+  const bool lowp_mode = ctx->mode != BSMM_COMPUTE_FP64;
+  const double kmin = ksizes.empty() ? 1.0 : (double)ksizes.front();
+  const double grow = lowp_mode ? 0.5 * (kmin + 3.0) / kmin : (kmin + 1.0) / kmin;
+  const bool quads = !ksizes.empty() && ksizes.size() <= 8 &&
+                     (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
+                     (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
   DBuf<int32_t> cnt_g;
   if (quads && (int64_t)max_row * (int64_t)ksizes.size() > 8192) {
     cnt_g = DBuf<int32_t>(al, nc1 * ksizes.size());
@@ -355,9 +361,9 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   exclusive_scan_i64(al, row_real.p, real_scan.p, nbr, s);
   // packed operand offsets for the quad path (op(A) row-major, op(B) column-major)
   DBuf<int64_t> a_poff, b_poff;
-  const bool lowp = ctx->mode != BSMM_COMPUTE_FP64;
+  const bool lowp = lowp_mode;
   if (lowp && !quads && nnzb_c > 0)
-    fail(BSMM_ERR_UNSUPPORTED, "FP32 / split modes need operands below 1 GB and at most 8 distinct k block sizes");
+    fail(BSMM_ERR_UNSUPPORTED, "FP32 / split modes need packed operands below 2 GB and at most 8 distinct k block sizes");
   if (quads) {
     a_poff = DBuf<int64_t>(al, (size_t)A->nnzb + 1);
     b_poff = DBuf<int64_t>(al, (size_t)B->nnzb + 1);
@@ -505,6 +511,7 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     }
     ga.zeros = ctx->zeros;
     ga.quads = quads;
+    for (int t = 0; t < 16; t++) ga.variant[t] = ctx->gemm_variant[t];
     int max_edge = 1;
     for (int32_t v : opa_r) max_edge = std::max(max_edge, v);
     for (int32_t v : opb_c) max_edge = std::max(max_edge, v);
@@ -792,6 +799,15 @@ bsmm_status bsmm_ctx_set_compute_mode(bsmm_ctx ctx, bsmm_compute_mode mode) {
   if (mode != BSMM_COMPUTE_FP64 && mode != BSMM_COMPUTE_FP32 && mode != BSMM_COMPUTE_SPLIT)
     fail(BSMM_ERR_INVALID_ARG, "unknown compute mode");
   ctx->mode = mode;
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_t variant) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  if (m < 1 || m > MAX_BLOCK || n < 1 || n > MAX_BLOCK) fail(BSMM_ERR_INVALID_ARG, "block edge outside 1..32");
+  if (variant < 0 || variant > 2) fail(BSMM_ERR_INVALID_ARG, "variant must be 0, 1 or 2");
+  ctx->gemm_variant[((m + 7) / 8 - 1) * 4 + ((n + 7) / 8 - 1)] = (uint8_t)variant;
   ABI_END
 }
 

@@ -55,6 +55,7 @@ struct GemmP {
   double alpha, beta;
   uint32_t a_bytes, b_bytes;   // buffer extents (BUF path)
   const double *zeros;         // zero page (pointer path)
+  uint8_t variant[16];         // kernel variant per (m, n) size class (BUF path)
 };
 
 constexpr int ROUND = 256;   // products whose parameters sit in LDS at once
@@ -384,7 +385,6 @@ __device__ __forceinline__ void gemm_block_44(const GemmP &P, int32_t c, ParamLd
 // The pad's zero times zero adds an exact 0 when K is odd.  Arrays below
 // 2 GB (32-bit offsets with an out-of-range mark that no k offset can wrap).
 constexpr uint32_t QOOB = 0x80000000u;
-constexpr int PF2 = 3;   // pairs of k-steps in flight
 
 struct QuadLds {
   uint32_t oa[ROUND];   // byte offsets of packed op(A) / op(B) blocks (QOOB = null)
@@ -413,12 +413,17 @@ __device__ __forceinline__ d2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff,
   return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, soff, 0));
 }
 
+// SIXTEEN: V_MFMA_F64_16X16X4F64 on MT x NT tiles of 16 (MT, NT in {1, 2});
+// otherwise V_MFMA_F64_4X4X4F64 on MT x NT subtiles of 4 (even counts).
 template <bool SIXTEEN, int MT, int NT>
 __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadLds &ql) {
-  constexpr int HM = SIXTEEN ? 1 : MT / 2, HN = SIXTEEN ? 1 : NT / 2;
+  constexpr int HM = SIXTEEN ? MT : MT / 2, HN = SIXTEEN ? NT : NT / 2;
   // two accumulator sets (the two k-steps of a pair) when a step has a single
   // MFMA chain: a dependent FP64 MFMA waits for the previous result
-  constexpr int NC = (SIXTEEN || HM * HN == 1) ? 2 : 1;
+  constexpr int NC = (HM * HN == 1) ? 2 : 1;
+  // pairs in flight: shallower for shapes with many loads per pair, whose
+  // ring registers would otherwise cut the wavefronts per SIMD
+  constexpr int PF2 = (HM + HN > 3) ? 2 : 3;
   const int lane = threadIdx.x & 63;
   // one C block per wavefront: its sizes are uniform (scalar registers)
   const int m = __builtin_amdgcn_readfirstlane(P.rbs[P.c_row[c]]);
@@ -428,8 +433,10 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
   // lane's rows of op(A) / columns of op(B) (-1 if padding)
   int ra[HM], cb[HN];
   if (SIXTEEN) {
-    ra[0] = (lane & 15) < m ? (lane & 15) : -1;
-    cb[0] = (lane & 15) < n ? (lane & 15) : -1;
+#pragma unroll
+    for (int u = 0; u < HM; u++) ra[u] = (lane & 15) + 16 * u < m ? (lane & 15) + 16 * u : -1;
+#pragma unroll
+    for (int v = 0; v < HN; v++) cb[v] = (lane & 15) + 16 * v < n ? (lane & 15) + 16 * v : -1;
   } else {
     const int L4 = lane & 3, bq = (lane >> 2) & 3;
     const int Pq = bq >> 1, Qq = bq & 1;
@@ -447,10 +454,11 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
   const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
   double acc[NC][SIXTEEN ? 1 : HM * HN];
-  d4 acc16[NC];
+  d4 acc16[NC][SIXTEEN ? HM * HN : 1];
 #pragma unroll
   for (int h = 0; h < NC; h++) {
-    acc16[h] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < (SIXTEEN ? HM * HN : 1); t++) acc16[h][t] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[h][t] = 0.0;
   }
@@ -522,7 +530,12 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
       for (int e = 0; e < 2; e++) {
         const int h = e % NC;
         if (SIXTEEN) {
-          acc16[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[0][e], xb[0][e], acc16[h], 0, 0, 0);
+#pragma unroll
+          for (int u = 0; u < HM; u++)
+#pragma unroll
+            for (int v = 0; v < HN; v++)
+              acc16[h][u * HN + v] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][e], xb[v][e], acc16[h][u * HN + v], 0, 0, 0);
         } else {
 #pragma unroll
           for (int u = 0; u < HM; u++)
@@ -566,7 +579,8 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
 
   // fold the accumulator sets in a fixed order
   if constexpr (NC == 2) {
-    acc16[0] += acc16[NC - 1];
+#pragma unroll
+    for (int t = 0; t < (SIXTEEN ? HM * HN : 1); t++) acc16[0][t] += acc16[NC - 1][t];
 #pragma unroll
     for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[0][t] += acc[NC - 1][t];
   }
@@ -574,12 +588,15 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
   const double *old = old_block(P, c);
   double ss = 0.0;
   if (SIXTEEN) {
-    const int col = lane & 15;
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      const int row = 4 * r + kq;
-      if (row < m && col < n) store_c(P, old, co, m, row, col, acc16[0][r], ss);
-    }
+    for (int u = 0; u < HM; u++)
+#pragma unroll
+      for (int v = 0; v < HN; v++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int row = 16 * u + 4 * r + kq, col = 16 * v + (lane & 15);
+          if (row < m && col < n) store_c(P, old, co, m, row, col, acc16[0][u * HN + v][r], ss);
+        }
   } else {
     const int L4 = lane & 3, bq = (lane >> 2) & 3;
     const int Pq = bq >> 1, Qq = bq & 1;
@@ -618,11 +635,27 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t
   const int nt = edge_tiles(P.cbs[P.c_ci[c]]);
   const int key = mt * 16 + nt;
   if constexpr (BUF) {
+    // kernel variant of this (m, n) class: 0 = default (16x16 tile when both
+    // edges are in 9..16, else 4x4 subtiles), 1 = 16x16 tiles, 2 = 4x4 subtiles
+    const int vid = P.variant[(mt / 2 - 1) * 4 + (nt / 2 - 1)];
+    if (vid == 1 || (vid == 0 && mt == 4 && nt == 4)) {
+      const int tm = mt <= 4 ? 1 : 2, tn = nt <= 4 ? 1 : 2;
+      if (tm == 1 && tn == 1) {
+        gemm_block_quad<true, 1, 1>(P, c, ql);
+        return;
+      }
+      if constexpr (MAXT > 4) {
+        if (tm == 1) gemm_block_quad<true, 1, 2>(P, c, ql);
+        else if (tn == 1) gemm_block_quad<true, 2, 1>(P, c, ql);
+        else gemm_block_quad<true, 2, 2>(P, c, ql);
+      }
+      return;
+    }
     switch (key) {
       case 2 * 16 + 2: gemm_block_quad<false, 2, 2>(P, c, ql); return;
       case 2 * 16 + 4: gemm_block_quad<false, 2, 4>(P, c, ql); return;
       case 4 * 16 + 2: gemm_block_quad<false, 4, 2>(P, c, ql); return;
-      case 4 * 16 + 4: gemm_block_quad<true, 4, 4>(P, c, ql); return;
+      case 4 * 16 + 4: gemm_block_quad<false, 4, 4>(P, c, ql); return;
       default: break;
     }
     if constexpr (MAXT > 4) {
@@ -885,6 +918,7 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
   p.a_bytes = buf ? (uint32_t)g.a_bytes : 0u;
   p.b_bytes = buf ? (uint32_t)g.b_bytes : 0u;
   p.zeros = g.zeros;
+  for (int t = 0; t < 16; t++) p.variant[t] = g.variant[t];
   if (max_edge <= 16 && buf)
     hipLaunchKernelGGL((k_gemm_f64<4, true>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
   else if (max_edge <= 16)

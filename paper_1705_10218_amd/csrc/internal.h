@@ -52,6 +52,7 @@ struct bsmm_ctx_s {
   bsmm_compute_mode mode = BSMM_COMPUTE_FP64;
   bsmm::Allocator alloc;
   int64_t *pinned = nullptr;   // small host buffer for size read-backs
+  uint8_t gemm_variant[16] = {};   // GEMM kernel variant per (m, n) size class
   double *zeros = nullptr;     // 4 KB zero page on the device
   int live_mats = 0;
 };
@@ -210,6 +211,7 @@ struct GemmArgs {
   const float *b_hi = nullptr, *b_lo = nullptr;
   uint64_t a_bytes = 0, b_bytes = 0; // sizes of the two value arrays the kernel reads
   bool quads = false;                // stacks padded to k-homogeneous quads (quad path)
+  uint8_t variant[16] = {};          // GEMM kernel variant per (m, n) size class
   const double *zeros = nullptr;     // >= 4 KB of zeros
 };
 

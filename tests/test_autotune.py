@@ -1,0 +1,68 @@
+"""Autotuner table handling (CPU) and GEMM kernel variants vs the oracle (GPU)."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_10218_amd import autotune, inputs
+from _util import rel_fro
+
+
+def test_size_classes():
+    assert [autotune.size_class(e) for e in (1, 8, 9, 16, 17, 24, 25, 32)] == [0, 0, 1, 1, 2, 2, 3, 3]
+    with pytest.raises(ValueError):
+        autotune.size_class(33)
+
+
+def test_apply_sets_every_class(tmp_path):
+    calls = []
+
+    class FakeCtx:
+        def set_gemm_variant(self, m, n, v):
+            calls.append((autotune.size_class(m), autotune.size_class(n), v))
+
+    t1 = {"sizes": [5, 23], "classes": [{"m_class": 0, "n_class": 2, "variant": 1},
+                                        {"m_class": 2, "n_class": 2, "variant": 2}]}
+    t2 = {"sizes": [13], "classes": [{"m_class": 1, "n_class": 1, "variant": 2}]}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps({"tables": [t2, t1]}))
+    assert autotune.apply(FakeCtx(), str(p), sizes=(23, 5)) == 2
+    assert calls == [(0, 2, 1), (2, 2, 2)]
+    assert autotune.apply(FakeCtx(), str(p), sizes=(5, 13)) == 0   # no table for that set
+    assert autotune.apply(FakeCtx(), t2) == 1 and calls[-1] == (1, 1, 2)
+
+
+def test_class_workload_shapes():
+    a, b = autotune.class_workload(13, 23, (5, 13), atoms=200, cutoff=5.0)
+    assert set(a.rbs.tolist()) == {13} and set(b.cbs.tolist()) == {23}
+    assert np.array_equal(a.cbs, b.rbs)
+
+
+@pytest.mark.gpu
+def test_variants_agree_with_oracle():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1705_10218_amd import bsmm
+    a, b, _ = inputs.dft_like_pair(400, config=92, sizes=(5, 13, 23), cutoff=6.0)
+    ref = oracle.multiply("N", "N", 1.0, a, b, nthreads=8)
+    ctx = bsmm.Context(0)
+    A = bsmm.Matrix.from_host(ctx, a)
+    B = bsmm.Matrix.from_host(ctx, b)
+    results = {}
+    for v in (0, 1, 2):
+        for m in (5, 13, 23, 32):
+            for n in (5, 13, 23, 32):
+                ctx.set_gemm_variant(m, n, v)
+        C, info = bsmm.multiply(ctx, "N", "N", 1.0, A, B)
+        h = C.to_host()
+        C.close()
+        assert np.array_equal(h.col_idx, ref.col_idx) and np.array_equal(h.row_ptr, ref.row_ptr)
+        err = rel_fro(h.values, ref.values)
+        print(f"variant {v}: rel err {err:.2e}, gemm {info.ms_gemm:.3f} ms", flush=True)
+        assert err <= 1e-12
+        results[v] = h.values
+    A.close()
+    B.close()
+    ctx.close()
