@@ -44,6 +44,7 @@ extern "C" {
 
 typedef struct bsmm_ctx_s *bsmm_ctx;
 typedef struct bsmm_mat_s *bsmm_mat;
+typedef struct bsmm_plan_s *bsmm_plan;
 
 typedef enum {
   BSMM_OK = 0,
@@ -169,6 +170,37 @@ bsmm_status bsmm_multiply(bsmm_ctx ctx, char transa, char transb, double alpha,
 /* New matrix holding the blocks of m whose Frobenius norm is >= eps
  * (the post-multiply filter of Section 1 applied on its own). */
 bsmm_status bsmm_filter(bsmm_mat m, double eps, bsmm_mat *out);
+
+/* ------------------------------------------------------------- plans
+ * A plan splits one multiplication (same arguments as bsmm_multiply) into
+ *   - bsmm_plan_create: the structural part, run once -- validation, index
+ *     views, block norms, symbolic phase, stacks with the on-the-fly filter
+ *     decisions taken on the values A and B have now, and every buffer of
+ *     the numeric part (synchronises the stream);
+ *   - bsmm_plan_execute: the numeric part -- packed operand copies and the
+ *     block GEMM -- on the context's stream, asynchronous, reading the
+ *     *current* values of A, B and C_old (the matrices must stay alive and
+ *     keep their patterns; their value buffers may be rewritten between
+ *     executions).  It launches kernels only: no host synchronisation,
+ *     allocation or memset;
+ *   - bsmm_plan_capture: records the numeric part once in a HIP graph on the
+ *     context's stream (which must not be the default stream); from then on
+ *     bsmm_plan_execute replays the graph;
+ *   - bsmm_plan_result: the post filter (if filter_eps > 0 and not
+ *     retain_sparsity) and a new matrix holding the last execution's result
+ *     (synchronises the stream).
+ * This is the repeated-multiplication case of the iterative methods of
+ * Section 1 (a fixed pattern whose values change).  info (may be NULL)
+ * receives the sizes, counts and the structural phase times. */
+bsmm_status bsmm_plan_create(bsmm_ctx ctx, char transa, char transb, double alpha, bsmm_mat a, bsmm_mat b,
+                             double beta, bsmm_mat c_old, double filter_eps, int retain_sparsity, bsmm_plan *out,
+                             bsmm_multiply_info *info);
+bsmm_status bsmm_plan_execute(bsmm_plan plan);
+bsmm_status bsmm_plan_capture(bsmm_plan plan);
+bsmm_status bsmm_plan_result(bsmm_plan plan, bsmm_mat *c_out);
+/* Waits for the plan's stream, then frees it (a plan counts as a live object
+ * of its context until destroyed). */
+bsmm_status bsmm_plan_destroy(bsmm_plan plan);
 
 /* Statistics of a sign iteration. */
 typedef struct {

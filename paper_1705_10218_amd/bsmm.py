@@ -34,6 +34,7 @@ SYMBOLS = (
     "bsmm_ctx_synchronize", "bsmm_ctx_destroy", "bsmm_mat_create", "bsmm_mat_info",
     "bsmm_mat_get_index", "bsmm_mat_get_block_sizes", "bsmm_mat_values", "bsmm_mat_copy_values",
     "bsmm_mat_destroy", "bsmm_block_norms", "bsmm_multiply", "bsmm_filter", "bsmm_sign_newton_schulz",
+    "bsmm_plan_create", "bsmm_plan_execute", "bsmm_plan_capture", "bsmm_plan_result", "bsmm_plan_destroy",
 )
 
 
@@ -109,6 +110,13 @@ def lib() -> ctypes.CDLL:
                                     _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_vp),
                                     ctypes.POINTER(MultiplyInfo)]
         L.bsmm_filter.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_vp)]
+        L.bsmm_plan_create.argtypes = [_vp, ctypes.c_char, ctypes.c_char, ctypes.c_double, _vp, _vp,
+                                       ctypes.c_double, _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_vp),
+                                       ctypes.POINTER(MultiplyInfo)]
+        L.bsmm_plan_execute.argtypes = [_vp]
+        L.bsmm_plan_capture.argtypes = [_vp]
+        L.bsmm_plan_result.argtypes = [_vp, ctypes.POINTER(_vp)]
+        L.bsmm_plan_destroy.argtypes = [_vp]
         L.bsmm_sign_newton_schulz.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                               ctypes.POINTER(_vp), ctypes.POINTER(SignInfo),
                                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -301,6 +309,45 @@ def filter(m: Matrix, eps: float) -> Matrix:  # noqa: A001 - mirrors bsmm_filter
     out = _vp()
     _check(lib().bsmm_filter(m.handle, float(eps), ctypes.byref(out)))
     return Matrix(m.ctx, out)
+
+
+class Plan:
+    """bsmm_plan_*: a multiplication whose structure is fixed once; execute()
+    reruns its numeric part on the current values of A, B and C_old (which
+    must stay alive), capture() records that part in a HIP graph."""
+
+    def __init__(self, ctx: Context, transa: str, transb: str, alpha: float, a: Matrix, b: Matrix,
+                 beta: float = 0.0, c: Matrix | None = None, filter_eps: float = 0.0, retain_sparsity: bool = False):
+        self.ctx = ctx
+        self.handle = _vp()
+        self.info = MultiplyInfo()
+        self._keep = (a, b, c)
+        _check(lib().bsmm_plan_create(ctx.handle, transa.encode(), transb.encode(), float(alpha), a.handle,
+                                      b.handle, float(beta), c.handle if c is not None else None,
+                                      float(filter_eps), 1 if retain_sparsity else 0, ctypes.byref(self.handle),
+                                      ctypes.byref(self.info)))
+
+    def execute(self):
+        _check(lib().bsmm_plan_execute(self.handle))
+
+    def capture(self):
+        _check(lib().bsmm_plan_capture(self.handle))
+
+    def result(self) -> Matrix:
+        out = _vp()
+        _check(lib().bsmm_plan_result(self.handle, ctypes.byref(out)))
+        return Matrix(self.ctx, out)
+
+    def close(self):
+        if self.handle:
+            _check(lib().bsmm_plan_destroy(self.handle))
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sign_newton_schulz(ctx: Context, x0: Matrix, max_iter: int, filter_eps: float = 0.0, tol: float = 0.0):

@@ -220,13 +220,50 @@ struct Timer {
   }
 };
 
-static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double alpha, bsmm_mat_s *A,
-                                 bsmm_mat_s *B, double beta, bsmm_mat_s *C0, double eps, int retain,
-                                 bsmm_multiply_info *info) {
+// One multiplication, split into its structural part (validation, index
+// views, norms, symbolic phase, stacks, work list, every buffer of the
+// numeric part), its numeric part (packed operand copies and the block GEMM:
+// kernels only -- no host synchronisation, allocation or memset, so it can
+// be captured in a HIP graph and replayed while the values of A, B and C_old
+// change) and the post-filter that sizes and assembles the result.  The
+// filter decisions of the stacks are taken on the values A and B have when
+// the plan is built.
+struct Plan {
+  bsmm_ctx ctx = nullptr;
+  bsmm_mat_s *A = nullptr, *B = nullptr, *C0 = nullptr;
+  bool ta = false, tb = false, filt = false, post = false, quads = false, lowp = false;
+  double alpha = 1.0, beta = 0.0, eps = 0.0;
+  int retain = 0;
+  bsmm_compute_mode mode = BSMM_COMPUTE_FP64;
+  int32_t nbr = 0, nbc = 0, max_edge = 1;
+  std::vector<int32_t> opa_r, opb_c;
+  int64_t nnzb_c = 0, nval_c = 0, nstack = 0, nprod = 0, kmn_total = 0, ncand = 0;
+  int64_t a_pack_n = 0, b_pack_n = 0;
+  OpIndex oa, ob;
+  DBuf<int64_t> c_rp, c_off, seg_off, a_poff, b_poff;
+  DBuf<int32_t> c_ci, c_row, old_blk, c_list;
+  DBuf<int2> stack;
+  DBuf<double> a_pack, b_pack, a_lo, b_lo, a_t, b_t, c_norm, c_values;
+  GemmArgs ga;
+  Timer tm;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  explicit Plan(bsmm_ctx c) : ctx(c), tm(c) {}
+  ~Plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+static void plan_build(Plan &P, char transa, char transb) {
+  bsmm_ctx ctx = P.ctx;
   hipStream_t s = ctx->stream;
   Allocator &al = ctx->alloc;
-  const bool ta = (transa == 'T' || transa == 't');
-  const bool tb = (transb == 'T' || transb == 't');
+  bsmm_mat_s *A = P.A, *B = P.B, *C0 = P.C0;
+  const double beta = P.beta, eps = P.eps;
+  const int retain = P.retain;
+  const bool ta = P.ta = (transa == 'T' || transa == 't');
+  const bool tb = P.tb = (transb == 'T' || transb == 't');
   // ---------------------------------------------------------- validation
   const std::vector<int32_t> &opa_r = ta ? A->h_cbs : A->h_rbs;
   const std::vector<int32_t> &opa_c = ta ? A->h_rbs : A->h_cbs;
@@ -246,18 +283,21 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
       fail(BSMM_ERR_ALIAS, "c_old values alias an operand");
   }
   if (!(eps >= 0.0)) fail(BSMM_ERR_INVALID_ARG, "filter_eps must be >= 0");
-  const int32_t nbr = (int32_t)opa_r.size(), nbc = (int32_t)opb_c.size();
+  const int32_t nbr = P.nbr = (int32_t)opa_r.size(), nbc = P.nbc = (int32_t)opb_c.size();
+  P.opa_r = opa_r;
+  P.opb_c = opb_c;
+  P.mode = ctx->mode;
 
-  Timer tm(ctx);
+  Timer &tm = P.tm;
   tm.mark();  // 0
   // ------------------------------------------------------- a0: op index
-  OpIndex oa, ob;
+  OpIndex &oa = P.oa, &ob = P.ob;
   make_op(ctx, A, ta, oa);
   make_op(ctx, B, tb, ob);
   tm.mark();  // 1
   // ------------------------------------------------------- a1: norms
   DBuf<double> na, nb;
-  const bool filt = eps > 0.0;
+  const bool filt = P.filt = eps > 0.0;
   if (filt) {
     na = DBuf<double>(al, std::max<int64_t>(A->nnzb, 1));
     nb = DBuf<double>(al, std::max<int64_t>(B->nnzb, 1));
@@ -276,7 +316,7 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     sym.cold_rp = C0->d_row_ptr;
     sym.cold_ci = C0->d_col_idx;
   }
-  DBuf<int64_t> c_rp(al, (size_t)nbr + 1);
+  P.c_rp = DBuf<int64_t>(al, (size_t)nbr + 1);
   int64_t nnzb_c = 0;
   int32_t max_row = 0;
   {
@@ -285,7 +325,7 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     HIPCHECK(hipMemsetAsync(dmax.p, 0, sizeof(int32_t), s));
     if (retain) {
       // pattern = C_old pattern; row lengths from its row_ptr
-      HIPCHECK(hipMemcpyAsync(c_rp.p, C0->d_row_ptr, sizeof(int64_t) * ((size_t)nbr + 1), hipMemcpyDeviceToDevice, s));
+      HIPCHECK(hipMemcpyAsync(P.c_rp.p, C0->d_row_ptr, sizeof(int64_t) * ((size_t)nbr + 1), hipMemcpyDeviceToDevice, s));
       nnzb_c = C0->nnzb;
       // max row length on the host side from a read-back of row_ptr
       std::vector<int64_t> h(nbr + 1);
@@ -295,24 +335,26 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     } else {
       symbolic_count(sym, row_nnz.p, dmax.p, s);
       if (nbr > 0) {
-        exclusive_scan_i64(al, row_nnz.p, c_rp.p, nbr, s);
+        exclusive_scan_i64(al, row_nnz.p, P.c_rp.p, nbr, s);
       } else {
-        HIPCHECK(hipMemsetAsync(c_rp.p, 0, sizeof(int64_t), s));
+        HIPCHECK(hipMemsetAsync(P.c_rp.p, 0, sizeof(int64_t), s));
       }
-      HIPCHECK(hipMemcpyAsync(ctx->pinned, c_rp.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipMemcpyAsync(ctx->pinned, P.c_rp.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
       HIPCHECK(hipMemcpyAsync(ctx->pinned + 1, dmax.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
       nnzb_c = ctx->pinned[0];
       max_row = (int32_t)(ctx->pinned[1] & 0xffffffff);
     }
   }
+  P.nnzb_c = nnzb_c;
   if (nnzb_c > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "more than 2^31 result blocks");
   if (A->nnzb > INT32_MAX || B->nnzb > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "more than 2^31 operand blocks");
   const size_t nc1 = (size_t)std::max<int64_t>(nnzb_c, 1);
-  DBuf<int32_t> c_ci(al, nc1), c_row(al, nc1), c_cnt(al, nc1);
+  P.c_ci = DBuf<int32_t>(al, nc1);
+  P.c_row = DBuf<int32_t>(al, nc1);
+  DBuf<int32_t> c_cnt(al, nc1);
   DBuf<int64_t> c_size(al, nc1), row_kmn(al, std::max<int32_t>(nbr, 1)), row_cand(al, std::max<int32_t>(nbr, 1)),
       row_real(al, std::max<int32_t>(nbr, 1));
-  // quad path of the GEMM: value arrays below 2 GB and few distinct k sizes
   std::vector<int32_t> ksizes(opa_c.begin(), opa_c.end());
   std::sort(ksizes.begin(), ksizes.end());
   ksizes.erase(std::unique(ksizes.begin(), ksizes.end()), ksizes.end());
@@ -322,12 +364,12 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   // block pads its contraction extent k to a multiple of 2 (FP64) or 4
   // (FP32 / split, half the bytes), so it holds at most (k + 1) / k or
   // (k + 3) / k times the values of the stored block; kmin bounds both.
-  const bool lowp_mode = ctx->mode != BSMM_COMPUTE_FP64;
+  const bool lowp = P.lowp = ctx->mode != BSMM_COMPUTE_FP64;
   const double kmin = ksizes.empty() ? 1.0 : (double)ksizes.front();
-  const double grow = lowp_mode ? 0.5 * (kmin + 3.0) / kmin : (kmin + 1.0) / kmin;
-  const bool quads = !ksizes.empty() && ksizes.size() <= 8 &&
-                     (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
-                     (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
+  const double grow = lowp ? 0.5 * (kmin + 3.0) / kmin : (kmin + 1.0) / kmin;
+  const bool quads = P.quads = !ksizes.empty() && ksizes.size() <= 8 &&
+                               (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
+                               (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
   DBuf<int32_t> cnt_g;
   if (quads && (int64_t)max_row * (int64_t)ksizes.size() > 8192) {
     cnt_g = DBuf<int32_t>(al, nc1 * ksizes.size());
@@ -336,9 +378,9 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   HIPCHECK(hipMemsetAsync(c_cnt.p, 0, sizeof(int32_t) * nc1, s));
   FillArgs fa;
   fa.sym = sym;
-  fa.c_rp = c_rp.p;
-  fa.c_ci = c_ci.p;
-  fa.c_row = c_row.p;
+  fa.c_rp = P.c_rp.p;
+  fa.c_ci = P.c_ci.p;
+  fa.c_row = P.c_row.p;
   fa.c_size = c_size.p;
   fa.c_cnt = c_cnt.p;
   fa.c_kflops = row_kmn.p;
@@ -352,70 +394,52 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   fa.eps = eps;
   fa.max_row = max_row;
   symbolic_fill(fa, s);
-  DBuf<int64_t> c_off(al, nc1 + 1), seg_off(al, nc1 + 1), kmn_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1),
+  P.c_off = DBuf<int64_t>(al, nc1 + 1);
+  P.seg_off = DBuf<int64_t>(al, nc1 + 1);
+  DBuf<int64_t> kmn_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1),
       cand_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1), real_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1);
-  exclusive_scan_i64(al, c_size.p, c_off.p, nnzb_c, s);
-  exclusive_scan_i32(al, c_cnt.p, seg_off.p, nnzb_c, s);
+  exclusive_scan_i64(al, c_size.p, P.c_off.p, nnzb_c, s);
+  exclusive_scan_i32(al, c_cnt.p, P.seg_off.p, nnzb_c, s);
   exclusive_scan_i64(al, row_kmn.p, kmn_scan.p, nbr, s);
   exclusive_scan_i64(al, row_cand.p, cand_scan.p, nbr, s);
   exclusive_scan_i64(al, row_real.p, real_scan.p, nbr, s);
   // packed operand offsets for the quad path (op(A) row-major, op(B) column-major)
-  DBuf<int64_t> a_poff, b_poff;
-  const bool lowp = lowp_mode;
   if (lowp && !quads && nnzb_c > 0)
     fail(BSMM_ERR_UNSUPPORTED, "FP32 / split modes need packed operands below 2 GB and at most 8 distinct k block sizes");
   if (quads) {
-    a_poff = DBuf<int64_t>(al, (size_t)A->nnzb + 1);
-    b_poff = DBuf<int64_t>(al, (size_t)B->nnzb + 1);
+    P.a_poff = DBuf<int64_t>(al, (size_t)A->nnzb + 1);
+    P.b_poff = DBuf<int64_t>(al, (size_t)B->nnzb + 1);
     if (lowp) {   // FP32 k-quad slabs
-      pack32_offsets(al, *A, ta, a_poff.p, s);
-      pack32_offsets(al, *B, !tb, b_poff.p, s);
+      pack32_offsets(al, *A, ta, P.a_poff.p, s);
+      pack32_offsets(al, *B, !tb, P.b_poff.p, s);
     } else {      // FP64 k-pair slabs
-      pack_offsets(al, *A, ta, a_poff.p, s);
-      pack_offsets(al, *B, !tb, b_poff.p, s);
+      pack_offsets(al, *A, ta, P.a_poff.p, s);
+      pack_offsets(al, *B, !tb, P.b_poff.p, s);
     }
-    HIPCHECK(hipMemcpyAsync(ctx->pinned + 5, a_poff.p + A->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(ctx->pinned + 6, b_poff.p + B->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(ctx->pinned + 5, P.a_poff.p + A->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(ctx->pinned + 6, P.b_poff.p + B->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   }
-  HIPCHECK(hipMemcpyAsync(ctx->pinned, c_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipMemcpyAsync(ctx->pinned + 1, seg_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(ctx->pinned, P.c_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(ctx->pinned + 1, P.seg_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(ctx->pinned + 2, kmn_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(ctx->pinned + 3, cand_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(ctx->pinned + 4, real_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
-  const int64_t nval_c = ctx->pinned[0];
-  const int64_t nstack = ctx->pinned[1];   // stack entries, padding included
-  const int64_t nprod = ctx->pinned[4];
-  const int64_t kmn_total = ctx->pinned[2];
-  const int64_t ncand = ctx->pinned[3];
-  const int64_t a_pack_n = quads ? ctx->pinned[5] : 0, b_pack_n = quads ? ctx->pinned[6] : 0;
-  DBuf<int32_t> old_blk;
+  P.nval_c = ctx->pinned[0];
+  P.nstack = ctx->pinned[1];   // stack entries, padding included
+  P.nprod = ctx->pinned[4];
+  P.kmn_total = ctx->pinned[2];
+  P.ncand = ctx->pinned[3];
+  P.a_pack_n = quads ? ctx->pinned[5] : 0;
+  P.b_pack_n = quads ? ctx->pinned[6] : 0;
   if (C0 && beta != 0.0 && nnzb_c > 0) {
-    old_blk = DBuf<int32_t>(al, nc1);
-    HIPCHECK(hipMemsetAsync(old_blk.p, 0xff, sizeof(int32_t) * nc1, s));
-    old_block_map(C0->d_row_ptr, C0->d_col_idx, nbr, c_rp.p, c_ci.p, old_blk.p, s);
+    P.old_blk = DBuf<int32_t>(al, nc1);
+    HIPCHECK(hipMemsetAsync(P.old_blk.p, 0xff, sizeof(int32_t) * nc1, s));
+    old_block_map(C0->d_row_ptr, C0->d_col_idx, nbr, P.c_rp.p, P.c_ci.p, P.old_blk.p, s);
   }
   tm.mark();  // 3
   // ------------------------------------------------------- a4: stacks
-  // packed operand copies (a_pack_n / b_pack_n are in units of 8 bytes)
-  DBuf<double> a_pack, b_pack, a_lo, b_lo;
-  if (quads && nprod > 0) {
-    a_pack = DBuf<double>(al, (size_t)std::max<int64_t>(a_pack_n, 2));
-    b_pack = DBuf<double>(al, (size_t)std::max<int64_t>(b_pack_n, 2));
-    if (lowp) {
-      const bool split = ctx->mode == BSMM_COMPUTE_SPLIT;
-      if (split) {
-        a_lo = DBuf<double>(al, (size_t)std::max<int64_t>(a_pack_n, 2));
-        b_lo = DBuf<double>(al, (size_t)std::max<int64_t>(b_pack_n, 2));
-      }
-      pack32_values(*A, ta, a_poff.p, reinterpret_cast<float *>(a_pack.p), reinterpret_cast<float *>(a_lo.p), s);
-      pack32_values(*B, !tb, b_poff.p, reinterpret_cast<float *>(b_pack.p), reinterpret_cast<float *>(b_lo.p), s);
-    } else {
-      pack_values(*A, ta, a_poff.p, a_pack.p, s);
-      pack_values(*B, !tb, b_poff.p, b_pack.p, s);
-    }
-  }
-  DBuf<int2> stack(al, (size_t)std::max<int64_t>(nstack, 1));
+  P.stack = DBuf<int2>(al, (size_t)std::max<int64_t>(P.nstack, 1));
   {
     DBuf<int32_t> run;
     if (max_row > 8192) {
@@ -425,10 +449,10 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     StackArgs sa;
     sa.a = &oa;
     sa.b = &ob;
-    sa.c_rp = c_rp.p;
-    sa.c_ci = c_ci.p;
-    sa.seg_off = seg_off.p;
-    sa.stack = stack.p;
+    sa.c_rp = P.c_rp.p;
+    sa.c_ci = P.c_ci.p;
+    sa.seg_off = P.seg_off.p;
+    sa.stack = P.stack.p;
     sa.na = filt ? na.p : nullptr;
     sa.nb = filt ? nb.p : nullptr;
     sa.eps = eps;
@@ -438,117 +462,135 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
     sa.ksizes = ksizes;
     sa.pad4 = quads;
     sa.encode = quads;
-    sa.a_poff = a_poff.p;
-    sa.b_poff = b_poff.p;
-    if (nprod > 0) stack_fill(sa, run.p, s);
+    sa.a_poff = P.a_poff.p;
+    sa.b_poff = P.b_poff.p;
+    if (P.nprod > 0) stack_fill(sa, run.p, s);
   }
   // GEMM work list: tiles of rows in the planner's locality order, columns
   // inside a tile in the same order when C is square over the same blocks
-  DBuf<int32_t> c_list;
   if (nnzb_c > 0) {
     const int32_t *ord = row_order(ctx, A);
     if (ord) {
-      c_list = DBuf<int32_t>(al, nc1);
+      P.c_list = DBuf<int32_t>(al, nc1);
       const int32_t *rank = (nbc == nbr) ? ord + nbr : nullptr;
       const int32_t tile_rows = 16;
       if ((size_t)nbc * 4 > 160 * 1024) {
         // columns too many for one LDS histogram: plain row order
-        build_work_list(al, ord, nullptr, c_rp.p, c_ci.p, nbr, 0, tile_rows, c_list.p, s);
+        build_work_list(al, ord, nullptr, P.c_rp.p, P.c_ci.p, nbr, 0, tile_rows, P.c_list.p, s);
       } else {
-        build_work_list(al, ord, rank, c_rp.p, c_ci.p, nbr, nbc, tile_rows, c_list.p, s);
+        build_work_list(al, ord, rank, P.c_rp.p, P.c_ci.p, nbr, nbc, tile_rows, P.c_list.p, s);
       }
     }
   }
+  // ------------------------------------- buffers of the numeric part
+  P.post = filt && !retain;
+  if (P.post) P.c_norm = DBuf<double>(al, nc1);
+  P.c_values = DBuf<double>(al, (size_t)std::max<int64_t>(P.nval_c, 1));
+  if (quads && P.nprod > 0) {   // packed copies (sizes in units of 8 bytes)
+    P.a_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.a_pack_n, 2));
+    P.b_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
+    if (ctx->mode == BSMM_COMPUTE_SPLIT) {
+      P.a_lo = DBuf<double>(al, (size_t)std::max<int64_t>(P.a_pack_n, 2));
+      P.b_lo = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
+    }
+  }
+  if (!quads && ta && P.nprod > 0) P.a_t = DBuf<double>(al, (size_t)std::max<int64_t>(A->n_values, 1));
+  if (!quads && !tb && P.nprod > 0) P.b_t = DBuf<double>(al, (size_t)std::max<int64_t>(B->n_values, 1));
+  if (!ctx->zeros) {
+    ctx->zeros = static_cast<double *>(al.alloc(4096));
+    HIPCHECK(hipMemsetAsync(ctx->zeros, 0, 4096, s));
+  }
+  GemmArgs &ga = P.ga;
+  ga.a = &oa;
+  ga.b = &ob;
+  ga.c_list = P.c_list.p;
+  ga.c_row = P.c_row.p;
+  ga.c_ci = P.c_ci.p;
+  ga.c_off = P.c_off.p;
+  ga.seg_off = P.seg_off.p;
+  ga.stack = P.stack.p;
+  ga.c_old_blk = P.old_blk.p;
+  ga.old_off = C0 ? C0->d_blk_off : nullptr;
+  ga.old_values = C0 ? C0->d_values : nullptr;
+  ga.c_values = P.c_values.p;
+  ga.c_norm = P.post ? P.c_norm.p : nullptr;
+  ga.alpha = P.alpha;
+  ga.beta = P.beta;
+  ga.mode = ctx->mode;
+  // operand layouts: packed copies (quad path), or op(A) column-major and
+  // op(B) row-major (walker path)
+  ga.a_cm = ta ? P.a_t.p : A->d_values;
+  ga.b_rm = tb ? B->d_values : P.b_t.p;
+  ga.a_pack = P.a_pack.p;
+  ga.b_pack = P.b_pack.p;
+  ga.a_hi = reinterpret_cast<const float *>(P.a_pack.p);
+  ga.b_hi = reinterpret_cast<const float *>(P.b_pack.p);
+  ga.a_lo = reinterpret_cast<const float *>(P.a_lo.p);
+  ga.b_lo = reinterpret_cast<const float *>(P.b_lo.p);
+  ga.a_bytes = (uint64_t)(quads ? P.a_pack_n : A->n_values) * sizeof(double);
+  ga.b_bytes = (uint64_t)(quads ? P.b_pack_n : B->n_values) * sizeof(double);
+  ga.zeros = ctx->zeros;
+  ga.quads = quads;
+  for (int t = 0; t < 16; t++) ga.variant[t] = ctx->gemm_variant[t];
+  P.max_edge = 1;
+  for (int32_t v : opa_r) P.max_edge = std::max(P.max_edge, v);
+  for (int32_t v : opb_c) P.max_edge = std::max(P.max_edge, v);
   tm.mark();  // 4
-  // ------------------------------------------------------- a5: GEMM
-  const bool post = filt && !retain;
-  DBuf<double> c_norm;
-  if (post) c_norm = DBuf<double>(al, nc1);
-  double *c_values = static_cast<double *>(al.alloc(sizeof(double) * (size_t)std::max<int64_t>(nval_c, 1)));
-  bsmm_mat_s *R = nullptr;
+}
+
+// The numeric part: operand copies and the block GEMM (kernels only).
+static void plan_numeric(Plan &P, bool marks) {
+  hipStream_t s = P.ctx->stream;
+  const bool ta = P.ta, tb = P.tb;
+  if (P.nprod > 0) {
+    if (P.quads && P.lowp) {
+      pack32_values(*P.A, ta, P.a_poff.p, reinterpret_cast<float *>(P.a_pack.p), reinterpret_cast<float *>(P.a_lo.p), s);
+      pack32_values(*P.B, !tb, P.b_poff.p, reinterpret_cast<float *>(P.b_pack.p), reinterpret_cast<float *>(P.b_lo.p), s);
+    } else if (P.quads) {
+      pack_values(*P.A, ta, P.a_poff.p, P.a_pack.p, s);
+      pack_values(*P.B, !tb, P.b_poff.p, P.b_pack.p, s);
+    } else {
+      if (ta) transpose_blocks(*P.A, P.a_t.p, s);
+      if (!tb) transpose_blocks(*P.B, P.b_t.p, s);
+    }
+  }
+  if (marks) P.tm.mark();  // 5
+  if (P.lowp)
+    gemm_launch_lowp(P.ga, P.nnzb_c, P.max_edge, s);
+  else
+    gemm_launch(P.ga, P.nnzb_c, P.max_edge, s);
+  if (marks) P.tm.mark();  // 6
+}
+
+// Post-filter and the result matrix.  consume: the plan's C buffers become
+// the result (one-shot multiply); otherwise they are copied.
+static bsmm_mat_s *plan_finish(Plan &P, bool consume) {
+  bsmm_ctx ctx = P.ctx;
+  hipStream_t s = ctx->stream;
+  Allocator &al = ctx->alloc;
+  const int64_t nnzb_c = P.nnzb_c;
+  bsmm_mat_s *R = new_result(ctx, P.nbr, P.nbc, P.opa_r, P.opb_c);
   try {
-    GemmArgs ga;
-    ga.a = &oa;
-    ga.b = &ob;
-    ga.c_list = c_list.p;
-    ga.c_row = c_row.p;
-    ga.c_ci = c_ci.p;
-    ga.c_off = c_off.p;
-    ga.seg_off = seg_off.p;
-    ga.stack = stack.p;
-    ga.c_old_blk = old_blk.p;
-    ga.old_off = C0 ? C0->d_blk_off : nullptr;
-    ga.old_values = C0 ? C0->d_values : nullptr;
-    ga.c_values = c_values;
-    ga.c_norm = post ? c_norm.p : nullptr;
-    ga.alpha = alpha;
-    ga.beta = beta;
-    ga.mode = ctx->mode;
-    // operand layouts for the matrix cores.  Quad path: the packed copies.
-    // Walker path: op(A) column-major, op(B) row-major.
-    DBuf<double> a_t, b_t;
-    if (!quads && ta && nprod > 0) {
-      a_t = DBuf<double>(al, (size_t)std::max<int64_t>(A->n_values, 1));
-      transpose_blocks(*A, a_t.p, s);
-    }
-    if (!quads && !tb && nprod > 0) {
-      b_t = DBuf<double>(al, (size_t)std::max<int64_t>(B->n_values, 1));
-      transpose_blocks(*B, b_t.p, s);
-    }
-    ga.a_cm = ta ? a_t.p : A->d_values;
-    ga.b_rm = tb ? B->d_values : b_t.p;
-    ga.a_pack = a_pack.p;
-    ga.b_pack = b_pack.p;
-    ga.a_hi = reinterpret_cast<const float *>(a_pack.p);
-    ga.b_hi = reinterpret_cast<const float *>(b_pack.p);
-    ga.a_lo = reinterpret_cast<const float *>(a_lo.p);
-    ga.b_lo = reinterpret_cast<const float *>(b_lo.p);
-    ga.a_bytes = (uint64_t)(quads ? a_pack_n : A->n_values) * sizeof(double);
-    ga.b_bytes = (uint64_t)(quads ? b_pack_n : B->n_values) * sizeof(double);
-    if (!ctx->zeros) {
-      ctx->zeros = static_cast<double *>(al.alloc(4096));
-      HIPCHECK(hipMemsetAsync(ctx->zeros, 0, 4096, s));
-    }
-    ga.zeros = ctx->zeros;
-    ga.quads = quads;
-    for (int t = 0; t < 16; t++) ga.variant[t] = ctx->gemm_variant[t];
-    int max_edge = 1;
-    for (int32_t v : opa_r) max_edge = std::max(max_edge, v);
-    for (int32_t v : opb_c) max_edge = std::max(max_edge, v);
-    if (lowp)
-      gemm_launch_lowp(ga, nnzb_c, max_edge, s);
-    else
-      gemm_launch(ga, nnzb_c, max_edge, s);
-    a_t.reset();
-    b_t.reset();
-    a_pack.reset();
-    b_pack.reset();
-    a_lo.reset();
-    b_lo.reset();
-    tm.mark();  // 5
-    // ----------------------------------------------------- a6: post-filter
-    R = new_result(ctx, nbr, nbc, opa_r, opb_c);
     int64_t kept = nnzb_c;
     DBuf<int64_t> rank;
-    if (post && nnzb_c > 0) {
+    if (P.post && nnzb_c > 0) {
       CompactArgs ca;
-      ca.nbr = nbr;
+      ca.nbr = P.nbr;
       ca.nnzb = nnzb_c;
-      ca.rp = c_rp.p;
-      ca.ci = c_ci.p;
-      ca.off = c_off.p;
-      ca.values = c_values;
-      ca.norm = c_norm.p;
-      ca.eps = eps;
-      kept = count_kept(al, ca, c_cnt.p /* reused as flag space */, ctx->pinned, s, rank);
+      ca.rp = P.c_rp.p;
+      ca.ci = P.c_ci.p;
+      ca.off = P.c_off.p;
+      ca.values = P.c_values.p;
+      ca.norm = P.c_norm.p;
+      ca.eps = P.eps;
+      DBuf<int32_t> flags(al, (size_t)std::max<int64_t>(nnzb_c, 1));
+      kept = count_kept(al, ca, flags.p, ctx->pinned, s, rank);
       if (kept < nnzb_c) {
-        DBuf<int64_t> nrp(al, (size_t)nbr + 1), noff(al, (size_t)std::max<int64_t>(kept, 1) + 1);
+        DBuf<int64_t> nrp(al, (size_t)P.nbr + 1), noff(al, (size_t)std::max<int64_t>(kept, 1) + 1);
         DBuf<int32_t> nci(al, (size_t)std::max<int64_t>(kept, 1));
         double *nv = nullptr;
         int64_t nval = 0;
-        compact(al, ca, rank.p, oa.rbs, ob.cbs, nrp.p, nci.p, noff.p, ctx->pinned, &nv, &nval, s);
-        al.release(c_values);
-        c_values = nullptr;
+        compact(al, ca, rank.p, P.oa.rbs, P.ob.cbs, nrp.p, nci.p, noff.p, ctx->pinned, &nv, &nval, s);
         R->d_row_ptr = nrp.release_ownership();
         R->d_col_idx = nci.release_ownership();
         R->d_blk_off = noff.release_ownership();
@@ -557,34 +599,72 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
         R->n_values = nval;
       }
     }
-    if (c_values) {
-      R->d_row_ptr = c_rp.release_ownership();
-      R->d_col_idx = c_ci.release_ownership();
-      R->d_blk_off = c_off.release_ownership();
-      R->d_values = c_values;
-      c_values = nullptr;
+    if (kept == nnzb_c) {
+      if (consume) {
+        R->d_row_ptr = P.c_rp.release_ownership();
+        R->d_col_idx = P.c_ci.release_ownership();
+        R->d_blk_off = P.c_off.release_ownership();
+        R->d_values = P.c_values.release_ownership();
+      } else {
+        const size_t nc1 = (size_t)std::max<int64_t>(nnzb_c, 1);
+        R->d_row_ptr = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * ((size_t)P.nbr + 1)));
+        R->d_col_idx = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nc1));
+        R->d_blk_off = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * (nc1 + 1)));
+        R->d_values = static_cast<double *>(al.alloc(sizeof(double) * (size_t)std::max<int64_t>(P.nval_c, 1)));
+        HIPCHECK(hipMemcpyAsync(R->d_row_ptr, P.c_rp.p, sizeof(int64_t) * ((size_t)P.nbr + 1), hipMemcpyDeviceToDevice, s));
+        if (nnzb_c) {
+          HIPCHECK(hipMemcpyAsync(R->d_col_idx, P.c_ci.p, sizeof(int32_t) * (size_t)nnzb_c, hipMemcpyDeviceToDevice, s));
+          HIPCHECK(hipMemcpyAsync(R->d_values, P.c_values.p, sizeof(double) * (size_t)P.nval_c, hipMemcpyDeviceToDevice, s));
+        }
+        HIPCHECK(hipMemcpyAsync(R->d_blk_off, P.c_off.p, sizeof(int64_t) * ((size_t)nnzb_c + 1), hipMemcpyDeviceToDevice, s));
+      }
       R->nnzb = nnzb_c;
-      R->n_values = nval_c;
-    }
-    tm.mark();  // 6
-    if (info) {
-      info->c_nnzb_symbolic = nnzb_c;
-      info->c_nnzb = R->nnzb;
-      info->c_n_values = R->n_values;
-      info->n_products = nprod;
-      info->n_candidates = ncand;
-      info->useful_flops = 2.0 * (double)kmn_total;
-      info->ms_index = tm.between(0, 1);
-      info->ms_norms = tm.between(1, 2);
-      info->ms_symbolic = tm.between(2, 3);
-      info->ms_stacks = tm.between(3, 4);
-      info->ms_gemm = tm.between(4, 5);
-      info->ms_filter = tm.between(5, 6);
-      info->ms_total = tm.between(0, 6);
+      R->n_values = P.nval_c;
     }
   } catch (...) {
-    if (c_values) al.release(c_values);
-    if (R) free_mat(R);
+    free_mat(R);
+    throw;
+  }
+  return R;
+}
+
+static void plan_info(Plan &P, const bsmm_mat_s *R, bsmm_multiply_info *info) {
+  if (!info) return;
+  Timer &tm = P.tm;
+  info->c_nnzb_symbolic = P.nnzb_c;
+  info->c_nnzb = R ? R->nnzb : P.nnzb_c;
+  info->c_n_values = R ? R->n_values : P.nval_c;
+  info->n_products = P.nprod;
+  info->n_candidates = P.ncand;
+  info->useful_flops = 2.0 * (double)P.kmn_total;
+  info->ms_index = tm.between(0, 1);
+  info->ms_norms = tm.between(1, 2);
+  info->ms_symbolic = tm.between(2, 3);
+  info->ms_stacks = tm.between(3, 4) + tm.between(4, 5);   // stacks, work list, operand copies
+  info->ms_gemm = tm.between(5, 6);
+  info->ms_filter = tm.between(6, 7);
+  info->ms_total = tm.between(0, 7);
+}
+
+static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double alpha, bsmm_mat_s *A,
+                                 bsmm_mat_s *B, double beta, bsmm_mat_s *C0, double eps, int retain,
+                                 bsmm_multiply_info *info) {
+  Plan P(ctx);
+  P.A = A;
+  P.B = B;
+  P.C0 = C0;
+  P.alpha = alpha;
+  P.beta = beta;
+  P.eps = eps;
+  P.retain = retain;
+  plan_build(P, transa, transb);
+  plan_numeric(P, true);
+  bsmm_mat_s *R = plan_finish(P, true);
+  P.tm.mark();  // 7
+  try {
+    plan_info(P, R, info);
+  } catch (...) {
+    free_mat(R);
     throw;
   }
   return R;
@@ -990,6 +1070,112 @@ bsmm_status bsmm_multiply(bsmm_ctx ctx, char transa, char transb, double alpha, 
   bsmm_mat_s *r = multiply_impl(ctx, transa, transb, alpha, a, b, beta, c_old, filter_eps, retain_sparsity, info);
   ctx->live_mats++;
   *c_out = r;
+  ABI_END
+}
+
+// ------------------------------------------------------------------ plans
+struct bsmm_plan_s {
+  Plan plan;
+  explicit bsmm_plan_s(bsmm_ctx c) : plan(c) {}
+};
+
+bsmm_status bsmm_plan_create(bsmm_ctx ctx, char transa, char transb, double alpha, bsmm_mat a, bsmm_mat b,
+                             double beta, bsmm_mat c_old, double filter_eps, int retain_sparsity, bsmm_plan *out,
+                             bsmm_multiply_info *info) {
+  ABI_BEGIN
+  if (!ctx || !a || !b || !out) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  if (!(transa == 'N' || transa == 'n' || transa == 'T' || transa == 't') ||
+      !(transb == 'N' || transb == 'n' || transb == 'T' || transb == 't'))
+    fail(BSMM_ERR_INVALID_ARG, "trans must be 'N' or 'T'");
+  if (a->ctx != ctx || b->ctx != ctx || (c_old && c_old->ctx != ctx))
+    fail(BSMM_ERR_INVALID_ARG, "matrices belong to another context");
+  DeviceGuard g(ctx->device);
+  auto *pl = new bsmm_plan_s(ctx);
+  try {
+    Plan &P = pl->plan;
+    P.A = a;
+    P.B = b;
+    P.C0 = c_old;
+    P.alpha = alpha;
+    P.beta = beta;
+    P.eps = filter_eps;
+    P.retain = retain_sparsity;
+    plan_build(P, transa, transb);
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    if (info) {
+      *info = bsmm_multiply_info{};
+      info->c_nnzb_symbolic = P.nnzb_c;
+      info->c_nnzb = P.nnzb_c;
+      info->c_n_values = P.nval_c;
+      info->n_products = P.nprod;
+      info->n_candidates = P.ncand;
+      info->useful_flops = 2.0 * (double)P.kmn_total;
+      info->ms_index = P.tm.between(0, 1);
+      info->ms_norms = P.tm.between(1, 2);
+      info->ms_symbolic = P.tm.between(2, 3);
+      info->ms_stacks = P.tm.between(3, 4);
+    }
+  } catch (...) {
+    delete pl;
+    throw;
+  }
+  ctx->live_mats++;
+  *out = pl;
+  ABI_END
+}
+
+bsmm_status bsmm_plan_execute(bsmm_plan plan) {
+  ABI_BEGIN
+  if (!plan) fail(BSMM_ERR_INVALID_ARG, "plan is NULL");
+  Plan &P = plan->plan;
+  DeviceGuard g(P.ctx->device);
+  if (P.exec)
+    HIPCHECK(hipGraphLaunch(P.exec, P.ctx->stream));
+  else
+    plan_numeric(P, false);
+  ABI_END
+}
+
+bsmm_status bsmm_plan_capture(bsmm_plan plan) {
+  ABI_BEGIN
+  if (!plan) fail(BSMM_ERR_INVALID_ARG, "plan is NULL");
+  Plan &P = plan->plan;
+  if (P.exec) return BSMM_OK;   // already captured
+  if (P.ctx->stream == nullptr) fail(BSMM_ERR_UNSUPPORTED, "graph capture needs a non-default stream");
+  DeviceGuard g(P.ctx->device);
+  HIPCHECK(hipStreamBeginCapture(P.ctx->stream, hipStreamCaptureModeThreadLocal));
+  try {
+    plan_numeric(P, false);
+  } catch (...) {
+    hipGraph_t tmp = nullptr;
+    (void)hipStreamEndCapture(P.ctx->stream, &tmp);
+    if (tmp) (void)hipGraphDestroy(tmp);
+    throw;
+  }
+  HIPCHECK(hipStreamEndCapture(P.ctx->stream, &P.graph));
+  HIPCHECK(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+  ABI_END
+}
+
+bsmm_status bsmm_plan_result(bsmm_plan plan, bsmm_mat *c_out) {
+  ABI_BEGIN
+  if (!plan || !c_out) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  Plan &P = plan->plan;
+  DeviceGuard g(P.ctx->device);
+  bsmm_mat_s *r = plan_finish(P, false);
+  P.ctx->live_mats++;
+  *c_out = r;
+  ABI_END
+}
+
+bsmm_status bsmm_plan_destroy(bsmm_plan plan) {
+  ABI_BEGIN
+  if (!plan) return BSMM_OK;
+  bsmm_ctx ctx = plan->plan.ctx;
+  DeviceGuard g(ctx->device);
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  delete plan;
+  ctx->live_mats--;
   ABI_END
 }
 
