@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 SIGN_ATOMS, SIGN_EPS, SIGN_TOL, SIGN_MAX_ITER = 1000, 1e-6, 1e-4, 20
+SERVE_ATOMS, SERVE_BUDGET_GB = (200, 1500), 64
 BATCH_ATOMS = 3500   # 23x23 blocks at 3 % occupancy: the packed operands just fit 32-bit offsets
 HBM_PEAK_GBS = 8000.0
 METRIC = "useful FP64 GFLOP/s of block-sparse C+=A·B, % MFMA peak; p99 serve latency"
@@ -163,6 +164,72 @@ def time_mode(bsmm, ctx, A, Bm, eps, steps, warmup):
     return ev0.elapsed_time(ev1) / steps, infos, last
 
 
+def tiny_latency(bsmm, torch, reps: int = 50) -> dict:
+    from paper_1705_10218_amd import inputs
+    st = torch.cuda.Stream()
+    res = {"workload": "tiny_100x100_blocks_5", "reps": reps}
+    with torch.cuda.stream(st):
+        ctx = bsmm.Context(0, stream=st)
+        a, b = inputs.config_tiny(0), inputs.config_tiny(1)
+        A, Bm = bsmm.Matrix.from_host(ctx, a), bsmm.Matrix.from_host(ctx, b)
+        st.synchronize()
+
+        def timed(fn):
+            fn()
+            st.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            st.synchronize()
+            return (time.perf_counter() - t0) / reps * 1e6
+
+        def one_shot():
+            C, _ = bsmm.multiply(ctx, "N", "N", 1.0, A, Bm)
+            C.close()
+
+        plan = bsmm.Plan(ctx, "N", "N", 1.0, A, Bm)
+        res["useful_flops"] = plan.info.useful_flops
+        res["multiply_us"] = round(timed(one_shot), 2)
+        res["plan_execute_us"] = round(timed(plan.execute), 2)
+        plan.capture()
+        res["graph_replay_us"] = round(timed(plan.execute), 2)
+        plan.close()
+        A.close()
+        Bm.close()
+        ctx.close()
+    _log(f"tiny latency: {res}")
+    return res
+
+
+def serving_leg(bsmm, ctx, n: int) -> dict:
+    import numpy as np
+
+    from paper_1705_10218_amd import inputs, serve
+    gen = inputs.serving_requests(n, atoms=SERVE_ATOMS, occupancy=(0.02, 0.20), seed=1)
+    budget = SERVE_BUDGET_GB << 30
+
+    def requests(arrivals):
+        return [serve.Request(rid=i, a=a, b=b, eps=1e-10, arrival=float(t)) for i, ((a, b, _), t) in
+                enumerate(zip(gen, arrivals))]
+
+    srv = serve.Server(ctx, budget, max_batch=64)
+    sat = serve.summary(srv.run(requests(np.zeros(n))))
+    rate = 0.7 * sat["requests_per_s"]
+    srv2 = serve.Server(ctx, budget, max_batch=64)
+    done = srv2.run(requests(serve.poisson_arrivals(n, rate, np.random.default_rng(5))))
+    st = serve.summary(done)
+    _log(f"serving: saturation {sat['requests_per_s']:.1f} req/s, at 0.7x: p50 {st['latency_p50_ms']:.1f} ms "
+         f"p99 {st['latency_p99_ms']:.1f} ms")
+    return {"requests": n, "atoms_log_uniform": list(SERVE_ATOMS), "occupancy_uniform": [0.02, 0.20],
+            "block_sizes": [5, 13, 23], "filter_eps": 1e-10, "hbm_budget_gb": SERVE_BUDGET_GB,
+            "saturation": {"requests_per_s": round(sat["requests_per_s"], 3),
+                           "gflops": round(sat["throughput_gflops"], 2), "batches": len(srv.batches)},
+            "arrival_rate_per_s": round(rate, 3),
+            "latency_p50_ms": round(st["latency_p50_ms"], 3), "latency_p99_ms": round(st["latency_p99_ms"], 3),
+            "throughput_gflops": round(st["throughput_gflops"], 2), "batches": len(srv2.batches),
+            "mean_batch": round(float(np.mean(srv2.batches)), 2), "useful_flops": st["useful_flops"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +240,7 @@ def main():
     ap.add_argument("--fp64-only", action="store_true",
                     help="only the headline FP64 workload (no precision, batching or sign-iteration legs)")
     ap.add_argument("--no-tuning", action="store_true", help="default GEMM kernel variants instead of the tuned table")
+    ap.add_argument("--serve-requests", type=int, default=40, help="requests of the serving leg (0: skip it)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run plain device copies of this size (HBM counter calibration)")
@@ -304,6 +372,18 @@ def main():
             Ab.close()
             Bb.close()
         out["batching"] = batching
+    # latency of the tiny multiply (100x100 blocks of 5): one-shot multiply,
+    # re-execution of its plan's numeric part, and the same part replayed
+    # from a HIP graph (fixed pattern, values changing between calls)
+    if not args.fp64_only:
+        out["tiny_latency"] = tiny_latency(bsmm, torch)
+    # serving: independent requests (DFT-like, sizes {5, 13, 23}, 2-20 %
+    # occupancy) through the continuous-batching loop; first all at once
+    # (saturation throughput), then Poisson arrivals at 0.7 of that rate
+    if not args.fp64_only and args.serve_requests > 0:
+        variants = tune_for((5, 13, 23))
+        out["serving"] = serving_leg(bsmm, ctx, args.serve_requests)
+        out["serving"]["gemm_variants"] = variants
     # second workload: Newton-Schulz sign iteration (two filtered multiplies
     # per step, pattern evolving then stabilising)
     if not args.fp64_only:

@@ -198,6 +198,18 @@ bsmm_status bsmm_plan_create(bsmm_ctx ctx, char transa, char transb, double alph
 bsmm_status bsmm_plan_execute(bsmm_plan plan);
 bsmm_status bsmm_plan_capture(bsmm_plan plan);
 bsmm_status bsmm_plan_result(bsmm_plan plan, bsmm_mat *c_out);
+/* The numeric parts of n plans of one context (each plan at most once) as
+ * one batch: the operand copies of every plan, then ONE block-GEMM launch
+ * over the result blocks of all of them (each wavefront takes one result
+ * block of one plan), so the requests' work shares the device.  Every
+ * result block is computed exactly as in a launch of its own plan, so each
+ * plan's result is bitwise the one it gets alone.  Plans outside the FP64
+ * packed-operand path run one after another instead.  Asynchronous; waits
+ * only for the previous batched launch of the context to have read its
+ * staging buffer.  The batching of stacks across independent requests is
+ * what a serving loop uses (admit requests, build their plans, execute them
+ * together). */
+bsmm_status bsmm_plans_execute(int32_t n, bsmm_plan *plans);
 /* Waits for the plan's stream, then frees it (a plan counts as a live object
  * of its context until destroyed). */
 bsmm_status bsmm_plan_destroy(bsmm_plan plan);

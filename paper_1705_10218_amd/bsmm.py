@@ -35,6 +35,7 @@ SYMBOLS = (
     "bsmm_mat_get_index", "bsmm_mat_get_block_sizes", "bsmm_mat_values", "bsmm_mat_copy_values",
     "bsmm_mat_destroy", "bsmm_block_norms", "bsmm_multiply", "bsmm_filter", "bsmm_sign_newton_schulz",
     "bsmm_plan_create", "bsmm_plan_execute", "bsmm_plan_capture", "bsmm_plan_result", "bsmm_plan_destroy",
+    "bsmm_plans_execute",
 )
 
 
@@ -117,6 +118,7 @@ def lib() -> ctypes.CDLL:
         L.bsmm_plan_capture.argtypes = [_vp]
         L.bsmm_plan_result.argtypes = [_vp, ctypes.POINTER(_vp)]
         L.bsmm_plan_destroy.argtypes = [_vp]
+        L.bsmm_plans_execute.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp)]
         L.bsmm_sign_newton_schulz.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                               ctypes.POINTER(_vp), ctypes.POINTER(SignInfo),
                                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -348,6 +350,12 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def plans_execute(plans) -> None:
+    """bsmm_plans_execute: the numeric parts of several plans in one batch."""
+    arr = (_vp * max(len(plans), 1))(*[p.handle for p in plans])
+    _check(lib().bsmm_plans_execute(len(plans), arr))
 
 
 def sign_newton_schulz(ctx: Context, x0: Matrix, max_iter: int, filter_eps: float = 0.0, tol: float = 0.0):

@@ -922,6 +922,7 @@ bsmm_status bsmm_ctx_destroy(bsmm_ctx ctx) {
   DeviceGuard g(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipHostFree(ctx->pinned);
+  if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
   delete ctx;
   ABI_END
 }
@@ -1154,6 +1155,65 @@ bsmm_status bsmm_plan_capture(bsmm_plan plan) {
   }
   HIPCHECK(hipStreamEndCapture(P.ctx->stream, &P.graph));
   HIPCHECK(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+  ABI_END
+}
+
+bsmm_status bsmm_plans_execute(int32_t n, bsmm_plan *plans) {
+  ABI_BEGIN
+  if (n < 0 || (n > 0 && !plans)) fail(BSMM_ERR_INVALID_ARG, "bad plan list");
+  if (n == 0) return BSMM_OK;
+  bsmm_ctx ctx = nullptr;
+  for (int32_t r = 0; r < n; r++) {
+    if (!plans[r]) fail(BSMM_ERR_INVALID_ARG, "plan is NULL");
+    if (r == 0) ctx = plans[0]->plan.ctx;
+    if (plans[r]->plan.ctx != ctx) fail(BSMM_ERR_INVALID_ARG, "plans of different contexts");
+    for (int32_t q = 0; q < r; q++)
+      if (plans[q] == plans[r]) fail(BSMM_ERR_INVALID_ARG, "a plan appears twice");
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = ctx->stream;
+  bool batched = true;
+  for (int32_t r = 0; r < n; r++) batched = batched && plans[r]->plan.quads && !plans[r]->plan.lowp;
+  if (!batched) {   // one after another, as bsmm_plan_execute
+    for (int32_t r = 0; r < n; r++) {
+      Plan &P = plans[r]->plan;
+      if (P.exec) HIPCHECK(hipGraphLaunch(P.exec, s));
+      else plan_numeric(P, false);
+    }
+    return BSMM_OK;
+  }
+  std::vector<const GemmArgs *> gs;
+  std::vector<int64_t> nnzb;
+  int max_edge = 1;
+  for (int32_t r = 0; r < n; r++) {
+    Plan &P = plans[r]->plan;
+    if (P.nprod > 0) {
+      pack_values(*P.A, P.ta, P.a_poff.p, P.a_pack.p, s);
+      pack_values(*P.B, !P.tb, P.b_poff.p, P.b_pack.p, s);
+    }
+    gs.push_back(&P.ga);
+    nnzb.push_back(P.nnzb_c);
+    max_edge = std::max(max_edge, P.max_edge);
+  }
+  // the staging buffers are reused: wait until the previous batched launch
+  // on this stream has read them
+  HIPCHECK(hipStreamSynchronize(s));
+  const size_t need = gemm_multi_stage_bytes(n);
+  if (need > ctx->batch_bytes) {
+    if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
+    ctx->alloc.release(ctx->batch_dev);
+    ctx->batch_host = nullptr;
+    ctx->batch_dev = nullptr;
+    ctx->batch_bytes = 0;
+    const size_t cap = std::max<size_t>(need, 64 * 1024);
+    if (hipHostMalloc(&ctx->batch_host, cap, hipHostMallocDefault) != hipSuccess) {
+      ctx->batch_host = nullptr;
+      fail(BSMM_ERR_OUT_OF_MEMORY, "pinned staging buffer");
+    }
+    ctx->batch_dev = ctx->alloc.alloc(cap);
+    ctx->batch_bytes = cap;
+  }
+  gemm_launch_multi(ctx->alloc, gs, nnzb, max_edge, ctx->batch_host, ctx->batch_bytes, ctx->batch_dev, s);
   ABI_END
 }
 

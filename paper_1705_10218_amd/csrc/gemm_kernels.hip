@@ -621,20 +621,13 @@ __device__ __forceinline__ int edge_tiles(int e) { return ((((e + 3) >> 2) + 1) 
 // that each of the 8 XCDs (ids are dealt to XCDs round-robin) walks one
 // contiguous stretch of the order, keeping its L2 on a compact region.
 // MAXT bounds the subtile counts compiled in (4: blocks up to 16).
-template <int MAXT, bool BUF>
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t per_xcd) {
-  __shared__ ParamLds lds[4];
-  ParamLds &pl = lds[threadIdx.x >> 6];
-  QuadLds &ql = *reinterpret_cast<QuadLds *>(&pl);
-  const int64_t b = blockIdx.x;
-  const int64_t lb = (b & 7) * per_xcd + (b >> 3);
-  const int64_t w = lb * 4 + (threadIdx.x >> 6);
-  if (w >= nblk) return;   // uniform per wavefront
-  const int32_t c = __builtin_amdgcn_readfirstlane(P.c_list ? P.c_list[w] : (int32_t)w);
+// Quad-path dispatch of one C block on its (m, n) class and the class's
+// kernel variant.
+template <int MAXT>
+__device__ __forceinline__ void dispatch_quad(const GemmP &P, int32_t c, QuadLds &ql) {
   const int mt = edge_tiles(P.rbs[P.c_row[c]]);
   const int nt = edge_tiles(P.cbs[P.c_ci[c]]);
   const int key = mt * 16 + nt;
-  if constexpr (BUF) {
     // kernel variant of this (m, n) class: 0 = default (16x16 tile when both
     // edges are in 9..16, else 4x4 subtiles), 1 = 16x16 tiles, 2 = 4x4 subtiles
     const int vid = P.variant[(mt / 2 - 1) * 4 + (nt / 2 - 1)];
@@ -675,6 +668,23 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t
         default: break;
       }
     }
+}
+
+template <int MAXT, bool BUF>
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t per_xcd) {
+  __shared__ ParamLds lds[4];
+  ParamLds &pl = lds[threadIdx.x >> 6];
+  QuadLds &ql = *reinterpret_cast<QuadLds *>(&pl);
+  const int64_t b = blockIdx.x;
+  const int64_t lb = (b & 7) * per_xcd + (b >> 3);
+  const int64_t w = lb * 4 + (threadIdx.x >> 6);
+  if (w >= nblk) return;   // uniform per wavefront
+  const int32_t c = __builtin_amdgcn_readfirstlane(P.c_list ? P.c_list[w] : (int32_t)w);
+  const int mt = edge_tiles(P.rbs[P.c_row[c]]);
+  const int nt = edge_tiles(P.cbs[P.c_ci[c]]);
+  const int key = mt * 16 + nt;
+  if constexpr (BUF) {
+    dispatch_quad<MAXT>(P, c, ql);
     return;
   } else {
   switch (key) {
@@ -703,6 +713,29 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t
       break;
   }
   }
+}
+
+// Several multiplications in one launch: wavefront w takes C block
+// w - start[r] of request r (start: prefix of the requests' C block counts),
+// with request r's parameters.  Every request's C blocks are computed exactly
+// as in a launch of its own, so its results are bitwise the same.
+template <int MAXT>
+__global__ __launch_bounds__(256) void k_gemm_f64_multi(const GemmP *ps, const int64_t *start, int nreq,
+                                                        int64_t nblk, int64_t per_xcd) {
+  __shared__ ParamLds lds[4];
+  ParamLds &pl = lds[threadIdx.x >> 6];
+  QuadLds &ql = *reinterpret_cast<QuadLds *>(&pl);
+  const int64_t b = blockIdx.x;
+  const int64_t lb = (b & 7) * per_xcd + (b >> 3);
+  const int64_t w = lb * 4 + (threadIdx.x >> 6);
+  if (w >= nblk) return;   // uniform per wavefront
+  int r = 0;
+  while (r + 1 < nreq && start[r + 1] <= w) r++;
+  r = __builtin_amdgcn_readfirstlane(r);
+  const GemmP &P = ps[r];
+  const int64_t lw = w - start[r];
+  const int32_t c = __builtin_amdgcn_readfirstlane(P.c_list ? P.c_list[lw] : (int32_t)lw);
+  dispatch_quad<MAXT>(P, c, ql);
 }
 
 // Work list: tiles of `tr` consecutive rows of the locality order; inside a
@@ -883,9 +916,7 @@ void build_work_list(Allocator &al, const int32_t *d_ord, const int32_t *d_rank,
   HIPCHECK(hipGetLastError());
 }
 
-void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s) {
-  if (nnzb_c <= 0) return;
-  if (max_edge > 32) fail(BSMM_ERR_UNSUPPORTED, "block size above 32");
+static GemmP make_params(const GemmArgs &g) {
   GemmP p;
   p.a_off = g.a->blk_off;
   p.a_val = g.a_cm;
@@ -906,10 +937,6 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
   p.c_norm = g.c_norm;
   p.alpha = g.alpha;
   p.beta = g.beta;
-  const int64_t nwg = (nnzb_c + 3) / 4;
-  const int64_t per_xcd = (nwg + 7) / 8;
-  const int64_t grid = per_xcd * 8;
-  if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   const bool buf = g.quads;
   if (buf) {   // quad path: packed copies (op(A) row-major, op(B) column-major, k padded to even)
     p.a_val = g.a_pack;
@@ -919,6 +946,18 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
   p.b_bytes = buf ? (uint32_t)g.b_bytes : 0u;
   p.zeros = g.zeros;
   for (int t = 0; t < 16; t++) p.variant[t] = g.variant[t];
+  return p;
+}
+
+void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s) {
+  if (nnzb_c <= 0) return;
+  if (max_edge > 32) fail(BSMM_ERR_UNSUPPORTED, "block size above 32");
+  const GemmP p = make_params(g);
+  const bool buf = g.quads;
+  const int64_t nwg = (nnzb_c + 3) / 4;
+  const int64_t per_xcd = (nwg + 7) / 8;
+  const int64_t grid = per_xcd * 8;
+  if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   if (max_edge <= 16 && buf)
     hipLaunchKernelGGL((k_gemm_f64<4, true>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
   else if (max_edge <= 16)
@@ -928,6 +967,40 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
   else
     hipLaunchKernelGGL((k_gemm_f64<8, false>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
   HIPCHECK(hipGetLastError());
+}
+
+size_t gemm_multi_stage_bytes(int n) { return sizeof(GemmP) * (size_t)n + sizeof(int64_t) * ((size_t)n + 1); }
+
+void gemm_launch_multi(Allocator &al, const std::vector<const GemmArgs *> &gs, const std::vector<int64_t> &nnzb,
+                       int max_edge, void *h_stage, size_t stage_bytes, void *d_stage, hipStream_t s) {
+  const int n = (int)gs.size();
+  if (n == 0) return;
+  if (max_edge > 32) fail(BSMM_ERR_UNSUPPORTED, "block size above 32");
+  const size_t need = sizeof(GemmP) * n + sizeof(int64_t) * (n + 1);
+  if (need > stage_bytes) fail(BSMM_ERR_UNSUPPORTED, "too many requests in one batch");
+  GemmP *hp = static_cast<GemmP *>(h_stage);
+  int64_t *hs = reinterpret_cast<int64_t *>(static_cast<char *>(h_stage) + sizeof(GemmP) * n);
+  hs[0] = 0;
+  for (int r = 0; r < n; r++) {
+    if (!gs[r]->quads) fail(BSMM_ERR_UNSUPPORTED, "batched execution needs the packed-operand path");
+    hp[r] = make_params(*gs[r]);
+    hs[r + 1] = hs[r] + std::max<int64_t>(nnzb[r], 0);
+  }
+  const int64_t total = hs[n];
+  if (total == 0) return;
+  HIPCHECK(hipMemcpyAsync(d_stage, h_stage, need, hipMemcpyHostToDevice, s));
+  const GemmP *dp = static_cast<const GemmP *>(d_stage);
+  const int64_t *ds = reinterpret_cast<const int64_t *>(static_cast<const char *>(d_stage) + sizeof(GemmP) * n);
+  const int64_t nwg = (total + 3) / 4;
+  const int64_t per_xcd = (nwg + 7) / 8;
+  const int64_t grid = per_xcd * 8;
+  if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
+  if (max_edge <= 16)
+    hipLaunchKernelGGL((k_gemm_f64_multi<4>), dim3((unsigned)grid), dim3(256), 0, s, dp, ds, n, total, per_xcd);
+  else
+    hipLaunchKernelGGL((k_gemm_f64_multi<8>), dim3((unsigned)grid), dim3(256), 0, s, dp, ds, n, total, per_xcd);
+  HIPCHECK(hipGetLastError());
+  (void)al;
 }
 
 }  // namespace bsmm

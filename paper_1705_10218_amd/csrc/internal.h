@@ -53,6 +53,9 @@ struct bsmm_ctx_s {
   bsmm::Allocator alloc;
   int64_t *pinned = nullptr;   // small host buffer for size read-backs
   uint8_t gemm_variant[16] = {};   // GEMM kernel variant per (m, n) size class
+  void *batch_host = nullptr;      // pinned staging of batched launch parameters
+  void *batch_dev = nullptr;       // device copy (reused once the stream has passed the last launch)
+  size_t batch_bytes = 0;
   double *zeros = nullptr;     // 4 KB zero page on the device
   int live_mats = 0;
 };
@@ -239,6 +242,14 @@ void transpose_blocks(const bsmm_mat_s &x, double *out, hipStream_t s);
 // a5: batched small-GEMM over the stacks, one launch over all C blocks in
 // c_list order (max_edge: largest C block edge).
 void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s);
+
+// a5 for several multiplications in one launch (packed-operand FP64 path):
+// the parameter blocks go through h_stage (pinned host) to d_stage (device),
+// both stage_bytes large; the caller keeps d_stage untouched until the
+// launch has finished.
+void gemm_launch_multi(Allocator &al, const std::vector<const GemmArgs *> &gs, const std::vector<int64_t> &nnzb,
+                       int max_edge, void *h_stage, size_t stage_bytes, void *d_stage, hipStream_t s);
+size_t gemm_multi_stage_bytes(int n);   // staging bytes for n requests
 
 // c_list = C blocks in tiles of consecutive rows of ord (device), column by
 // column inside a tile.
