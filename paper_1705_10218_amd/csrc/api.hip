@@ -242,6 +242,7 @@ struct Plan {
   OpIndex oa, ob;
   DBuf<int64_t> c_rp, c_off, seg_off, a_poff, b_poff;
   DBuf<int32_t> c_ci, c_row, old_blk, c_list;
+  DBuf<BlkDesc> desc;
   DBuf<int2> stack;
   DBuf<double> a_pack, b_pack, a_lo, b_lo, a_t, b_t, c_norm, c_values;
   GemmArgs ga;
@@ -482,6 +483,11 @@ static void plan_build(Plan &P, char transa, char transb) {
       }
     }
   }
+  // work-item descriptors of the quad path
+  if (quads && nnzb_c > 0) {
+    P.desc = DBuf<BlkDesc>(al, nc1);
+    build_desc(nnzb_c, P.c_list.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, P.desc.p, s);
+  }
   // ------------------------------------- buffers of the numeric part
   P.post = filt && !retain;
   if (P.post) P.c_norm = DBuf<double>(al, nc1);
@@ -504,6 +510,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   ga.a = &oa;
   ga.b = &ob;
   ga.c_list = P.c_list.p;
+  ga.desc = P.desc.p;
   ga.c_row = P.c_row.p;
   ga.c_ci = P.c_ci.p;
   ga.c_off = P.c_off.p;

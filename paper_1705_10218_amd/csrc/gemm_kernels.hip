@@ -43,6 +43,7 @@ struct GemmP {
   const int64_t *b_off;
   const double *b_val;   // op(B) blocks row-major
   const int32_t *c_list;
+  const BlkDesc *desc;         // work-item descriptors (quad path)
   const int32_t *c_row, *c_ci;
   const int32_t *rbs, *cbs;   // C block sizes (= op(A) rows, op(B) columns)
   const int64_t *c_off, *seg;
@@ -59,6 +60,11 @@ struct GemmP {
 };
 
 constexpr int ROUND = 256;   // products whose parameters sit in LDS at once
+// Wavefronts per workgroup of the GEMM launches: one.  The C blocks of a
+// launch take very different times (their stack segments differ by an order
+// of magnitude), and a workgroup frees its slot only when its slowest
+// wavefront ends; single-wavefront groups keep the SIMDs filled.
+constexpr int WPG = 1;
 constexpr int PF = 4;        // operand prefetch depth (k-steps)
 
 struct ParamLds {
@@ -416,7 +422,8 @@ __device__ __forceinline__ d2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 // SIXTEEN: V_MFMA_F64_16X16X4F64 on MT x NT tiles of 16 (MT, NT in {1, 2});
 // otherwise V_MFMA_F64_4X4X4F64 on MT x NT subtiles of 4 (even counts).
 template <bool SIXTEEN, int MT, int NT>
-__device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadLds &ql) {
+__device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql) {
+  const int32_t c = D.c;
   constexpr int HM = SIXTEEN ? MT : MT / 2, HN = SIXTEEN ? NT : NT / 2;
   // two accumulator sets (the two k-steps of a pair) when a step has a single
   // MFMA chain: a dependent FP64 MFMA waits for the previous result
@@ -426,8 +433,8 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
   constexpr int PF2 = (HM + HN > 3) ? 2 : 3;
   const int lane = threadIdx.x & 63;
   // one C block per wavefront: its sizes are uniform (scalar registers)
-  const int m = __builtin_amdgcn_readfirstlane(P.rbs[P.c_row[c]]);
-  const int n = __builtin_amdgcn_readfirstlane(P.cbs[P.c_ci[c]]);
+  const int m = D.mn & 0xffff;
+  const int n = D.mn >> 16;
   const int m16 = 16 * m, n16 = 16 * n;   // bytes of one k-pair slab of op(A) / op(B)
   const int kq = lane >> 4;
   // lane's rows of op(A) / columns of op(B) (-1 if padding)
@@ -463,7 +470,7 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
     for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[h][t] = 0.0;
   }
 
-  const int64_t s0 = P.seg[c], s1 = P.seg[c + 1];
+  const int64_t s0 = D.s0, s1 = D.s0 + D.ns;
   for (int64_t rbase = s0; rbase < s1; rbase += ROUND) {
     const int nr = (int)min<int64_t>(ROUND, s1 - rbase);   // multiple of 4
     const int nq = nr >> 2;
@@ -584,7 +591,7 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, int32_t c, QuadL
 #pragma unroll
     for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[0][t] += acc[NC - 1][t];
   }
-  const int64_t co = P.c_off[c];
+  const int64_t co = D.co;
   const double *old = old_block(P, c);
   double ss = 0.0;
   if (SIXTEEN) {
@@ -621,12 +628,27 @@ __device__ __forceinline__ int edge_tiles(int e) { return ((((e + 3) >> 2) + 1) 
 // that each of the 8 XCDs (ids are dealt to XCDs round-robin) walks one
 // contiguous stretch of the order, keeping its L2 on a compact region.
 // MAXT bounds the subtile counts compiled in (4: blocks up to 16).
+// A work item's descriptor in scalar registers (the index is uniform).
+__device__ __forceinline__ BlkDesc load_desc(const BlkDesc *desc, int64_t w) {
+  const BlkDesc *d = desc + __builtin_amdgcn_readfirstlane((int)w);
+  BlkDesc r;
+  r.c = __builtin_amdgcn_readfirstlane(d->c);
+  r.mn = __builtin_amdgcn_readfirstlane(d->mn);
+  r.s0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(d->s0 >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)d->s0);
+  r.co = ((int64_t)__builtin_amdgcn_readfirstlane((int)(d->co >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)d->co);
+  r.ns = __builtin_amdgcn_readfirstlane(d->ns);
+  r.pad = 0;
+  return r;
+}
+
 // Quad-path dispatch of one C block on its (m, n) class and the class's
 // kernel variant.
 template <int MAXT>
-__device__ __forceinline__ void dispatch_quad(const GemmP &P, int32_t c, QuadLds &ql) {
-  const int mt = edge_tiles(P.rbs[P.c_row[c]]);
-  const int nt = edge_tiles(P.cbs[P.c_ci[c]]);
+__device__ __forceinline__ void dispatch_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql) {
+  const int mt = edge_tiles(D.mn & 0xffff);
+  const int nt = edge_tiles(D.mn >> 16);
   const int key = mt * 16 + nt;
     // kernel variant of this (m, n) class: 0 = default (16x16 tile when both
     // edges are in 9..16, else 4x4 subtiles), 1 = 16x16 tiles, 2 = 4x4 subtiles
@@ -634,59 +656,60 @@ __device__ __forceinline__ void dispatch_quad(const GemmP &P, int32_t c, QuadLds
     if (vid == 1 || (vid == 0 && mt == 4 && nt == 4)) {
       const int tm = mt <= 4 ? 1 : 2, tn = nt <= 4 ? 1 : 2;
       if (tm == 1 && tn == 1) {
-        gemm_block_quad<true, 1, 1>(P, c, ql);
+        gemm_block_quad<true, 1, 1>(P, D, ql);
         return;
       }
       if constexpr (MAXT > 4) {
-        if (tm == 1) gemm_block_quad<true, 1, 2>(P, c, ql);
-        else if (tn == 1) gemm_block_quad<true, 2, 1>(P, c, ql);
-        else gemm_block_quad<true, 2, 2>(P, c, ql);
+        if (tm == 1) gemm_block_quad<true, 1, 2>(P, D, ql);
+        else if (tn == 1) gemm_block_quad<true, 2, 1>(P, D, ql);
+        else gemm_block_quad<true, 2, 2>(P, D, ql);
       }
       return;
     }
     switch (key) {
-      case 2 * 16 + 2: gemm_block_quad<false, 2, 2>(P, c, ql); return;
-      case 2 * 16 + 4: gemm_block_quad<false, 2, 4>(P, c, ql); return;
-      case 4 * 16 + 2: gemm_block_quad<false, 4, 2>(P, c, ql); return;
-      case 4 * 16 + 4: gemm_block_quad<false, 4, 4>(P, c, ql); return;
+      case 2 * 16 + 2: gemm_block_quad<false, 2, 2>(P, D, ql); return;
+      case 2 * 16 + 4: gemm_block_quad<false, 2, 4>(P, D, ql); return;
+      case 4 * 16 + 2: gemm_block_quad<false, 4, 2>(P, D, ql); return;
+      case 4 * 16 + 4: gemm_block_quad<false, 4, 4>(P, D, ql); return;
       default: break;
     }
     if constexpr (MAXT > 4) {
       switch (key) {
-        case 2 * 16 + 6: gemm_block_quad<false, 2, 6>(P, c, ql); return;
-        case 2 * 16 + 8: gemm_block_quad<false, 2, 8>(P, c, ql); return;
-        case 4 * 16 + 6: gemm_block_quad<false, 4, 6>(P, c, ql); return;
-        case 4 * 16 + 8: gemm_block_quad<false, 4, 8>(P, c, ql); return;
-        case 6 * 16 + 2: gemm_block_quad<false, 6, 2>(P, c, ql); return;
-        case 6 * 16 + 4: gemm_block_quad<false, 6, 4>(P, c, ql); return;
-        case 6 * 16 + 6: gemm_block_quad<false, 6, 6>(P, c, ql); return;
-        case 6 * 16 + 8: gemm_block_quad<false, 6, 8>(P, c, ql); return;
-        case 8 * 16 + 2: gemm_block_quad<false, 8, 2>(P, c, ql); return;
-        case 8 * 16 + 4: gemm_block_quad<false, 8, 4>(P, c, ql); return;
-        case 8 * 16 + 6: gemm_block_quad<false, 8, 6>(P, c, ql); return;
-        case 8 * 16 + 8: gemm_block_quad<false, 8, 8>(P, c, ql); return;
+        case 2 * 16 + 6: gemm_block_quad<false, 2, 6>(P, D, ql); return;
+        case 2 * 16 + 8: gemm_block_quad<false, 2, 8>(P, D, ql); return;
+        case 4 * 16 + 6: gemm_block_quad<false, 4, 6>(P, D, ql); return;
+        case 4 * 16 + 8: gemm_block_quad<false, 4, 8>(P, D, ql); return;
+        case 6 * 16 + 2: gemm_block_quad<false, 6, 2>(P, D, ql); return;
+        case 6 * 16 + 4: gemm_block_quad<false, 6, 4>(P, D, ql); return;
+        case 6 * 16 + 6: gemm_block_quad<false, 6, 6>(P, D, ql); return;
+        case 6 * 16 + 8: gemm_block_quad<false, 6, 8>(P, D, ql); return;
+        case 8 * 16 + 2: gemm_block_quad<false, 8, 2>(P, D, ql); return;
+        case 8 * 16 + 4: gemm_block_quad<false, 8, 4>(P, D, ql); return;
+        case 8 * 16 + 6: gemm_block_quad<false, 8, 6>(P, D, ql); return;
+        case 8 * 16 + 8: gemm_block_quad<false, 8, 8>(P, D, ql); return;
         default: break;
       }
     }
 }
 
 template <int MAXT, bool BUF>
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t per_xcd) {
-  __shared__ ParamLds lds[4];
+__global__ __launch_bounds__(64 * WPG) void k_gemm_f64(GemmP P, int64_t nblk, int64_t per_xcd) {
+  __shared__ ParamLds lds[WPG];
   ParamLds &pl = lds[threadIdx.x >> 6];
   QuadLds &ql = *reinterpret_cast<QuadLds *>(&pl);
   const int64_t b = blockIdx.x;
   const int64_t lb = (b & 7) * per_xcd + (b >> 3);
-  const int64_t w = lb * 4 + (threadIdx.x >> 6);
+  const int64_t w = lb * WPG + (threadIdx.x >> 6);
   if (w >= nblk) return;   // uniform per wavefront
+  if constexpr (BUF) {
+    const BlkDesc D = load_desc(P.desc, w);
+    dispatch_quad<MAXT>(P, D, ql);
+    return;
+  } else {
   const int32_t c = __builtin_amdgcn_readfirstlane(P.c_list ? P.c_list[w] : (int32_t)w);
   const int mt = edge_tiles(P.rbs[P.c_row[c]]);
   const int nt = edge_tiles(P.cbs[P.c_ci[c]]);
   const int key = mt * 16 + nt;
-  if constexpr (BUF) {
-    dispatch_quad<MAXT>(P, c, ql);
-    return;
-  } else {
   switch (key) {
     case 2 * 16 + 2: gemm_block_44<BUF, 2, 2>(P, c, pl); break;
     case 2 * 16 + 4: gemm_block_44<BUF, 2, 4>(P, c, pl); break;
@@ -720,22 +743,22 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmP P, int64_t nblk, int64_t
 // with request r's parameters.  Every request's C blocks are computed exactly
 // as in a launch of its own, so its results are bitwise the same.
 template <int MAXT>
-__global__ __launch_bounds__(256) void k_gemm_f64_multi(const GemmP *ps, const int64_t *start, int nreq,
+__global__ __launch_bounds__(64 * WPG) void k_gemm_f64_multi(const GemmP *ps, const int64_t *start, int nreq,
                                                         int64_t nblk, int64_t per_xcd) {
-  __shared__ ParamLds lds[4];
+  __shared__ ParamLds lds[WPG];
   ParamLds &pl = lds[threadIdx.x >> 6];
   QuadLds &ql = *reinterpret_cast<QuadLds *>(&pl);
   const int64_t b = blockIdx.x;
   const int64_t lb = (b & 7) * per_xcd + (b >> 3);
-  const int64_t w = lb * 4 + (threadIdx.x >> 6);
+  const int64_t w = lb * WPG + (threadIdx.x >> 6);
   if (w >= nblk) return;   // uniform per wavefront
   int r = 0;
   while (r + 1 < nreq && start[r + 1] <= w) r++;
   r = __builtin_amdgcn_readfirstlane(r);
   const GemmP &P = ps[r];
   const int64_t lw = w - start[r];
-  const int32_t c = __builtin_amdgcn_readfirstlane(P.c_list ? P.c_list[lw] : (int32_t)lw);
-  dispatch_quad<MAXT>(P, c, ql);
+  const BlkDesc D = load_desc(P.desc, lw);
+  dispatch_quad<MAXT>(P, D, ql);
 }
 
 // Work list: tiles of `tr` consecutive rows of the locality order; inside a
@@ -871,7 +894,31 @@ __global__ __launch_bounds__(256) void k_pack_blocks(const int64_t *rp, const in
   }
 }
 
+__global__ void k_build_desc(int64_t n, const int32_t *c_list, const int32_t *c_row, const int32_t *c_ci,
+                             const int32_t *rbs, const int32_t *cbs, const int64_t *seg, const int64_t *c_off,
+                             BlkDesc *desc) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n) return;
+  const int32_t c = c_list ? c_list[w] : (int32_t)w;
+  BlkDesc d;
+  d.c = c;
+  d.mn = rbs[c_row[c]] | (cbs[c_ci[c]] << 16);
+  d.s0 = seg[c];
+  d.ns = (int32_t)(seg[c + 1] - seg[c]);
+  d.co = c_off[c];
+  d.pad = 0;
+  desc[w] = d;
+}
+
 }  // namespace
+
+void build_desc(int64_t n, const int32_t *c_list, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
+                const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_build_desc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, c_list, c_row, c_ci, rbs,
+                     cbs, seg, c_off, desc);
+  HIPCHECK(hipGetLastError());
+}
 
 void pack_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_poff, hipStream_t s) {
   if (x.nnzb == 0) {
@@ -923,6 +970,7 @@ static GemmP make_params(const GemmArgs &g) {
   p.b_off = g.b->blk_off;
   p.b_val = g.b_rm;
   p.c_list = g.c_list;
+  p.desc = g.desc;
   p.c_row = g.c_row;
   p.c_ci = g.c_ci;
   p.rbs = g.a->rbs;
@@ -954,18 +1002,18 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
   if (max_edge > 32) fail(BSMM_ERR_UNSUPPORTED, "block size above 32");
   const GemmP p = make_params(g);
   const bool buf = g.quads;
-  const int64_t nwg = (nnzb_c + 3) / 4;
+  const int64_t nwg = (nnzb_c + WPG - 1) / WPG;
   const int64_t per_xcd = (nwg + 7) / 8;
   const int64_t grid = per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   if (max_edge <= 16 && buf)
-    hipLaunchKernelGGL((k_gemm_f64<4, true>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64<4, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   else if (max_edge <= 16)
-    hipLaunchKernelGGL((k_gemm_f64<4, false>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64<4, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   else if (buf)
-    hipLaunchKernelGGL((k_gemm_f64<8, true>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64<8, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   else
-    hipLaunchKernelGGL((k_gemm_f64<8, false>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64<8, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   HIPCHECK(hipGetLastError());
 }
 
@@ -991,14 +1039,14 @@ void gemm_launch_multi(Allocator &al, const std::vector<const GemmArgs *> &gs, c
   HIPCHECK(hipMemcpyAsync(d_stage, h_stage, need, hipMemcpyHostToDevice, s));
   const GemmP *dp = static_cast<const GemmP *>(d_stage);
   const int64_t *ds = reinterpret_cast<const int64_t *>(static_cast<const char *>(d_stage) + sizeof(GemmP) * n);
-  const int64_t nwg = (total + 3) / 4;
+  const int64_t nwg = (total + WPG - 1) / WPG;
   const int64_t per_xcd = (nwg + 7) / 8;
   const int64_t grid = per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   if (max_edge <= 16)
-    hipLaunchKernelGGL((k_gemm_f64_multi<4>), dim3((unsigned)grid), dim3(256), 0, s, dp, ds, n, total, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64_multi<4>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, per_xcd);
   else
-    hipLaunchKernelGGL((k_gemm_f64_multi<8>), dim3((unsigned)grid), dim3(256), 0, s, dp, ds, n, total, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64_multi<8>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, per_xcd);
   HIPCHECK(hipGetLastError());
   (void)al;
 }

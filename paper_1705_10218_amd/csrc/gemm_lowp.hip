@@ -39,6 +39,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr uint32_t QOOB = 0x80000000u;
 constexpr int ROUND = 256;
 constexpr int PF = 2;   // k-quad slabs in flight
+constexpr int WPG = 1;  // wavefronts per workgroup (see the FP64 kernel)
 
 struct LowpP {
   const float *a_hi, *a_lo, *b_hi, *b_lo;   // packed slabs (lo only for SPLIT)
@@ -264,12 +265,12 @@ __device__ __forceinline__ void gemm_block_lowp(const LowpP &P, int32_t c, QuadL
 // BIG: C edges up to 32 (tiles 2x2 compiled in); otherwise up to 16, so the
 // register budget (and occupancy) is that of the single-tile case.
 template <bool SPLIT, bool BIG>
-__global__ __launch_bounds__(256) void k_gemm_lowp(LowpP P, int64_t nblk, int64_t per_xcd) {
-  __shared__ QuadLds lds[4];
+__global__ __launch_bounds__(64 * WPG) void k_gemm_lowp(LowpP P, int64_t nblk, int64_t per_xcd) {
+  __shared__ QuadLds lds[WPG];
   QuadLds &ql = lds[threadIdx.x >> 6];
   const int64_t b = blockIdx.x;
   const int64_t lb = (b & 7) * per_xcd + (b >> 3);
-  const int64_t w = lb * 4 + (threadIdx.x >> 6);
+  const int64_t w = lb * WPG + (threadIdx.x >> 6);
   if (w >= nblk) return;   // uniform per wavefront
   const int32_t c = __builtin_amdgcn_readfirstlane(P.c_list ? P.c_list[w] : (int32_t)w);
   if constexpr (!BIG) {
@@ -369,19 +370,19 @@ void gemm_launch_lowp(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream
   p.c_norm = g.c_norm;
   p.alpha = g.alpha;
   p.beta = g.beta;
-  const int64_t nwg = (nnzb_c + 3) / 4;
+  const int64_t nwg = (nnzb_c + WPG - 1) / WPG;
   const int64_t per_xcd = (nwg + 7) / 8;
   const int64_t grid = per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   const bool split = g.mode == BSMM_COMPUTE_SPLIT, big = max_edge > 16;
   if (split && big)
-    hipLaunchKernelGGL((k_gemm_lowp<true, true>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_lowp<true, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   else if (split)
-    hipLaunchKernelGGL((k_gemm_lowp<true, false>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_lowp<true, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   else if (big)
-    hipLaunchKernelGGL((k_gemm_lowp<false, true>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_lowp<false, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   else
-    hipLaunchKernelGGL((k_gemm_lowp<false, false>), dim3((unsigned)grid), dim3(256), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_lowp<false, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   HIPCHECK(hipGetLastError());
 }
 

@@ -191,9 +191,21 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s);
 void old_block_map(const int64_t *cold_rp, const int32_t *cold_ci, int32_t nbr, const int64_t *c_rp,
                    const int32_t *c_ci, int32_t *old_blk, hipStream_t s);
 
+// Per work item of the GEMM (one C block, in work-list order): everything a
+// wavefront needs before its first stack round, in one 32-byte record.
+struct alignas(32) BlkDesc {
+  int32_t c;    // C block id
+  int32_t mn;   // m | n << 16 (block edges)
+  int64_t s0;   // first stack entry of the block's segment
+  int64_t co;   // value offset of the C block
+  int32_t ns;   // stack entries of the segment
+  int32_t pad;
+};
+
 struct GemmArgs {
   const OpIndex *a, *b;
   const int32_t *c_list = nullptr;   // C blocks ordered by class
+  const BlkDesc *desc = nullptr;     // work-item descriptors (quad path)
   const int32_t *c_row = nullptr;
   const int32_t *c_ci = nullptr;
   const int64_t *c_off = nullptr;    // value offsets of C blocks
@@ -250,6 +262,10 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
 void gemm_launch_multi(Allocator &al, const std::vector<const GemmArgs *> &gs, const std::vector<int64_t> &nnzb,
                        int max_edge, void *h_stage, size_t stage_bytes, void *d_stage, hipStream_t s);
 size_t gemm_multi_stage_bytes(int n);   // staging bytes for n requests
+
+// desc[w] for the work items w < n (C block c_list[w], or w without a list).
+void build_desc(int64_t n, const int32_t *c_list, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
+                const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s);
 
 // c_list = C blocks in tiles of consecutive rows of ord (device), column by
 // column inside a tile.
