@@ -377,6 +377,9 @@ static void plan_build(Plan &P, char transa, char transb) {
     HIPCHECK(hipMemsetAsync(cnt_g.p, 0, sizeof(int32_t) * nc1 * ksizes.size(), s));
   }
   HIPCHECK(hipMemsetAsync(c_cnt.p, 0, sizeof(int32_t) * nc1, s));
+  // start of every k-size run inside its segment (quad path)
+  DBuf<int32_t> kofs;
+  if (quads) kofs = DBuf<int32_t>(al, nc1 * ksizes.size());
   FillArgs fa;
   fa.sym = sym;
   fa.c_rp = P.c_rp.p;
@@ -390,6 +393,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   fa.pad4 = quads;
   fa.ksizes = ksizes;
   fa.cnt_g = cnt_g.p;
+  fa.kofs = kofs.p;
   fa.na = filt ? na.p : nullptr;
   fa.nb = filt ? nb.p : nullptr;
   fa.eps = eps;
@@ -442,10 +446,13 @@ static void plan_build(Plan &P, char transa, char transb) {
   // ------------------------------------------------------- a4: stacks
   P.stack = DBuf<int2>(al, (size_t)std::max<int64_t>(P.nstack, 1));
   {
+    // rows wider than the stack generator's LDS cursors use global cursors,
+    // one per (C block, k-size run)
     DBuf<int32_t> run;
-    if (max_row > 8192) {
-      run = DBuf<int32_t>(al, nc1);
-      HIPCHECK(hipMemsetAsync(run.p, 0, sizeof(int32_t) * nc1, s));
+    if (max_row > 4096) {
+      const size_t nr = nc1 * (quads ? ksizes.size() : 1);
+      run = DBuf<int32_t>(al, nr);
+      HIPCHECK(hipMemsetAsync(run.p, 0, sizeof(int32_t) * nr, s));
     }
     StackArgs sa;
     sa.a = &oa;
@@ -463,6 +470,7 @@ static void plan_build(Plan &P, char transa, char transb) {
     sa.ksizes = ksizes;
     sa.pad4 = quads;
     sa.encode = quads;
+    sa.kofs = kofs.p;
     sa.a_poff = P.a_poff.p;
     sa.b_poff = P.b_poff.p;
     if (P.nprod > 0) stack_fill(sa, run.p, s);

@@ -398,16 +398,20 @@ struct QuadLds {
   int32_t Kq[ROUND / 4];
 };
 
-__device__ __forceinline__ void load_quads(const GemmP &P, QuadLds &ql, int64_t rb, int nr, int lane) {
+// Stack entry q of the round into the parameter LDS.
+__device__ __forceinline__ void stage_entry(QuadLds &ql, int q, int2 e) {
   // entries: byte offsets of the two packed blocks with (k - 1) in their low
   // 3 + 2 bits; nulls are QOOB (a quad's first entry is never null)
-  for (int q = lane; q < nr; q += 64) {
-    const int2 e = P.stack[rb + q];
-    const uint32_t oa = (uint32_t)e.x, ob = (uint32_t)e.y;
-    ql.oa[q] = oa & ~7u;
-    ql.ob[q] = ob & ~7u;
-    if ((q & 3) == 0) ql.Kq[q >> 2] = (int)((oa & 7u) | ((ob & 7u) << 3)) + 1;
-  }
+  const uint32_t oa = (uint32_t)e.x, ob = (uint32_t)e.y;
+  ql.oa[q] = oa & ~7u;
+  ql.ob[q] = ob & ~7u;
+  if ((q & 3) == 0) ql.Kq[q >> 2] = (int)((oa & 7u) | ((ob & 7u) << 3)) + 1;
+}
+
+// Entries [from, nr) of the round starting at rb (those below `from` are
+// already staged).
+__device__ __forceinline__ void load_quads(const GemmP &P, QuadLds &ql, int64_t rb, int nr, int lane, int from = 0) {
+  for (int q = from + lane; q < nr; q += 64) stage_entry(ql, q, P.stack[rb + q]);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -422,7 +426,7 @@ __device__ __forceinline__ d2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 // SIXTEEN: V_MFMA_F64_16X16X4F64 on MT x NT tiles of 16 (MT, NT in {1, 2});
 // otherwise V_MFMA_F64_4X4X4F64 on MT x NT subtiles of 4 (even counts).
 template <bool SIXTEEN, int MT, int NT>
-__device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql) {
+__device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql, int pre = 0) {
   const int32_t c = D.c;
   constexpr int HM = SIXTEEN ? MT : MT / 2, HN = SIXTEEN ? NT : NT / 2;
   // two accumulator sets (the two k-steps of a pair) when a step has a single
@@ -474,7 +478,7 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
   for (int64_t rbase = s0; rbase < s1; rbase += ROUND) {
     const int nr = (int)min<int64_t>(ROUND, s1 - rbase);   // multiple of 4
     const int nq = nr >> 2;
-    load_quads(P, ql, rbase, nr, lane);
+    load_quads(P, ql, rbase, nr, lane, rbase == s0 ? pre : 0);
     // total pairs of the round
     int steps = 0;
     for (int q = lane; q < nq; q += 64) steps += (ql.Kq[q] + 1) >> 1;
@@ -646,7 +650,7 @@ __device__ __forceinline__ BlkDesc load_desc(const BlkDesc *desc, int64_t w) {
 // Quad-path dispatch of one C block on its (m, n) class and the class's
 // kernel variant.
 template <int MAXT>
-__device__ __forceinline__ void dispatch_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql) {
+__device__ __forceinline__ void dispatch_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql, int pre = 0) {
   const int mt = edge_tiles(D.mn & 0xffff);
   const int nt = edge_tiles(D.mn >> 16);
   const int key = mt * 16 + nt;
@@ -656,37 +660,37 @@ __device__ __forceinline__ void dispatch_quad(const GemmP &P, const BlkDesc &D, 
     if (vid == 1 || (vid == 0 && mt == 4 && nt == 4)) {
       const int tm = mt <= 4 ? 1 : 2, tn = nt <= 4 ? 1 : 2;
       if (tm == 1 && tn == 1) {
-        gemm_block_quad<true, 1, 1>(P, D, ql);
+        gemm_block_quad<true, 1, 1>(P, D, ql, pre);
         return;
       }
       if constexpr (MAXT > 4) {
-        if (tm == 1) gemm_block_quad<true, 1, 2>(P, D, ql);
-        else if (tn == 1) gemm_block_quad<true, 2, 1>(P, D, ql);
-        else gemm_block_quad<true, 2, 2>(P, D, ql);
+        if (tm == 1) gemm_block_quad<true, 1, 2>(P, D, ql, pre);
+        else if (tn == 1) gemm_block_quad<true, 2, 1>(P, D, ql, pre);
+        else gemm_block_quad<true, 2, 2>(P, D, ql, pre);
       }
       return;
     }
     switch (key) {
-      case 2 * 16 + 2: gemm_block_quad<false, 2, 2>(P, D, ql); return;
-      case 2 * 16 + 4: gemm_block_quad<false, 2, 4>(P, D, ql); return;
-      case 4 * 16 + 2: gemm_block_quad<false, 4, 2>(P, D, ql); return;
-      case 4 * 16 + 4: gemm_block_quad<false, 4, 4>(P, D, ql); return;
+      case 2 * 16 + 2: gemm_block_quad<false, 2, 2>(P, D, ql, pre); return;
+      case 2 * 16 + 4: gemm_block_quad<false, 2, 4>(P, D, ql, pre); return;
+      case 4 * 16 + 2: gemm_block_quad<false, 4, 2>(P, D, ql, pre); return;
+      case 4 * 16 + 4: gemm_block_quad<false, 4, 4>(P, D, ql, pre); return;
       default: break;
     }
     if constexpr (MAXT > 4) {
       switch (key) {
-        case 2 * 16 + 6: gemm_block_quad<false, 2, 6>(P, D, ql); return;
-        case 2 * 16 + 8: gemm_block_quad<false, 2, 8>(P, D, ql); return;
-        case 4 * 16 + 6: gemm_block_quad<false, 4, 6>(P, D, ql); return;
-        case 4 * 16 + 8: gemm_block_quad<false, 4, 8>(P, D, ql); return;
-        case 6 * 16 + 2: gemm_block_quad<false, 6, 2>(P, D, ql); return;
-        case 6 * 16 + 4: gemm_block_quad<false, 6, 4>(P, D, ql); return;
-        case 6 * 16 + 6: gemm_block_quad<false, 6, 6>(P, D, ql); return;
-        case 6 * 16 + 8: gemm_block_quad<false, 6, 8>(P, D, ql); return;
-        case 8 * 16 + 2: gemm_block_quad<false, 8, 2>(P, D, ql); return;
-        case 8 * 16 + 4: gemm_block_quad<false, 8, 4>(P, D, ql); return;
-        case 8 * 16 + 6: gemm_block_quad<false, 8, 6>(P, D, ql); return;
-        case 8 * 16 + 8: gemm_block_quad<false, 8, 8>(P, D, ql); return;
+        case 2 * 16 + 6: gemm_block_quad<false, 2, 6>(P, D, ql, pre); return;
+        case 2 * 16 + 8: gemm_block_quad<false, 2, 8>(P, D, ql, pre); return;
+        case 4 * 16 + 6: gemm_block_quad<false, 4, 6>(P, D, ql, pre); return;
+        case 4 * 16 + 8: gemm_block_quad<false, 4, 8>(P, D, ql, pre); return;
+        case 6 * 16 + 2: gemm_block_quad<false, 6, 2>(P, D, ql, pre); return;
+        case 6 * 16 + 4: gemm_block_quad<false, 6, 4>(P, D, ql, pre); return;
+        case 6 * 16 + 6: gemm_block_quad<false, 6, 6>(P, D, ql, pre); return;
+        case 6 * 16 + 8: gemm_block_quad<false, 6, 8>(P, D, ql, pre); return;
+        case 8 * 16 + 2: gemm_block_quad<false, 8, 2>(P, D, ql, pre); return;
+        case 8 * 16 + 4: gemm_block_quad<false, 8, 4>(P, D, ql, pre); return;
+        case 8 * 16 + 6: gemm_block_quad<false, 8, 6>(P, D, ql, pre); return;
+        case 8 * 16 + 8: gemm_block_quad<false, 8, 8>(P, D, ql, pre); return;
         default: break;
       }
     }

@@ -156,6 +156,8 @@ struct FillArgs {
   bool pad4 = false;               // pad every equal-k-size run of a segment to 4 entries
   std::vector<int32_t> ksizes;     // distinct k block sizes, ascending (when pad4)
   int32_t *cnt_g = nullptr;        // nnzb_C * |ksizes| zeroed counters for wide rows
+  int32_t *kofs = nullptr;         // out (when pad4): start of every k-size run inside its
+                                   // C block's segment, nnzb_C * |ksizes| entries
   const double *na = nullptr, *nb = nullptr;   // block norms (null when eps == 0)
   double eps = 0.0;
   int32_t max_row = 0;
@@ -178,6 +180,7 @@ struct StackArgs {
   std::vector<int32_t> ksizes;       // distinct k block sizes, ascending
   bool pad4 = false;                 // pad every equal-k-size run to 4 entries (null = -1)
   bool encode = false;               // entries = byte offsets | (k-1) bits (quad path), null = 0x80000000
+  const int32_t *kofs = nullptr;     // k-size run starts inside each segment (pad4)
   const int64_t *a_poff = nullptr;   // packed block offsets used by the encoded entries
   const int64_t *b_poff = nullptr;
 };

@@ -161,7 +161,8 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
                                                           int32_t *c_row, int64_t *c_size, int32_t *c_cnt,
                                                           int64_t *row_kmn, int64_t *row_cand, int64_t *row_real,
                                                           const double *na, const double *nb, double eps,
-                                                          int32_t cnt_cap, KSizes ksz, int nkp, int32_t *cnt_g) {
+                                                          int32_t cnt_cap, KSizes ksz, int nkp, int32_t *cnt_g,
+                                                          int32_t *kofs) {
   extern __shared__ uint32_t sm[];
   __shared__ int32_t shi[SYM_THREADS / 64];
   __shared__ int64_t shl[SYM_THREADS / 64];
@@ -248,6 +249,7 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
     int32_t tot_real = 0, tot_pad = 0;
     for (int kx = 0; kx < nk1; kx++) {
       const int32_t v = lds_cnt ? cnt[t * nk1 + kx] : gcnt[t * nk1 + kx];
+      if (kofs) kofs[(cbase + t) * nk1 + kx] = tot_pad;   // this k size's run starts here
       tot_real += v;
       tot_pad += nkp > 0 ? (v + 3) & ~3 : v;
     }
@@ -281,24 +283,34 @@ __global__ void k_old_map(const int64_t *cold_rp, const int32_t *cold_ci, const 
 // j appears once per k, so the per-C-block write cursors never collide
 // inside one step, and successive steps are ordered: every C block's
 // segment comes out sorted by k, identically on every run.
+// One wavefront per (C block row, k size): the k-size runs of a segment are
+// independent (their starts come from the symbolic phase), so the passes of
+// a row run side by side.  Inside a run, products are written in ascending k
+// through a per-C-block cursor in LDS; the run's start offsets (relative to
+// the row's first segment) are staged in LDS too, so a product costs one
+// global load of its B column index on the dependent path.
 __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t nbc, const int64_t *c_rp,
-                                                   const int32_t *c_ci, const int64_t *seg_off, int2 *stack,
-                                                   const double *na, const double *nb, double eps,
-                                                   int32_t cnt_cap, int32_t *run, KSizes ksz, int nks, int pad4,
-                                                   int enc) {
+                                                   const int32_t *c_ci, const int64_t *seg_off,
+                                                   const int32_t *kofs, int2 *stack, const double *na,
+                                                   const double *nb, double eps, int32_t cnt_cap, int32_t *run,
+                                                   KSizes ksz, int nks, int pad4, int enc) {
   extern __shared__ uint32_t sm[];
-  int32_t i = blockIdx.x;
-  int lane = threadIdx.x;
-  int32_t words_total = (nbc + 31) >> 5;
-  int32_t W = min(words_total, MAX_WORDS);
-  bool lds_slot = words_total <= MAX_WORDS;
+  const int32_t i = blockIdx.x;
+  const int pass = blockIdx.y;   // k-size index (0 when nks == 0)
+  const int lane = threadIdx.x;
+  const int32_t words_total = (nbc + 31) >> 5;
+  const int32_t W = min(words_total, MAX_WORDS);
+  const bool lds_slot = words_total <= MAX_WORDS;
   const int64_t cbase = c_rp[i];
   const int32_t R = (int32_t)(c_rp[i + 1] - cbase);
   if (R == 0) return;
-  bool lds_cnt = R <= cnt_cap;
+  const bool lds_cnt = R <= cnt_cap;
+  const int nk1 = nks > 0 ? nks : 1;
   uint32_t *bm = sm;
   int32_t *pre = reinterpret_cast<int32_t *>(sm + W);
   int32_t *cnt = pre + W;
+  int32_t *sbase = cnt + (lds_cnt ? R : 0);
+  const int64_t row0 = seg_off[cbase];
   if (lds_slot) {
     for (int32_t t = lane; t < W; t += 64) bm[t] = 0u;
     __syncthreads();
@@ -322,51 +334,64 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
     }
   }
   if (lds_cnt)
-    for (int32_t t = lane; t < R; t += 64) cnt[t] = 0;
+    for (int32_t t = lane; t < R; t += 64) {
+      cnt[t] = 0;
+      sbase[t] = (int32_t)(seg_off[cbase + t] - row0) + (kofs ? kofs[(cbase + t) * nk1 + pass] : 0);
+    }
   __syncthreads();
-  // one pass per distinct k block size (ascending): every C block's segment
-  // is grouped by k size, ascending k inside a group, so the GEMM can run
-  // products of equal k size in lockstep
-  const int npass = nks > 0 ? nks : 1;
-  for (int pass = 0; pass < npass; pass++) {
+  int32_t *gcur = run ? run + cbase * nk1 : nullptr;   // wide rows: global cursors per (slot, pass)
   for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) {
-    int32_t k = A.ci[p];
+    const int32_t k = A.ci[p];
     if (nks > 0 && A.cbs[k] != ksz.v[pass]) continue;
-    int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
-    double nA = na ? na[ablk] : 0.0;
-    int64_t q1 = B.rp[k + 1];
+    const int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
+    const double nA = na ? na[ablk] : 0.0;
+    const uint32_t ea = enc ? ((uint32_t)(A.off[ablk] * 8) | (uint32_t)((A.cbs[k] - 1) & 7)) : (uint32_t)ablk;
+    const uint32_t kb = enc ? (uint32_t)((A.cbs[k] - 1) >> 3) : 0u;
+    const int64_t q1 = B.rp[k + 1];
     for (int64_t q = B.rp[k] + lane; q < q1; q += 64) {
-      int32_t j = B.ci[q];
-      int32_t bblk = B.blk ? B.blk[q] : (int32_t)q;
+      const int32_t j = B.ci[q];
+      const int32_t bblk = B.blk ? B.blk[q] : (int32_t)q;
       if (na && (nA * nb[bblk] < eps)) continue;
       int32_t slot;
       if (lds_slot) slot = bm_test(bm, j) ? bm_slot(bm, pre, j) : -1;
       else slot = bsearch_slot(c_ci, cbase, cbase + R, j);
       if (slot < 0) continue;
-      int32_t at;
-      if (lds_cnt) { at = cnt[slot]; cnt[slot] = at + 1; }
-      else at = atomicAdd(&run[cbase + slot], 1);
-      if (enc)   // byte offsets of the two blocks, k size - 1 in their low 3 + 2 bits
-        stack[seg_off[cbase + slot] + at] =
-            make_int2((int)((uint32_t)(A.off[ablk] * 8) | (uint32_t)((A.cbs[k] - 1) & 7)),
-                      (int)((uint32_t)(B.off[bblk] * 8) | (uint32_t)((A.cbs[k] - 1) >> 3)));
+      int64_t pos;
+      if (lds_cnt) {
+        const int32_t at = cnt[slot];
+        cnt[slot] = at + 1;
+        pos = row0 + sbase[slot] + at;
+      } else {
+        const int32_t at = atomicAdd(&gcur[slot * nk1 + pass], 1);
+        pos = seg_off[cbase + slot] + (kofs ? kofs[(cbase + slot) * nk1 + pass] : 0) + at;
+      }
+      if (enc)   // byte offsets of the two packed blocks, k size - 1 in their low 3 + 2 bits
+        stack[pos] = make_int2((int)ea, (int)((uint32_t)(B.off[bblk] * 8) | kb));
       else
-        stack[seg_off[cbase + slot] + at] = make_int2(ablk, bblk);
+        stack[pos] = make_int2((int)ea, bblk);
     }
-    __syncthreads();
+    // no barrier: one wavefront, whose LDS accesses complete in program
+    // order, so the cursor updates of this k precede the next k's reads
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (pad4) {
     // close this k size: pad every C block's run to a multiple of 4 entries
     for (int32_t t = lane; t < R; t += 64) {
-      int32_t at = lds_cnt ? cnt[t] : atomicAdd(&run[cbase + t], 0);
+      int32_t at;
+      int64_t b0;
+      if (lds_cnt) {
+        at = cnt[t];
+        b0 = row0 + sbase[t];
+      } else {
+        at = atomicAdd(&gcur[t * nk1 + pass], 0);
+        b0 = seg_off[cbase + t] + (kofs ? kofs[(cbase + t) * nk1 + pass] : 0);
+      }
       const int32_t end = (at + 3) & ~3;
       for (; at < end; at++)
-        stack[seg_off[cbase + t] + at] = enc ? make_int2((int)0x80000000u, (int)0x80000000u) : make_int2(-1, -1);
-      if (lds_cnt) cnt[t] = end;
-      else atomicExch(&run[cbase + t], end);
+        stack[b0 + at] = enc ? make_int2((int)0x80000000u, (int)0x80000000u) : make_int2(-1, -1);
     }
-    __syncthreads();
-  }
   }
 }
 
@@ -400,7 +425,7 @@ void symbolic_fill(const FillArgs &f, hipStream_t s) {
   hipLaunchKernelGGL(k_sym_fill, dim3(nbr), dim3(SYM_THREADS), lds, s, view(*f.sym.a), view(*f.sym.b),
                      f.sym.cold_rp, f.sym.cold_ci, f.sym.use_cold ? 1 : 0, f.sym.retain ? 1 : 0, f.sym.nbc,
                      f.c_rp, f.c_ci, f.c_row, f.c_size, f.c_cnt, f.c_kflops, f.row_cand, f.row_real, f.na, f.nb,
-                     f.eps, cap, ks, nkp, f.cnt_g);
+                     f.eps, cap, ks, nkp, f.cnt_g, nkp > 0 ? f.kofs : nullptr);
   HIPCHECK(hipGetLastError());
 }
 
@@ -416,10 +441,10 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
   int32_t words_total = (g.nbc + 31) >> 5;
   int32_t W = std::min(words_total, MAX_WORDS);
   if (W == 0) W = 1;
-  int32_t cap = std::min(g.max_row, CNT_CAP);
-  size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 4;
+  int32_t cap = std::min(g.max_row, CNT_CAP / 2);
+  size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 8;   // bitmap + prefix, cursors + run starts
   KSizes ks;
-  int nks = (int)g.ksizes.size();
+  int nks = g.pad4 ? (int)g.ksizes.size() : 0;
   if (nks > MAX_KSIZES) nks = 0;
   for (int t = 0; t < nks; t++) ks.v[t] = g.ksizes[t];
   OpView va = view(*g.a), vb = view(*g.b);
@@ -427,8 +452,9 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
     va.off = g.a_poff;
     vb.off = g.b_poff;
   }
-  hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr), dim3(64), lds, s, va, vb, g.nbc, g.c_rp, g.c_ci,
-                     g.seg_off, g.stack, g.na, g.nb, g.eps, cap, run, ks, nks, g.pad4 ? 1 : 0, g.encode ? 1 : 0);
+  hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr, std::max(nks, 1)), dim3(64), lds, s, va, vb, g.nbc, g.c_rp, g.c_ci,
+                     g.seg_off, nks > 0 ? g.kofs : nullptr, g.stack, g.na, g.nb, g.eps, cap, run, ks, nks,
+                     g.pad4 ? 1 : 0, g.encode ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
 
