@@ -562,8 +562,7 @@ static void plan_numeric(Plan &P, bool marks) {
       pack32_values(*P.A, ta, P.a_poff.p, reinterpret_cast<float *>(P.a_pack.p), reinterpret_cast<float *>(P.a_lo.p), s);
       pack32_values(*P.B, !tb, P.b_poff.p, reinterpret_cast<float *>(P.b_pack.p), reinterpret_cast<float *>(P.b_lo.p), s);
     } else if (P.quads) {
-      pack_values(*P.A, ta, P.a_poff.p, P.a_pack.p, s);
-      pack_values(*P.B, !tb, P.b_poff.p, P.b_pack.p, s);
+      pack_values(*P.A, ta, P.a_poff.p, P.a_pack.p, *P.B, !tb, P.b_poff.p, P.b_pack.p, s);
     } else {
       if (ta) transpose_blocks(*P.A, P.a_t.p, s);
       if (!tb) transpose_blocks(*P.B, P.b_t.p, s);
@@ -1202,10 +1201,7 @@ bsmm_status bsmm_plans_execute(int32_t n, bsmm_plan *plans) {
   int max_edge = 1;
   for (int32_t r = 0; r < n; r++) {
     Plan &P = plans[r]->plan;
-    if (P.nprod > 0) {
-      pack_values(*P.A, P.ta, P.a_poff.p, P.a_pack.p, s);
-      pack_values(*P.B, !P.tb, P.b_poff.p, P.b_pack.p, s);
-    }
+    if (P.nprod > 0) pack_values(*P.A, P.ta, P.a_poff.p, P.a_pack.p, *P.B, !P.tb, P.b_poff.p, P.b_pack.p, s);
     gs.push_back(&P.ga);
     nnzb.push_back(P.nnzb_c);
     max_edge = std::max(max_edge, P.max_edge);

@@ -878,22 +878,37 @@ __global__ __launch_bounds__(64) void k_pack_sizes(const int64_t *rp, const int3
   }
 }
 
-__global__ __launch_bounds__(256) void k_pack_blocks(const int64_t *rp, const int32_t *ci, const int32_t *rbs,
-                                                     const int32_t *cbs, const int64_t *off, const double *in,
-                                                     int k_is_row, const int64_t *poff, double *out) {
-  const int32_t i = blockIdx.x;
-  const int R = rbs[i];
-  for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
-    const int C = cbs[ci[p]];
-    const int K = k_is_row ? R : C, nr = k_is_row ? C : R;
+// One workgroup per block row of A and then of B (one launch for both); its
+// four wavefronts take every fourth block of the row, the 64 lanes of a
+// wavefront the block's values.
+struct PackSide {
+  const int64_t *rp;
+  const int32_t *ci, *rbs, *cbs;
+  const int64_t *off;
+  const double *in;
+  int k_is_row;
+  const int64_t *poff;
+  double *out;
+  int32_t nbr;
+};
+
+__global__ __launch_bounds__(256) void k_pack_blocks(PackSide a, PackSide b) {
+  const bool first = (int32_t)blockIdx.x < a.nbr;
+  const PackSide &X = first ? a : b;
+  const int32_t i = first ? (int32_t)blockIdx.x : (int32_t)blockIdx.x - a.nbr;
+  const int R = X.rbs[i];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t p = X.rp[i] + wv; p < X.rp[i + 1]; p += 4) {
+    const int C = X.cbs[X.ci[p]];
+    const int K = X.k_is_row ? R : C, nr = X.k_is_row ? C : R;
     const int Kp = K + (K & 1);
-    const int64_t o = off[p], po = poff[p];
-    for (int e = threadIdx.x; e < nr * Kp; e += blockDim.x) {
+    const int64_t o = X.off[p], po = X.poff[p];
+    for (int e = lane; e < nr * Kp; e += 64) {
       const int slab = e / (2 * nr), w = e - slab * 2 * nr;
       const int r = w >> 1, k = 2 * slab + (w & 1);
       double x = 0.0;
-      if (k < K) x = k_is_row ? in[o + k + (int64_t)r * R] : in[o + r + (int64_t)k * R];
-      out[po + e] = x;
+      if (k < K) x = X.k_is_row ? X.in[o + k + (int64_t)r * R] : X.in[o + r + (int64_t)k * R];
+      X.out[po + e] = x;
     }
   }
 }
@@ -936,10 +951,26 @@ void pack_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_
   exclusive_scan_i64(al, sizes.p, d_poff, x.nnzb, s);
 }
 
-void pack_values(const bsmm_mat_s &x, bool k_is_row, const int64_t *d_poff, double *out, hipStream_t s) {
-  if (x.nbr == 0 || x.nnzb == 0) return;
-  hipLaunchKernelGGL(k_pack_blocks, dim3(x.nbr), dim3(256), 0, s, x.d_row_ptr, x.d_col_idx, x.d_rbs, x.d_cbs,
-                     x.d_blk_off, x.d_values, k_is_row ? 1 : 0, d_poff, out);
+void pack_values(const bsmm_mat_s &a, bool a_k_is_row, const int64_t *a_poff, double *a_out, const bsmm_mat_s &b,
+                 bool b_k_is_row, const int64_t *b_poff, double *b_out, hipStream_t s) {
+  auto side = [](const bsmm_mat_s &x, bool kr, const int64_t *poff, double *out) {
+    PackSide v;
+    v.rp = x.d_row_ptr;
+    v.ci = x.d_col_idx;
+    v.rbs = x.d_rbs;
+    v.cbs = x.d_cbs;
+    v.off = x.d_blk_off;
+    v.in = x.d_values;
+    v.k_is_row = kr ? 1 : 0;
+    v.poff = poff;
+    v.out = out;
+    v.nbr = (x.nnzb > 0) ? x.nbr : 0;
+    return v;
+  };
+  const PackSide va = side(a, a_k_is_row, a_poff, a_out), vb = side(b, b_k_is_row, b_poff, b_out);
+  const int64_t grid = (int64_t)va.nbr + vb.nbr;
+  if (grid == 0) return;
+  hipLaunchKernelGGL(k_pack_blocks, dim3((unsigned)grid), dim3(256), 0, s, va, vb);
   HIPCHECK(hipGetLastError());
 }
 

@@ -340,38 +340,81 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
     }
   __syncthreads();
   int32_t *gcur = run ? run + cbase * nk1 : nullptr;   // wide rows: global cursors per (slot, pass)
-  for (int64_t p = A.rp[i]; p < A.rp[i + 1]; p++) {
-    const int32_t k = A.ci[p];
-    if (nks > 0 && A.cbs[k] != ksz.v[pass]) continue;
-    const int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
-    const double nA = na ? na[ablk] : 0.0;
-    const uint32_t ea = enc ? ((uint32_t)(A.off[ablk] * 8) | (uint32_t)((A.cbs[k] - 1) & 7)) : (uint32_t)ablk;
-    const uint32_t kb = enc ? (uint32_t)((A.cbs[k] - 1) >> 3) : 0u;
-    const int64_t q1 = B.rp[k + 1];
-    for (int64_t q = B.rp[k] + lane; q < q1; q += 64) {
-      const int32_t j = B.ci[q];
-      const int32_t bblk = B.blk ? B.blk[q] : (int32_t)q;
-      if (na && (nA * nb[bblk] < eps)) continue;
-      int32_t slot;
-      if (lds_slot) slot = bm_test(bm, j) ? bm_slot(bm, pre, j) : -1;
-      else slot = bsearch_slot(c_ci, cbase, cbase + R, j);
-      if (slot < 0) continue;
-      int64_t pos;
-      if (lds_cnt) {
-        const int32_t at = cnt[slot];
-        cnt[slot] = at + 1;
-        pos = row0 + sbase[slot] + at;
-      } else {
-        const int32_t at = atomicAdd(&gcur[slot * nk1 + pass], 1);
-        pos = seg_off[cbase + slot] + (kofs ? kofs[(cbase + slot) * nk1 + pass] : 0) + at;
-      }
-      if (enc)   // byte offsets of the two packed blocks, k size - 1 in their low 3 + 2 bits
-        stack[pos] = make_int2((int)ea, (int)((uint32_t)(B.off[bblk] * 8) | kb));
-      else
-        stack[pos] = make_int2((int)ea, bblk);
+  // Chunks of 64 products: (A entry p, 64 consecutive entries of B row k_p).
+  // The loads of the next chunk are issued before the current chunk's LDS
+  // cursor work, so their latency overlaps it; chunks are processed in
+  // order, which keeps every C block's entries in ascending k.
+  const int64_t pa0 = A.rp[i], pa1 = A.rp[i + 1];
+  struct Cur {
+    int64_t p, q, q1;   // A entry, this lane's B entry, end of the B row
+    uint32_t ea, kb;    // encoded A part, high bits of k - 1
+    double nA;
+  };
+  // first chunk of A entry p or later (of this pass's k size); p = pa1 when none
+  auto open_p = [&](int64_t p, Cur &c) {
+    for (; p < pa1; p++) {
+      const int32_t k = A.ci[p];
+      if (nks > 0 && A.cbs[k] != ksz.v[pass]) continue;
+      const int64_t qb = B.rp[k], qe = B.rp[k + 1];
+      if (qb == qe) continue;
+      const int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
+      c.p = p;
+      c.q = qb + lane;
+      c.q1 = qe;
+      c.nA = na ? na[ablk] : 0.0;
+      c.ea = enc ? ((uint32_t)(A.off[ablk] * 8) | (uint32_t)((A.cbs[k] - 1) & 7)) : (uint32_t)ablk;
+      c.kb = enc ? (uint32_t)((A.cbs[k] - 1) >> 3) : 0u;
+      return;
     }
-    // no barrier: one wavefront, whose LDS accesses complete in program
-    // order, so the cursor updates of this k precede the next k's reads
+    c.p = pa1;
+  };
+  // values of one lane's product in a chunk (loaded ahead)
+  struct Val {
+    int32_t j, bblk;
+    double nb;
+    uint32_t eb;
+  };
+  auto load_val = [&](const Cur &c, Val &v) {
+    v.j = -1;
+    if (c.p < pa1 && c.q < c.q1) {
+      v.j = B.ci[c.q];
+      v.bblk = B.blk ? B.blk[c.q] : (int32_t)c.q;
+      v.nb = na ? nb[v.bblk] : 0.0;
+      v.eb = enc ? (uint32_t)(B.off[v.bblk] * 8) : 0u;
+    }
+  };
+  Cur cur;
+  open_p(pa0, cur);
+  Val val;
+  load_val(cur, val);
+  while (cur.p < pa1) {
+    // next chunk: the rest of this B row, else the next A entry
+    Cur nxt = cur;
+    nxt.q += 64;
+    if (nxt.q - lane >= nxt.q1) open_p(cur.p + 1, nxt);
+    Val nv;
+    load_val(nxt, nv);
+    // this chunk
+    if (val.j >= 0 && !(na && (cur.nA * val.nb < eps))) {
+      int32_t slot;
+      if (lds_slot) slot = bm_test(bm, val.j) ? bm_slot(bm, pre, val.j) : -1;
+      else slot = bsearch_slot(c_ci, cbase, cbase + R, val.j);
+      if (slot >= 0) {
+        int64_t pos;
+        if (lds_cnt) {
+          const int32_t at = cnt[slot];
+          cnt[slot] = at + 1;
+          pos = row0 + sbase[slot] + at;
+        } else {
+          const int32_t at = atomicAdd(&gcur[slot * nk1 + pass], 1);
+          pos = seg_off[cbase + slot] + (kofs ? kofs[(cbase + slot) * nk1 + pass] : 0) + at;
+        }
+        // encoded: byte offsets of the two packed blocks, k size - 1 in their low 3 + 2 bits
+        stack[pos] = enc ? make_int2((int)cur.ea, (int)(val.eb | cur.kb)) : make_int2((int)cur.ea, val.bblk);
+      }
+    }
+    cur = nxt;
+    val = nv;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
