@@ -337,3 +337,21 @@ def test_errors(B, ctx):
     for m in (X, Y, G, S, A, Bm):
         m.close()
     small.close()
+
+
+# ------------------------------------------------------------ wide rows
+@pytest.mark.parametrize("nbc,p", [(9000, 0.3), (140000, 0.012)])
+def test_wide_result_rows(B, ctx, nbc, p):
+    """C rows wider than the LDS counters (> 8,192 blocks: global counters and
+    cursors) and wider than one bitmap window (> 131,072 block columns)."""
+    rng = np.random.default_rng(nbc)
+    ks = rng.choice(np.array([2, 3], dtype=np.int32), 40)
+    a = random_bcsr(rng, 3, 40, p=0.6, rbs=rng.choice(np.array([1, 2], dtype=np.int32), 3), cbs=ks)
+    b = random_bcsr(rng, 40, nbc, p=p, rbs=ks, cbs=rng.choice(np.array([1, 2], dtype=np.int32), nbc))
+    for eps in (0.0, 0.5):
+        ref = oracle.multiply("N", "N", 1.0, a, b, eps=eps, nthreads=8)
+        rows = np.diff(ref.row_ptr)
+        _log(f"wide rows nbc={nbc} eps={eps}: widest C row {rows.max()} blocks")
+        host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=eps)
+        _check_exact(host, info, ref)
+    assert rows.max() > 8192
