@@ -680,12 +680,17 @@ __device__ __forceinline__ void dispatch_quad(const GemmP &P, const BlkDesc &D, 
     if constexpr (MAXT > 4) {
       switch (key) {
         case 2 * 16 + 6: gemm_block_quad<false, 2, 6>(P, D, ql, pre); return;
-        case 2 * 16 + 8: gemm_block_quad<false, 2, 8>(P, D, ql, pre); return;
         case 4 * 16 + 6: gemm_block_quad<false, 4, 6>(P, D, ql, pre); return;
-        case 4 * 16 + 8: gemm_block_quad<false, 4, 8>(P, D, ql, pre); return;
         case 6 * 16 + 2: gemm_block_quad<false, 6, 2>(P, D, ql, pre); return;
         case 6 * 16 + 4: gemm_block_quad<false, 6, 4>(P, D, ql, pre); return;
         case 6 * 16 + 6: gemm_block_quad<false, 6, 6>(P, D, ql, pre); return;
+        default: break;
+      }
+    }
+    if constexpr (MAXT > 6) {
+      switch (key) {
+        case 2 * 16 + 8: gemm_block_quad<false, 2, 8>(P, D, ql, pre); return;
+        case 4 * 16 + 8: gemm_block_quad<false, 4, 8>(P, D, ql, pre); return;
         case 6 * 16 + 8: gemm_block_quad<false, 6, 8>(P, D, ql, pre); return;
         case 8 * 16 + 2: gemm_block_quad<false, 8, 2>(P, D, ql, pre); return;
         case 8 * 16 + 4: gemm_block_quad<false, 8, 4>(P, D, ql, pre); return;
@@ -1043,6 +1048,8 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   if (max_edge <= 16 && buf)
     hipLaunchKernelGGL((k_gemm_f64<4, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+  else if (max_edge <= 24 && buf)   // shapes up to 24: the register budget of the 24-wide shapes
+    hipLaunchKernelGGL((k_gemm_f64<6, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   else if (max_edge <= 16)
     hipLaunchKernelGGL((k_gemm_f64<4, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
   else if (buf)
@@ -1080,6 +1087,8 @@ void gemm_launch_multi(Allocator &al, const std::vector<const GemmArgs *> &gs, c
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   if (max_edge <= 16)
     hipLaunchKernelGGL((k_gemm_f64_multi<4>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, per_xcd);
+  else if (max_edge <= 24)
+    hipLaunchKernelGGL((k_gemm_f64_multi<6>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, per_xcd);
   else
     hipLaunchKernelGGL((k_gemm_f64_multi<8>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, per_xcd);
   HIPCHECK(hipGetLastError());
