@@ -394,20 +394,6 @@ static void plan_build(Plan &P, char transa, char transb) {
   fa.ksizes = ksizes;
   fa.cnt_g = cnt_g.p;
   fa.kofs = kofs.p;
-  fa.na = filt ? na.p : nullptr;
-  fa.nb = filt ? nb.p : nullptr;
-  fa.eps = eps;
-  fa.max_row = max_row;
-  symbolic_fill(fa, s);
-  P.c_off = DBuf<int64_t>(al, nc1 + 1);
-  P.seg_off = DBuf<int64_t>(al, nc1 + 1);
-  DBuf<int64_t> kmn_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1),
-      cand_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1), real_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1);
-  exclusive_scan_i64(al, c_size.p, P.c_off.p, nnzb_c, s);
-  exclusive_scan_i32(al, c_cnt.p, P.seg_off.p, nnzb_c, s);
-  exclusive_scan_i64(al, row_kmn.p, kmn_scan.p, nbr, s);
-  exclusive_scan_i64(al, row_cand.p, cand_scan.p, nbr, s);
-  exclusive_scan_i64(al, row_real.p, real_scan.p, nbr, s);
   // packed operand offsets for the quad path (op(A) row-major, op(B) column-major)
   if (lowp && !quads && nnzb_c > 0)
     fail(BSMM_ERR_UNSUPPORTED, "FP32 / split modes need packed operands below 2 GB and at most 8 distinct k block sizes");
@@ -421,6 +407,25 @@ static void plan_build(Plan &P, char transa, char transb) {
       pack_offsets(al, *A, ta, P.a_poff.p, s);
       pack_offsets(al, *B, !tb, P.b_poff.p, s);
     }
+  }
+  // one record per entry of op(B) for the product loops of a2 and a4
+  DBuf<int4> bent(al, (size_t)std::max<int64_t>(ob.nnzb, 1));
+  product_records(ob, filt ? nb.p : nullptr, quads ? P.b_poff.p : nullptr, bent.p, s);
+  fa.na = filt ? na.p : nullptr;
+  fa.bent = bent.p;
+  fa.eps = eps;
+  fa.max_row = max_row;
+  symbolic_fill(fa, s);
+  P.c_off = DBuf<int64_t>(al, nc1 + 1);
+  P.seg_off = DBuf<int64_t>(al, nc1 + 1);
+  DBuf<int64_t> kmn_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1),
+      cand_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1), real_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1);
+  exclusive_scan_i64(al, c_size.p, P.c_off.p, nnzb_c, s);
+  exclusive_scan_i32(al, c_cnt.p, P.seg_off.p, nnzb_c, s);
+  exclusive_scan_i64(al, row_kmn.p, kmn_scan.p, nbr, s);
+  exclusive_scan_i64(al, row_cand.p, cand_scan.p, nbr, s);
+  exclusive_scan_i64(al, row_real.p, real_scan.p, nbr, s);
+  if (quads) {
     HIPCHECK(hipMemcpyAsync(ctx->pinned + 5, P.a_poff.p + A->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipMemcpyAsync(ctx->pinned + 6, P.b_poff.p + B->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   }
@@ -462,7 +467,6 @@ static void plan_build(Plan &P, char transa, char transb) {
     sa.seg_off = P.seg_off.p;
     sa.stack = P.stack.p;
     sa.na = filt ? na.p : nullptr;
-    sa.nb = filt ? nb.p : nullptr;
     sa.eps = eps;
     sa.nbc = nbc;
     sa.nbr = nbr;
@@ -472,7 +476,7 @@ static void plan_build(Plan &P, char transa, char transb) {
     sa.encode = quads;
     sa.kofs = kofs.p;
     sa.a_poff = P.a_poff.p;
-    sa.b_poff = P.b_poff.p;
+    sa.bent = bent.p;
     if (P.nprod > 0) stack_fill(sa, run.p, s);
   }
   // GEMM work list: tiles of rows in the planner's locality order, columns

@@ -883,9 +883,13 @@ __global__ __launch_bounds__(64) void k_pack_sizes(const int64_t *rp, const int3
   }
 }
 
-// One workgroup per block row of A and then of B (one launch for both); its
-// four wavefronts take every fourth block of the row, the 64 lanes of a
-// wavefront the block's values.
+// One workgroup per block row of A and then of B (one launch for both).  The
+// row's blocks are taken 256 at a time: first every thread reads one
+// block's sizes and offsets into LDS, then each group of 16 lanes packs
+// every 16th block, PACK_NV values per lane per step: the step's loads are
+// all issued before its stores, and a lane's position in the packed order
+// (slab, r, k parity) advances by a precomputed stride, without a division
+// per value.
 struct PackSide {
   const int64_t *rp;
   const int32_t *ci, *rbs, *cbs;
@@ -897,24 +901,60 @@ struct PackSide {
   int32_t nbr;
 };
 
+constexpr int PACK_NV = 12;
+
 __global__ __launch_bounds__(256) void k_pack_blocks(PackSide a, PackSide b) {
+  __shared__ int64_t m_o[256], m_po[256];
+  __shared__ int32_t m_K[256], m_nr[256];
   const bool first = (int32_t)blockIdx.x < a.nbr;
   const PackSide &X = first ? a : b;
   const int32_t i = first ? (int32_t)blockIdx.x : (int32_t)blockIdx.x - a.nbr;
   const int R = X.rbs[i];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int64_t p = X.rp[i] + wv; p < X.rp[i + 1]; p += 4) {
-    const int C = X.cbs[X.ci[p]];
-    const int K = X.k_is_row ? R : C, nr = X.k_is_row ? C : R;
-    const int Kp = K + (K & 1);
-    const int64_t o = X.off[p], po = X.poff[p];
-    for (int e = lane; e < nr * Kp; e += 64) {
-      const int slab = e / (2 * nr), w = e - slab * 2 * nr;
-      const int r = w >> 1, k = 2 * slab + (w & 1);
-      double x = 0.0;
-      if (k < K) x = X.k_is_row ? X.in[o + k + (int64_t)r * R] : X.in[o + r + (int64_t)k * R];
-      X.out[po + e] = x;
+  const int lane = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int64_t p0 = X.rp[i], p1 = X.rp[i + 1];
+  for (int64_t pb = p0; pb < p1; pb += 256) {
+    const int nb = (int)min<int64_t>(256, p1 - pb);
+    if ((int)threadIdx.x < nb) {
+      const int64_t p = pb + threadIdx.x;
+      const int C = X.cbs[X.ci[p]];
+      m_K[threadIdx.x] = X.k_is_row ? R : C;
+      m_nr[threadIdx.x] = X.k_is_row ? C : R;
+      m_o[threadIdx.x] = X.off[p];
+      m_po[threadIdx.x] = X.poff[p];
     }
+    __syncthreads();
+    for (int j = grp; j < nb; j += 16) {
+      const int K = m_K[j], nr = m_nr[j], two = 2 * nr;
+      const int n = nr * (K + (K & 1));
+      const int64_t o = m_o[j], po = m_po[j];
+      // stride of 16 in the packed order: qd slabs and rd more positions
+      const int qd = 16 / two, rd = 16 - qd * two;
+      int slab = lane / two, w = lane - (lane / two) * two;   // position of e = lane
+      for (int e0 = 0; e0 < n; e0 += 16 * PACK_NV) {
+        double x[PACK_NV];
+        int sl[PACK_NV], ww[PACK_NV];
+#pragma unroll
+        for (int t = 0; t < PACK_NV; t++) {
+          sl[t] = slab;
+          ww[t] = w;
+          const int k = min(2 * slab + (w & 1), K - 1), r = min(w >> 1, nr - 1);
+          const int64_t src = X.k_is_row ? o + k + (int64_t)r * R : o + r + (int64_t)k * R;
+          x[t] = X.in[src];
+          slab += qd;
+          w += rd;
+          if (w >= two) {
+            w -= two;
+            slab++;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < PACK_NV; t++) {
+          const int e = e0 + 16 * t + lane;
+          if (e < n) X.out[po + e] = (2 * sl[t] + (ww[t] & 1) < K) ? x[t] : 0.0;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 

@@ -147,23 +147,46 @@ __global__ __launch_bounds__(64) void k_tr_fill(const int64_t *rp, const int32_t
 }
 
 // ------------------------------------------------------------------ norms
-// G lanes per block: G = 16 for small blocks, 64 otherwise.
-template <int G>
+// 16 lanes per block, U blocks per lane group in flight: the group reads the
+// U blocks' offsets together, then issues one load per block per step
+// (indices clamped into the block, so there are no branches between the
+// loads) before it accumulates.  Each lane sums its elements in ascending
+// order and the 16 partial sums combine in a fixed tree: the result does not
+// depend on the launch.
+template <int U>
 __global__ __launch_bounds__(256) void k_block_norms(const int64_t *off, const double *v, int64_t nnzb,
                                                      double *out) {
-  int lane = threadIdx.x % G;
-  int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
-  for (int64_t b = grp; b < nnzb; b += ngrp) {
-    int64_t o0 = off[b], o1 = off[b + 1];
-    double s = 0.0;
-    for (int64_t e = o0 + lane; e < o1; e += G) {
-      double x = v[e];
-      s = fma(x, x, s);
+  constexpr int G = 16;
+  const int lane = threadIdx.x % G;
+  const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / G;
+  for (int64_t b0 = grp * U; b0 < nnzb; b0 += ngrp * U) {
+    int64_t o0[U], len[U];
+    int64_t lmax = 0;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t b = min(b0 + u, nnzb - 1);
+      o0[u] = off[b];
+      len[u] = (b0 + u < nnzb) ? off[b + 1] - o0[u] : 0;
+      lmax = max(lmax, len[u]);
+    }
+    double s[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) s[u] = 0.0;
+    for (int64_t d = lane; d < lmax; d += G) {
+      double x[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) x[u] = v[o0[u] + min(d, max(len[u] - 1, (int64_t)0))];
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (d < len[u]) s[u] = fma(x[u], x[u], s[u]);
     }
 #pragma unroll
-    for (int d = G / 2; d >= 1; d >>= 1) s += __shfl_xor(s, d, G);
-    if (lane == 0) out[b] = sqrt(s);
+    for (int u = 0; u < U; u++) {
+#pragma unroll
+      for (int dd = G / 2; dd >= 1; dd >>= 1) s[u] += __shfl_xor(s[u], dd, G);
+      if (lane == 0 && b0 + u < nnzb) out[b0 + u] = sqrt(s[u]);
+    }
   }
 }
 
@@ -256,17 +279,10 @@ void transpose_index(Allocator &al, const bsmm_mat_s &x, OpIndex &op, hipStream_
 
 void block_norms(const bsmm_mat_s &x, double *norms, hipStream_t s) {
   if (x.nnzb == 0) return;
-  int32_t mr = 0, mc = 0;
-  for (int32_t a : x.h_rbs) mr = std::max(mr, a);
-  for (int32_t b : x.h_cbs) mc = std::max(mc, b);
-  int64_t maxa = (int64_t)mr * mc;
-  if (maxa <= 64) {
-    hipLaunchKernelGGL(k_block_norms<16>, dim3(grid_for(x.nnzb * 16, 256)), dim3(256), 0, s, x.d_blk_off,
-                       x.d_values, x.nnzb, norms);
-  } else {
-    hipLaunchKernelGGL(k_block_norms<64>, dim3(grid_for(x.nnzb * 64, 256)), dim3(256), 0, s, x.d_blk_off,
-                       x.d_values, x.nnzb, norms);
-  }
+  constexpr int U = 4;
+  const int64_t groups = (x.nnzb + U - 1) / U;
+  hipLaunchKernelGGL(k_block_norms<U>, dim3(grid_for(groups * 16, 256)), dim3(256), 0, s, x.d_blk_off, x.d_values,
+                     x.nnzb, norms);
   HIPCHECK(hipGetLastError());
 }
 

@@ -158,7 +158,8 @@ struct FillArgs {
   int32_t *cnt_g = nullptr;        // nnzb_C * |ksizes| zeroed counters for wide rows
   int32_t *kofs = nullptr;         // out (when pad4): start of every k-size run inside its
                                    // C block's segment, nnzb_C * |ksizes| entries
-  const double *na = nullptr, *nb = nullptr;   // block norms (null when eps == 0)
+  const double *na = nullptr;      // norms of A's blocks (null when eps == 0)
+  const int4 *bent = nullptr;      // product records of op(B) (product_records)
   double eps = 0.0;
   int32_t max_row = 0;
 };
@@ -172,7 +173,7 @@ struct StackArgs {
   const int32_t *c_ci = nullptr;
   const int64_t *seg_off = nullptr;  // start of every C block's stack segment
   int2 *stack = nullptr;             // out: (a_blk, b_blk)
-  const double *na = nullptr, *nb = nullptr;
+  const double *na = nullptr;        // norms of op(A)'s blocks (null: no filter)
   double eps = 0.0;
   int32_t nbc = 0;
   int32_t nbr = 0;
@@ -181,9 +182,15 @@ struct StackArgs {
   bool pad4 = false;                 // pad every equal-k-size run to 4 entries (null = -1)
   bool encode = false;               // entries = byte offsets | (k-1) bits (quad path), null = 0x80000000
   const int32_t *kofs = nullptr;     // k-size run starts inside each segment (pad4)
-  const int64_t *a_poff = nullptr;   // packed block offsets used by the encoded entries
-  const int64_t *b_poff = nullptr;
+  const int64_t *a_poff = nullptr;   // packed block offsets of A used by the encoded entries
+  const int4 *bent = nullptr;        // product records of op(B) (product_records)
 };
+
+// Per entry of op(B), one 16-byte record read by the symbolic fill and the
+// stack generator: block column, the B half of a stack entry (byte offset
+// into the packed copy of op(B) when b_poff is given, else the block id) and
+// the block norm (0 when nb is null).
+void product_records(const OpIndex &b, const double *nb, const int64_t *b_poff, int4 *out, hipStream_t s);
 
 // a4: stack entries, grouped by C block, ascending k inside a block.  `run`
 // (nnzb of C, zeroed) serves rows too wide for the LDS cursors.

@@ -8,6 +8,8 @@
 // columns in a bitmap held in LDS; the bitmap doubles as the map from a
 // block column to its position inside the row (prefix popcounts), so
 // neither a dense column map nor a sort is needed.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace bsmm {
@@ -18,6 +20,7 @@ constexpr int SYM_THREADS = 256;
 constexpr int32_t MAX_WORDS = 4096;      // bitmap window: 131072 block columns
 constexpr int32_t CNT_CAP = 8192;        // per-row counters kept in LDS up to this
 constexpr int MAX_KSIZES = 8;            // k-size grouping of the stacks up to this many sizes
+constexpr size_t STACK_LDS_HEAD = 1792;  // stack fill: 64 opened A entries (B row start, norm, count, A half, k bits)
 
 // Distinct k block sizes, ascending (nks == 0: no grouping by size).
 struct KSizes {
@@ -68,16 +71,119 @@ __device__ inline T block_sum(T v, T *sh) {
 }
 
 // Mark every candidate block column of row i that falls in [j0, j1).
-__device__ inline void mark_candidates(const OpView &A, const OpView &B, int32_t i, int32_t j0, int32_t j1,
-                                       uint32_t *bm) {
-  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int64_t p = A.rp[i] + wv; p < A.rp[i + 1]; p += nw) {
-    int32_t k = A.ci[p];
-    int64_t q1 = B.rp[k + 1];
-    for (int64_t q = B.rp[k] + lane; q < q1; q += 64) {
-      int32_t j = B.ci[q];
-      if (j >= j0 && j < j1) bm_set(bm, j - j0);
+// One record per entry q of op(B): the block column, the B half of a stack
+// entry (byte offset into the packed copy, or the block id) and the block
+// norm, so a product costs one 16-byte load on the B side.
+struct alignas(16) BEnt {
+  int32_t j;
+  uint32_t eb;
+  double nb;
+};
+
+// Up to 64 opened A entries of one block row, staged in LDS per wavefront.
+struct AOpen {
+  int64_t qb[64];   // first entry of B row k
+  double na[64];    // norm of A(i,k) (0 without filter)
+  int32_t nq[64];   // entries of B row k (> 0)
+  int32_t kk[64];   // k block size
+  int32_t kx[64];   // index of the k size in the size list (0 without grouping)
+};
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Opens A entries p0 + lane (below p1), one per lane: those with a non-empty
+// B row are compacted into st in ascending order.  Returns their number;
+// adds each lane's candidate products (entries of its B row) to *cand.
+__device__ inline int open_a(const OpView &A, const OpView &B, int64_t p0, int64_t p1, const double *na,
+                             const KSizes *ksz, int nkp, AOpen &st, int64_t *cand) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = p0 + lane;
+  bool ok = false;
+  int64_t qb = 0;
+  int32_t nq = 0, kk = 0, kx = 0;
+  double nA = 0.0;
+  if (p < p1) {
+    const int32_t k = A.ci[p];
+    kk = A.cbs[k];
+    qb = B.rp[k];
+    nq = (int32_t)(B.rp[k + 1] - qb);
+    ok = nq > 0;
+    if (na) nA = na[A.blk ? A.blk[p] : (int32_t)p];
+    if (nkp > 0)
+      while (kx + 1 < nkp && ksz->v[kx] != kk) kx++;
+  }
+  if (cand) *cand += nq;
+  const uint64_t m = __ballot(ok);
+  if (ok) {
+    const int t = __popcll(m & ((1ull << lane) - 1ull));
+    st.qb[t] = qb;
+    st.na[t] = nA;
+    st.nq[t] = nq;
+    st.kk[t] = kk;
+    st.kx[t] = kx;
+  }
+  return __popcll(m);
+}
+
+// Visits the products of the opened entries of one wavefront (B row starts
+// qb[e], lengths nq[e], e < ne) in chunks of up to 64 consecutive entries
+// of one B row, a lane per product, in ascending (entry, q) order, calling
+// f(e, load(q)) on the lanes that hold a product.  WALK_DEPTH chunks are
+// loaded back to back (every lane loads; a lane without a product loads
+// item 0, so no branch separates the loads) before they are handled: one
+// memory latency per WALK_DEPTH chunks.  load(0) must be a valid item
+// whenever some opened entry exists.
+constexpr int WALK_DEPTH = 8;
+
+template <typename T, typename L, typename F>
+__device__ inline void chunk_walk(const int64_t *qb, const int32_t *nq, int ne, L load, F f) {
+  const int lane = threadIdx.x & 63;
+  int e = 0;   // next chunk: entry e, offset o
+  int32_t o = 0;
+  while (e < ne) {
+    int pe[WALK_DEPTH];
+    bool pv[WALK_DEPTH];
+    T v[WALK_DEPTH];
+#pragma unroll
+    for (int d = 0; d < WALK_DEPTH; d++) {
+      const bool live = e < ne;   // uniform
+      const int es = live ? e : 0;
+      const int32_t n = nq[es];
+      pe[d] = es;
+      pv[d] = live && o + lane < n;
+      v[d] = load(pv[d] ? qb[es] + o + lane : (int64_t)0);
+      if (live) {
+        o += 64;
+        if (o >= n) {
+          e++;
+          o = 0;
+        }
+      }
     }
+#pragma unroll
+    for (int d = 0; d < WALK_DEPTH; d++)
+      if (pv[d]) f(pe[d], v[d]);
+  }
+}
+
+// Marks the block columns in [j0, j1) reachable from row i of A.  Each
+// wavefront opens every (nw*64)-th batch of the row's A entries.
+__device__ inline void mark_candidates(const OpView &A, const OpView &B, int32_t i, int32_t j0, int32_t j1,
+                                       uint32_t *bm, AOpen *stage) {
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  AOpen &st = stage[wv];
+  const int64_t pa1 = A.rp[i + 1];
+  for (int64_t pb = A.rp[i] + (int64_t)wv * 64; pb < pa1; pb += (int64_t)nw * 64) {
+    const int ne = open_a(A, B, pb, pa1, nullptr, nullptr, 0, st, nullptr);
+    wave_sync();
+    chunk_walk<int32_t>(st.qb, st.nq, ne, [&](int64_t q) { return B.ci[q]; }, [&](int, int32_t j) {
+      if (j >= j0 && j < j1) bm_set(bm, j - j0);
+    });
+    wave_sync();
   }
 }
 
@@ -124,6 +230,7 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_count(OpView A, OpView B, c
                                                            int64_t *row_nnz, int32_t *max_row) {
   extern __shared__ uint32_t bm[];
   __shared__ int64_t red[SYM_THREADS / 64];
+  __shared__ AOpen stage[SYM_THREADS / 64];
   int32_t i = blockIdx.x;
   int32_t words_total = (nbc + 31) >> 5;
   if (words_total == 0) {
@@ -138,7 +245,7 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_count(OpView A, OpView B, c
     for (int32_t t = threadIdx.x; t < W; t += blockDim.x) bm[t] = 0u;
     __syncthreads();
     if (use_cold) mark_row(cold_rp, cold_ci, i, j0, j1, bm);
-    mark_candidates(A, B, i, j0, j1, bm);
+    mark_candidates(A, B, i, j0, j1, bm, stage);
     __syncthreads();
     int64_t c = 0;
     for (int32_t t = threadIdx.x; t < W; t += blockDim.x) c += __popc(bm[t]);
@@ -160,12 +267,13 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
                                                           int32_t nbc, const int64_t *c_rp, int32_t *c_ci,
                                                           int32_t *c_row, int64_t *c_size, int32_t *c_cnt,
                                                           int64_t *row_kmn, int64_t *row_cand, int64_t *row_real,
-                                                          const double *na, const double *nb, double eps,
+                                                          const BEnt *bent, const double *na, double eps,
                                                           int32_t cnt_cap, KSizes ksz, int nkp, int32_t *cnt_g,
                                                           int32_t *kofs) {
   extern __shared__ uint32_t sm[];
   __shared__ int32_t shi[SYM_THREADS / 64];
   __shared__ int64_t shl[SYM_THREADS / 64];
+  __shared__ AOpen stage[SYM_THREADS / 64];
   int32_t i = blockIdx.x;
   int32_t words_total = (nbc + 31) >> 5;
   if (words_total == 0) {
@@ -189,7 +297,7 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
       mark_row(cold_rp, cold_ci, i, j0, j1, bm);
     } else {
       if (use_cold) mark_row(cold_rp, cold_ci, i, j0, j1, bm);
-      mark_candidates(A, B, i, j0, j1, bm);
+      mark_candidates(A, B, i, j0, j1, bm, stage);
     }
     __syncthreads();
     word_prefix(bm, pre, W, shi);
@@ -220,41 +328,57 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
   if (lds_cnt)
     for (int32_t t = threadIdx.x; t < R * nk1; t += blockDim.x) cnt[t] = 0;
   __syncthreads();
-  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int64_t kmn = 0, cand = 0;
-  for (int64_t p = A.rp[i] + wv; p < A.rp[i + 1]; p += nw) {
-    int32_t k = A.ci[p];
-    int32_t kk = A.cbs[k];
-    double nA = na ? na[A.blk ? A.blk[p] : (int32_t)p] : 0.0;
-    int64_t q1 = B.rp[k + 1];
-    if (lane == 0) cand += q1 - B.rp[k];
-    for (int64_t q = B.rp[k] + lane; q < q1; q += 64) {
-      int32_t j = B.ci[q];
-      if (na && (nA * nb[B.blk ? B.blk[q] : (int32_t)q] < eps)) continue;
-      int32_t slot;
-      if (lds_slot) slot = bm_test(bm, j) ? bm_slot(bm, pre, j) : -1;
-      else slot = bsearch_slot(c_ci, cbase, cbase + R, j);
-      if (slot < 0) continue;   // only under retain_sparsity
-      int kx = 0;
-      if (nkp > 0)
-        while (kx + 1 < nkp && ksz.v[kx] != kk) kx++;
-      if (lds_cnt) atomicAdd(&cnt[slot * nk1 + kx], 1);
-      else atomicAdd(&gcnt[slot * nk1 + kx], 1);
-      kmn += (int64_t)kk * B.cbs[j];
+  {
+    AOpen &st = stage[wv];
+    const int64_t pa1 = A.rp[i + 1];
+    for (int64_t pb = A.rp[i] + (int64_t)wv * 64; pb < pa1; pb += (int64_t)nw * 64) {
+      const int ne = open_a(A, B, pb, pa1, na, &ksz, nkp, st, &cand);
+      wave_sync();
+      auto walk = [&](auto fast) {
+        constexpr bool FAST = decltype(fast)::value;
+        chunk_walk<BEnt>(st.qb, st.nq, ne, [&](int64_t q) { return bent[q]; }, [&](int e, const BEnt &v) {
+          if (na && (st.na[e] * v.nb < eps)) return;
+          if constexpr (FAST) {
+            if (!bm_test(bm, v.j)) return;   // only under retain_sparsity
+            atomicAdd(&cnt[bm_slot(bm, pre, v.j) * nk1 + st.kx[e]], 1);
+          } else {
+            int32_t slot;
+            if (lds_slot) slot = bm_test(bm, v.j) ? bm_slot(bm, pre, v.j) : -1;
+            else slot = bsearch_slot(c_ci, cbase, cbase + R, v.j);
+            if (slot < 0) return;
+            const int kx = st.kx[e];
+            if (lds_cnt) atomicAdd(&cnt[slot * nk1 + kx], 1);
+            else atomicAdd(&gcnt[slot * nk1 + kx], 1);
+            if (nkp == 0) kmn += (int64_t)st.kk[e] * B.cbs[v.j];
+          }
+        });
+      };
+      // slots and counters in LDS with k sizes known per run: a loop with no
+      // global load besides the ring's
+      if (lds_slot && lds_cnt && nkp > 0) walk(std::true_type{});
+      else walk(std::false_type{});
+      wave_sync();
     }
   }
   __syncthreads();
+  // per C block: run starts of its k sizes, padded and kept counts; with k
+  // sizes known per run, its share of the useful flops (sum of k * n)
   int64_t real = 0;
   for (int32_t t = threadIdx.x; t < R; t += blockDim.x) {
     int32_t tot_real = 0, tot_pad = 0;
+    int64_t ksum = 0;
     for (int kx = 0; kx < nk1; kx++) {
       const int32_t v = lds_cnt ? cnt[t * nk1 + kx] : gcnt[t * nk1 + kx];
       if (kofs) kofs[(cbase + t) * nk1 + kx] = tot_pad;   // this k size's run starts here
       tot_real += v;
       tot_pad += nkp > 0 ? (v + 3) & ~3 : v;
+      if (nkp > 0) ksum += (int64_t)v * ksz.v[kx];
     }
     c_cnt[cbase + t] = tot_pad;
     real += tot_real;
+    if (nkp > 0) kmn += ksum * B.cbs[c_ci[cbase + t]];
   }
   int64_t tot = block_sum<int64_t>(kmn, shl);
   int64_t tcand = block_sum<int64_t>(cand, shl);
@@ -278,21 +402,32 @@ __global__ void k_old_map(const int64_t *cold_rp, const int32_t *cold_ci, const 
 }
 
 // ------------------------------------------------------ a4: stack fill
-// One wavefront per C block row walks the k of row i in ascending order;
-// for each k its lanes take the block columns j of row k of op(B).  A given
-// j appears once per k, so the per-C-block write cursors never collide
-// inside one step, and successive steps are ordered: every C block's
-// segment comes out sorted by k, identically on every run.
-// One wavefront per (C block row, k size): the k-size runs of a segment are
-// independent (their starts come from the symbolic phase), so the passes of
-// a row run side by side.  Inside a run, products are written in ascending k
-// through a per-C-block cursor in LDS; the run's start offsets (relative to
-// the row's first segment) are staged in LDS too, so a product costs one
-// global load of its B column index on the dependent path.
+__global__ __launch_bounds__(256) void k_product_records(OpView B, int64_t nq, const double *nb, int enc, BEnt *out) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t bblk = B.blk ? B.blk[q] : (int32_t)q;
+    BEnt e;
+    e.j = B.ci[q];
+    e.eb = enc ? (uint32_t)(B.off[bblk] * 8) : (uint32_t)bblk;
+    e.nb = nb ? nb[bblk] : 0.0;
+    out[q] = e;
+  }
+}
+
+// One wavefront per (C block row i, k size): the k-size runs of a segment
+// are independent (their starts come from the symbolic phase), so the
+// passes of a row run side by side.  The A entries of row i are opened 64 at
+// a time, one per lane (k, the range of B row k, the norm and the A half of
+// the entry); those of this pass's k size with a non-empty B row are
+// compacted into LDS in ascending k.  Their products are then taken in
+// chunks of up to 64 consecutive entries of one B row, a lane per product.
+// A given block column appears once in a B row, so the per-C-block write
+// cursors (in LDS, beside the run starts) never collide inside a chunk, and
+// chunks go in ascending k: every C block's run comes out sorted by k,
+// identically on every run.
 __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t nbc, const int64_t *c_rp,
                                                    const int32_t *c_ci, const int64_t *seg_off,
-                                                   const int32_t *kofs, int2 *stack, const double *na,
-                                                   const double *nb, double eps, int32_t cnt_cap, int32_t *run,
+                                                   const int32_t *kofs, int2 *stack, const BEnt *bent,
+                                                   const double *na, double eps, int32_t cnt_cap, int32_t *run,
                                                    KSizes ksz, int nks, int pad4, int enc) {
   extern __shared__ uint32_t sm[];
   const int32_t i = blockIdx.x;
@@ -306,8 +441,14 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
   if (R == 0) return;
   const bool lds_cnt = R <= cnt_cap;
   const int nk1 = nks > 0 ? nks : 1;
-  uint32_t *bm = sm;
-  int32_t *pre = reinterpret_cast<int32_t *>(sm + W);
+  // opened A entries (64 at most at a time)
+  int64_t *s_qb = reinterpret_cast<int64_t *>(sm);
+  double *s_na = reinterpret_cast<double *>(sm + 128);
+  int32_t *s_nq = reinterpret_cast<int32_t *>(sm + 256);
+  uint32_t *s_ea = sm + 320;
+  uint32_t *s_kb = sm + 384;
+  uint32_t *bm = sm + STACK_LDS_HEAD / 4;
+  int32_t *pre = reinterpret_cast<int32_t *>(bm + W);
   int32_t *cnt = pre + W;
   int32_t *sbase = cnt + (lds_cnt ? R : 0);
   const int64_t row0 = seg_off[cbase];
@@ -340,81 +481,72 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
     }
   __syncthreads();
   int32_t *gcur = run ? run + cbase * nk1 : nullptr;   // wide rows: global cursors per (slot, pass)
-  // Chunks of 64 products: (A entry p, 64 consecutive entries of B row k_p).
-  // The loads of the next chunk are issued before the current chunk's LDS
-  // cursor work, so their latency overlaps it; chunks are processed in
-  // order, which keeps every C block's entries in ascending k.
   const int64_t pa0 = A.rp[i], pa1 = A.rp[i + 1];
-  struct Cur {
-    int64_t p, q, q1;   // A entry, this lane's B entry, end of the B row
-    uint32_t ea, kb;    // encoded A part, high bits of k - 1
-    double nA;
-  };
-  // first chunk of A entry p or later (of this pass's k size); p = pa1 when none
-  auto open_p = [&](int64_t p, Cur &c) {
-    for (; p < pa1; p++) {
+  for (int64_t pb = pa0; pb < pa1; pb += 64) {
+    const int64_t p = pb + lane;
+    bool ok = false;
+    int64_t qb = 0;
+    int32_t nq = 0;
+    uint32_t ea = 0u, kb = 0u;
+    double nA = 0.0;
+    if (p < pa1) {
       const int32_t k = A.ci[p];
-      if (nks > 0 && A.cbs[k] != ksz.v[pass]) continue;
-      const int64_t qb = B.rp[k], qe = B.rp[k + 1];
-      if (qb == qe) continue;
-      const int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
-      c.p = p;
-      c.q = qb + lane;
-      c.q1 = qe;
-      c.nA = na ? na[ablk] : 0.0;
-      c.ea = enc ? ((uint32_t)(A.off[ablk] * 8) | (uint32_t)((A.cbs[k] - 1) & 7)) : (uint32_t)ablk;
-      c.kb = enc ? (uint32_t)((A.cbs[k] - 1) >> 3) : 0u;
-      return;
+      const int32_t kc = A.cbs[k];
+      if (nks == 0 || kc == ksz.v[pass]) {
+        qb = B.rp[k];
+        nq = (int32_t)(B.rp[k + 1] - qb);
+        ok = nq > 0;
+        const int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
+        nA = na ? na[ablk] : 0.0;
+        ea = enc ? ((uint32_t)(A.off[ablk] * 8) | (uint32_t)((kc - 1) & 7)) : (uint32_t)ablk;
+        kb = enc ? (uint32_t)((kc - 1) >> 3) : 0u;
+      }
     }
-    c.p = pa1;
-  };
-  // values of one lane's product in a chunk (loaded ahead)
-  struct Val {
-    int32_t j, bblk;
-    double nb;
-    uint32_t eb;
-  };
-  auto load_val = [&](const Cur &c, Val &v) {
-    v.j = -1;
-    if (c.p < pa1 && c.q < c.q1) {
-      v.j = B.ci[c.q];
-      v.bblk = B.blk ? B.blk[c.q] : (int32_t)c.q;
-      v.nb = na ? nb[v.bblk] : 0.0;
-      v.eb = enc ? (uint32_t)(B.off[v.bblk] * 8) : 0u;
+    const uint64_t m = __ballot(ok);
+    const int ne = __popcll(m);
+    if (ok) {
+      const int t = __popcll(m & ((1ull << lane) - 1ull));
+      s_qb[t] = qb;
+      s_na[t] = nA;
+      s_nq[t] = nq;
+      s_ea[t] = ea;
+      s_kb[t] = kb;
     }
-  };
-  Cur cur;
-  open_p(pa0, cur);
-  Val val;
-  load_val(cur, val);
-  while (cur.p < pa1) {
-    // next chunk: the rest of this B row, else the next A entry
-    Cur nxt = cur;
-    nxt.q += 64;
-    if (nxt.q - lane >= nxt.q1) open_p(cur.p + 1, nxt);
-    Val nv;
-    load_val(nxt, nv);
-    // this chunk
-    if (val.j >= 0 && !(na && (cur.nA * val.nb < eps))) {
-      int32_t slot;
-      if (lds_slot) slot = bm_test(bm, val.j) ? bm_slot(bm, pre, val.j) : -1;
-      else slot = bsearch_slot(c_ci, cbase, cbase + R, val.j);
-      if (slot >= 0) {
+    __syncthreads();
+    // the common case (slots and cursors in LDS) has a loop of its own, with
+    // no global load besides the ring's, so the loads stay in flight
+    auto walk = [&](auto fast) {
+      constexpr bool FAST = decltype(fast)::value;
+      chunk_walk<BEnt>(s_qb, s_nq, ne, [&](int64_t q) { return bent[q]; }, [&](int e, const BEnt &v) {
+        if (na && (s_na[e] * v.nb < eps)) return;
+        int32_t slot;
         int64_t pos;
-        if (lds_cnt) {
+        if constexpr (FAST) {
+          if (!bm_test(bm, v.j)) return;
+          slot = bm_slot(bm, pre, v.j);
           const int32_t at = cnt[slot];
           cnt[slot] = at + 1;
           pos = row0 + sbase[slot] + at;
         } else {
-          const int32_t at = atomicAdd(&gcur[slot * nk1 + pass], 1);
-          pos = seg_off[cbase + slot] + (kofs ? kofs[(cbase + slot) * nk1 + pass] : 0) + at;
+          if (lds_slot) slot = bm_test(bm, v.j) ? bm_slot(bm, pre, v.j) : -1;
+          else slot = bsearch_slot(c_ci, cbase, cbase + R, v.j);
+          if (slot < 0) return;
+          if (lds_cnt) {
+            const int32_t at = cnt[slot];
+            cnt[slot] = at + 1;
+            pos = row0 + sbase[slot] + at;
+          } else {
+            const int32_t at = atomicAdd(&gcur[slot * nk1 + pass], 1);
+            pos = seg_off[cbase + slot] + (kofs ? kofs[(cbase + slot) * nk1 + pass] : 0) + at;
+          }
         }
         // encoded: byte offsets of the two packed blocks, k size - 1 in their low 3 + 2 bits
-        stack[pos] = enc ? make_int2((int)cur.ea, (int)(val.eb | cur.kb)) : make_int2((int)cur.ea, val.bblk);
-      }
-    }
-    cur = nxt;
-    val = nv;
+        stack[pos] = make_int2((int)s_ea[e], (int)(v.eb | s_kb[e]));
+      });
+    };
+    if (lds_slot && lds_cnt) walk(std::true_type{});
+    else walk(std::false_type{});
+    __syncthreads();   // the opened entries are rewritten by the next batch
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -465,10 +597,13 @@ void symbolic_fill(const FillArgs &f, hipStream_t s) {
   for (int t = 0; t < nkp; t++) ks.v[t] = f.ksizes[t];
   int32_t cap = (int32_t)std::min<int64_t>((int64_t)f.max_row * std::max(nkp, 1), CNT_CAP);
   size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 4;
+  if (lds + sizeof(AOpen) * (SYM_THREADS / 64) + 1024 > 65536)
+    HIPCHECK(hipFuncSetAttribute((const void *)k_sym_fill, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_sym_fill, dim3(nbr), dim3(SYM_THREADS), lds, s, view(*f.sym.a), view(*f.sym.b),
                      f.sym.cold_rp, f.sym.cold_ci, f.sym.use_cold ? 1 : 0, f.sym.retain ? 1 : 0, f.sym.nbc,
-                     f.c_rp, f.c_ci, f.c_row, f.c_size, f.c_cnt, f.c_kflops, f.row_cand, f.row_real, f.na, f.nb,
-                     f.eps, cap, ks, nkp, f.cnt_g, nkp > 0 ? f.kofs : nullptr);
+                     f.c_rp, f.c_ci, f.c_row, f.c_size, f.c_cnt, f.c_kflops, f.row_cand, f.row_real,
+                     reinterpret_cast<const BEnt *>(f.bent), f.na, f.eps, cap, ks, nkp, f.cnt_g,
+                     nkp > 0 ? f.kofs : nullptr);
   HIPCHECK(hipGetLastError());
 }
 
@@ -479,13 +614,23 @@ void old_block_map(const int64_t *cold_rp, const int32_t *cold_ci, int32_t nbr, 
   HIPCHECK(hipGetLastError());
 }
 
+void product_records(const OpIndex &b, const double *nb, const int64_t *b_poff, int4 *out, hipStream_t s) {
+  if (b.nnzb == 0) return;
+  OpView vb = view(b);
+  if (b_poff) vb.off = b_poff;   // encoded entries: offsets into the packed copy of op(B)
+  hipLaunchKernelGGL(k_product_records, dim3((unsigned)std::min<int64_t>((b.nnzb + 255) / 256, 65536)), dim3(256), 0, s,
+                     vb, b.nnzb, nb, b_poff ? 1 : 0, reinterpret_cast<BEnt *>(out));
+  HIPCHECK(hipGetLastError());
+}
+
 void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
   if (g.nbr == 0) return;
   int32_t words_total = (g.nbc + 31) >> 5;
   int32_t W = std::min(words_total, MAX_WORDS);
   if (W == 0) W = 1;
   int32_t cap = std::min(g.max_row, CNT_CAP / 2);
-  size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 8;   // bitmap + prefix, cursors + run starts
+  // opened A entries, bitmap + prefix, cursors + run starts
+  size_t lds = STACK_LDS_HEAD + (size_t)W * 8 + (size_t)std::max(cap, 1) * 8;
   KSizes ks;
   int nks = g.pad4 ? (int)g.ksizes.size() : 0;
   if (nks > MAX_KSIZES) nks = 0;
@@ -493,10 +638,10 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
   OpView va = view(*g.a), vb = view(*g.b);
   if (g.encode) {   // entries carry offsets into the packed operand copies
     va.off = g.a_poff;
-    vb.off = g.b_poff;
   }
+  const BEnt *bent = reinterpret_cast<const BEnt *>(g.bent);
   hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr, std::max(nks, 1)), dim3(64), lds, s, va, vb, g.nbc, g.c_rp, g.c_ci,
-                     g.seg_off, nks > 0 ? g.kofs : nullptr, g.stack, g.na, g.nb, g.eps, cap, run, ks, nks,
+                     g.seg_off, nks > 0 ? g.kofs : nullptr, g.stack, bent, g.na, g.eps, cap, run, ks, nks,
                      g.pad4 ? 1 : 0, g.encode ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
