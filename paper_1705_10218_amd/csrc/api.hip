@@ -416,6 +416,19 @@ static void plan_build(Plan &P, char transa, char transb) {
   fa.eps = eps;
   fa.max_row = max_row;
   symbolic_fill(fa, s);
+  // column windows of the stack generator (bounds of C's and op(B)'s rows)
+  const StackWindows sw = quads ? stack_windows(nbc, max_row, (int)ksizes.size()) : StackWindows{};
+  DBuf<int64_t> wslot, bwin;
+  DBuf<int32_t> dmax_ns;
+  if (sw.nwin > 0 && nnzb_c > 0) {
+    wslot = DBuf<int64_t>(al, (size_t)nbr * (sw.nwin + 1));
+    bwin = DBuf<int64_t>(al, (size_t)std::max<int32_t>(ob.nbr, 1) * (sw.nwin + 1));
+    dmax_ns = DBuf<int32_t>(al, 2);
+    HIPCHECK(hipMemsetAsync(dmax_ns.p, 0, sizeof(int32_t) * 2, s));
+    window_bounds(P.c_rp.p, P.c_ci.p, nbr, sw, wslot.p, dmax_ns.p, s);
+    window_bounds(ob.row_ptr, ob.col_idx, ob.nbr, sw, bwin.p, nullptr, s);
+    HIPCHECK(hipMemcpyAsync(ctx->pinned + 7, dmax_ns.p, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+  }
   P.c_off = DBuf<int64_t>(al, nc1 + 1);
   P.seg_off = DBuf<int64_t>(al, nc1 + 1);
   DBuf<int64_t> kmn_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1),
@@ -442,6 +455,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   P.ncand = ctx->pinned[3];
   P.a_pack_n = quads ? ctx->pinned[5] : 0;
   P.b_pack_n = quads ? ctx->pinned[6] : 0;
+  const int32_t max_ns = (sw.nwin > 0 && nnzb_c > 0) ? (int32_t)(ctx->pinned[7] & 0x7fffffff) : 0;
   if (C0 && beta != 0.0 && nnzb_c > 0) {
     P.old_blk = DBuf<int32_t>(al, nc1);
     HIPCHECK(hipMemsetAsync(P.old_blk.p, 0xff, sizeof(int32_t) * nc1, s));
@@ -477,6 +491,12 @@ static void plan_build(Plan &P, char transa, char transb) {
     sa.kofs = kofs.p;
     sa.a_poff = P.a_poff.p;
     sa.bent = bent.p;
+    if (sw.nwin > 0 && max_ns > 0) {
+      sa.win = sw;
+      sa.wslot = wslot.p;
+      sa.bwin = bwin.p;
+      sa.max_ns = max_ns;
+    }
     if (P.nprod > 0) stack_fill(sa, run.p, s);
   }
   // GEMM work list: tiles of rows in the planner's locality order, columns

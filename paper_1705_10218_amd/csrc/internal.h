@@ -167,6 +167,24 @@ struct FillArgs {
 // a2 (fill) + a4 (count): C col_idx, block sizes, product counts.
 void symbolic_fill(const FillArgs &f, hipStream_t s);
 
+// Column windows of the stack generator: window w holds block columns
+// [w*wc, (w+1)*wc).  nwin = 0: no windows (one pass per row and k size).
+struct StackWindows {
+  int nwin = 0;
+  int32_t wc = 0;
+};
+
+// Windows for a product with nbc block columns whose widest result row has
+// max_row blocks, nks k sizes; nwin = 0 where the windowed generator does
+// not apply (it needs the quad path's k-size runs and LDS-sized rows).
+StackWindows stack_windows(int32_t nbc, int32_t max_row, int nks);
+
+// out[r*(nwin+1) + w] = first entry of row r with column >= w*wc (the row's
+// end for w = nwin); max_cnt (optional, preset to 0) receives the largest
+// number of entries of one row inside one window.
+void window_bounds(const int64_t *rp, const int32_t *ci, int32_t nrows, const StackWindows &sw, int64_t *out,
+                   int32_t *max_cnt, hipStream_t s);
+
 struct StackArgs {
   const OpIndex *a, *b;
   const int64_t *c_rp = nullptr;
@@ -184,6 +202,10 @@ struct StackArgs {
   const int32_t *kofs = nullptr;     // k-size run starts inside each segment (pad4)
   const int64_t *a_poff = nullptr;   // packed block offsets of A used by the encoded entries
   const int4 *bent = nullptr;        // product records of op(B) (product_records)
+  StackWindows win;                  // windowed generation when win.nwin > 0:
+  const int64_t *wslot = nullptr;    //   window bounds of C's rows
+  const int64_t *bwin = nullptr;     //   window bounds of op(B)'s rows
+  int32_t max_ns = 0;                //   most C blocks of one row in one window
 };
 
 // Per entry of op(B), one 16-byte record read by the symbolic fill and the

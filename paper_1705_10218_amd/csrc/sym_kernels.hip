@@ -21,6 +21,7 @@ constexpr int32_t MAX_WORDS = 4096;      // bitmap window: 131072 block columns
 constexpr int32_t CNT_CAP = 8192;        // per-row counters kept in LDS up to this
 constexpr int MAX_KSIZES = 8;            // k-size grouping of the stacks up to this many sizes
 constexpr size_t STACK_LDS_HEAD = 1792;  // stack fill: 64 opened A entries (B row start, norm, count, A half, k bits)
+constexpr int64_t STACK_BUF_BYTES = 16384;  // windowed stack fill: LDS for buffered entries (32 B per C block)
 
 // Distinct k block sizes, ascending (nks == 0: no grouping by size).
 struct KSizes {
@@ -570,6 +571,177 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
   }
 }
 
+// First entry of every block row whose column is at least w * wc, for
+// w = 0 .. nwin (one row per workgroup; the last is the row's end).  With
+// max_cnt, the largest number of entries of a row inside one window.
+__global__ __launch_bounds__(64) void k_window_bounds(const int64_t *rp, const int32_t *ci, int32_t wc, int nwin,
+                                                      int64_t *out, int32_t *max_cnt) {
+  extern __shared__ int64_t wb[];
+  const int32_t r = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t q0 = rp[r], q1 = rp[r + 1];
+  for (int w = lane; w <= nwin; w += 64) wb[w] = q1;
+  __syncthreads();
+  for (int64_t q = q0 + lane; q < q1; q += 64) {
+    const int wq = ci[q] / wc;
+    const int wp = (q == q0) ? -1 : ci[q - 1] / wc;
+    for (int w = wp + 1; w <= wq; w++) wb[w] = q;   // windows opened by entry q
+  }
+  __syncthreads();
+  for (int w = lane; w <= nwin; w += 64) out[(int64_t)r * (nwin + 1) + w] = wb[w];
+  if (max_cnt)
+    for (int w = lane; w < nwin; w += 64) atomicMax(max_cnt, (int32_t)(wb[w + 1] - wb[w]));
+}
+
+// Stack generation for one (C block row i, k size, column window): the
+// window holds the C blocks of row i with j in [w*wc, (w+1)*wc), and the
+// products are taken from the part of each B row inside the window (the
+// window bounds of op(B)'s rows).  Products go through the same ordered LDS
+// cursors as above, but a C block's entries are not written one by one:
+// they gather in an LDS group of four, and the fourth sends the group (32
+// aligned bytes, runs being padded to groups of four) in one write; the
+// last group of a run is completed with null entries at the end.  The window
+// keeps the LDS cost per C block (group, cursor, run start) within budget,
+// so memory sees whole 32-byte groups instead of scattered 8-byte writes.
+// Without buffering (more C blocks in the window than buf_cap), entries go
+// straight to memory and the runs are padded afterwards.
+__global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const int64_t *wslot, const int64_t *bwin,
+                                                       int nwin, int32_t wc, const int32_t *c_ci,
+                                                       const int64_t *seg_off, const int32_t *kofs, int2 *stack,
+                                                       const BEnt *bent, const double *na, double eps,
+                                                       int32_t buf_cap, KSizes ksz, int nks) {
+  extern __shared__ uint32_t sm[];
+  const int32_t i = blockIdx.x;
+  const int pass = blockIdx.y / nwin, w = blockIdx.y - pass * nwin;
+  const int lane = threadIdx.x;
+  const int64_t s0 = wslot[(int64_t)i * (nwin + 1) + w], s1 = wslot[(int64_t)i * (nwin + 1) + w + 1];
+  const int32_t ns = (int32_t)(s1 - s0);
+  if (ns == 0) return;
+  const int32_t j0 = w * wc;
+  const int32_t W = (wc + 31) >> 5;
+  const bool buffered = ns <= buf_cap;
+  int64_t *s_qb = reinterpret_cast<int64_t *>(sm);
+  double *s_na = reinterpret_cast<double *>(sm + 128);
+  int32_t *s_nq = reinterpret_cast<int32_t *>(sm + 256);
+  uint32_t *s_ea = sm + 320;
+  uint32_t *s_kb = sm + 384;
+  int2 *buf = reinterpret_cast<int2 *>(sm + STACK_LDS_HEAD / 4);   // a group of 4 per C block
+  uint32_t *bm = reinterpret_cast<uint32_t *>(buf + (buffered ? 4 * ns : 0));
+  int32_t *pre = reinterpret_cast<int32_t *>(bm + W);
+  int32_t *cnt = pre + W;
+  int32_t *sbase = cnt + ns;
+  const int64_t g0 = seg_off[s0];
+  for (int32_t t = lane; t < W; t += 64) bm[t] = 0u;
+  __syncthreads();
+  for (int64_t c = s0 + lane; c < s1; c += 64) bm_set(bm, c_ci[c] - j0);
+  __syncthreads();
+  {
+    const int32_t per = (W + 63) / 64;
+    const int32_t w0 = lane * per, w1 = min(W, w0 + per);
+    int32_t sum = 0;
+    for (int32_t u = w0; u < w1; u++) sum += __popc(bm[u]);
+    int32_t inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    int32_t r = inc - sum;
+    for (int32_t u = w0; u < w1; u++) {
+      pre[u] = r;
+      r += __popc(bm[u]);
+    }
+  }
+  for (int32_t t = lane; t < ns; t += 64) {
+    cnt[t] = 0;
+    sbase[t] = (int32_t)(seg_off[s0 + t] - g0) + kofs[(s0 + t) * nks + pass];
+  }
+  __syncthreads();
+  int2 *base = stack + g0;
+  const int64_t pa0 = A.rp[i], pa1 = A.rp[i + 1];
+  for (int64_t pb = pa0; pb < pa1; pb += 64) {
+    const int64_t p = pb + lane;
+    bool ok = false;
+    int64_t qb = 0;
+    int32_t nq = 0;
+    uint32_t ea = 0u, kb = 0u;
+    double nA = 0.0;
+    if (p < pa1) {
+      const int32_t k = A.ci[p];
+      const int32_t kc = A.cbs[k];
+      if (kc == ksz.v[pass]) {
+        const int64_t *bw = bwin + (int64_t)k * (nwin + 1) + w;
+        qb = bw[0];
+        nq = (int32_t)(bw[1] - qb);
+        ok = nq > 0;
+        const int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
+        nA = na ? na[ablk] : 0.0;
+        ea = (uint32_t)(A.off[ablk] * 8) | (uint32_t)((kc - 1) & 7);
+        kb = (uint32_t)((kc - 1) >> 3);
+      }
+    }
+    const uint64_t m = __ballot(ok);
+    const int ne = __popcll(m);
+    if (ok) {
+      const int t = __popcll(m & ((1ull << lane) - 1ull));
+      s_qb[t] = qb;
+      s_na[t] = nA;
+      s_nq[t] = nq;
+      s_ea[t] = ea;
+      s_kb[t] = kb;
+    }
+    __syncthreads();
+    // buffered and direct writing are separate loops: a store common to both
+    // would be merged into one generic (flat) store, which the compiler
+    // then orders against every load in flight
+    auto walk = [&](auto buffered_t) {
+      constexpr bool BUF = decltype(buffered_t)::value;
+      chunk_walk<BEnt>(s_qb, s_nq, ne, [&](int64_t q) { return bent[q]; }, [&](int e, const BEnt &v) {
+        if (na && (s_na[e] * v.nb < eps)) return;
+        const int32_t jj = v.j - j0;
+        if (!bm_test(bm, jj)) return;   // only under retain_sparsity
+        const int32_t slot = bm_slot(bm, pre, jj);
+        const int32_t at = cnt[slot];
+        cnt[slot] = at + 1;
+        // encoded: byte offsets of the two packed blocks, k size - 1 in their low 3 + 2 bits
+        const int2 ent = make_int2((int)s_ea[e], (int)(v.eb | s_kb[e]));
+        if constexpr (BUF) {
+          buf[slot * 4 + (at & 3)] = ent;
+          if ((at & 3) == 3) {   // group complete: its 32 bytes in one go
+            const int4 *src = reinterpret_cast<const int4 *>(buf + slot * 4);
+            int4 *dst = reinterpret_cast<int4 *>(base + sbase[slot] + (at - 3));
+            dst[0] = src[0];
+            dst[1] = src[1];
+          }
+        } else {
+          base[sbase[slot] + at] = ent;
+        }
+      });
+    };
+    if (buffered) walk(std::true_type{});
+    else walk(std::false_type{});
+    __syncthreads();   // the opened entries are rewritten by the next batch
+  }
+  // close every run of this k size: the last group of four, null-padded
+  const int nul = (int)0x80000000u;
+  for (int32_t t = lane; t < ns; t += 64) {
+    const int32_t at = cnt[t];
+    const int32_t rem = at & 3;
+    if (rem == 0) continue;
+    int2 *g = base + sbase[t] + (at - rem);
+    if (buffered) {
+      int2 x[3];
+#pragma unroll
+      for (int u = 0; u < 3; u++) x[u] = u < rem ? buf[t * 4 + u] : make_int2(nul, nul);
+      int4 *dst = reinterpret_cast<int4 *>(g);
+      dst[0] = make_int4(x[0].x, x[0].y, x[1].x, x[1].y);
+      dst[1] = make_int4(x[2].x, x[2].y, nul, nul);
+    } else {
+      for (int u = rem; u < 4; u++) g[u] = make_int2(nul, nul);
+    }
+  }
+}
+
 }  // namespace
 
 void symbolic_count(const SymArgs &g, int64_t *row_nnz, int32_t *max_row, hipStream_t s) {
@@ -623,6 +795,31 @@ void product_records(const OpIndex &b, const double *nb, const int64_t *b_poff, 
   HIPCHECK(hipGetLastError());
 }
 
+StackWindows stack_windows(int32_t nbc, int32_t max_row, int nks) {
+  StackWindows sw;
+  const int32_t words_total = (nbc + 31) >> 5;
+  if (nks < 1 || nks > MAX_KSIZES || words_total == 0 || words_total > MAX_WORDS || max_row < 1 ||
+      max_row > CNT_CAP / 2)
+    return sw;
+  // 32 bytes of LDS per C block of a window for its group of four entries:
+  // windows narrow enough that the widest row's share fits
+  int nwin = (int)std::min<int64_t>(16, std::max<int64_t>(1, ((int64_t)max_row * 32 + STACK_BUF_BYTES - 1) /
+                                                                 STACK_BUF_BYTES));
+  const int32_t wc = (int32_t)((((int64_t)nbc + nwin - 1) / nwin + 31) & ~(int64_t)31);
+  nwin = (int)(((int64_t)nbc + wc - 1) / wc);
+  sw.nwin = nwin;
+  sw.wc = wc;
+  return sw;
+}
+
+void window_bounds(const int64_t *rp, const int32_t *ci, int32_t nrows, const StackWindows &sw, int64_t *out,
+                   int32_t *max_cnt, hipStream_t s) {
+  if (nrows == 0 || sw.nwin < 1) return;
+  hipLaunchKernelGGL(k_window_bounds, dim3(nrows), dim3(64), sizeof(int64_t) * (sw.nwin + 1), s, rp, ci, sw.wc,
+                     sw.nwin, out, max_cnt);
+  HIPCHECK(hipGetLastError());
+}
+
 void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
   if (g.nbr == 0) return;
   int32_t words_total = (g.nbc + 31) >> 5;
@@ -640,6 +837,20 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
     va.off = g.a_poff;
   }
   const BEnt *bent = reinterpret_cast<const BEnt *>(g.bent);
+  if (g.win.nwin > 0 && g.pad4 && g.encode && nks > 0) {
+    const int32_t buf_cap = (int32_t)(STACK_BUF_BYTES / 32);
+    const int32_t ns = std::max(g.max_ns, 1);
+    const int32_t Ww = (g.win.wc + 31) >> 5;
+    const size_t lw = STACK_LDS_HEAD + (size_t)std::min(ns, buf_cap) * 32 + (size_t)Ww * 8 + (size_t)ns * 8;
+    if (lw > 65536)
+      HIPCHECK(hipFuncSetAttribute((const void *)k_stack_fill_win, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lw));
+    hipLaunchKernelGGL(k_stack_fill_win, dim3(g.nbr, nks * g.win.nwin), dim3(64), lw, s, va, vb, g.wslot, g.bwin,
+                       g.win.nwin, g.win.wc, g.c_ci, g.seg_off, g.kofs, g.stack, bent, g.na, g.eps, buf_cap, ks,
+                       nks);
+    HIPCHECK(hipGetLastError());
+    return;
+  }
   hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr, std::max(nks, 1)), dim3(64), lds, s, va, vb, g.nbc, g.c_rp, g.c_ci,
                      g.seg_off, nks > 0 ? g.kofs : nullptr, g.stack, bent, g.na, g.eps, cap, run, ks, nks,
                      g.pad4 ? 1 : 0, g.encode ? 1 : 0);
