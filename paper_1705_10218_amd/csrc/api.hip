@@ -311,6 +311,9 @@ static void plan_build(Plan &P, char transa, char transb) {
   sym.a = &oa;
   sym.b = &ob;
   sym.nbc = nbc;
+  // rows in the planner's locality order: neighbouring rows share most of
+  // their op(B) rows, so the row-parallel kernels reuse them through L2
+  sym.ord = nbr > 0 ? row_order(ctx, A) : nullptr;
   sym.retain = retain != 0;
   sym.use_cold = (beta != 0.0) && !retain && C0;
   if (C0) {
@@ -491,6 +494,7 @@ static void plan_build(Plan &P, char transa, char transb) {
     sa.kofs = kofs.p;
     sa.a_poff = P.a_poff.p;
     sa.bent = bent.p;
+    sa.ord = sym.ord;
     if (sw.nwin > 0 && max_ns > 0) {
       sa.win = sw;
       sa.wslot = wslot.p;

@@ -958,10 +958,14 @@ __global__ __launch_bounds__(256) void k_pack_blocks(PackSide a, PackSide b) {
   }
 }
 
+// Workgroup ids are remapped as in the GEMM (each XCD a contiguous stretch
+// of the work list): the C blocks of a stretch lie in few row tiles, so
+// each XCD's L2 holds the index data of its own tiles only.
 __global__ void k_build_desc(int64_t n, const int32_t *c_list, const int32_t *c_row, const int32_t *c_ci,
                              const int32_t *rbs, const int32_t *cbs, const int64_t *seg, const int64_t *c_off,
-                             BlkDesc *desc) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                             BlkDesc *desc, int64_t per_xcd) {
+  const int64_t b = blockIdx.x;
+  const int64_t w = ((b & 7) * per_xcd + (b >> 3)) * blockDim.x + threadIdx.x;
   if (w >= n) return;
   const int32_t c = c_list ? c_list[w] : (int32_t)w;
   BlkDesc d;
@@ -979,8 +983,9 @@ __global__ void k_build_desc(int64_t n, const int32_t *c_list, const int32_t *c_
 void build_desc(int64_t n, const int32_t *c_list, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
                 const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_build_desc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, c_list, c_row, c_ci, rbs,
-                     cbs, seg, c_off, desc);
+  const int64_t per_xcd = ((n + 255) / 256 + 7) / 8;
+  hipLaunchKernelGGL(k_build_desc, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s, n, c_list, c_row, c_ci, rbs, cbs,
+                     seg, c_off, desc, per_xcd);
   HIPCHECK(hipGetLastError());
 }
 

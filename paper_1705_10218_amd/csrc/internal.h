@@ -138,6 +138,7 @@ struct SymArgs {
   bool use_cold = false;     // include C_old pattern (beta != 0 && !retain)
   bool retain = false;       // pattern = C_old pattern exactly
   int32_t nbc = 0;           // block columns of C
+  const int32_t *ord = nullptr;   // order in which rows are handed out (device; null = 0..nbr-1)
 };
 
 // a2: per C block row, number of distinct result block columns.
@@ -206,6 +207,7 @@ struct StackArgs {
   const int64_t *wslot = nullptr;    //   window bounds of C's rows
   const int64_t *bwin = nullptr;     //   window bounds of op(B)'s rows
   int32_t max_ns = 0;                //   most C blocks of one row in one window
+  const int32_t *ord = nullptr;      // order in which rows are handed out (device; null = 0..nbr-1)
 };
 
 // Per entry of op(B), one 16-byte record read by the symbolic fill and the

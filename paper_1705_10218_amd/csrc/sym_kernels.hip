@@ -196,6 +196,32 @@ __device__ inline void mark_row(const int64_t *rp, const int32_t *ci, int32_t i,
   }
 }
 
+// Work unit of a workgroup in the row-parallel kernels.  A launch has
+// 8 * per_xcd workgroups, which the hardware deals to the 8 XCDs
+// round-robin; unit ids are remapped so that each XCD takes one contiguous
+// stretch of rows, in the locality order ord when given (nu units per row),
+// and its L2 holds the op(B) rows that stretch needs.  ok = false for the
+// padding workgroups past the last unit.
+struct RowUnit {
+  int32_t row;
+  int unit;
+  bool ok;
+};
+
+__device__ inline RowUnit row_unit(int32_t nrows, int nu, int64_t per_xcd, const int32_t *ord) {
+  const int64_t b = blockIdx.x;
+  const int64_t id = (b & 7) * per_xcd + (b >> 3);
+  RowUnit r{0, 0, id < (int64_t)nrows * nu};
+  if (r.ok) {
+    const int32_t pos = (int32_t)(id / nu);
+    r.unit = (int)(id - (int64_t)pos * nu);
+    r.row = ord ? ord[pos] : pos;
+  }
+  return r;
+}
+
+inline int64_t row_units_per_xcd(int32_t nrows, int nu) { return ((int64_t)nrows * nu + 7) / 8; }
+
 // Exclusive prefix popcount over W words (block-wide, simple two-level).
 __device__ inline void word_prefix(const uint32_t *bm, int32_t *pre, int32_t W, int32_t *sh) {
   int t = threadIdx.x, nt = blockDim.x;
@@ -228,11 +254,14 @@ __device__ inline void word_prefix(const uint32_t *bm, int32_t *pre, int32_t W, 
 // ------------------------------------------------------------ a2: count
 __global__ __launch_bounds__(SYM_THREADS) void k_sym_count(OpView A, OpView B, const int64_t *cold_rp,
                                                            const int32_t *cold_ci, int use_cold, int32_t nbc,
-                                                           int64_t *row_nnz, int32_t *max_row) {
+                                                           int64_t *row_nnz, int32_t *max_row, int32_t nbr,
+                                                           const int32_t *ord, int64_t per_xcd) {
   extern __shared__ uint32_t bm[];
   __shared__ int64_t red[SYM_THREADS / 64];
   __shared__ AOpen stage[SYM_THREADS / 64];
-  int32_t i = blockIdx.x;
+  const RowUnit ru = row_unit(nbr, 1, per_xcd, ord);
+  if (!ru.ok) return;
+  const int32_t i = ru.row;
   int32_t words_total = (nbc + 31) >> 5;
   if (words_total == 0) {
     if (threadIdx.x == 0) row_nnz[i] = 0;
@@ -270,12 +299,15 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
                                                           int64_t *row_kmn, int64_t *row_cand, int64_t *row_real,
                                                           const BEnt *bent, const double *na, double eps,
                                                           int32_t cnt_cap, KSizes ksz, int nkp, int32_t *cnt_g,
-                                                          int32_t *kofs) {
+                                                          int32_t *kofs, int32_t nbr, const int32_t *ord,
+                                                          int64_t per_xcd) {
   extern __shared__ uint32_t sm[];
   __shared__ int32_t shi[SYM_THREADS / 64];
   __shared__ int64_t shl[SYM_THREADS / 64];
   __shared__ AOpen stage[SYM_THREADS / 64];
-  int32_t i = blockIdx.x;
+  const RowUnit ru = row_unit(nbr, 1, per_xcd, ord);
+  if (!ru.ok) return;
+  const int32_t i = ru.row;
   int32_t words_total = (nbc + 31) >> 5;
   if (words_total == 0) {
     if (threadIdx.x == 0) { row_kmn[i] = 0; row_cand[i] = 0; row_real[i] = 0; }
@@ -429,10 +461,13 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
                                                    const int32_t *c_ci, const int64_t *seg_off,
                                                    const int32_t *kofs, int2 *stack, const BEnt *bent,
                                                    const double *na, double eps, int32_t cnt_cap, int32_t *run,
-                                                   KSizes ksz, int nks, int pad4, int enc) {
+                                                   KSizes ksz, int nks, int pad4, int enc, int32_t nbr,
+                                                   const int32_t *ord, int64_t per_xcd) {
   extern __shared__ uint32_t sm[];
-  const int32_t i = blockIdx.x;
-  const int pass = blockIdx.y;   // k-size index (0 when nks == 0)
+  const RowUnit ru = row_unit(nbr, nks > 0 ? nks : 1, per_xcd, ord);
+  if (!ru.ok) return;
+  const int32_t i = ru.row;
+  const int pass = ru.unit;   // k-size index (0 when nks == 0)
   const int lane = threadIdx.x;
   const int32_t words_total = (nbc + 31) >> 5;
   const int32_t W = min(words_total, MAX_WORDS);
@@ -574,23 +609,28 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
 // First entry of every block row whose column is at least w * wc, for
 // w = 0 .. nwin (one row per workgroup; the last is the row's end).  With
 // max_cnt, the largest number of entries of a row inside one window.
-__global__ __launch_bounds__(64) void k_window_bounds(const int64_t *rp, const int32_t *ci, int32_t wc, int nwin,
+__global__ __launch_bounds__(256) void k_window_bounds(const int64_t *rp, const int32_t *ci, int32_t wc, int nwin,
                                                       int64_t *out, int32_t *max_cnt) {
   extern __shared__ int64_t wb[];
   const int32_t r = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x, nt = blockDim.x;
   const int64_t q0 = rp[r], q1 = rp[r + 1];
-  for (int w = lane; w <= nwin; w += 64) wb[w] = q1;
+  for (int w = t; w <= nwin; w += nt) wb[w] = q1;
   __syncthreads();
-  for (int64_t q = q0 + lane; q < q1; q += 64) {
+  for (int64_t q = q0 + t; q < q1; q += nt) {
     const int wq = ci[q] / wc;
     const int wp = (q == q0) ? -1 : ci[q - 1] / wc;
     for (int w = wp + 1; w <= wq; w++) wb[w] = q;   // windows opened by entry q
   }
   __syncthreads();
-  for (int w = lane; w <= nwin; w += 64) out[(int64_t)r * (nwin + 1) + w] = wb[w];
-  if (max_cnt)
-    for (int w = lane; w < nwin; w += 64) atomicMax(max_cnt, (int32_t)(wb[w + 1] - wb[w]));
+  for (int w = t; w <= nwin; w += nt) out[(int64_t)r * (nwin + 1) + w] = wb[w];
+  if (max_cnt) {   // one atomic per wavefront that holds windows
+    int32_t mx = 0;
+    for (int w = t; w < nwin; w += nt) mx = max(mx, (int32_t)(wb[w + 1] - wb[w]));
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d, 64));
+    if ((t & 63) == 0 && t < nwin && mx > 0) atomicMax(max_cnt, mx);
+  }
 }
 
 // Stack generation for one (C block row i, k size, column window): the
@@ -609,10 +649,13 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
                                                        int nwin, int32_t wc, const int32_t *c_ci,
                                                        const int64_t *seg_off, const int32_t *kofs, int2 *stack,
                                                        const BEnt *bent, const double *na, double eps,
-                                                       int32_t buf_cap, KSizes ksz, int nks) {
+                                                       int32_t buf_cap, KSizes ksz, int nks, int32_t nbr,
+                                                       const int32_t *ord, int64_t per_xcd) {
   extern __shared__ uint32_t sm[];
-  const int32_t i = blockIdx.x;
-  const int pass = blockIdx.y / nwin, w = blockIdx.y - pass * nwin;
+  const RowUnit ru = row_unit(nbr, nks * nwin, per_xcd, ord);
+  if (!ru.ok) return;
+  const int32_t i = ru.row;
+  const int pass = ru.unit / nwin, w = ru.unit - pass * nwin;
   const int lane = threadIdx.x;
   const int64_t s0 = wslot[(int64_t)i * (nwin + 1) + w], s1 = wslot[(int64_t)i * (nwin + 1) + w + 1];
   const int32_t ns = (int32_t)(s1 - s0);
@@ -753,8 +796,9 @@ void symbolic_count(const SymArgs &g, int64_t *row_nnz, int32_t *max_row, hipStr
     HIPCHECK(hipMemsetAsync(row_nnz, 0, sizeof(int64_t) * nbr, s));
     return;
   }
-  hipLaunchKernelGGL(k_sym_count, dim3(nbr), dim3(SYM_THREADS), W * sizeof(uint32_t), s, view(*g.a), view(*g.b),
-                     g.cold_rp, g.cold_ci, g.use_cold ? 1 : 0, g.nbc, row_nnz, max_row);
+  const int64_t px = row_units_per_xcd(nbr, 1);
+  hipLaunchKernelGGL(k_sym_count, dim3((unsigned)(px * 8)), dim3(SYM_THREADS), W * sizeof(uint32_t), s, view(*g.a),
+                     view(*g.b), g.cold_rp, g.cold_ci, g.use_cold ? 1 : 0, g.nbc, row_nnz, max_row, nbr, g.ord, px);
   HIPCHECK(hipGetLastError());
 }
 
@@ -771,11 +815,12 @@ void symbolic_fill(const FillArgs &f, hipStream_t s) {
   size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 4;
   if (lds + sizeof(AOpen) * (SYM_THREADS / 64) + 1024 > 65536)
     HIPCHECK(hipFuncSetAttribute((const void *)k_sym_fill, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_sym_fill, dim3(nbr), dim3(SYM_THREADS), lds, s, view(*f.sym.a), view(*f.sym.b),
+  const int64_t px = row_units_per_xcd(nbr, 1);
+  hipLaunchKernelGGL(k_sym_fill, dim3((unsigned)(px * 8)), dim3(SYM_THREADS), lds, s, view(*f.sym.a), view(*f.sym.b),
                      f.sym.cold_rp, f.sym.cold_ci, f.sym.use_cold ? 1 : 0, f.sym.retain ? 1 : 0, f.sym.nbc,
                      f.c_rp, f.c_ci, f.c_row, f.c_size, f.c_cnt, f.c_kflops, f.row_cand, f.row_real,
                      reinterpret_cast<const BEnt *>(f.bent), f.na, f.eps, cap, ks, nkp, f.cnt_g,
-                     nkp > 0 ? f.kofs : nullptr);
+                     nkp > 0 ? f.kofs : nullptr, nbr, f.sym.ord, px);
   HIPCHECK(hipGetLastError());
 }
 
@@ -815,7 +860,7 @@ StackWindows stack_windows(int32_t nbc, int32_t max_row, int nks) {
 void window_bounds(const int64_t *rp, const int32_t *ci, int32_t nrows, const StackWindows &sw, int64_t *out,
                    int32_t *max_cnt, hipStream_t s) {
   if (nrows == 0 || sw.nwin < 1) return;
-  hipLaunchKernelGGL(k_window_bounds, dim3(nrows), dim3(64), sizeof(int64_t) * (sw.nwin + 1), s, rp, ci, sw.wc,
+  hipLaunchKernelGGL(k_window_bounds, dim3(nrows), dim3(256), sizeof(int64_t) * (sw.nwin + 1), s, rp, ci, sw.wc,
                      sw.nwin, out, max_cnt);
   HIPCHECK(hipGetLastError());
 }
@@ -845,15 +890,17 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
     if (lw > 65536)
       HIPCHECK(hipFuncSetAttribute((const void *)k_stack_fill_win, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lw));
-    hipLaunchKernelGGL(k_stack_fill_win, dim3(g.nbr, nks * g.win.nwin), dim3(64), lw, s, va, vb, g.wslot, g.bwin,
+    const int64_t px = row_units_per_xcd(g.nbr, nks * g.win.nwin);
+    hipLaunchKernelGGL(k_stack_fill_win, dim3((unsigned)(px * 8)), dim3(64), lw, s, va, vb, g.wslot, g.bwin,
                        g.win.nwin, g.win.wc, g.c_ci, g.seg_off, g.kofs, g.stack, bent, g.na, g.eps, buf_cap, ks,
-                       nks);
+                       nks, g.nbr, g.ord, px);
     HIPCHECK(hipGetLastError());
     return;
   }
-  hipLaunchKernelGGL(k_stack_fill, dim3(g.nbr, std::max(nks, 1)), dim3(64), lds, s, va, vb, g.nbc, g.c_rp, g.c_ci,
+  const int64_t px = row_units_per_xcd(g.nbr, std::max(nks, 1));
+  hipLaunchKernelGGL(k_stack_fill, dim3((unsigned)(px * 8)), dim3(64), lds, s, va, vb, g.nbc, g.c_rp, g.c_ci,
                      g.seg_off, nks > 0 ? g.kofs : nullptr, g.stack, bent, g.na, g.eps, cap, run, ks, nks,
-                     g.pad4 ? 1 : 0, g.encode ? 1 : 0);
+                     g.pad4 ? 1 : 0, g.encode ? 1 : 0, g.nbr, g.ord, px);
   HIPCHECK(hipGetLastError());
 }
 
