@@ -339,6 +339,47 @@ def test_errors(B, ctx):
     small.close()
 
 
+# ------------------------------------------------- stack generator windows
+def _windows(max_row, nbc):
+    """Column windows the stack generator uses: 32 bytes of LDS per C block
+    of a window within a 16 KB budget (mirrors the library's choice)."""
+    nwin = min(16, max(1, -(-max_row * 32 // 16384)))
+    wc = (-(-nbc // nwin) + 31) // 32 * 32
+    return -(-nbc // wc), wc
+
+
+def test_stack_windows(B, ctx):
+    """Result rows crowded into one column window, with more C blocks there
+    than the LDS groups hold (entries written one by one), beside windows
+    whose entries go out in groups of four; with and without filtering, and
+    under retain_sparsity (products whose C block is absent are skipped)."""
+    rng = np.random.default_rng(77)
+    nk, nbc, nbr = 40, 3000, 96
+    ks = rng.choice(np.array([2, 3], dtype=np.int32), nk)
+    a = random_bcsr(rng, nbr, nk, p=0.5, rbs=rng.choice(np.array([1, 2, 3], dtype=np.int32), nbr), cbs=ks)
+    rows, cols = [], []
+    for k in range(nk):   # dense-ish in columns [0, 900), sparse beyond
+        c = np.concatenate([np.nonzero(rng.random(900) < 0.5)[0], 900 + np.nonzero(rng.random(nbc - 900) < 0.02)[0]])
+        rows.append(np.full(c.size, k))
+        cols.append(c)
+    b = inputs.from_pattern(ks, rng.choice(np.array([1, 2], dtype=np.int32), nbc), np.concatenate(rows),
+                            np.concatenate(cols), rng)
+    for eps in (0.0, 2.0):
+        ref = oracle.multiply("N", "N", 1.0, a, b, eps=eps, nthreads=8)
+        host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=eps)
+        _check_exact(host, info, ref)
+    widths = np.diff(ref.row_ptr)
+    nwin, wc = _windows(int(widths.max()), nbc)
+    per_win = [np.bincount(ref.col_idx[ref.row_ptr[i]:ref.row_ptr[i + 1]] // wc, minlength=nwin) for i in range(nbr)]
+    per_win = np.concatenate(per_win)
+    _log(f"stack windows: {nwin} of {wc} columns, most C blocks in one window {per_win.max()}")
+    assert nwin > 1 and per_win.max() > 512 and np.any((per_win > 0) & (per_win <= 512))
+    cold = random_bcsr(rng, nbr, nbc, p=0.2, rbs=a.rbs, cbs=b.cbs)
+    ref = oracle.multiply("N", "N", 1.0, a, b, 0.5, cold, retain_sparsity=True)
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, 0.5, cold, retain=True)
+    _check_exact(host, info, ref)
+
+
 # ------------------------------------------------------------ wide rows
 @pytest.mark.parametrize("nbc,p", [(9000, 0.3), (140000, 0.012)])
 def test_wide_result_rows(B, ctx, nbc, p):
