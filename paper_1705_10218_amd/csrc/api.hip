@@ -306,6 +306,38 @@ static void plan_build(Plan &P, char transa, char transb) {
     block_norms(*B, nb.p, s);
   }
   tm.mark();  // 2
+  std::vector<int32_t> ksizes(opa_c.begin(), opa_c.end());
+  std::sort(ksizes.begin(), ksizes.end());
+  ksizes.erase(std::unique(ksizes.begin(), ksizes.end()), ksizes.end());
+  const uint64_t two_gb = 1ull << 31;
+  // quad path of the GEMM: packed operand copies below 2 GB (32-bit byte
+  // offsets in the stack entries), at most 8 distinct k sizes.  A packed
+  // block pads its contraction extent k to a multiple of 2 (FP64) or 4
+  // (FP32 / split, half the bytes), so it holds at most (k + 1) / k or
+  // (k + 3) / k times the values of the stored block; kmin bounds both.
+  const bool lowp = P.lowp = ctx->mode != BSMM_COMPUTE_FP64;
+  const double kmin = ksizes.empty() ? 1.0 : (double)ksizes.front();
+  const double grow = lowp ? 0.5 * (kmin + 3.0) / kmin : (kmin + 1.0) / kmin;
+  const bool quads = P.quads = !ksizes.empty() && ksizes.size() <= 8 &&
+                               (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
+                               (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
+  // packed operand offsets for the quad path (op(A) row-major, op(B)
+  // column-major) and one record per entry of op(B) for the product loops
+  // of a2 and a4: both depend on A and B only, so they are queued before
+  // the symbolic phase's size read-back and run while the host waits
+  if (quads) {
+    P.a_poff = DBuf<int64_t>(al, (size_t)A->nnzb + 1);
+    P.b_poff = DBuf<int64_t>(al, (size_t)B->nnzb + 1);
+    if (lowp) {   // FP32 k-quad slabs
+      pack32_offsets(al, *A, ta, P.a_poff.p, s);
+      pack32_offsets(al, *B, !tb, P.b_poff.p, s);
+    } else {      // FP64 k-pair slabs
+      pack_offsets(al, *A, ta, P.a_poff.p, s);
+      pack_offsets(al, *B, !tb, P.b_poff.p, s);
+    }
+  }
+  DBuf<int4> bent(al, (size_t)std::max<int64_t>(ob.nnzb, 1));
+  product_records(ob, filt ? nb.p : nullptr, quads ? P.b_poff.p : nullptr, bent.p, s);
   // ------------------------------------------------------- a2: symbolic
   SymArgs sym;
   sym.a = &oa;
@@ -359,21 +391,6 @@ static void plan_build(Plan &P, char transa, char transb) {
   DBuf<int32_t> c_cnt(al, nc1);
   DBuf<int64_t> c_size(al, nc1), row_kmn(al, std::max<int32_t>(nbr, 1)), row_cand(al, std::max<int32_t>(nbr, 1)),
       row_real(al, std::max<int32_t>(nbr, 1));
-  std::vector<int32_t> ksizes(opa_c.begin(), opa_c.end());
-  std::sort(ksizes.begin(), ksizes.end());
-  ksizes.erase(std::unique(ksizes.begin(), ksizes.end()), ksizes.end());
-  const uint64_t two_gb = 1ull << 31;
-  // quad path of the GEMM: packed operand copies below 2 GB (32-bit byte
-  // offsets in the stack entries), at most 8 distinct k sizes.  A packed
-  // block pads its contraction extent k to a multiple of 2 (FP64) or 4
-  // (FP32 / split, half the bytes), so it holds at most (k + 1) / k or
-  // (k + 3) / k times the values of the stored block; kmin bounds both.
-  const bool lowp = P.lowp = ctx->mode != BSMM_COMPUTE_FP64;
-  const double kmin = ksizes.empty() ? 1.0 : (double)ksizes.front();
-  const double grow = lowp ? 0.5 * (kmin + 3.0) / kmin : (kmin + 1.0) / kmin;
-  const bool quads = P.quads = !ksizes.empty() && ksizes.size() <= 8 &&
-                               (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
-                               (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
   DBuf<int32_t> cnt_g;
   if (quads && (int64_t)max_row * (int64_t)ksizes.size() > 8192) {
     cnt_g = DBuf<int32_t>(al, nc1 * ksizes.size());
@@ -397,23 +414,8 @@ static void plan_build(Plan &P, char transa, char transb) {
   fa.ksizes = ksizes;
   fa.cnt_g = cnt_g.p;
   fa.kofs = kofs.p;
-  // packed operand offsets for the quad path (op(A) row-major, op(B) column-major)
   if (lowp && !quads && nnzb_c > 0)
     fail(BSMM_ERR_UNSUPPORTED, "FP32 / split modes need packed operands below 2 GB and at most 8 distinct k block sizes");
-  if (quads) {
-    P.a_poff = DBuf<int64_t>(al, (size_t)A->nnzb + 1);
-    P.b_poff = DBuf<int64_t>(al, (size_t)B->nnzb + 1);
-    if (lowp) {   // FP32 k-quad slabs
-      pack32_offsets(al, *A, ta, P.a_poff.p, s);
-      pack32_offsets(al, *B, !tb, P.b_poff.p, s);
-    } else {      // FP64 k-pair slabs
-      pack_offsets(al, *A, ta, P.a_poff.p, s);
-      pack_offsets(al, *B, !tb, P.b_poff.p, s);
-    }
-  }
-  // one record per entry of op(B) for the product loops of a2 and a4
-  DBuf<int4> bent(al, (size_t)std::max<int64_t>(ob.nnzb, 1));
-  product_records(ob, filt ? nb.p : nullptr, quads ? P.b_poff.p : nullptr, bent.p, s);
   fa.na = filt ? na.p : nullptr;
   fa.bent = bent.p;
   fa.eps = eps;
