@@ -375,11 +375,15 @@ static void plan_build(Plan &P, char transa, char transb) {
       } else {
         HIPCHECK(hipMemsetAsync(P.c_rp.p, 0, sizeof(int64_t), s));
       }
-      HIPCHECK(hipMemcpyAsync(ctx->pinned, P.c_rp.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipMemcpyAsync(ctx->pinned + 1, dmax.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      PlanTotals T;
+      T.at[0] = P.c_rp.p + nbr;
+      T.at32 = dmax.p;
+      DBuf<int64_t> tot(al, 8);
+      plan_totals(T, tot.p, s);
+      HIPCHECK(hipMemcpyAsync(ctx->pinned, tot.p, sizeof(int64_t) * 8, hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
       nnzb_c = ctx->pinned[0];
-      max_row = (int32_t)(ctx->pinned[1] & 0xffffffff);
+      max_row = (int32_t)ctx->pinned[7];
     }
   }
   P.nnzb_c = nnzb_c;
@@ -432,35 +436,38 @@ static void plan_build(Plan &P, char transa, char transb) {
     HIPCHECK(hipMemsetAsync(dmax_ns.p, 0, sizeof(int32_t) * 2, s));
     window_bounds(P.c_rp.p, P.c_ci.p, nbr, sw, wslot.p, dmax_ns.p, s);
     window_bounds(ob.row_ptr, ob.col_idx, ob.nbr, sw, bwin.p, nullptr, s);
-    HIPCHECK(hipMemcpyAsync(ctx->pinned + 7, dmax_ns.p, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
   }
   P.c_off = DBuf<int64_t>(al, nc1 + 1);
   P.seg_off = DBuf<int64_t>(al, nc1 + 1);
-  DBuf<int64_t> kmn_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1),
-      cand_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1), real_scan(al, (size_t)std::max<int32_t>(nbr, 1) + 1);
   exclusive_scan_i64(al, c_size.p, P.c_off.p, nnzb_c, s);
   exclusive_scan_i32(al, c_cnt.p, P.seg_off.p, nnzb_c, s);
-  exclusive_scan_i64(al, row_kmn.p, kmn_scan.p, nbr, s);
-  exclusive_scan_i64(al, row_cand.p, cand_scan.p, nbr, s);
-  exclusive_scan_i64(al, row_real.p, real_scan.p, nbr, s);
-  if (quads) {
-    HIPCHECK(hipMemcpyAsync(ctx->pinned + 5, P.a_poff.p + A->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(ctx->pinned + 6, P.b_poff.p + B->nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  // every size the rest of the plan needs, in one read-back
+  {
+    PlanTotals T;
+    T.at[0] = P.c_off.p + nnzb_c;     // C values
+    T.at[1] = P.seg_off.p + nnzb_c;   // stack entries, padding included
+    if (quads) {
+      T.at[2] = P.a_poff.p + A->nnzb;   // packed copies, in units of 8 bytes
+      T.at[3] = P.b_poff.p + B->nnzb;
+    }
+    T.sum[0] = row_kmn.p;
+    T.sum[1] = row_cand.p;
+    T.sum[2] = row_real.p;
+    T.n = nbr;
+    T.at32 = (sw.nwin > 0 && nnzb_c > 0) ? dmax_ns.p : nullptr;
+    DBuf<int64_t> tot(al, 8);
+    plan_totals(T, tot.p, s);
+    HIPCHECK(hipMemcpyAsync(ctx->pinned, tot.p, sizeof(int64_t) * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
   }
-  HIPCHECK(hipMemcpyAsync(ctx->pinned, P.c_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipMemcpyAsync(ctx->pinned + 1, P.seg_off.p + nnzb_c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipMemcpyAsync(ctx->pinned + 2, kmn_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipMemcpyAsync(ctx->pinned + 3, cand_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipMemcpyAsync(ctx->pinned + 4, real_scan.p + nbr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
   P.nval_c = ctx->pinned[0];
-  P.nstack = ctx->pinned[1];   // stack entries, padding included
-  P.nprod = ctx->pinned[4];
-  P.kmn_total = ctx->pinned[2];
-  P.ncand = ctx->pinned[3];
-  P.a_pack_n = quads ? ctx->pinned[5] : 0;
-  P.b_pack_n = quads ? ctx->pinned[6] : 0;
-  const int32_t max_ns = (sw.nwin > 0 && nnzb_c > 0) ? (int32_t)(ctx->pinned[7] & 0x7fffffff) : 0;
+  P.nstack = ctx->pinned[1];
+  P.a_pack_n = quads ? ctx->pinned[2] : 0;
+  P.b_pack_n = quads ? ctx->pinned[3] : 0;
+  P.kmn_total = ctx->pinned[4];
+  P.ncand = ctx->pinned[5];
+  P.nprod = ctx->pinned[6];
+  const int32_t max_ns = (int32_t)ctx->pinned[7];
   if (C0 && beta != 0.0 && nnzb_c > 0) {
     P.old_blk = DBuf<int32_t>(al, nc1);
     HIPCHECK(hipMemsetAsync(P.old_blk.p, 0xff, sizeof(int32_t) * nc1, s));

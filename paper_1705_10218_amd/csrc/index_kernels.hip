@@ -277,6 +277,41 @@ void transpose_index(Allocator &al, const bsmm_mat_s &x, OpIndex &op, hipStream_
   op.blk = op.own_blk.p;
 }
 
+namespace {
+// One workgroup: out[0..3] = *at[0..3], out[4..6] = sums of the three
+// arrays over n entries, out[7] = *at32 (0 for a null pointer).  Integer
+// sums: the result does not depend on the order.
+__global__ __launch_bounds__(1024) void k_plan_totals(PlanTotals T, int64_t *out) {
+  __shared__ int64_t red[3][16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+  int64_t acc[3] = {0, 0, 0};
+  for (int64_t i = t; i < T.n; i += blockDim.x)
+#pragma unroll
+    for (int u = 0; u < 3; u++) acc[u] += T.sum[u][i];
+#pragma unroll
+  for (int u = 0; u < 3; u++) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc[u] += __shfl_xor(acc[u], d, 64);
+    if (lane == 0) red[u][wv] = acc[u];
+  }
+  __syncthreads();
+  if (t < 3) {
+    int64_t v = 0;
+    for (int w = 0; w < nw; w++) v += red[t][w];
+    out[4 + t] = v;
+  } else if (t >= 8 && t < 12) {
+    out[t - 8] = T.at[t - 8] ? *T.at[t - 8] : 0;
+  } else if (t == 12) {
+    out[7] = T.at32 ? (int64_t)*T.at32 : 0;
+  }
+}
+}  // namespace
+
+void plan_totals(const PlanTotals &T, int64_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan_totals, dim3(1), dim3(1024), 0, s, T, out);
+  HIPCHECK(hipGetLastError());
+}
+
 void block_norms(const bsmm_mat_s &x, double *norms, hipStream_t s) {
   if (x.nnzb == 0) return;
   constexpr int U = 4;

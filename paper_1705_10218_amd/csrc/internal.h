@@ -130,6 +130,18 @@ void transpose_index(Allocator &al, const bsmm_mat_s &x, OpIndex &op, hipStream_
 // Frobenius norm of every block (a1).
 void block_norms(const bsmm_mat_s &x, double *norms, hipStream_t s);
 
+// Sizes the plan reads back after the symbolic phase, gathered in one
+// 8-entry record (one copy to the host): out[0..3] = *at[0..3],
+// out[4..6] = the sums of sum[0..2] over n entries, out[7] = *at32; a null
+// pointer reads as 0.
+struct PlanTotals {
+  const int64_t *at[4] = {nullptr, nullptr, nullptr, nullptr};
+  const int64_t *sum[3] = {nullptr, nullptr, nullptr};
+  int64_t n = 0;
+  const int32_t *at32 = nullptr;
+};
+void plan_totals(const PlanTotals &T, int64_t *out, hipStream_t s);
+
 struct SymArgs {
   const OpIndex *a, *b;
   // C_old pattern (may be null)
