@@ -348,6 +348,14 @@ static void plan_build(Plan &P, char transa, char transb) {
   sym.ord = nbr > 0 ? row_order(ctx, A) : nullptr;
   sym.retain = retain != 0;
   sym.use_cold = (beta != 0.0) && !retain && C0;
+  DBuf<uint32_t> sym_bits;
+  if (!retain) {
+    const size_t nw = symbolic_bits_words(nbr, nbc);
+    if (nw > 0) {
+      sym_bits = DBuf<uint32_t>(al, nw);
+      sym.bits = sym_bits.p;
+    }
+  }
   if (C0) {
     sym.cold_rp = C0->d_row_ptr;
     sym.cold_ci = C0->d_col_idx;

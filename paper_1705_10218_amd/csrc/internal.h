@@ -151,7 +151,13 @@ struct SymArgs {
   bool retain = false;       // pattern = C_old pattern exactly
   int32_t nbc = 0;           // block columns of C
   const int32_t *ord = nullptr;   // order in which rows are handed out (device; null = 0..nbr-1)
+  uint32_t *bits = nullptr;       // per-row column bitmaps kept from count to fill (optional,
+                                  // symbolic_bits_words(nbr, nbc) words)
 };
+
+// Words of the per-row bitmaps the counting pass can keep for the fill; 0
+// when the columns need several bitmap windows or the bitmaps would be large.
+size_t symbolic_bits_words(int32_t nbr, int32_t nbc);
 
 // a2: per C block row, number of distinct result block columns.
 void symbolic_count(const SymArgs &g, int64_t *row_nnz, int32_t *max_row, hipStream_t s);

@@ -133,24 +133,24 @@ __device__ inline int open_a(const OpView &A, const OpView &B, int64_t p0, int64
 // Visits the products of the opened entries of one wavefront (B row starts
 // qb[e], lengths nq[e], e < ne) in chunks of up to 64 consecutive entries
 // of one B row, a lane per product, in ascending (entry, q) order, calling
-// f(e, load(q)) on the lanes that hold a product.  WALK_DEPTH chunks are
+// f(e, load(q)) on the lanes that hold a product.  D chunks are
 // loaded back to back (every lane loads; a lane without a product loads
 // item 0, so no branch separates the loads) before they are handled: one
-// memory latency per WALK_DEPTH chunks.  load(0) must be a valid item
+// memory latency per D chunks.  load(0) must be a valid item
 // whenever some opened entry exists.
 constexpr int WALK_DEPTH = 8;
 
-template <typename T, typename L, typename F>
+template <typename T, int D = WALK_DEPTH, typename L, typename F>
 __device__ inline void chunk_walk(const int64_t *qb, const int32_t *nq, int ne, L load, F f) {
   const int lane = threadIdx.x & 63;
   int e = 0;   // next chunk: entry e, offset o
   int32_t o = 0;
   while (e < ne) {
-    int pe[WALK_DEPTH];
-    bool pv[WALK_DEPTH];
-    T v[WALK_DEPTH];
+    int pe[D];
+    bool pv[D];
+    T v[D];
 #pragma unroll
-    for (int d = 0; d < WALK_DEPTH; d++) {
+    for (int d = 0; d < D; d++) {
       const bool live = e < ne;   // uniform
       const int es = live ? e : 0;
       const int32_t n = nq[es];
@@ -166,7 +166,7 @@ __device__ inline void chunk_walk(const int64_t *qb, const int32_t *nq, int ne, 
       }
     }
 #pragma unroll
-    for (int d = 0; d < WALK_DEPTH; d++)
+    for (int d = 0; d < D; d++)
       if (pv[d]) f(pe[d], v[d]);
   }
 }
@@ -255,7 +255,7 @@ __device__ inline void word_prefix(const uint32_t *bm, int32_t *pre, int32_t W, 
 __global__ __launch_bounds__(SYM_THREADS) void k_sym_count(OpView A, OpView B, const int64_t *cold_rp,
                                                            const int32_t *cold_ci, int use_cold, int32_t nbc,
                                                            int64_t *row_nnz, int32_t *max_row, int32_t nbr,
-                                                           const int32_t *ord, int64_t per_xcd) {
+                                                           const int32_t *ord, int64_t per_xcd, uint32_t *gbits) {
   extern __shared__ uint32_t bm[];
   __shared__ int64_t red[SYM_THREADS / 64];
   __shared__ AOpen stage[SYM_THREADS / 64];
@@ -278,7 +278,10 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_count(OpView A, OpView B, c
     mark_candidates(A, B, i, j0, j1, bm, stage);
     __syncthreads();
     int64_t c = 0;
-    for (int32_t t = threadIdx.x; t < W; t += blockDim.x) c += __popc(bm[t]);
+    for (int32_t t = threadIdx.x; t < W; t += blockDim.x) {
+      c += __popc(bm[t]);
+      if (gbits) gbits[(int64_t)i * W + t] = bm[t];   // kept for the fill (single window)
+    }
     total += block_sum<int64_t>(c, red);
   }
   if (threadIdx.x == 0) {
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
                                                           const BEnt *bent, const double *na, double eps,
                                                           int32_t cnt_cap, KSizes ksz, int nkp, int32_t *cnt_g,
                                                           int32_t *kofs, int32_t nbr, const int32_t *ord,
-                                                          int64_t per_xcd) {
+                                                          int64_t per_xcd, const uint32_t *gbits) {
   extern __shared__ uint32_t sm[];
   __shared__ int32_t shi[SYM_THREADS / 64];
   __shared__ int64_t shl[SYM_THREADS / 64];
@@ -324,13 +327,17 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
   int64_t wbase = cbase;
   for (int32_t win = 0; win < nwin; win++) {
     int32_t j0 = win * W * 32, j1 = min(nbc, j0 + W * 32);
-    for (int32_t t = threadIdx.x; t < W; t += blockDim.x) bm[t] = 0u;
-    __syncthreads();
-    if (retain) {
-      mark_row(cold_rp, cold_ci, i, j0, j1, bm);
+    if (gbits) {   // the counting pass's bitmap of this row (single window)
+      for (int32_t t = threadIdx.x; t < W; t += blockDim.x) bm[t] = gbits[(int64_t)i * W + t];
     } else {
-      if (use_cold) mark_row(cold_rp, cold_ci, i, j0, j1, bm);
-      mark_candidates(A, B, i, j0, j1, bm, stage);
+      for (int32_t t = threadIdx.x; t < W; t += blockDim.x) bm[t] = 0u;
+      __syncthreads();
+      if (retain) {
+        mark_row(cold_rp, cold_ci, i, j0, j1, bm);
+      } else {
+        if (use_cold) mark_row(cold_rp, cold_ci, i, j0, j1, bm);
+        mark_candidates(A, B, i, j0, j1, bm, stage);
+      }
     }
     __syncthreads();
     word_prefix(bm, pre, W, shi);
@@ -739,7 +746,7 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
     // then orders against every load in flight
     auto walk = [&](auto buffered_t) {
       constexpr bool BUF = decltype(buffered_t)::value;
-      chunk_walk<BEnt>(s_qb, s_nq, ne, [&](int64_t q) { return bent[q]; }, [&](int e, const BEnt &v) {
+      chunk_walk<BEnt, 16>(s_qb, s_nq, ne, [&](int64_t q) { return bent[q]; }, [&](int e, const BEnt &v) {
         if (na && (s_na[e] * v.nb < eps)) return;
         const int32_t jj = v.j - j0;
         if (!bm_test(bm, jj)) return;   // only under retain_sparsity
@@ -787,6 +794,13 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
 
 }  // namespace
 
+size_t symbolic_bits_words(int32_t nbr, int32_t nbc) {
+  const int64_t words_total = ((int64_t)nbc + 31) >> 5;
+  if (words_total == 0 || words_total > MAX_WORDS) return 0;
+  const size_t n = (size_t)nbr * (size_t)words_total;
+  return n * 4 <= ((size_t)256 << 20) ? n : 0;
+}
+
 void symbolic_count(const SymArgs &g, int64_t *row_nnz, int32_t *max_row, hipStream_t s) {
   int32_t nbr = g.a->nbr;
   if (nbr == 0) return;
@@ -798,7 +812,8 @@ void symbolic_count(const SymArgs &g, int64_t *row_nnz, int32_t *max_row, hipStr
   }
   const int64_t px = row_units_per_xcd(nbr, 1);
   hipLaunchKernelGGL(k_sym_count, dim3((unsigned)(px * 8)), dim3(SYM_THREADS), W * sizeof(uint32_t), s, view(*g.a),
-                     view(*g.b), g.cold_rp, g.cold_ci, g.use_cold ? 1 : 0, g.nbc, row_nnz, max_row, nbr, g.ord, px);
+                     view(*g.b), g.cold_rp, g.cold_ci, g.use_cold ? 1 : 0, g.nbc, row_nnz, max_row, nbr, g.ord, px,
+                     words_total <= MAX_WORDS ? g.bits : nullptr);
   HIPCHECK(hipGetLastError());
 }
 
@@ -820,7 +835,8 @@ void symbolic_fill(const FillArgs &f, hipStream_t s) {
                      f.sym.cold_rp, f.sym.cold_ci, f.sym.use_cold ? 1 : 0, f.sym.retain ? 1 : 0, f.sym.nbc,
                      f.c_rp, f.c_ci, f.c_row, f.c_size, f.c_cnt, f.c_kflops, f.row_cand, f.row_real,
                      reinterpret_cast<const BEnt *>(f.bent), f.na, f.eps, cap, ks, nkp, f.cnt_g,
-                     nkp > 0 ? f.kofs : nullptr, nbr, f.sym.ord, px);
+                     nkp > 0 ? f.kofs : nullptr, nbr, f.sym.ord, px,
+                     (words_total <= MAX_WORDS && !f.sym.retain) ? f.sym.bits : nullptr);
   HIPCHECK(hipGetLastError());
 }
 
