@@ -365,8 +365,6 @@ static void plan_build(Plan &P, char transa, char transb) {
   int32_t max_row = 0;
   {
     DBuf<int64_t> row_nnz(al, std::max<int32_t>(nbr, 1));
-    DBuf<int32_t> dmax(al, 1);
-    HIPCHECK(hipMemsetAsync(dmax.p, 0, sizeof(int32_t), s));
     if (retain) {
       // pattern = C_old pattern; row lengths from its row_ptr
       HIPCHECK(hipMemcpyAsync(P.c_rp.p, C0->d_row_ptr, sizeof(int64_t) * ((size_t)nbr + 1), hipMemcpyDeviceToDevice, s));
@@ -377,7 +375,7 @@ static void plan_build(Plan &P, char transa, char transb) {
       HIPCHECK(hipStreamSynchronize(s));
       for (int32_t i = 0; i < nbr; i++) max_row = std::max<int32_t>(max_row, (int32_t)(h[i + 1] - h[i]));
     } else {
-      symbolic_count(sym, row_nnz.p, dmax.p, s);
+      symbolic_count(sym, row_nnz.p, nullptr, s);
       if (nbr > 0) {
         exclusive_scan_i64(al, row_nnz.p, P.c_rp.p, nbr, s);
       } else {
@@ -385,7 +383,8 @@ static void plan_build(Plan &P, char transa, char transb) {
       }
       PlanTotals T;
       T.at[0] = P.c_rp.p + nbr;
-      T.at32 = dmax.p;
+      T.mx64 = row_nnz.p;   // widest result row
+      T.nmx = nbr;
       DBuf<int64_t> tot(al, 8);
       plan_totals(T, tot.p, s);
       HIPCHECK(hipMemcpyAsync(ctx->pinned, tot.p, sizeof(int64_t) * 8, hipMemcpyDeviceToHost, s));
@@ -440,8 +439,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   if (sw.nwin > 0 && nnzb_c > 0) {
     wslot = DBuf<int64_t>(al, (size_t)nbr * (sw.nwin + 1));
     bwin = DBuf<int64_t>(al, (size_t)std::max<int32_t>(ob.nbr, 1) * (sw.nwin + 1));
-    dmax_ns = DBuf<int32_t>(al, 2);
-    HIPCHECK(hipMemsetAsync(dmax_ns.p, 0, sizeof(int32_t) * 2, s));
+    dmax_ns = DBuf<int32_t>(al, (size_t)std::max<int32_t>(nbr, 1));   // per row
     window_bounds(P.c_rp.p, P.c_ci.p, nbr, sw, wslot.p, dmax_ns.p, s);
     window_bounds(ob.row_ptr, ob.col_idx, ob.nbr, sw, bwin.p, nullptr, s);
   }
@@ -462,7 +460,10 @@ static void plan_build(Plan &P, char transa, char transb) {
     T.sum[1] = row_cand.p;
     T.sum[2] = row_real.p;
     T.n = nbr;
-    T.at32 = (sw.nwin > 0 && nnzb_c > 0) ? dmax_ns.p : nullptr;
+    if (sw.nwin > 0 && nnzb_c > 0) {   // most C blocks of one row in one window
+      T.mx32 = dmax_ns.p;
+      T.nmx = nbr;
+    }
     DBuf<int64_t> tot(al, 8);
     plan_totals(T, tot.p, s);
     HIPCHECK(hipMemcpyAsync(ctx->pinned, tot.p, sizeof(int64_t) * 8, hipMemcpyDeviceToHost, s));

@@ -279,30 +279,34 @@ void transpose_index(Allocator &al, const bsmm_mat_s &x, OpIndex &op, hipStream_
 
 namespace {
 // One workgroup: out[0..3] = *at[0..3], out[4..6] = sums of the three
-// arrays over n entries, out[7] = *at32 (0 for a null pointer).  Integer
-// sums: the result does not depend on the order.
+// arrays over n entries, out[7] = the largest entry of the max array (0 for
+// a null pointer).  Integer sums and maxima: the result does not depend on
+// the order.
 __global__ __launch_bounds__(1024) void k_plan_totals(PlanTotals T, int64_t *out) {
-  __shared__ int64_t red[3][16];
+  __shared__ int64_t red[4][16];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
-  int64_t acc[3] = {0, 0, 0};
+  int64_t acc[4] = {0, 0, 0, 0};
   for (int64_t i = t; i < T.n; i += blockDim.x)
 #pragma unroll
     for (int u = 0; u < 3; u++) acc[u] += T.sum[u][i];
+  for (int64_t i = t; i < T.nmx; i += blockDim.x)
+    acc[3] = max(acc[3], T.mx64 ? T.mx64[i] : (int64_t)T.mx32[i]);
 #pragma unroll
-  for (int u = 0; u < 3; u++) {
+  for (int u = 0; u < 4; u++) {
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) acc[u] += __shfl_xor(acc[u], d, 64);
+    for (int d = 32; d >= 1; d >>= 1) {
+      const int64_t o = __shfl_xor(acc[u], d, 64);
+      acc[u] = u < 3 ? acc[u] + o : max(acc[u], o);
+    }
     if (lane == 0) red[u][wv] = acc[u];
   }
   __syncthreads();
-  if (t < 3) {
+  if (t < 4) {
     int64_t v = 0;
-    for (int w = 0; w < nw; w++) v += red[t][w];
-    out[4 + t] = v;
+    for (int w = 0; w < nw; w++) v = t < 3 ? v + red[t][w] : max(v, red[t][w]);
+    out[t < 3 ? 4 + t : 7] = v;
   } else if (t >= 8 && t < 12) {
     out[t - 8] = T.at[t - 8] ? *T.at[t - 8] : 0;
-  } else if (t == 12) {
-    out[7] = T.at32 ? (int64_t)*T.at32 : 0;
   }
 }
 }  // namespace

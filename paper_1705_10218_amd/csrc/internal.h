@@ -130,15 +130,17 @@ void transpose_index(Allocator &al, const bsmm_mat_s &x, OpIndex &op, hipStream_
 // Frobenius norm of every block (a1).
 void block_norms(const bsmm_mat_s &x, double *norms, hipStream_t s);
 
-// Sizes the plan reads back after the symbolic phase, gathered in one
-// 8-entry record (one copy to the host): out[0..3] = *at[0..3],
-// out[4..6] = the sums of sum[0..2] over n entries, out[7] = *at32; a null
-// pointer reads as 0.
+// Sizes the plan reads back, gathered in one 8-entry record (one copy to
+// the host): out[0..3] = *at[0..3], out[4..6] = the sums of sum[0..2] over
+// n entries, out[7] = the largest of mx64[0..nmx) or mx32[0..nmx) (0 if
+// neither); a null pointer reads as 0.
 struct PlanTotals {
   const int64_t *at[4] = {nullptr, nullptr, nullptr, nullptr};
   const int64_t *sum[3] = {nullptr, nullptr, nullptr};
   int64_t n = 0;
-  const int32_t *at32 = nullptr;
+  const int64_t *mx64 = nullptr;
+  const int32_t *mx32 = nullptr;
+  int64_t nmx = 0;
 };
 void plan_totals(const PlanTotals &T, int64_t *out, hipStream_t s);
 
@@ -159,7 +161,8 @@ struct SymArgs {
 // when the columns need several bitmap windows or the bitmaps would be large.
 size_t symbolic_bits_words(int32_t nbr, int32_t nbc);
 
-// a2: per C block row, number of distinct result block columns.
+// a2: per C block row, number of distinct result block columns (max_row:
+// optional, receives the largest by atomics).
 void symbolic_count(const SymArgs &g, int64_t *row_nnz, int32_t *max_row, hipStream_t s);
 
 struct FillArgs {
@@ -199,10 +202,10 @@ struct StackWindows {
 StackWindows stack_windows(int32_t nbc, int32_t max_row, int nks);
 
 // out[r*(nwin+1) + w] = first entry of row r with column >= w*wc (the row's
-// end for w = nwin); max_cnt (optional, preset to 0) receives the largest
-// number of entries of one row inside one window.
+// end for w = nwin); row_max (optional, nrows entries) receives for every
+// row the largest number of its entries inside one window.
 void window_bounds(const int64_t *rp, const int32_t *ci, int32_t nrows, const StackWindows &sw, int64_t *out,
-                   int32_t *max_cnt, hipStream_t s);
+                   int32_t *row_max, hipStream_t s);
 
 struct StackArgs {
   const OpIndex *a, *b;

@@ -286,7 +286,7 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_count(OpView A, OpView B, c
   }
   if (threadIdx.x == 0) {
     row_nnz[i] = total;
-    atomicMax(max_row, (int32_t)total);
+    if (max_row) atomicMax(max_row, (int32_t)total);
   }
 }
 
@@ -615,9 +615,9 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
 
 // First entry of every block row whose column is at least w * wc, for
 // w = 0 .. nwin (one row per workgroup; the last is the row's end).  With
-// max_cnt, the largest number of entries of a row inside one window.
+// row_max, the largest number of entries of row r inside one window (in row_max[r]).
 __global__ __launch_bounds__(256) void k_window_bounds(const int64_t *rp, const int32_t *ci, int32_t wc, int nwin,
-                                                      int64_t *out, int32_t *max_cnt) {
+                                                      int64_t *out, int32_t *row_max) {
   extern __shared__ int64_t wb[];
   const int32_t r = blockIdx.x;
   const int t = threadIdx.x, nt = blockDim.x;
@@ -631,13 +631,14 @@ __global__ __launch_bounds__(256) void k_window_bounds(const int64_t *rp, const 
   }
   __syncthreads();
   for (int w = t; w <= nwin; w += nt) out[(int64_t)r * (nwin + 1) + w] = wb[w];
-  if (max_cnt) {   // one atomic per wavefront that holds windows
+  if (row_max) {   // windows are held by the first wavefront (nwin <= 64)
     int32_t mx = 0;
     for (int w = t; w < nwin; w += nt) mx = max(mx, (int32_t)(wb[w + 1] - wb[w]));
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d, 64));
-    if ((t & 63) == 0 && t < nwin && mx > 0) atomicMax(max_cnt, mx);
+    if (t == 0) row_max[r] = mx;
   }
+
 }
 
 // Stack generation for one (C block row i, k size, column window): the
@@ -874,10 +875,10 @@ StackWindows stack_windows(int32_t nbc, int32_t max_row, int nks) {
 }
 
 void window_bounds(const int64_t *rp, const int32_t *ci, int32_t nrows, const StackWindows &sw, int64_t *out,
-                   int32_t *max_cnt, hipStream_t s) {
+                   int32_t *row_max, hipStream_t s) {
   if (nrows == 0 || sw.nwin < 1) return;
   hipLaunchKernelGGL(k_window_bounds, dim3(nrows), dim3(256), sizeof(int64_t) * (sw.nwin + 1), s, rp, ci, sw.wc,
-                     sw.nwin, out, max_cnt);
+                     sw.nwin, out, row_max);
   HIPCHECK(hipGetLastError());
 }
 
