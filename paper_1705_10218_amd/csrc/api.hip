@@ -232,6 +232,9 @@ struct Plan {
   bsmm_ctx ctx = nullptr;
   bsmm_mat_s *A = nullptr, *B = nullptr, *C0 = nullptr;
   bool ta = false, tb = false, filt = false, post = false, quads = false, lowp = false;
+  // one_shot: built, executed once and consumed (bsmm_multiply); packed:
+  // the build already made the packed operand copies of the current values
+  bool one_shot = false, packed = false;
   double alpha = 1.0, beta = 0.0, eps = 0.0;
   int retain = 0;
   bsmm_compute_mode mode = BSMM_COMPUTE_FP64;
@@ -296,16 +299,6 @@ static void plan_build(Plan &P, char transa, char transb) {
   make_op(ctx, A, ta, oa);
   make_op(ctx, B, tb, ob);
   tm.mark();  // 1
-  // ------------------------------------------------------- a1: norms
-  DBuf<double> na, nb;
-  const bool filt = P.filt = eps > 0.0;
-  if (filt) {
-    na = DBuf<double>(al, std::max<int64_t>(A->nnzb, 1));
-    nb = DBuf<double>(al, std::max<int64_t>(B->nnzb, 1));
-    block_norms(*A, na.p, s);
-    block_norms(*B, nb.p, s);
-  }
-  tm.mark();  // 2
   std::vector<int32_t> ksizes(opa_c.begin(), opa_c.end());
   std::sort(ksizes.begin(), ksizes.end());
   ksizes.erase(std::unique(ksizes.begin(), ksizes.end()), ksizes.end());
@@ -321,6 +314,22 @@ static void plan_build(Plan &P, char transa, char transb) {
   const bool quads = P.quads = !ksizes.empty() && ksizes.size() <= 8 &&
                                (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
                                (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
+  // ------------------------------------------------------- a1: norms
+  // A one-shot FP64 product on the packed path reads A and B once: the
+  // packing kernel computes the block norms as well (after the symbolic
+  // count, when the packed sizes are known), bitwise equal to block_norms.
+  DBuf<double> na, nb;
+  const bool filt = P.filt = eps > 0.0;
+  const bool fuse = P.one_shot && quads && !lowp && filt && !retain;
+  if (filt) {
+    na = DBuf<double>(al, std::max<int64_t>(A->nnzb, 1));
+    nb = DBuf<double>(al, std::max<int64_t>(B->nnzb, 1));
+    if (!fuse) {
+      block_norms(*A, na.p, s);
+      block_norms(*B, nb.p, s);
+    }
+  }
+  tm.mark();  // 2
   // packed operand offsets for the quad path (op(A) row-major, op(B)
   // column-major) and one record per entry of op(B) for the product loops
   // of a2 and a4: both depend on A and B only, so they are queued before
@@ -337,7 +346,7 @@ static void plan_build(Plan &P, char transa, char transb) {
     }
   }
   DBuf<int4> bent(al, (size_t)std::max<int64_t>(ob.nnzb, 1));
-  product_records(ob, filt ? nb.p : nullptr, quads ? P.b_poff.p : nullptr, bent.p, s);
+  if (!fuse) product_records(ob, filt ? nb.p : nullptr, quads ? P.b_poff.p : nullptr, bent.p, s);
   // ------------------------------------------------------- a2: symbolic
   SymArgs sym;
   sym.a = &oa;
@@ -383,12 +392,25 @@ static void plan_build(Plan &P, char transa, char transb) {
       }
       PlanTotals T;
       T.at[0] = P.c_rp.p + nbr;
+      if (fuse) {   // packed sizes, for the fused packing below
+        T.at[1] = P.a_poff.p + A->nnzb;
+        T.at[2] = P.b_poff.p + B->nnzb;
+      }
       T.mx64 = row_nnz.p;   // widest result row
       T.nmx = nbr;
       DBuf<int64_t> tot(al, 8);
       plan_totals(T, tot.p, s);
       HIPCHECK(hipMemcpyAsync(ctx->pinned, tot.p, sizeof(int64_t) * 8, hipMemcpyDeviceToHost, s));
       HIPCHECK(hipStreamSynchronize(s));
+      if (fuse) {
+        P.a_pack_n = ctx->pinned[1];
+        P.b_pack_n = ctx->pinned[2];
+        P.a_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.a_pack_n, 2));
+        P.b_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
+        pack_values(*A, ta, P.a_poff.p, P.a_pack.p, *B, !tb, P.b_poff.p, P.b_pack.p, s, na.p, nb.p);
+        P.packed = true;
+        product_records(ob, nb.p, P.b_poff.p, bent.p, s);
+      }
       nnzb_c = ctx->pinned[0];
       max_row = (int32_t)ctx->pinned[7];
     }
@@ -547,8 +569,10 @@ static void plan_build(Plan &P, char transa, char transb) {
   if (P.post) P.c_norm = DBuf<double>(al, nc1);
   P.c_values = DBuf<double>(al, (size_t)std::max<int64_t>(P.nval_c, 1));
   if (quads && P.nprod > 0) {   // packed copies (sizes in units of 8 bytes)
-    P.a_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.a_pack_n, 2));
-    P.b_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
+    if (!P.packed) {
+      P.a_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.a_pack_n, 2));
+      P.b_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
+    }
     if (ctx->mode == BSMM_COMPUTE_SPLIT) {
       P.a_lo = DBuf<double>(al, (size_t)std::max<int64_t>(P.a_pack_n, 2));
       P.b_lo = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
@@ -608,7 +632,8 @@ static void plan_numeric(Plan &P, bool marks) {
       pack32_values(*P.A, ta, P.a_poff.p, reinterpret_cast<float *>(P.a_pack.p), reinterpret_cast<float *>(P.a_lo.p), s);
       pack32_values(*P.B, !tb, P.b_poff.p, reinterpret_cast<float *>(P.b_pack.p), reinterpret_cast<float *>(P.b_lo.p), s);
     } else if (P.quads) {
-      pack_values(*P.A, ta, P.a_poff.p, P.a_pack.p, *P.B, !tb, P.b_poff.p, P.b_pack.p, s);
+      if (!P.packed) pack_values(*P.A, ta, P.a_poff.p, P.a_pack.p, *P.B, !tb, P.b_poff.p, P.b_pack.p, s);
+      P.packed = false;   // a later execution packs the values it finds
     } else {
       if (ta) transpose_blocks(*P.A, P.a_t.p, s);
       if (!tb) transpose_blocks(*P.B, P.b_t.p, s);
@@ -717,6 +742,7 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   P.beta = beta;
   P.eps = eps;
   P.retain = retain;
+  P.one_shot = true;
   plan_build(P, transa, transb);
   plan_numeric(P, true);
   bsmm_mat_s *R = plan_finish(P, true);

@@ -295,9 +295,11 @@ void shift_dist_rows(const bsmm_mat_s &x, double shift, double *row_out, hipStre
 // row count is the contraction extent (op(A) = A^T or op(B) = B).
 // pack_offsets writes nnzb + 1 offsets (exclusive scan, total last).
 void pack_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_poff, hipStream_t s);
-// Both packed operand copies in one launch.
+// Both packed operand copies in one launch; with a_norm / b_norm, the block
+// norms as well, bitwise equal to block_norms (same summation order).
 void pack_values(const bsmm_mat_s &a, bool a_k_is_row, const int64_t *a_poff, double *a_out, const bsmm_mat_s &b,
-                 bool b_k_is_row, const int64_t *b_poff, double *b_out, hipStream_t s);
+                 bool b_k_is_row, const int64_t *b_poff, double *b_out, hipStream_t s, double *a_norm = nullptr,
+                 double *b_norm = nullptr);
 // FP32 k-quad slabs (FP32 / split modes): offsets in units of 8 bytes; lo
 // (the rounding remainder x - fp32(x)) is written only when non-null.
 void pack32_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_poff, hipStream_t s);

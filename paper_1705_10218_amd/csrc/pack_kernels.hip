@@ -44,6 +44,7 @@ struct PackSide {
   const int64_t *poff;
   double *out;
   int32_t nbr;
+  double *norm;   // optional: Frobenius norm of every stored block
 };
 
 constexpr int PACK_NV = 12;                  // values per lane per step
@@ -87,13 +88,29 @@ __global__ __launch_bounds__(256) void k_pack_blocks(PackSide a, PackSide b) {
       // stride of 16 in the packed order: qd slabs and rd more positions
       const int qd = 16 / two, rd = 16 - qd * two;
       int slab = lane / two, w = lane - (lane / two) * two;   // position of e = lane
+      // the block norm in the order of the norm kernel: lane sums elements
+      // lane, lane + 16, ... of the stored block, then a fixed 16-lane tree
+      double ss = 0.0;
       if (active && staged) {
         double x[PACK_NV];
 #pragma unroll
         for (int t = 0; t < PACK_NV; t++) x[t] = X.in[o + min(lane + 16 * t, n_in - 1)];
 #pragma unroll
         for (int t = 0; t < PACK_NV; t++)
-          if (lane + 16 * t < n_in) st[lane + 16 * t] = x[t];
+          if (lane + 16 * t < n_in) {
+            st[lane + 16 * t] = x[t];
+            ss = fma(x[t], x[t], ss);
+          }
+      } else if (active && X.norm) {
+        for (int d = lane; d < n_in; d += 16) {
+          const double x = X.in[o + d];
+          ss = fma(x, x, ss);
+        }
+      }
+      if (X.norm) {   // uniform: every lane takes part in the tree
+#pragma unroll
+        for (int dd = 8; dd >= 1; dd >>= 1) ss += __shfl_xor(ss, dd, 16);
+        if (active && lane == 0) X.norm[pb + j] = sqrt(ss);
       }
       group_sync();
       if (active && staged) {
@@ -158,8 +175,9 @@ void pack_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_
 }
 
 void pack_values(const bsmm_mat_s &a, bool a_k_is_row, const int64_t *a_poff, double *a_out, const bsmm_mat_s &b,
-                 bool b_k_is_row, const int64_t *b_poff, double *b_out, hipStream_t s) {
-  auto side = [](const bsmm_mat_s &x, bool kr, const int64_t *poff, double *out) {
+                 bool b_k_is_row, const int64_t *b_poff, double *b_out, hipStream_t s, double *a_norm,
+                 double *b_norm) {
+  auto side = [](const bsmm_mat_s &x, bool kr, const int64_t *poff, double *out, double *norm) {
     PackSide v;
     v.rp = x.d_row_ptr;
     v.ci = x.d_col_idx;
@@ -171,9 +189,10 @@ void pack_values(const bsmm_mat_s &a, bool a_k_is_row, const int64_t *a_poff, do
     v.poff = poff;
     v.out = out;
     v.nbr = (x.nnzb > 0) ? x.nbr : 0;
+    v.norm = norm;
     return v;
   };
-  const PackSide va = side(a, a_k_is_row, a_poff, a_out), vb = side(b, b_k_is_row, b_poff, b_out);
+  const PackSide va = side(a, a_k_is_row, a_poff, a_out, a_norm), vb = side(b, b_k_is_row, b_poff, b_out, b_norm);
   const int64_t grid = (int64_t)va.nbr + vb.nbr;
   if (grid == 0) return;
   hipLaunchKernelGGL(k_pack_blocks, dim3((unsigned)grid), dim3(256), 0, s, va, vb);
