@@ -1,10 +1,11 @@
 """Autotuner for the block GEMM's kernel variant per (m, n) size class.
 
-The FP64 block GEMM has two ways to cover a result block on the matrix
-cores: 16x16x4 MFMA tiles (few loads per k-step, padding to 16) or 4x4x4
-MFMA subtiles (padding to 4, more loads).  Which is faster depends on the
-block edges, so it is chosen per size class (edges 1-8, 9-16, 17-24, 25-32)
-by timing: for every (m, n) pair of a block-size set, a synthetic DFT-like
+The FP64 block GEMM has several ways to cover a result block on the matrix
+cores: 16x16x4 MFMA tiles (few loads per k-step, padding to 16), 4x4x4
+MFMA subtiles (padding to 4, more loads), and, for edges up to 8, one
+16x16x4 tile carrying two products per k-slice in its diagonal quadrants.
+Which is faster depends on the block edges, so it is chosen per size class
+(edges 1-8, 9-16, 17-24, 25-32) by timing: for every (m, n) pair of a block-size set, a synthetic DFT-like
 workload whose result blocks all have that shape (contraction sizes drawn
 from the same set) is multiplied with each variant, and the fastest GEMM
 time wins.  The best variant depends on the contraction-size mix as well,
@@ -25,7 +26,12 @@ import sys
 
 import numpy as np
 
-VARIANTS = {1: "mfma16x16x4_tiles", 2: "mfma4x4x4_subtiles"}
+VARIANTS = {1: "mfma16x16x4_tiles", 2: "mfma4x4x4_subtiles", 3: "mfma16x16x4_diagonal_pairs"}
+
+
+def applies(v: int, m: int, n: int) -> bool:
+    """Variant 3 exists for blocks with both edges at most 8."""
+    return v != 3 or (m <= 8 and n <= 8)
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.json")
 
 
@@ -79,6 +85,8 @@ def tune(sizes=(5, 13, 23), atoms: int = 1500, reps: int = 3, log=None) -> dict:
             B = bsmm.Matrix.from_host(ctx, b)
             times = {}
             for v in VARIANTS:
+                if not applies(v, m, n):
+                    continue
                 ctx.set_gemm_variant(m, n, v)
                 times[v] = time_gemm(bsmm, ctx, A, B, reps)
             ctx.set_gemm_variant(m, n, 0)

@@ -449,6 +449,10 @@ static void plan_build(Plan &P, char transa, char transb) {
   fa.kofs = kofs.p;
   if (lowp && !quads && nnzb_c > 0)
     fail(BSMM_ERR_UNSUPPORTED, "FP32 / split modes need packed operands below 2 GB and at most 8 distinct k block sizes");
+  // the diagonal-packed GEMM variant (blocks with both edges <= 8) takes
+  // its products in groups of eight: such runs are padded to eight
+  const bool diag8 = quads && !lowp && ctx->gemm_variant[0] == 3;
+  fa.diag8 = diag8;
   fa.na = filt ? na.p : nullptr;
   fa.bent = bent.p;
   fa.eps = eps;
@@ -535,6 +539,7 @@ static void plan_build(Plan &P, char transa, char transb) {
     sa.a_poff = P.a_poff.p;
     sa.bent = bent.p;
     sa.ord = sym.ord;
+    sa.diag8 = diag8;
     if (sw.nwin > 0 && max_ns > 0) {
       sa.win = sw;
       sa.wslot = wslot.p;
@@ -972,7 +977,8 @@ bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_
   ABI_BEGIN
   if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
   if (m < 1 || m > MAX_BLOCK || n < 1 || n > MAX_BLOCK) fail(BSMM_ERR_INVALID_ARG, "block edge outside 1..32");
-  if (variant < 0 || variant > 2) fail(BSMM_ERR_INVALID_ARG, "variant must be 0, 1 or 2");
+  if (variant < 0 || variant > 3) fail(BSMM_ERR_INVALID_ARG, "variant must be 0, 1, 2 or 3");
+  if (variant == 3 && (m > 8 || n > 8)) fail(BSMM_ERR_INVALID_ARG, "variant 3 needs both block edges <= 8");
   ctx->gemm_variant[((m + 7) / 8 - 1) * 4 + ((n + 7) / 8 - 1)] = (uint8_t)variant;
   ABI_END
 }

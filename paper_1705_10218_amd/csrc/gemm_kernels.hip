@@ -425,8 +425,17 @@ __device__ __forceinline__ d2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 
 // SIXTEEN: V_MFMA_F64_16X16X4F64 on MT x NT tiles of 16 (MT, NT in {1, 2});
 // otherwise V_MFMA_F64_4X4X4F64 on MT x NT subtiles of 4 (even counts).
-template <bool SIXTEEN, int MT, int NT>
+// DIAG (one 16x16 tile, both edges at most 8): each 16-lane k-group carries
+// two products, lanes 0-7 one and lanes 8-15 another, for rows of op(A) and
+// columns of op(B) alike.  One MFMA then sums eight products: the first
+// four land in the tile's upper-left 8x8 quadrant, the other four in the
+// lower-right one, and the mixed quadrants are discarded.  The segment's
+// equal-k runs are padded to groups of eight, so a group of eight products
+// shares one k size; the two quadrants are added at the end.
+template <bool SIXTEEN, int MT, int NT, bool DIAG = false>
 __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql, int pre = 0) {
+  static_assert(!DIAG || (SIXTEEN && MT == 1 && NT == 1), "diagonal packing uses one 16x16 tile");
+  constexpr int G = DIAG ? 8 : 4;   // products per MFMA step
   const int32_t c = D.c;
   constexpr int HM = SIXTEEN ? MT : MT / 2, HN = SIXTEEN ? NT : NT / 2;
   // two accumulator sets (the two k-steps of a pair) when a step has a single
@@ -443,7 +452,12 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
   const int kq = lane >> 4;
   // lane's rows of op(A) / columns of op(B) (-1 if padding)
   int ra[HM], cb[HN];
-  if (SIXTEEN) {
+  // DIAG: which product of the k-group's pair a lane serves
+  const int hh = DIAG ? (lane & 15) >> 3 : 0;
+  if (DIAG) {
+    ra[0] = (lane & 7) < m ? (lane & 7) : -1;
+    cb[0] = (lane & 7) < n ? (lane & 7) : -1;
+  } else if (SIXTEEN) {
 #pragma unroll
     for (int u = 0; u < HM; u++) ra[u] = (lane & 15) + 16 * u < m ? (lane & 15) + 16 * u : -1;
 #pragma unroll
@@ -476,12 +490,12 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
 
   const int64_t s0 = D.s0, s1 = D.s0 + D.ns;
   for (int64_t rbase = s0; rbase < s1; rbase += ROUND) {
-    const int nr = (int)min<int64_t>(ROUND, s1 - rbase);   // multiple of 4
-    const int nq = nr >> 2;
+    const int nr = (int)min<int64_t>(ROUND, s1 - rbase);   // multiple of G
+    const int nq = nr / G;   // product groups of the round
     load_quads(P, ql, rbase, nr, lane, rbase == s0 ? pre : 0);
     // total pairs of the round
     int steps = 0;
-    for (int q = lane; q < nq; q += 64) steps += (ql.Kq[q] + 1) >> 1;
+    for (int q = lane; q < nq; q += 64) steps += (ql.Kq[q * (G / 4)] + 1) >> 1;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) steps += __shfl_xor(steps, d, 64);
     steps = __builtin_amdgcn_readfirstlane(steps);
@@ -500,14 +514,15 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
       for (int v = 0; v < HN; v++) vb[v] = (cb[v] < 0 || ob == QOOB) ? QOOB : ob + 16u * (uint32_t)cb[v];
     };
     int iP;
+    const int slot = 4 * hh + kq;   // this lane's product within a group
     {
       const int K0 = __builtin_amdgcn_readfirstlane(ql.Kq[0]);
       iP = (K0 + 1) >> 1;
-      lane_offsets(ql.oa[kq], ql.ob[kq], K0);
+      lane_offsets(ql.oa[slot], ql.ob[slot], K0);
       if (nq > 1) {
-        noa = ql.oa[4 + kq];
-        nob = ql.ob[4 + kq];
-        nK = ql.Kq[1];
+        noa = ql.oa[G + slot];
+        nob = ql.ob[G + slot];
+        nK = ql.Kq[G / 4];
       }
     }
     d2 qa[PF2][HM], qb[PF2][HN];
@@ -524,10 +539,10 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
         iP = (K + 1) >> 1;
         lane_offsets(noa, nob, K);
         if (iq + 1 < nq) {
-          const int t = 4 * (iq + 1) + kq;
+          const int t = G * (iq + 1) + slot;
           noa = ql.oa[t];
           nob = ql.ob[t];
-          nK = ql.Kq[iq + 1];
+          nK = ql.Kq[(iq + 1) * (G / 4)];
         } else {
           // past the last quad: further issues read zeros (out of range)
           noa = QOOB;
@@ -598,7 +613,16 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
   const int64_t co = D.co;
   const double *old = old_block(P, c);
   double ss = 0.0;
-  if (SIXTEEN) {
+  if (DIAG) {
+    // C(i, j) = upper-left (i, j) + lower-right (i + 8, j + 8): the latter
+    // sits two registers on and eight lanes over
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const double v = acc16[0][0][r] + __shfl_xor(acc16[0][0][r + 2], 8, 64);
+      const int row = 4 * r + kq, col = lane & 15;
+      if (row < m && col < n) store_c(P, old, co, m, row, col, v, ss);
+    }
+  } else if (SIXTEEN) {
 #pragma unroll
     for (int u = 0; u < HM; u++)
 #pragma unroll
@@ -655,8 +679,14 @@ __device__ __forceinline__ void dispatch_quad(const GemmP &P, const BlkDesc &D, 
   const int nt = edge_tiles(D.mn >> 16);
   const int key = mt * 16 + nt;
     // kernel variant of this (m, n) class: 0 = default (16x16 tile when both
-    // edges are in 9..16, else 4x4 subtiles), 1 = 16x16 tiles, 2 = 4x4 subtiles
+    // edges are in 9..16, else 4x4 subtiles), 1 = 16x16 tiles, 2 = 4x4
+    // subtiles, 3 = one 16x16 tile packed with two products per k-group
+    // (edges up to 8; the stacks were padded to groups of eight for it)
     const int vid = P.variant[(mt / 2 - 1) * 4 + (nt / 2 - 1)];
+    if (vid == 3 && mt == 2 && nt == 2) {
+      gemm_block_quad<true, 1, 1, true>(P, D, ql, pre);
+      return;
+    }
     if (vid == 1 || (vid == 0 && mt == 4 && nt == 4)) {
       const int tm = mt <= 4 ? 1 : 2, tn = nt <= 4 ? 1 : 2;
       if (tm == 1 && tn == 1) {

@@ -180,6 +180,7 @@ struct FillArgs {
   int32_t *cnt_g = nullptr;        // nnzb_C * |ksizes| zeroed counters for wide rows
   int32_t *kofs = nullptr;         // out (when pad4): start of every k-size run inside its
                                    // C block's segment, nnzb_C * |ksizes| entries
+  bool diag8 = false;              // pad runs of blocks with both edges <= 8 to groups of eight
   const double *na = nullptr;      // norms of A's blocks (null when eps == 0)
   const int4 *bent = nullptr;      // product records of op(B) (product_records)
   double eps = 0.0;
@@ -229,6 +230,7 @@ struct StackArgs {
   const int64_t *bwin = nullptr;     //   window bounds of op(B)'s rows
   int32_t max_ns = 0;                //   most C blocks of one row in one window
   const int32_t *ord = nullptr;      // order in which rows are handed out (device; null = 0..nbr-1)
+  bool diag8 = false;                // runs of blocks with both edges <= 8 padded to groups of eight
 };
 
 // Per entry of op(B), one 16-byte record read by the symbolic fill and the

@@ -303,7 +303,7 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
                                                           const BEnt *bent, const double *na, double eps,
                                                           int32_t cnt_cap, KSizes ksz, int nkp, int32_t *cnt_g,
                                                           int32_t *kofs, int32_t nbr, const int32_t *ord,
-                                                          int64_t per_xcd, const uint32_t *gbits) {
+                                                          int64_t per_xcd, const uint32_t *gbits, int diag8) {
   extern __shared__ uint32_t sm[];
   __shared__ int32_t shi[SYM_THREADS / 64];
   __shared__ int64_t shl[SYM_THREADS / 64];
@@ -409,11 +409,14 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
   for (int32_t t = threadIdx.x; t < R; t += blockDim.x) {
     int32_t tot_real = 0, tot_pad = 0;
     int64_t ksum = 0;
+    // runs padded to groups of four products, of eight for the blocks of the
+    // diagonal-packed GEMM variant (both edges at most 8)
+    const int32_t gm = (diag8 && m <= 8 && B.cbs[c_ci[cbase + t]] <= 8) ? 7 : 3;
     for (int kx = 0; kx < nk1; kx++) {
       const int32_t v = lds_cnt ? cnt[t * nk1 + kx] : gcnt[t * nk1 + kx];
       if (kofs) kofs[(cbase + t) * nk1 + kx] = tot_pad;   // this k size's run starts here
       tot_real += v;
-      tot_pad += nkp > 0 ? (v + 3) & ~3 : v;
+      tot_pad += nkp > 0 ? (v + gm) & ~gm : v;
       if (nkp > 0) ksum += (int64_t)v * ksz.v[kx];
     }
     c_cnt[cbase + t] = tot_pad;
@@ -469,7 +472,7 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
                                                    const int32_t *kofs, int2 *stack, const BEnt *bent,
                                                    const double *na, double eps, int32_t cnt_cap, int32_t *run,
                                                    KSizes ksz, int nks, int pad4, int enc, int32_t nbr,
-                                                   const int32_t *ord, int64_t per_xcd) {
+                                                   const int32_t *ord, int64_t per_xcd, int diag8) {
   extern __shared__ uint32_t sm[];
   const RowUnit ru = row_unit(nbr, nks > 0 ? nks : 1, per_xcd, ord);
   if (!ru.ok) return;
@@ -606,7 +609,8 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
         at = atomicAdd(&gcur[t * nk1 + pass], 0);
         b0 = seg_off[cbase + t] + (kofs ? kofs[(cbase + t) * nk1 + pass] : 0);
       }
-      const int32_t end = (at + 3) & ~3;
+      const int32_t gm = (diag8 && A.rbs[i] <= 8 && B.cbs[c_ci[cbase + t]] <= 8) ? 7 : 3;
+      const int32_t end = (at + gm) & ~gm;
       for (; at < end; at++)
         stack[b0 + at] = enc ? make_int2((int)0x80000000u, (int)0x80000000u) : make_int2(-1, -1);
     }
@@ -658,7 +662,7 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
                                                        const int64_t *seg_off, const int32_t *kofs, int2 *stack,
                                                        const BEnt *bent, const double *na, double eps,
                                                        int32_t buf_cap, KSizes ksz, int nks, int32_t nbr,
-                                                       const int32_t *ord, int64_t per_xcd) {
+                                                       const int32_t *ord, int64_t per_xcd, int diag8) {
   extern __shared__ uint32_t sm[];
   const RowUnit ru = row_unit(nbr, nks * nwin, per_xcd, ord);
   if (!ru.ok) return;
@@ -773,22 +777,27 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
     else walk(std::false_type{});
     __syncthreads();   // the opened entries are rewritten by the next batch
   }
-  // close every run of this k size: the last group of four, null-padded
+  // close every run of this k size: the groups of four from the one holding
+  // the last entry up to the padded end (a multiple of four, of eight for
+  // the diagonal-packed variant's blocks), null entries past the last
   const int nul = (int)0x80000000u;
+  const bool m8 = diag8 && A.rbs[i] <= 8;
   for (int32_t t = lane; t < ns; t += 64) {
     const int32_t at = cnt[t];
-    const int32_t rem = at & 3;
-    if (rem == 0) continue;
-    int2 *g = base + sbase[t] + (at - rem);
-    if (buffered) {
-      int2 x[3];
+    const int32_t gm = (m8 && B.cbs[c_ci[s0 + t]] <= 8) ? 7 : 3;
+    const int32_t end = (at + gm) & ~gm;
+    for (int32_t gs = at & ~3; gs < end; gs += 4) {
+      int2 *g = base + sbase[t] + gs;
+      if (buffered) {
+        int2 x[4];
 #pragma unroll
-      for (int u = 0; u < 3; u++) x[u] = u < rem ? buf[t * 4 + u] : make_int2(nul, nul);
-      int4 *dst = reinterpret_cast<int4 *>(g);
-      dst[0] = make_int4(x[0].x, x[0].y, x[1].x, x[1].y);
-      dst[1] = make_int4(x[2].x, x[2].y, nul, nul);
-    } else {
-      for (int u = rem; u < 4; u++) g[u] = make_int2(nul, nul);
+        for (int u = 0; u < 4; u++) x[u] = gs + u < at ? buf[t * 4 + u] : make_int2(nul, nul);
+        int4 *dst = reinterpret_cast<int4 *>(g);
+        dst[0] = make_int4(x[0].x, x[0].y, x[1].x, x[1].y);
+        dst[1] = make_int4(x[2].x, x[2].y, x[3].x, x[3].y);
+      } else {
+        for (int u = max(at - gs, 0); u < 4; u++) g[u] = make_int2(nul, nul);
+      }
     }
   }
 }
@@ -837,7 +846,8 @@ void symbolic_fill(const FillArgs &f, hipStream_t s) {
                      f.c_rp, f.c_ci, f.c_row, f.c_size, f.c_cnt, f.c_kflops, f.row_cand, f.row_real,
                      reinterpret_cast<const BEnt *>(f.bent), f.na, f.eps, cap, ks, nkp, f.cnt_g,
                      nkp > 0 ? f.kofs : nullptr, nbr, f.sym.ord, px,
-                     (words_total <= MAX_WORDS && !f.sym.retain) ? f.sym.bits : nullptr);
+                     (words_total <= MAX_WORDS && !f.sym.retain) ? f.sym.bits : nullptr,
+                     (f.diag8 && nkp > 0) ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
 
@@ -910,14 +920,14 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
     const int64_t px = row_units_per_xcd(g.nbr, nks * g.win.nwin);
     hipLaunchKernelGGL(k_stack_fill_win, dim3((unsigned)(px * 8)), dim3(64), lw, s, va, vb, g.wslot, g.bwin,
                        g.win.nwin, g.win.wc, g.c_ci, g.seg_off, g.kofs, g.stack, bent, g.na, g.eps, buf_cap, ks,
-                       nks, g.nbr, g.ord, px);
+                       nks, g.nbr, g.ord, px, g.diag8 ? 1 : 0);
     HIPCHECK(hipGetLastError());
     return;
   }
   const int64_t px = row_units_per_xcd(g.nbr, std::max(nks, 1));
   hipLaunchKernelGGL(k_stack_fill, dim3((unsigned)(px * 8)), dim3(64), lds, s, va, vb, g.nbc, g.c_rp, g.c_ci,
                      g.seg_off, nks > 0 ? g.kofs : nullptr, g.stack, bent, g.na, g.eps, cap, run, ks, nks,
-                     g.pad4 ? 1 : 0, g.encode ? 1 : 0, g.nbr, g.ord, px);
+                     g.pad4 ? 1 : 0, g.encode ? 1 : 0, g.nbr, g.ord, px, g.diag8 ? 1 : 0);
   HIPCHECK(hipGetLastError());
 }
 
