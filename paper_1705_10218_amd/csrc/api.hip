@@ -233,7 +233,7 @@ struct Plan {
   bsmm_mat_s *A = nullptr, *B = nullptr, *C0 = nullptr;
   bool ta = false, tb = false, filt = false, post = false, quads = false, lowp = false;
   // one_shot: built, executed once and consumed (bsmm_multiply); packed:
-  // the build already made the packed operand copies of the current values
+  // plan_build already made the packed operand copies of the current values
   bool one_shot = false, packed = false;
   double alpha = 1.0, beta = 0.0, eps = 0.0;
   int retain = 0;
