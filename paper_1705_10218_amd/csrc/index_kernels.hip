@@ -237,6 +237,79 @@ int grid_for(int64_t items, int per_block, int cap = 65536) {
 
 }  // namespace
 
+namespace {
+// Work list sorted by (tile of the row in the locality order, rank of the
+// column).  A tile of tile_rows rows is split into subtiles of 16 rows, one
+// workgroup each.  Pass 1 counts the subtile's C blocks per column in LDS
+// and stores the counts under the key (tile, column rank, subtile); an
+// exclusive scan over the keys gives every (tile, column, subtile) its first
+// place; pass 2 places the subtile's blocks through LDS cursors.  Blocks of
+// one column and subtile land in any order: the order of work items changes
+// no result (each C block is summed by one wavefront in its own fixed order).
+constexpr int32_t WL_SUB = 16;
+
+__global__ __launch_bounds__(256) void k_wl_count(const int32_t *ord, const int32_t *crank, const int64_t *c_rp,
+                                                  const int32_t *c_ci, int32_t nbr, int32_t nbc, int32_t nsub,
+                                                  int32_t *cnt) {
+  extern __shared__ int32_t hist[];
+  const int32_t g = blockIdx.x, tile = g / nsub, sub = g - tile * nsub;
+  for (int32_t j = threadIdx.x; j < nbc; j += blockDim.x) hist[j] = 0;
+  __syncthreads();
+  for (int32_t r = g * WL_SUB; r < min(nbr, (g + 1) * WL_SUB); r++) {
+    const int64_t c0 = c_rp[ord[r]], c1 = c_rp[ord[r] + 1];
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+      const int32_t col = c_ci[c];
+      atomicAdd(&hist[crank ? crank[col] : col], 1);
+    }
+  }
+  __syncthreads();
+  for (int32_t j = threadIdx.x; j < nbc; j += blockDim.x)
+    cnt[((int64_t)tile * nbc + j) * nsub + sub] = hist[j];
+}
+
+__global__ __launch_bounds__(256) void k_wl_place(const int32_t *ord, const int32_t *crank, const int64_t *c_rp,
+                                                  const int32_t *c_ci, int32_t nbr, int32_t nbc, int32_t nsub,
+                                                  const int64_t *first, int32_t *c_list) {
+  extern __shared__ int32_t cur[];
+  const int32_t g = blockIdx.x, tile = g / nsub, sub = g - tile * nsub;
+  for (int32_t j = threadIdx.x; j < nbc; j += blockDim.x)
+    cur[j] = (int32_t)first[((int64_t)tile * nbc + j) * nsub + sub];
+  __syncthreads();
+  for (int32_t r = g * WL_SUB; r < min(nbr, (g + 1) * WL_SUB); r++) {
+    const int64_t c0 = c_rp[ord[r]], c1 = c_rp[ord[r] + 1];
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+      const int32_t col = c_ci[c];
+      c_list[atomicAdd(&cur[crank ? crank[col] : col], 1)] = (int32_t)c;
+    }
+  }
+}
+}  // namespace
+
+void build_work_list_sorted(Allocator &al, const int32_t *ord, const int32_t *crank, const int64_t *c_rp,
+                            const int32_t *c_ci, int64_t nnzb_c, int32_t nbr, int32_t nbc, int32_t tile_rows,
+                            int32_t *c_list, hipStream_t s) {
+  if (nnzb_c <= 0 || nbr <= 0) return;
+  const int32_t nsub = tile_rows / WL_SUB;
+  const int32_t ngroups = (nbr + WL_SUB - 1) / WL_SUB;
+  const int64_t ntile = (ngroups + nsub - 1) / nsub;
+  const int64_t nkeys = ntile * nbc * nsub;
+  DBuf<int32_t> cnt(al, (size_t)nkeys);
+  DBuf<int64_t> first(al, (size_t)nkeys + 1);
+  const size_t lds = sizeof(int32_t) * (size_t)nbc;
+  if (lds > 65536) {
+    HIPCHECK(hipFuncSetAttribute((const void *)k_wl_count, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HIPCHECK(hipFuncSetAttribute((const void *)k_wl_place, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
+  // every (tile, subtile) slot writes its counts; those past the last row write zeros
+  hipLaunchKernelGGL(k_wl_count, dim3((unsigned)(ntile * nsub)), dim3(256), lds, s, ord, crank, c_rp, c_ci, nbr, nbc,
+                     nsub, cnt.p);
+  HIPCHECK(hipGetLastError());
+  exclusive_scan_i32(al, cnt.p, first.p, nkeys, s);
+  hipLaunchKernelGGL(k_wl_place, dim3(ngroups), dim3(256), lds, s, ord, crank, c_rp, c_ci, nbr, nbc, nsub, first.p,
+                     c_list);
+  HIPCHECK(hipGetLastError());
+}
+
 void exclusive_scan_i64(Allocator &al, const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
   scan_impl<int64_t>(al, in, out, n, s);
 }

@@ -333,6 +333,14 @@ void build_desc(int64_t n, const int32_t *c_list, const int32_t *c_row, const in
 void build_work_list(Allocator &al, const int32_t *d_ord, const int32_t *d_rank, const int64_t *c_rp,
                      const int32_t *c_ci, int32_t nbr, int32_t nbc, int32_t tile_rows, int32_t *c_list, hipStream_t s);
 
+// c_list = the C blocks sorted by (tile of their row, rank of their column):
+// tiles of tile_rows (a multiple of 16) consecutive rows of the locality
+// order ord, columns by crank (null: by index).  Needs nbc int32 counters in
+// LDS and ceil(nbr / tile_rows) * nbc * tile_rows / 16 keys in memory.
+void build_work_list_sorted(Allocator &al, const int32_t *ord, const int32_t *crank, const int64_t *c_rp,
+                            const int32_t *c_ci, int64_t nnzb_c, int32_t nbr, int32_t nbc, int32_t tile_rows,
+                            int32_t *c_list, hipStream_t s);
+
 // Locality order of the rows of a square block pattern (host planner).
 std::vector<int32_t> locality_order(int32_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci);
 
