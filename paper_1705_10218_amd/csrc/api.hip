@@ -550,16 +550,20 @@ static void plan_build(Plan &P, char transa, char transb) {
   }
   // GEMM work list: tiles of rows in the planner's locality order, columns
   // inside a tile in the same order when C is square over the same blocks.
-  // Tiles of about nbr/16 rows (16 to 256; on a 4,000-row product 128 rows
-  // took the GEMM from 11.37 to 10.97 ms against 16), sorted globally while
-  // the key count stays modest; else 16-row tiles, one workgroup each.
+  // A tile holds as many rows (16 to 256, at most nbr/16) as keep its rows
+  // of op(A) within about 16 MB: 128 rows of 5/13 blocks took the GEMM of a
+  // 4,000-row product from 11.37 to 10.97 ms against 16, while rows of
+  // 23x23 blocks, five times the bytes, lost with tiles that tall.  Sorted
+  // through per-subtile histograms while the key count stays modest; else
+  // 16-row tiles, one workgroup each.
   if (nnzb_c > 0) {
     const int32_t *ord = row_order(ctx, A);
     if (ord) {
       P.c_list = DBuf<int32_t>(al, nc1);
       const int32_t *rank = (nbc == nbr) ? ord + nbr : nullptr;
+      const double row_bytes = 8.0 * (double)A->n_values / (double)std::max(nbr, 1);
       int32_t big = 16;
-      while (big * 2 <= std::min(256, nbr / 16)) big *= 2;
+      while (big * 2 <= std::min(256, nbr / 16) && 2.0 * big * row_bytes <= 16.0 * (1 << 20)) big *= 2;
       const int64_t nkeys = (int64_t)((nbr + big - 1) / big) * nbc * (big / 16);
       const int32_t tile_rows = 16;
       if ((size_t)nbc * 4 <= 160 * 1024 && nkeys <= ((int64_t)1 << 24)) {
