@@ -652,9 +652,13 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
 __device__ __forceinline__ int edge_tiles(int e) { return ((((e + 3) >> 2) + 1) >> 1) << 1; }
 
 // One launch over all C blocks in the planner's order; every wavefront
-// dispatches on its own block's (m, n) class.  Workgroup ids are remapped so
-// that each of the 8 XCDs (ids are dealt to XCDs round-robin) walks one
-// contiguous stretch of the order, keeping its L2 on a compact region.
+// dispatches on its own block's (m, n) class.  Workgroup ids are remapped
+// (xcd_logical) so that the 8 XCDs, which the hardware deals ids to
+// round-robin, take chunks of 8,192 consecutive work items in turn: each
+// chunk keeps its XCD's L2 on a compact region, and the XCDs together stay
+// on neighbouring tiles, which their shared infinity cache serves (one
+// contiguous stretch per XCD took 11.0 ms on a 4,000-row product, chunks of
+// 8,192 10.6 ms, no remap 13.4 ms).
 // MAXT bounds the subtile counts compiled in (4: blocks up to 16).
 // A work item's descriptor in scalar registers (the index is uniform).
 __device__ __forceinline__ BlkDesc load_desc(const BlkDesc *desc, int64_t w) {
@@ -732,12 +736,12 @@ __device__ __forceinline__ void dispatch_quad(const GemmP &P, const BlkDesc &D, 
 }
 
 template <int MAXT, bool BUF>
-__global__ __launch_bounds__(64 * WPG) void k_gemm_f64(GemmP P, int64_t nblk, int64_t per_xcd) {
+__global__ __launch_bounds__(64 * WPG) void k_gemm_f64(GemmP P, int64_t nblk, int64_t chunk) {
   __shared__ ParamLds lds[WPG];
   ParamLds &pl = lds[threadIdx.x >> 6];
   QuadLds &ql = *reinterpret_cast<QuadLds *>(&pl);
   const int64_t b = blockIdx.x;
-  const int64_t lb = (b & 7) * per_xcd + (b >> 3);
+  const int64_t lb = xcd_logical(b, chunk);
   const int64_t w = lb * WPG + (threadIdx.x >> 6);
   if (w >= nblk) return;   // uniform per wavefront
   if constexpr (BUF) {
@@ -783,12 +787,12 @@ __global__ __launch_bounds__(64 * WPG) void k_gemm_f64(GemmP P, int64_t nblk, in
 // as in a launch of its own, so its results are bitwise the same.
 template <int MAXT>
 __global__ __launch_bounds__(64 * WPG) void k_gemm_f64_multi(const GemmP *ps, const int64_t *start, int nreq,
-                                                        int64_t nblk, int64_t per_xcd) {
+                                                        int64_t nblk, int64_t chunk) {
   __shared__ ParamLds lds[WPG];
   ParamLds &pl = lds[threadIdx.x >> 6];
   QuadLds &ql = *reinterpret_cast<QuadLds *>(&pl);
   const int64_t b = blockIdx.x;
-  const int64_t lb = (b & 7) * per_xcd + (b >> 3);
+  const int64_t lb = xcd_logical(b, chunk);
   const int64_t w = lb * WPG + (threadIdx.x >> 6);
   if (w >= nblk) return;   // uniform per wavefront
   int r = 0;
@@ -987,19 +991,19 @@ void gemm_launch(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream_t s)
   const GemmP p = make_params(g);
   const bool buf = g.quads;
   const int64_t nwg = (nnzb_c + WPG - 1) / WPG;
-  const int64_t per_xcd = (nwg + 7) / 8;
-  const int64_t grid = per_xcd * 8;
+  const XcdMap xm = xcd_map(nwg);
+  const int64_t grid = xm.per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   if (max_edge <= 16 && buf)
-    hipLaunchKernelGGL((k_gemm_f64<4, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64<4, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, xm.chunk);
   else if (max_edge <= 24 && buf)   // shapes up to 24: the register budget of the 24-wide shapes
-    hipLaunchKernelGGL((k_gemm_f64<6, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64<6, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, xm.chunk);
   else if (max_edge <= 16)
-    hipLaunchKernelGGL((k_gemm_f64<4, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64<4, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, xm.chunk);
   else if (buf)
-    hipLaunchKernelGGL((k_gemm_f64<8, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64<8, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, xm.chunk);
   else
-    hipLaunchKernelGGL((k_gemm_f64<8, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64<8, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, xm.chunk);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1026,15 +1030,15 @@ void gemm_launch_multi(Allocator &al, const std::vector<const GemmArgs *> &gs, c
   const GemmP *dp = static_cast<const GemmP *>(d_stage);
   const int64_t *ds = reinterpret_cast<const int64_t *>(static_cast<const char *>(d_stage) + sizeof(GemmP) * n);
   const int64_t nwg = (total + WPG - 1) / WPG;
-  const int64_t per_xcd = (nwg + 7) / 8;
-  const int64_t grid = per_xcd * 8;
+  const XcdMap xm = xcd_map(nwg);
+  const int64_t grid = xm.per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   if (max_edge <= 16)
-    hipLaunchKernelGGL((k_gemm_f64_multi<4>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64_multi<4>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, xm.chunk);
   else if (max_edge <= 24)
-    hipLaunchKernelGGL((k_gemm_f64_multi<6>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64_multi<6>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, xm.chunk);
   else
-    hipLaunchKernelGGL((k_gemm_f64_multi<8>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, per_xcd);
+    hipLaunchKernelGGL((k_gemm_f64_multi<8>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, dp, ds, n, total, xm.chunk);
   HIPCHECK(hipGetLastError());
   (void)al;
 }

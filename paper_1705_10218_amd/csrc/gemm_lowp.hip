@@ -265,11 +265,11 @@ __device__ __forceinline__ void gemm_block_lowp(const LowpP &P, int32_t c, QuadL
 // BIG: C edges up to 32 (tiles 2x2 compiled in); otherwise up to 16, so the
 // register budget (and occupancy) is that of the single-tile case.
 template <bool SPLIT, bool BIG>
-__global__ __launch_bounds__(64 * WPG) void k_gemm_lowp(LowpP P, int64_t nblk, int64_t per_xcd) {
+__global__ __launch_bounds__(64 * WPG) void k_gemm_lowp(LowpP P, int64_t nblk, int64_t chunk) {
   __shared__ QuadLds lds[WPG];
   QuadLds &ql = lds[threadIdx.x >> 6];
   const int64_t b = blockIdx.x;
-  const int64_t lb = (b & 7) * per_xcd + (b >> 3);
+  const int64_t lb = xcd_logical(b, chunk);
   const int64_t w = lb * WPG + (threadIdx.x >> 6);
   if (w >= nblk) return;   // uniform per wavefront
   const int32_t c = __builtin_amdgcn_readfirstlane(P.c_list ? P.c_list[w] : (int32_t)w);
@@ -371,18 +371,18 @@ void gemm_launch_lowp(const GemmArgs &g, int64_t nnzb_c, int max_edge, hipStream
   p.alpha = g.alpha;
   p.beta = g.beta;
   const int64_t nwg = (nnzb_c + WPG - 1) / WPG;
-  const int64_t per_xcd = (nwg + 7) / 8;
-  const int64_t grid = per_xcd * 8;
+  const XcdMap xm = xcd_map(nwg);
+  const int64_t grid = xm.per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many C blocks for one launch");
   const bool split = g.mode == BSMM_COMPUTE_SPLIT, big = max_edge > 16;
   if (split && big)
-    hipLaunchKernelGGL((k_gemm_lowp<true, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_lowp<true, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, xm.chunk);
   else if (split)
-    hipLaunchKernelGGL((k_gemm_lowp<true, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_lowp<true, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, xm.chunk);
   else if (big)
-    hipLaunchKernelGGL((k_gemm_lowp<false, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_lowp<false, true>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, xm.chunk);
   else
-    hipLaunchKernelGGL((k_gemm_lowp<false, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, per_xcd);
+    hipLaunchKernelGGL((k_gemm_lowp<false, false>), dim3((unsigned)grid), dim3(64 * WPG), 0, s, p, nnzb_c, xm.chunk);
   HIPCHECK(hipGetLastError());
 }
 

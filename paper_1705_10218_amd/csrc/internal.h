@@ -259,6 +259,28 @@ struct alignas(32) BlkDesc {
   int32_t pad;
 };
 
+// Workgroups of a GEMM launch to XCDs.  The hardware deals workgroup ids to
+// the 8 XCDs round-robin; the kernels remap them so that the XCDs take
+// chunks of `chunk` consecutive work items in turn, all working on
+// neighbouring tiles of the work list at once (their shared infinity cache
+// sees the same operands).  per_xcd (workgroups per XCD) is a multiple of
+// chunk, so the remap is a bijection onto [0, 8 * per_xcd); ids past the
+// last work item exit.  Small launches get one chunk per XCD.
+struct XcdMap {
+  int64_t per_xcd = 0, chunk = 1;
+};
+inline XcdMap xcd_map(int64_t nwg, int64_t max_chunk = 8192) {
+  XcdMap m;
+  const int64_t base = (nwg + 7) / 8;
+  m.chunk = std::max<int64_t>(1, std::min(max_chunk, base));
+  m.per_xcd = (base + m.chunk - 1) / m.chunk * m.chunk;
+  return m;
+}
+__device__ __forceinline__ int64_t xcd_logical(int64_t b, int64_t chunk) {
+  const int64_t g = b >> 3;
+  return (g / chunk) * (8 * chunk) + (b & 7) * chunk + g % chunk;
+}
+
 struct GemmArgs {
   const OpIndex *a, *b;
   const int32_t *c_list = nullptr;   // C blocks ordered by class
