@@ -556,6 +556,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   // 23x23 blocks, five times the bytes, lost with tiles that tall.  Sorted
   // through per-subtile histograms while the key count stays modest; else
   // 16-row tiles, one workgroup each.
+  DBuf<int32_t> wl_pos;   // place of every C block in the work list (sorted path)
   if (nnzb_c > 0) {
     const int32_t *ord = row_order(ctx, A);
     if (ord) {
@@ -567,7 +568,8 @@ static void plan_build(Plan &P, char transa, char transb) {
       const int64_t nkeys = (int64_t)((nbr + big - 1) / big) * nbc * (big / 16);
       const int32_t tile_rows = 16;
       if ((size_t)nbc * 4 <= 160 * 1024 && nkeys <= ((int64_t)1 << 24)) {
-        build_work_list_sorted(al, ord, rank, P.c_rp.p, P.c_ci.p, nnzb_c, nbr, nbc, big, P.c_list.p, s);
+        if (quads) wl_pos = DBuf<int32_t>(al, nc1);
+        build_work_list_sorted(al, ord, rank, P.c_rp.p, P.c_ci.p, nnzb_c, nbr, nbc, big, P.c_list.p, wl_pos.p, s);
       } else if ((size_t)nbc * 4 > 160 * 1024) {
         // columns too many for one LDS histogram: plain row order
         build_work_list(al, ord, nullptr, P.c_rp.p, P.c_ci.p, nbr, 0, tile_rows, P.c_list.p, s);
@@ -579,7 +581,10 @@ static void plan_build(Plan &P, char transa, char transb) {
   // work-item descriptors of the quad path
   if (quads && nnzb_c > 0) {
     P.desc = DBuf<BlkDesc>(al, nc1);
-    build_desc(nnzb_c, P.c_list.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, P.desc.p, s);
+    if (wl_pos.p)   // C blocks read in storage order, records written at their places
+      build_desc_by_block(nnzb_c, wl_pos.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, P.desc.p, s);
+    else
+      build_desc(nnzb_c, P.c_list.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, P.desc.p, s);
   }
   // ------------------------------------- buffers of the numeric part
   P.post = filt && !retain;

@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_wl_count(const int32_t *ord, const int3
 
 __global__ __launch_bounds__(256) void k_wl_place(const int32_t *ord, const int32_t *crank, const int64_t *c_rp,
                                                   const int32_t *c_ci, int32_t nbr, int32_t nbc, int32_t nsub,
-                                                  const int64_t *first, int32_t *c_list) {
+                                                  const int64_t *first, int32_t *c_list, int32_t *pos) {
   extern __shared__ int32_t cur[];
   const int32_t g = blockIdx.x, tile = g / nsub, sub = g - tile * nsub;
   for (int32_t j = threadIdx.x; j < nbc; j += blockDim.x)
@@ -279,7 +279,9 @@ __global__ __launch_bounds__(256) void k_wl_place(const int32_t *ord, const int3
     const int64_t c0 = c_rp[ord[r]], c1 = c_rp[ord[r] + 1];
     for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
       const int32_t col = c_ci[c];
-      c_list[atomicAdd(&cur[crank ? crank[col] : col], 1)] = (int32_t)c;
+      const int32_t at = atomicAdd(&cur[crank ? crank[col] : col], 1);
+      c_list[at] = (int32_t)c;
+      if (pos) pos[c] = at;
     }
   }
 }
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(256) void k_wl_place(const int32_t *ord, const int3
 
 void build_work_list_sorted(Allocator &al, const int32_t *ord, const int32_t *crank, const int64_t *c_rp,
                             const int32_t *c_ci, int64_t nnzb_c, int32_t nbr, int32_t nbc, int32_t tile_rows,
-                            int32_t *c_list, hipStream_t s) {
+                            int32_t *c_list, int32_t *pos, hipStream_t s) {
   if (nnzb_c <= 0 || nbr <= 0) return;
   const int32_t nsub = tile_rows / WL_SUB;
   const int32_t ngroups = (nbr + WL_SUB - 1) / WL_SUB;
@@ -306,7 +308,34 @@ void build_work_list_sorted(Allocator &al, const int32_t *ord, const int32_t *cr
   HIPCHECK(hipGetLastError());
   exclusive_scan_i32(al, cnt.p, first.p, nkeys, s);
   hipLaunchKernelGGL(k_wl_place, dim3(ngroups), dim3(256), lds, s, ord, crank, c_rp, c_ci, nbr, nbc, nsub, first.p,
-                     c_list);
+                     c_list, pos);
+  HIPCHECK(hipGetLastError());
+}
+
+namespace {
+// Work-item descriptors from the C blocks in storage order (contiguous
+// reads), each 32-byte record written at its place in the work list.
+__global__ __launch_bounds__(256) void k_desc_by_block(int64_t n, const int32_t *pos, const int32_t *c_row,
+                                                       const int32_t *c_ci, const int32_t *rbs, const int32_t *cbs,
+                                                       const int64_t *seg, const int64_t *c_off, BlkDesc *desc) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  BlkDesc d;
+  d.c = (int32_t)c;
+  d.mn = rbs[c_row[c]] | (cbs[c_ci[c]] << 16);
+  d.s0 = seg[c];
+  d.ns = (int32_t)(seg[c + 1] - d.s0);
+  d.co = c_off[c];
+  d.pad = 0;
+  desc[pos[c]] = d;
+}
+}  // namespace
+
+void build_desc_by_block(int64_t n, const int32_t *pos, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
+                         const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_desc_by_block, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pos, c_row, c_ci, rbs,
+                     cbs, seg, c_off, desc);
   HIPCHECK(hipGetLastError());
 }
 

@@ -359,9 +359,16 @@ void build_work_list(Allocator &al, const int32_t *d_ord, const int32_t *d_rank,
 // tiles of tile_rows (a multiple of 16) consecutive rows of the locality
 // order ord, columns by crank (null: by index).  Needs nbc int32 counters in
 // LDS and ceil(nbr / tile_rows) * nbc * tile_rows / 16 keys in memory.
+// pos (optional, nnzb_c entries) receives the place of every C block in
+// the list (the inverse of c_list).
 void build_work_list_sorted(Allocator &al, const int32_t *ord, const int32_t *crank, const int64_t *c_rp,
                             const int32_t *c_ci, int64_t nnzb_c, int32_t nbr, int32_t nbc, int32_t tile_rows,
-                            int32_t *c_list, hipStream_t s);
+                            int32_t *c_list, int32_t *pos, hipStream_t s);
+
+// desc[pos[c]] for every C block c < n (as build_desc, from the inverse of
+// the work list).
+void build_desc_by_block(int64_t n, const int32_t *pos, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
+                         const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s);
 
 // Locality order of the rows of a square block pattern (host planner).
 std::vector<int32_t> locality_order(int32_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci);
