@@ -103,14 +103,16 @@ bsmm_status bsmm_ctx_set_compute_mode(bsmm_ctx ctx, bsmm_compute_mode mode);
  *       MFMA subtiles otherwise), 1 = 16x16x4 MFMA tiles, 2 = 4x4x4 MFMA
  *       subtiles, 3 = one 16x16x4 MFMA tile carrying two block products per
  *       k-slice, one in each diagonal 8x8 quadrant (both edges <= 8 only;
- *       the stacks of such blocks are padded to groups of eight products).
+ *       the stacks of such blocks are padded to groups of eight products),
+ *   4 = one 16x16x4 MFMA tile plus 4x4x4 MFMA subtiles along the edges
+ *       beyond 16 (both edges in 9..24, one of them above 16).
  * The variant in force when a product is planned is the one it runs with.
  * All variants give results within FP64 rounding of each other; the choice
  * only changes speed (an autotuner picks it per size class).  Applies to the
  * packed-operand path (packed copies of op(A) and op(B) below 2 GB each, at
  * most 8 distinct k sizes).
- * Errors: BSMM_ERR_INVALID_ARG for edges outside 1..32, another variant, or
- * variant 3 with an edge above 8. */
+ * Errors: BSMM_ERR_INVALID_ARG for edges outside 1..32, another variant,
+ * variant 3 with an edge above 8, or variant 4 outside its edges. */
 bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_t variant);
 /* Bytes of device memory the library currently holds for this context
  * (live buffers plus its cache of freed ones). */

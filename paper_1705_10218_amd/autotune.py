@@ -2,8 +2,10 @@
 
 The FP64 block GEMM has several ways to cover a result block on the matrix
 cores: 16x16x4 MFMA tiles (few loads per k-step, padding to 16), 4x4x4
-MFMA subtiles (padding to 4, more loads), and, for edges up to 8, one
-16x16x4 tile carrying two products per k-slice in its diagonal quadrants.
+MFMA subtiles (padding to 4, more loads), for edges up to 8 one 16x16x4
+tile carrying two products per k-slice in its diagonal quadrants, and for
+edges in 9..24 one 16x16x4 tile plus 4x4x4 subtiles along the edges beyond
+16.
 Which is faster depends on the block edges, so it is chosen per size class
 (edges 1-8, 9-16, 17-24, 25-32) by timing: for every (m, n) pair of a block-size set, a synthetic DFT-like
 workload whose result blocks all have that shape (contraction sizes drawn
@@ -26,12 +28,18 @@ import sys
 
 import numpy as np
 
-VARIANTS = {1: "mfma16x16x4_tiles", 2: "mfma4x4x4_subtiles", 3: "mfma16x16x4_diagonal_pairs"}
+VARIANTS = {1: "mfma16x16x4_tiles", 2: "mfma4x4x4_subtiles", 3: "mfma16x16x4_diagonal_pairs",
+            4: "mfma16x16x4_with_4x4x4_edges"}
 
 
 def applies(v: int, m: int, n: int) -> bool:
-    """Variant 3 exists for blocks with both edges at most 8."""
-    return v != 3 or (m <= 8 and n <= 8)
+    """Variant 3 exists for blocks with both edges at most 8, variant 4 for
+    both edges in 9..24 with one above 16."""
+    if v == 3:
+        return m <= 8 and n <= 8
+    if v == 4:
+        return 9 <= m <= 24 and 9 <= n <= 24 and max(m, n) > 16
+    return True
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.json")
 
 

@@ -994,8 +994,10 @@ bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_
   ABI_BEGIN
   if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
   if (m < 1 || m > MAX_BLOCK || n < 1 || n > MAX_BLOCK) fail(BSMM_ERR_INVALID_ARG, "block edge outside 1..32");
-  if (variant < 0 || variant > 3) fail(BSMM_ERR_INVALID_ARG, "variant must be 0, 1, 2 or 3");
+  if (variant < 0 || variant > 4) fail(BSMM_ERR_INVALID_ARG, "variant must be 0, 1, 2, 3 or 4");
   if (variant == 3 && (m > 8 || n > 8)) fail(BSMM_ERR_INVALID_ARG, "variant 3 needs both block edges <= 8");
+  if (variant == 4 && (m < 9 || n < 9 || m > 24 || n > 24 || (m <= 16 && n <= 16)))
+    fail(BSMM_ERR_INVALID_ARG, "variant 4 needs both block edges in 9..24 and one above 16");
   ctx->gemm_variant[((m + 7) / 8 - 1) * 4 + ((n + 7) / 8 - 1)] = (uint8_t)variant;
   ABI_END
 }

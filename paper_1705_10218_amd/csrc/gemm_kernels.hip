@@ -419,6 +419,19 @@ __device__ __forceinline__ void load_quads(const GemmP &P, QuadLds &ql, int64_t 
 
 typedef double d2 __attribute__((ext_vector_type(2)));
 
+// Lane moves inside each 16-lane row (one k-group) of a double, in two
+// 32-bit DPP moves; lanes outside BANKS (groups of four lanes) keep x.
+template <int CTRL, int BANKS = 0xF>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int2 v = __builtin_bit_cast(int2, x);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(v.x, v.x, CTRL, 0xF, BANKS, false);
+  r.y = __builtin_amdgcn_update_dpp(v.y, v.y, CTRL, 0xF, BANKS, false);
+  return __builtin_bit_cast(double, r);
+}
+constexpr int DPP_ROW_SHR4 = 0x114;   // lane l takes lane l - 4 of its row
+constexpr int DPP_ROW_ROR4 = 0x124;   // lane l takes lane (l - 4) mod 16 of its row
+
 __device__ __forceinline__ d2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff, int soff) {
   return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, soff, 0));
 }
@@ -432,12 +445,33 @@ __device__ __forceinline__ d2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 // lower-right one, and the mixed quadrants are discarded.  The segment's
 // equal-k runs are padded to groups of eight, so a group of eight products
 // shares one k size; the two quadrants are added at the end.
-template <bool SIXTEEN, int MT, int NT, bool DIAG = false>
+// MIX (edges up to 24, one 16x16 tile plus 4x4 subtiles along an 8-wide
+// edge): bit 0 adds rows 16..23, bit 1 columns 16..23.  The edge rows of
+// op(A) are loaded once, lane l of a k-group holding row 16 + l % 8 (so
+// block b of a V_MFMA_F64_4X4X4F64 sees rows 16 + 4(b%2) ..), and likewise
+// the edge columns of op(B).  Per k-slice:
+//   rows 0..15 x cols 0..15   one 16x16x4 MFMA;
+//   rows 0..15 x cols 16..23  (A rows, B edge) and (A rows, B edge rotated by
+//                             four lanes): blocks b take row group b and
+//                             column group b%2, then the other one;
+//   rows 16..23 x cols 0..15  the same with the roles swapped;
+//   rows 16..23 x cols 16..23 (A edge, B edge with lanes 4..11 shifted by
+//                             four): block b takes row group b%2 and column
+//                             group b/2.
+// Four operand loads per k-pair cover 24 x 24, against six for 4x4
+// subtiles; the matrix cores do 1 + 5 narrow instructions instead of four
+// 16x16 tiles.
+template <bool SIXTEEN, int MT, int NT, bool DIAG = false, int MIX = 0>
 __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql, int pre = 0) {
   static_assert(!DIAG || (SIXTEEN && MT == 1 && NT == 1), "diagonal packing uses one 16x16 tile");
+  static_assert(MIX == 0 || (SIXTEEN && MT == 1 && NT == 1 && !DIAG), "edge subtiles extend one 16x16 tile");
+  constexpr bool XM = (MIX & 1) != 0, XN = (MIX & 2) != 0;
+  constexpr int NX = 2 * (int)XM + 2 * (int)XN + (int)(XM && XN);   // 4x4x4 MFMAs per k-slice
   constexpr int G = DIAG ? 8 : 4;   // products per MFMA step
   const int32_t c = D.c;
-  constexpr int HM = SIXTEEN ? MT : MT / 2, HN = SIXTEEN ? NT : NT / 2;
+  constexpr int HM = MIX ? 1 + (int)XM : (SIXTEEN ? MT : MT / 2);
+  constexpr int HN = MIX ? 1 + (int)XN : (SIXTEEN ? NT : NT / 2);
+  constexpr int T16 = MIX ? 1 : (SIXTEEN ? HM * HN : 1);   // 16x16 accumulators
   // two accumulator sets (the two k-steps of a pair) when a step has a single
   // MFMA chain: a dependent FP64 MFMA waits for the previous result
   constexpr int NC = (HM * HN == 1) ? 2 : 1;
@@ -454,7 +488,12 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
   int ra[HM], cb[HN];
   // DIAG: which product of the k-group's pair a lane serves
   const int hh = DIAG ? (lane & 15) >> 3 : 0;
-  if (DIAG) {
+  if constexpr (MIX) {
+    ra[0] = (lane & 15) < m ? (lane & 15) : -1;
+    cb[0] = (lane & 15) < n ? (lane & 15) : -1;
+    if constexpr (XM) ra[1] = 16 + (lane & 7) < m ? 16 + (lane & 7) : -1;
+    if constexpr (XN) cb[HN - 1] = 16 + (lane & 7) < n ? 16 + (lane & 7) : -1;
+  } else if (DIAG) {
     ra[0] = (lane & 7) < m ? (lane & 7) : -1;
     cb[0] = (lane & 7) < n ? (lane & 7) : -1;
   } else if (SIXTEEN) {
@@ -478,14 +517,15 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
   }
   const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
-  double acc[NC][SIXTEEN ? 1 : HM * HN];
-  d4 acc16[NC][SIXTEEN ? HM * HN : 1];
+  constexpr int TA = MIX ? (NX > 0 ? NX : 1) : (SIXTEEN ? 1 : HM * HN);   // 4x4 accumulators
+  double acc[NC][TA];
+  d4 acc16[NC][T16];
 #pragma unroll
   for (int h = 0; h < NC; h++) {
 #pragma unroll
-    for (int t = 0; t < (SIXTEEN ? HM * HN : 1); t++) acc16[h][t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < T16; t++) acc16[h][t] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[h][t] = 0.0;
+    for (int t = 0; t < TA; t++) acc[h][t] = 0.0;
   }
 
   const int64_t s0 = D.s0, s1 = D.s0 + D.ns;
@@ -555,7 +595,27 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
 #pragma unroll
       for (int e = 0; e < 2; e++) {
         const int h = e % NC;
-        if (SIXTEEN) {
+        if constexpr (MIX) {
+          acc16[h][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[0][e], xb[0][e], acc16[h][0], 0, 0, 0);
+          int x = 0;
+          if constexpr (XN) {
+            const double be = xb[HN - 1][e];
+            acc[h][x] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[0][e], be, acc[h][x], 0, 0, 0);
+            x++;
+            acc[h][x] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[0][e], dpp_f64<DPP_ROW_ROR4>(be), acc[h][x], 0, 0, 0);
+            x++;
+          }
+          if constexpr (XM) {
+            const double ae = xa[1][e];
+            acc[h][x] = __builtin_amdgcn_mfma_f64_4x4x4f64(ae, xb[0][e], acc[h][x], 0, 0, 0);
+            x++;
+            acc[h][x] = __builtin_amdgcn_mfma_f64_4x4x4f64(dpp_f64<DPP_ROW_ROR4>(ae), xb[0][e], acc[h][x], 0, 0, 0);
+            x++;
+          }
+          if constexpr (XM && XN)
+            acc[h][x] = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[1][e], dpp_f64<DPP_ROW_SHR4, 0x6>(xb[HN - 1][e]),
+                                                           acc[h][x], 0, 0, 0);
+        } else if (SIXTEEN) {
 #pragma unroll
           for (int u = 0; u < HM; u++)
 #pragma unroll
@@ -606,14 +666,35 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
   // fold the accumulator sets in a fixed order
   if constexpr (NC == 2) {
 #pragma unroll
-    for (int t = 0; t < (SIXTEEN ? HM * HN : 1); t++) acc16[0][t] += acc16[NC - 1][t];
+    for (int t = 0; t < T16; t++) acc16[0][t] += acc16[NC - 1][t];
 #pragma unroll
-    for (int t = 0; t < (SIXTEEN ? 1 : HM * HN); t++) acc[0][t] += acc[NC - 1][t];
+    for (int t = 0; t < TA; t++) acc[0][t] += acc[NC - 1][t];
   }
   const int64_t co = D.co;
   const double *old = old_block(P, c);
   double ss = 0.0;
-  if (DIAG) {
+  if constexpr (MIX) {
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = 4 * r + kq, col = lane & 15;
+      if (row < m && col < n) store_c(P, old, co, m, row, col, acc16[0][0][r], ss);
+    }
+    // 4x4x4 results: block b = (lane / 4) % 4, element (lane / 16, lane % 4)
+    const int i4 = lane >> 4, j4 = lane & 3, b4 = (lane >> 2) & 3, lo = b4 & 1;
+    int x = 0;
+    auto put = [&](int row, int col, double v) {
+      if (row < m && col < n) store_c(P, old, co, m, row, col, v, ss);
+    };
+    if constexpr (XN) {
+      put(4 * b4 + i4, 16 + 4 * lo + j4, acc[0][x++]);
+      put(4 * b4 + i4, 16 + 4 * (lo ^ 1) + j4, acc[0][x++]);
+    }
+    if constexpr (XM) {
+      put(16 + 4 * lo + i4, 4 * b4 + j4, acc[0][x++]);
+      put(16 + 4 * (lo ^ 1) + i4, 4 * b4 + j4, acc[0][x++]);
+    }
+    if constexpr (XM && XN) put(16 + 4 * lo + i4, 16 + 4 * (b4 >> 1) + j4, acc[0][x]);
+  } else if (DIAG) {
     // C(i, j) = upper-left (i, j) + lower-right (i + 8, j + 8): the latter
     // sits two registers on and eight lanes over
 #pragma unroll
@@ -685,11 +766,21 @@ __device__ __forceinline__ void dispatch_quad(const GemmP &P, const BlkDesc &D, 
     // kernel variant of this (m, n) class: 0 = default (16x16 tile when both
     // edges are in 9..16, else 4x4 subtiles), 1 = 16x16 tiles, 2 = 4x4
     // subtiles, 3 = one 16x16 tile packed with two products per k-group
-    // (edges up to 8; the stacks were padded to groups of eight for it)
+    // (edges up to 8; the stacks were padded to groups of eight for it),
+    // 4 = one 16x16 tile plus 4x4 subtiles along the edges beyond 16 (edges
+    // in 9..24, one of them above 16)
     const int vid = P.variant[(mt / 2 - 1) * 4 + (nt / 2 - 1)];
     if (vid == 3 && mt == 2 && nt == 2) {
       gemm_block_quad<true, 1, 1, true>(P, D, ql, pre);
       return;
+    }
+    if constexpr (MAXT > 4) {
+      if (vid == 4 && mt >= 4 && nt >= 4 && mt <= 6 && nt <= 6 && (mt == 6 || nt == 6)) {
+        if (mt == 6 && nt == 6) gemm_block_quad<true, 1, 1, false, 3>(P, D, ql, pre);
+        else if (mt == 6) gemm_block_quad<true, 1, 1, false, 1>(P, D, ql, pre);
+        else gemm_block_quad<true, 1, 1, false, 2>(P, D, ql, pre);
+        return;
+      }
     }
     if (vid == 1 || (vid == 0 && mt == 4 && nt == 4)) {
       const int tm = mt <= 4 ? 1 : 2, tn = nt <= 4 ? 1 : 2;

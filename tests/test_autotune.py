@@ -39,6 +39,14 @@ def test_class_workload_shapes():
     assert np.array_equal(a.cbs, b.rbs)
 
 
+def test_variant_edges():
+    """Which variants exist for which block edges (as the library checks)."""
+    assert autotune.applies(3, 8, 5) and not autotune.applies(3, 9, 5)
+    assert autotune.applies(4, 13, 23) and autotune.applies(4, 24, 9) and autotune.applies(4, 17, 17)
+    assert not autotune.applies(4, 16, 16) and not autotune.applies(4, 5, 23) and not autotune.applies(4, 25, 23)
+    assert all(autotune.applies(v, m, n) for v in (1, 2) for m in (1, 32) for n in (1, 32))
+
+
 @pytest.mark.gpu
 def test_variants_agree_with_oracle():
     import torch
@@ -51,10 +59,10 @@ def test_variants_agree_with_oracle():
     A = bsmm.Matrix.from_host(ctx, a)
     B = bsmm.Matrix.from_host(ctx, b)
     results = {}
-    for v in (0, 1, 2, 3):
+    for v in (0, 1, 2, 3, 4):
         for m in (5, 13, 23, 32):
-            for n in (5, 13, 23, 32):   # variant 3 exists for edges up to 8 only
-                ctx.set_gemm_variant(m, n, v if v < 3 or (m <= 8 and n <= 8) else 0)
+            for n in (5, 13, 23, 32):   # variants 3 and 4 exist for some edges only
+                ctx.set_gemm_variant(m, n, v if autotune.applies(v, m, n) else 0)
         C, info = bsmm.multiply(ctx, "N", "N", 1.0, A, B)
         h = C.to_host()
         C.close()
