@@ -299,9 +299,16 @@ static void plan_build(Plan &P, char transa, char transb) {
   make_op(ctx, A, ta, oa);
   make_op(ctx, B, tb, ob);
   tm.mark();  // 1
-  std::vector<int32_t> ksizes(opa_c.begin(), opa_c.end());
-  std::sort(ksizes.begin(), ksizes.end());
-  ksizes.erase(std::unique(ksizes.begin(), ksizes.end()), ksizes.end());
+  // distinct contraction block sizes, ascending (each in 1..MAX_BLOCK,
+  // checked above): a presence mask, not a sort of one entry per block
+  // column -- this runs on the host while the device waits for the plan
+  std::vector<int32_t> ksizes;
+  {
+    bool seen[MAX_BLOCK + 1] = {};
+    for (int32_t v : opa_c) seen[v] = true;
+    for (int32_t v = 1; v <= MAX_BLOCK; v++)
+      if (seen[v]) ksizes.push_back(v);
+  }
   const uint64_t two_gb = 1ull << 31;
   // quad path of the GEMM: packed operand copies below 2 GB (32-bit byte
   // offsets in the stack entries), at most 8 distinct k sizes.  A packed
