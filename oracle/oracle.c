@@ -21,7 +21,7 @@
  *   - Related work: the row-by-row serial sparse product of Gustavson is the
  *     classic algorithm; this oracle is that algorithm at block granularity.
  *
- * Readings taken where the paper is silent (all also listed in the design doc):
+ * Readings taken where the paper is silent:
  *   R1 norm = Frobenius norm, FP64, for both filter phases;
  *   R2 a block product is kept iff normA*normB >= eps, and a result block is
  *      kept iff its norm >= eps (so eps = 0 filters nothing);
