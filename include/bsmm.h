@@ -177,6 +177,27 @@ bsmm_status bsmm_multiply(bsmm_ctx ctx, char transa, char transb, double alpha,
  * (the post-multiply filter of Section 1 applied on its own). */
 bsmm_status bsmm_filter(bsmm_mat m, double eps, bsmm_mat *out);
 
+/* The filter above for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops and harnesses that forbid
+ * hipMalloc): the same result as bsmm_filter, bitwise, written into
+ * caller-owned device buffers on m's device, ordered on the context's stream.
+ * It calls no hipMalloc, hipFree or host synchronisation.
+ *   row_ptr_out : nbr + 1 entries (int64), the result's block-row pointers;
+ *   col_idx_out : room for nnzb(m) entries (int32); NULL allowed iff nnzb = 0;
+ *   values_out  : room for n_values(m) FP64 values; NULL allowed iff
+ *                 n_values = 0 -- the kept blocks in CSR order, each as stored;
+ *   counts_out  : 2 entries (int64): kept blocks, kept values.
+ * Its intermediates live in one fixed device array inside the library
+ * (about 22 MiB on every GPU the library runs on, held until the process
+ * ends), shared by every call on that GPU: calls that overlap on one GPU
+ * (from any context or stream) race, so the caller must order them.
+ * Errors: BSMM_ERR_INVALID_ARG (NULL buffer, eps < 0 or NaN),
+ * BSMM_ERR_UNSUPPORTED for m above 262,144 block rows or 16,777,216 blocks,
+ * BSMM_ERR_ALIAS when an output overlaps m's index or values; outputs are
+ * untouched on every error. */
+bsmm_status bsmm_filter_noalloc(bsmm_mat m, double eps, int64_t *row_ptr_out, int32_t *col_idx_out,
+                                double *values_out, int64_t *counts_out);
+
 /* ------------------------------------------------------------- plans
  * A plan splits one multiplication (same arguments as bsmm_multiply) into
  *   - bsmm_plan_create: the structural part, run once -- validation, index

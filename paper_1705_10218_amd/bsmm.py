@@ -35,7 +35,7 @@ SYMBOLS = (
     "bsmm_mat_get_index", "bsmm_mat_get_block_sizes", "bsmm_mat_values", "bsmm_mat_copy_values",
     "bsmm_mat_destroy", "bsmm_block_norms", "bsmm_multiply", "bsmm_filter", "bsmm_sign_newton_schulz",
     "bsmm_plan_create", "bsmm_plan_execute", "bsmm_plan_capture", "bsmm_plan_result", "bsmm_plan_destroy",
-    "bsmm_plans_execute",
+    "bsmm_plans_execute", "bsmm_filter_noalloc",
 )
 
 
@@ -111,6 +111,7 @@ def lib() -> ctypes.CDLL:
                                     _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_vp),
                                     ctypes.POINTER(MultiplyInfo)]
         L.bsmm_filter.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(_vp)]
+        L.bsmm_filter_noalloc.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
         L.bsmm_plan_create.argtypes = [_vp, ctypes.c_char, ctypes.c_char, ctypes.c_double, _vp, _vp,
                                        ctypes.c_double, _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_vp),
                                        ctypes.POINTER(MultiplyInfo)]
@@ -311,6 +312,16 @@ def filter(m: Matrix, eps: float) -> Matrix:  # noqa: A001 - mirrors bsmm_filter
     out = _vp()
     _check(lib().bsmm_filter(m.handle, float(eps), ctypes.byref(out)))
     return Matrix(m.ctx, out)
+
+
+def filter_noalloc(m: Matrix, eps: float, row_ptr_out, col_idx_out, values_out, counts_out) -> None:
+    """bsmm_filter_noalloc: the filter into caller-owned torch tensors
+    (int64 nbr+1, int32 >= nnzb, float64 >= n_values, int64 2); ordered on
+    the context's stream, no allocation inside the library."""
+    def p(t):
+        return _vp(t.data_ptr() if t is not None and t.numel() else 0)
+    _check(lib().bsmm_filter_noalloc(m.handle, float(eps), p(row_ptr_out), p(col_idx_out), p(values_out),
+                                     p(counts_out)))
 
 
 class Plan:

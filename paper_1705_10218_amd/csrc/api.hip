@@ -12,6 +12,8 @@ namespace bsmm {
 
 static thread_local std::string g_last_error;
 
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
 [[noreturn]] void fail(bsmm_status code, const std::string &msg) { throw Error{code, msg}; }
 
 void hip_check(hipError_t e, const char *what, const char *file, int line) {
@@ -917,23 +919,6 @@ static bsmm_mat_s *sign_impl(bsmm_ctx ctx, bsmm_mat_s *X0, int32_t max_iter, dou
 
 using namespace bsmm;
 
-#define ABI_BEGIN try {
-#define ABI_END                                   \
-  return BSMM_OK;                                 \
-  }                                               \
-  catch (const Error &e) {                        \
-    g_last_error = e.msg;                         \
-    return e.code;                                \
-  }                                               \
-  catch (const std::bad_alloc &) {                \
-    g_last_error = "host allocation failed";      \
-    return BSMM_ERR_OUT_OF_MEMORY;                \
-  }                                               \
-  catch (...) {                                   \
-    g_last_error = "unexpected internal error";   \
-    return BSMM_ERR_DEVICE;                       \
-  }
-
 extern "C" {
 
 const char *bsmm_status_string(bsmm_status s) {
@@ -963,6 +948,12 @@ bsmm_status bsmm_ctx_create(int device, void *stream, size_t hbm_budget_bytes, b
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
   c->alloc.init(device, hbm_budget_bytes);
+  try {
+    noalloc_init(device);   // device address of the allocation-free filter's scratch array
+  } catch (...) {
+    delete c;
+    throw;
+  }
   if (hipHostMalloc((void **)&c->pinned, 64 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
     delete c;
     fail(BSMM_ERR_OUT_OF_MEMORY, "pinned host buffer");

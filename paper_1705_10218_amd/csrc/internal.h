@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,8 @@ struct Error {
 };
 
 [[noreturn]] void fail(bsmm_status code, const std::string &msg);
+// Detail returned by bsmm_last_error() on this host thread.
+void set_last_error(const std::string &msg);
 void hip_check(hipError_t e, const char *what, const char *file, int line);
 #define HIPCHECK(x) ::bsmm::hip_check((x), #x, __FILE__, __LINE__)
 
@@ -44,6 +47,24 @@ class Allocator {
 };
 
 }  // namespace bsmm
+
+// Body of every ABI entry point: library errors become status codes.
+#define ABI_BEGIN try {
+#define ABI_END                                              \
+  return BSMM_OK;                                            \
+  }                                                          \
+  catch (const ::bsmm::Error &e) {                           \
+    ::bsmm::set_last_error(e.msg);                           \
+    return e.code;                                           \
+  }                                                          \
+  catch (const std::bad_alloc &) {                           \
+    ::bsmm::set_last_error("host allocation failed");        \
+    return BSMM_ERR_OUT_OF_MEMORY;                           \
+  }                                                          \
+  catch (...) {                                              \
+    ::bsmm::set_last_error("unexpected internal error");     \
+    return BSMM_ERR_DEVICE;                                  \
+  }
 
 struct bsmm_ctx_s {
   int device = 0;
@@ -369,6 +390,10 @@ void build_work_list_sorted(Allocator &al, const int32_t *ord, const int32_t *cr
 // the work list).
 void build_desc_by_block(int64_t n, const int32_t *pos, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
                          const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s);
+
+// Takes the device address of the allocation-free filter's scratch array on
+// `device` (the current device), once per device.
+void noalloc_init(int device);
 
 // Locality order of the rows of a square block pattern (host planner).
 std::vector<int32_t> locality_order(int32_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci);
