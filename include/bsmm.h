@@ -82,6 +82,10 @@ typedef struct {
   double useful_flops;      /* sum over kept products of 2*m*k*n               */
   /* device time per phase in ms (only when timing is enabled, else 0)         */
   float ms_index, ms_norms, ms_symbolic, ms_stacks, ms_gemm, ms_filter, ms_total;
+  /* block-GEMM path: 0 = packed operand copies (k-pair slabs, one wavefront
+     per result block), 1 = 64-bit pointer walker, 2 = tile path (2x2 tiles
+     of result blocks, operands staged in LDS), 3 = FP32 / split packed path */
+  int32_t gemm_path;
 } bsmm_multiply_info;
 
 /* Readable name of a status code (static storage). */
@@ -105,15 +109,32 @@ bsmm_status bsmm_ctx_set_compute_mode(bsmm_ctx ctx, bsmm_compute_mode mode);
  *       k-slice, one in each diagonal 8x8 quadrant (both edges <= 8 only;
  *       the stacks of such blocks are padded to groups of eight products),
  *   4 = one 16x16x4 MFMA tile plus 4x4x4 MFMA subtiles along the edges
- *       beyond 16 (both edges in 9..24, one of them above 16).
+ *       beyond 16 (both edges in 9..24, one of them above 16),
+ *   5 = the tile path (both edges in 17..24): one wavefront per 2x2 tile of
+ *       result blocks stages the operand blocks the tile uses at each k in
+ *       LDS, read straight from the stored values (no packed copies, no
+ *       2 GB limit), and runs the tile's products at that k from LDS with
+ *       the MFMA layout of variant 4.
+ * For the class of edges 17..24 x 17..24, variant 0 selects the tile path
+ * when every result block of the product is in that class and every
+ * contraction extent is at most 24 (else the packed-operand path).
  * The variant in force when a product is planned is the one it runs with.
  * All variants give results within FP64 rounding of each other; the choice
  * only changes speed (an autotuner picks it per size class).  Applies to the
  * packed-operand path (packed copies of op(A) and op(B) below 2 GB each, at
  * most 8 distinct k sizes).
  * Errors: BSMM_ERR_INVALID_ARG for edges outside 1..32, another variant,
- * variant 3 with an edge above 8, or variant 4 outside its edges. */
+ * variant 3 with an edge above 8, or variant 4 or 5 outside its edges. */
 bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_t variant);
+/* Result-block tile of the tile path (variant 5): ti x tj result blocks per
+ * workgroup, each of its (ti/2)(tj/2) wavefronts owning a 2 x 2 part; an
+ * operand block staged in LDS serves up to tj (A) or ti (B) products.
+ * Shapes: 2x2 (default: one wavefront, no barrier), 2x4, 4x2, 4x4, 4x8,
+ * 8x4 (several wavefronts sharing the staged blocks, one barrier per k).  Applies to products
+ * planned afterwards; results are bitwise the same for every shape (each
+ * result block sums its products in ascending k).
+ * Errors: BSMM_ERR_INVALID_ARG for another shape. */
+bsmm_status bsmm_ctx_set_tile_shape(bsmm_ctx ctx, int32_t ti, int32_t tj);
 /* Bytes of device memory the library currently holds for this context
  * (live buffers plus its cache of freed ones). */
 bsmm_status bsmm_ctx_memory(bsmm_ctx ctx, size_t *held_bytes, size_t *peak_bytes);

@@ -35,7 +35,7 @@ SYMBOLS = (
     "bsmm_mat_get_index", "bsmm_mat_get_block_sizes", "bsmm_mat_values", "bsmm_mat_copy_values",
     "bsmm_mat_destroy", "bsmm_block_norms", "bsmm_multiply", "bsmm_filter", "bsmm_sign_newton_schulz",
     "bsmm_plan_create", "bsmm_plan_execute", "bsmm_plan_capture", "bsmm_plan_result", "bsmm_plan_destroy",
-    "bsmm_plans_execute", "bsmm_filter_noalloc",
+    "bsmm_plans_execute", "bsmm_filter_noalloc", "bsmm_ctx_set_tile_shape",
 )
 
 
@@ -51,7 +51,7 @@ class MultiplyInfo(ctypes.Structure):
         ("n_candidates", ctypes.c_int64), ("n_products", ctypes.c_int64), ("useful_flops", ctypes.c_double),
         ("ms_index", ctypes.c_float), ("ms_norms", ctypes.c_float), ("ms_symbolic", ctypes.c_float),
         ("ms_stacks", ctypes.c_float), ("ms_gemm", ctypes.c_float), ("ms_filter", ctypes.c_float),
-        ("ms_total", ctypes.c_float),
+        ("ms_total", ctypes.c_float), ("gemm_path", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -62,7 +62,7 @@ class SignInfo(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("residual", ctypes.c_double),
         ("nnzb", ctypes.c_int64), ("nnzb_max", ctypes.c_int64), ("useful_flops", ctypes.c_double),
-        ("ms_total", ctypes.c_float),
+        ("ms_total", ctypes.c_float), ("gemm_path", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         L.bsmm_ctx_set_timing.argtypes = [_vp, ctypes.c_int]
         L.bsmm_ctx_set_compute_mode.argtypes = [_vp, ctypes.c_int]
         L.bsmm_ctx_set_gemm_variant.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.bsmm_ctx_set_tile_shape.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
         L.bsmm_ctx_memory.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
         L.bsmm_ctx_trim.argtypes = [_vp]
         L.bsmm_ctx_synchronize.argtypes = [_vp]
@@ -166,6 +167,9 @@ class Context:
 
     def set_gemm_variant(self, m: int, n: int, variant: int):
         _check(lib().bsmm_ctx_set_gemm_variant(self.handle, int(m), int(n), int(variant)))
+
+    def set_tile_shape(self, ti: int, tj: int):
+        _check(lib().bsmm_ctx_set_tile_shape(self.handle, int(ti), int(tj)))
 
     def memory(self):
         held, peak = ctypes.c_size_t(), ctypes.c_size_t()

@@ -233,7 +233,7 @@ struct Timer {
 struct Plan {
   bsmm_ctx ctx = nullptr;
   bsmm_mat_s *A = nullptr, *B = nullptr, *C0 = nullptr;
-  bool ta = false, tb = false, filt = false, post = false, quads = false, lowp = false;
+  bool ta = false, tb = false, filt = false, post = false, quads = false, lowp = false, tiles = false;
   // one_shot: built, executed once and consumed (bsmm_multiply); packed:
   // plan_build already made the packed operand copies of the current values
   bool one_shot = false, packed = false;
@@ -251,6 +251,9 @@ struct Plan {
   DBuf<int2> stack;
   DBuf<double> a_pack, b_pack, a_lo, b_lo, a_t, b_t, c_norm, c_values;
   GemmArgs ga;
+  // tile path: tiles of result blocks and their per-k step records
+  TilePlan tp;
+  TileArgs targs;
   Timer tm;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -311,6 +314,20 @@ static void plan_build(Plan &P, char transa, char transb) {
     for (int32_t v = 1; v <= MAX_BLOCK; v++)
       if (seen[v]) ksizes.push_back(v);
   }
+  // tile path of the GEMM (operand blocks staged in LDS per 2x2 tile of
+  // result blocks, read from the stored values): FP64, every result block
+  // edge in 17..24 and every contraction extent up to 24, unless another
+  // variant is requested for that size class
+  bool tiles = false;
+  if (ctx->mode == BSMM_COMPUTE_FP64 && nbr > 0 && nbc > 0 && !ksizes.empty()) {
+    const uint8_t v = ctx->gemm_variant[10];   // class of edges 17..24 x 17..24
+    tiles = v == 0 || v == 5;
+    for (int32_t x : opa_r) tiles = tiles && x >= 17 && x <= 24;
+    for (int32_t x : opb_c) tiles = tiles && x >= 17 && x <= 24;
+    tiles = tiles && ksizes.back() <= 24 &&
+            tile_path_fits(nbc, (int32_t)opa_c.size(), TileShape{ctx->tile_ti, ctx->tile_tj});
+  }
+  P.tiles = tiles;
   const uint64_t two_gb = 1ull << 31;
   // quad path of the GEMM: packed operand copies below 2 GB (32-bit byte
   // offsets in the stack entries), at most 8 distinct k sizes.  A packed
@@ -320,7 +337,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   const bool lowp = P.lowp = ctx->mode != BSMM_COMPUTE_FP64;
   const double kmin = ksizes.empty() ? 1.0 : (double)ksizes.front();
   const double grow = lowp ? 0.5 * (kmin + 3.0) / kmin : (kmin + 1.0) / kmin;
-  const bool quads = P.quads = !ksizes.empty() && ksizes.size() <= 8 &&
+  const bool quads = P.quads = !tiles && !ksizes.empty() && ksizes.size() <= 8 &&
                                (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
                                (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
   // ------------------------------------------------------- a1: norms
@@ -566,7 +583,18 @@ static void plan_build(Plan &P, char transa, char transb) {
   // through per-subtile histograms while the key count stays modest; else
   // 16-row tiles, one workgroup each.
   DBuf<int32_t> wl_pos;   // place of every C block in the work list (sorted path)
-  if (nnzb_c > 0) {
+  if (tiles && nnzb_c > 0) {
+    // tiles of the result pattern and their step records; the per-block
+    // stacks are not needed once merged into the steps
+    DBuf<int32_t> kidx(al, (size_t)std::max<int64_t>(A->nnzb, 1));
+    block_k_index(oa, kidx.p, s);
+    const int32_t *ord = sym.ord;
+    const int32_t *crank = (ord && nbc == nbr) ? ord + nbr : nullptr;
+    build_tile_plan(al, TileShape{ctx->tile_ti, ctx->tile_tj}, ord, crank, crank ? ord : nullptr, nbr, nbc, P.c_rp.p,
+                    P.c_ci.p, P.seg_off.p, P.stack.p, kidx.p, (int32_t)opa_c.size(), oa.cbs, A->d_blk_off,
+                    B->d_blk_off, ctx->pinned, P.tp, s);
+    P.stack.reset();
+  } else if (nnzb_c > 0) {
     const int32_t *ord = row_order(ctx, A);
     if (ord) {
       P.c_list = DBuf<int32_t>(al, nc1);
@@ -609,8 +637,8 @@ static void plan_build(Plan &P, char transa, char transb) {
       P.b_lo = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
     }
   }
-  if (!quads && ta && P.nprod > 0) P.a_t = DBuf<double>(al, (size_t)std::max<int64_t>(A->n_values, 1));
-  if (!quads && !tb && P.nprod > 0) P.b_t = DBuf<double>(al, (size_t)std::max<int64_t>(B->n_values, 1));
+  if (!quads && !tiles && ta && P.nprod > 0) P.a_t = DBuf<double>(al, (size_t)std::max<int64_t>(A->n_values, 1));
+  if (!quads && !tiles && !tb && P.nprod > 0) P.b_t = DBuf<double>(al, (size_t)std::max<int64_t>(B->n_values, 1));
   if (!ctx->zeros) {
     ctx->zeros = static_cast<double *>(al.alloc(4096));
     HIPCHECK(hipMemsetAsync(ctx->zeros, 0, 4096, s));
@@ -648,6 +676,23 @@ static void plan_build(Plan &P, char transa, char transb) {
   ga.zeros = ctx->zeros;
   ga.quads = quads;
   for (int t = 0; t < 16; t++) ga.variant[t] = ctx->gemm_variant[t];
+  TileArgs &tg = P.targs;
+  tg.rbs = oa.rbs;
+  tg.cbs = ob.cbs;
+  tg.a_val = A->d_values;
+  tg.b_val = B->d_values;
+  tg.a_n = A->n_values;
+  tg.b_n = B->n_values;
+  tg.ta = ta;
+  tg.tb = tb;
+  tg.c_off = P.c_off.p;
+  tg.old_blk = P.old_blk.p;
+  tg.old_off = C0 ? C0->d_blk_off : nullptr;
+  tg.old_val = C0 ? C0->d_values : nullptr;
+  tg.c_val = P.c_values.p;
+  tg.c_norm = P.post ? P.c_norm.p : nullptr;
+  tg.alpha = P.alpha;
+  tg.beta = P.beta;
   P.max_edge = 1;
   for (int32_t v : opa_r) P.max_edge = std::max(P.max_edge, v);
   for (int32_t v : opb_c) P.max_edge = std::max(P.max_edge, v);
@@ -658,6 +703,12 @@ static void plan_build(Plan &P, char transa, char transb) {
 static void plan_numeric(Plan &P, bool marks) {
   hipStream_t s = P.ctx->stream;
   const bool ta = P.ta, tb = P.tb;
+  if (P.tiles) {   // operands come straight from the stored values
+    if (marks) P.tm.mark();  // 5
+    tile_gemm_launch(P.tp, P.targs, s);
+    if (marks) P.tm.mark();  // 6
+    return;
+  }
   if (P.nprod > 0) {
     if (P.quads && P.lowp) {
       pack32_values(*P.A, ta, P.a_poff.p, reinterpret_cast<float *>(P.a_pack.p), reinterpret_cast<float *>(P.a_lo.p), s);
@@ -744,6 +795,8 @@ static bsmm_mat_s *plan_finish(Plan &P, bool consume) {
   return R;
 }
 
+static int32_t gemm_path(const Plan &P) { return P.tiles ? 2 : P.lowp ? 3 : P.quads ? 0 : 1; }
+
 static void plan_info(Plan &P, const bsmm_mat_s *R, bsmm_multiply_info *info) {
   if (!info) return;
   Timer &tm = P.tm;
@@ -760,6 +813,7 @@ static void plan_info(Plan &P, const bsmm_mat_s *R, bsmm_multiply_info *info) {
   info->ms_gemm = tm.between(5, 6);
   info->ms_filter = tm.between(6, 7);
   info->ms_total = tm.between(0, 7);
+  info->gemm_path = gemm_path(P);
 }
 
 static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double alpha, bsmm_mat_s *A,
@@ -992,11 +1046,22 @@ bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_
   ABI_BEGIN
   if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
   if (m < 1 || m > MAX_BLOCK || n < 1 || n > MAX_BLOCK) fail(BSMM_ERR_INVALID_ARG, "block edge outside 1..32");
-  if (variant < 0 || variant > 4) fail(BSMM_ERR_INVALID_ARG, "variant must be 0, 1, 2, 3 or 4");
+  if (variant < 0 || variant > 5) fail(BSMM_ERR_INVALID_ARG, "variant must be 0, 1, 2, 3, 4 or 5");
+  if (variant == 5 && (m < 17 || n < 17 || m > 24 || n > 24))
+    fail(BSMM_ERR_INVALID_ARG, "variant 5 needs both block edges in 17..24");
   if (variant == 3 && (m > 8 || n > 8)) fail(BSMM_ERR_INVALID_ARG, "variant 3 needs both block edges <= 8");
   if (variant == 4 && (m < 9 || n < 9 || m > 24 || n > 24 || (m <= 16 && n <= 16)))
     fail(BSMM_ERR_INVALID_ARG, "variant 4 needs both block edges in 9..24 and one above 16");
   ctx->gemm_variant[((m + 7) / 8 - 1) * 4 + ((n + 7) / 8 - 1)] = (uint8_t)variant;
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_set_tile_shape(bsmm_ctx ctx, int32_t ti, int32_t tj) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  if (!tile_shape_valid(ti, tj)) fail(BSMM_ERR_INVALID_ARG, "tile shape must be 2x2, 2x4, 4x2, 4x4, 4x8 or 8x4");
+  ctx->tile_ti = ti;
+  ctx->tile_tj = tj;
   ABI_END
 }
 
@@ -1224,6 +1289,7 @@ bsmm_status bsmm_plan_create(bsmm_ctx ctx, char transa, char transb, double alph
       info->ms_norms = P.tm.between(1, 2);
       info->ms_symbolic = P.tm.between(2, 3);
       info->ms_stacks = P.tm.between(3, 4);
+      info->gemm_path = gemm_path(P);
     }
   } catch (...) {
     delete pl;

@@ -74,6 +74,7 @@ struct bsmm_ctx_s {
   bsmm::Allocator alloc;
   int64_t *pinned = nullptr;   // small host buffer for size read-backs
   uint8_t gemm_variant[16] = {};   // GEMM kernel variant per (m, n) size class
+  int tile_ti = 2, tile_tj = 2;    // result-block tile of the tile path
   void *batch_host = nullptr;      // pinned staging of batched launch parameters
   void *batch_dev = nullptr;       // device copy (reused once the stream has passed the last launch)
   size_t batch_bytes = 0;
@@ -390,6 +391,52 @@ void build_work_list_sorted(Allocator &al, const int32_t *ord, const int32_t *cr
 // the work list).
 void build_desc_by_block(int64_t n, const int32_t *pos, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
                          const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s);
+
+// ---------------------------------------------------- tile path of the GEMM
+// Result blocks in tiles of ti x tj (rows adjacent in the locality order,
+// columns too); one workgroup per tile, (ti/2)(tj/2) wavefronts each owning
+// a 2 x 2 part of it; the operand blocks the tile uses at a k are staged in
+// LDS once for all its products.
+struct TileShape {
+  int ti = 2, tj = 2;
+};
+// Descriptors and step records of a product's tiles (layouts depend on the
+// shape; see tile_gemm.hip).
+struct TilePlan {
+  TileShape sh;
+  int64_t ntile = 0, nsteps = 0;
+  DBuf<int4> tiles, steps;
+};
+struct TileArgs {
+  const int32_t *rbs = nullptr, *cbs = nullptr;   // C block sizes
+  const double *a_val = nullptr, *b_val = nullptr;
+  int64_t a_n = 0, b_n = 0;   // stored values of A and B
+  bool ta = false, tb = false;
+  const int64_t *c_off = nullptr;
+  const int32_t *old_blk = nullptr;
+  const int64_t *old_off = nullptr;
+  const double *old_val = nullptr;
+  double *c_val = nullptr;
+  double *c_norm = nullptr;
+  double alpha = 1.0, beta = 0.0;
+};
+// Tile shapes the kernels are built for.
+bool tile_shape_valid(int ti, int tj);
+// Whether the tile plan's LDS bitmaps hold a product with nbc block columns
+// of C and nbk contraction blocks.
+bool tile_path_fits(int32_t nbc, int32_t nbk, TileShape sh);
+// kidx[stored block id of A] = its k (block column of op(A)).
+void block_k_index(const OpIndex &a, int32_t *kidx, hipStream_t s);
+// Tiles of the result pattern (rows grouped in the order ord, null =
+// natural; columns by crank, null = natural, cinv its inverse) and their step
+// records from the per-result-block stacks (entries = stored A and B block
+// ids, ascending k): two host synchronisations for the sizes.
+void build_tile_plan(Allocator &al, TileShape sh, const int32_t *ord, const int32_t *crank, const int32_t *cinv,
+                     int32_t nbr, int32_t nbc, const int64_t *c_rp, const int32_t *c_ci, const int64_t *seg,
+                     const int2 *stack, const int32_t *kidx, int32_t nbk, const int32_t *ksz, const int64_t *a_off,
+                     const int64_t *b_off, int64_t *pinned, TilePlan &tp, hipStream_t s);
+// a5 on the tile path.
+void tile_gemm_launch(const TilePlan &tp, const TileArgs &g, hipStream_t s);
 
 // Takes the device address of the allocation-free filter's scratch array on
 // `device` (the current device), once per device.

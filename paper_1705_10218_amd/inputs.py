@@ -200,6 +200,133 @@ def config_big23(n_atoms: int = 20000, occupancy: float = 0.03, sizes=(23,)):
     return dft_like_pair(n_atoms, config=3, sizes=sizes, cutoff=rc, decay=2.0)
 
 
+def morton_order(pos: np.ndarray, box: float, bits: int = 10) -> np.ndarray:
+    """Permutation that sorts positions along a Morton (Z-order) curve of the
+    periodic box: neighbouring indices are neighbouring points."""
+    q = np.clip(np.floor(pos / box * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+    code = np.zeros(pos.shape[0], dtype=np.int64)
+    for bit in range(bits):
+        for d in range(3):
+            code |= ((q[:, d] >> bit) & 1) << (3 * bit + d)
+    return np.argsort(code, kind="stable")
+
+
+PANEL_CHUNK = 256   # block rows per value stream of the batching workload
+
+
+@dataclass
+class BatchingProblem:
+    """Geometry of the batching workload: atoms on a Morton curve (so that a
+    contiguous range of block rows, a process's panel, is a compact region),
+    their block sizes and the cutoff."""
+    pos: np.ndarray
+    box: float
+    sizes: np.ndarray
+    cutoff: float
+    decay: float
+    config: int
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+
+def batching_problem(n_atoms: int = 20000, occupancy: float = 0.03, sizes=(23,), config: int = 3,
+                     decay: float = 2.0) -> BatchingProblem:
+    """20,000 atoms at 0.1 /A^3 (box 58.5 A), block sizes drawn from `sizes`,
+    cutoff giving `occupancy` of the block grid on average; atoms renumbered
+    along a Morton curve."""
+    rc = cutoff_for_occupancy(n_atoms, occupancy)
+    at = make_atoms(n_atoms, rng_for(config, 0, 0), sizes=sizes)
+    if rc >= at.box / 2:
+        raise ValueError("cutoff must stay below half the box edge for minimum-image distances")
+    perm = morton_order(at.pos, at.box)
+    return BatchingProblem(at.pos[perm], at.box, at.sizes[perm].astype(np.int32), rc, decay, config)
+
+
+def _pairs_of_rows(pb: BatchingProblem, r0: int, r1: int):
+    """(local row, column, distance) of every block of rows [r0, r1) within
+    the cutoff (minimum image, diagonal included), sorted by (row, column)."""
+    from scipy.spatial import cKDTree   # neighbour search only
+    full = cKDTree(pb.pos, boxsize=pb.box)
+    part = cKDTree(pb.pos[r0:r1], boxsize=pb.box)
+    pr = part.sparse_distance_matrix(full, pb.cutoff, output_type="ndarray")
+    keep = pr["v"] < pb.cutoff
+    rows, cols, dist = pr["i"][keep].astype(np.int64), pr["j"][keep].astype(np.int64), pr["v"][keep]
+    order = np.lexsort((cols, rows))
+    return rows[order], cols[order], dist[order]
+
+
+def batching_matrix(pb: BatchingProblem, matrix: int, row_range=None, row_mask=None,
+                    threads: int | None = None) -> BlockCSR:
+    """Rows [r0, r1) of matrix `matrix` (1 = A, 2 = B) of the batching
+    workload, over all n block columns: block (i, j) present when the
+    minimum-image distance is below the cutoff, values N(0,1) exp(-r/decay).
+    The values of every chunk of PANEL_CHUNK block rows come from their own
+    stream default_rng([config, matrix, chunk]) in storage order, so a panel
+    holds exactly the rows of the whole matrix.  row_mask (optional, n
+    booleans) leaves the unmasked rows empty (their products are never
+    formed when the other operand does not reach them)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    n = pb.n
+    r0, r1 = row_range if row_range is not None else (0, n)
+    c0, c1 = (r0 // PANEL_CHUNK) * PANEL_CHUNK, min(n, -(-r1 // PANEL_CHUNK) * PANEL_CHUNK)
+    rows, cols, dist = _pairs_of_rows(pb, c0, c1)
+    rows += c0
+    sizes_all = pb.sizes[rows].astype(np.int64) * pb.sizes[cols].astype(np.int64)
+    boff = np.zeros(rows.shape[0] + 1, dtype=np.int64)
+    np.cumsum(sizes_all, out=boff[1:])
+    row_start = np.searchsorted(rows, np.arange(c0, c1 + 1))
+    nchunk = (c1 - c0 + PANEL_CHUNK - 1) // PANEL_CHUNK
+    # the blocks kept: rows in [r0, r1) (and in the mask)
+    sel_rows = np.zeros(n, dtype=bool)
+    sel_rows[r0:r1] = True
+    if row_mask is not None:
+        sel_rows &= np.asarray(row_mask, dtype=bool)
+    keep_blk = sel_rows[rows]
+    kept_sizes = sizes_all[keep_blk]
+    koff = np.zeros(int(keep_blk.sum()) + 1, dtype=np.int64)
+    np.cumsum(kept_sizes, out=koff[1:])
+    vals = np.empty(int(koff[-1]), dtype=np.float64)
+    kidx = np.cumsum(keep_blk) - 1   # position of a kept block among kept blocks
+
+    def fill(ch: int):
+        a0 = c0 + ch * PANEL_CHUNK
+        a1 = min(c1, a0 + PANEL_CHUNK)
+        b0, b1 = int(row_start[a0 - c0]), int(row_start[a1 - c0])
+        if b0 == b1:
+            return
+        v = rng_for(pb.config, matrix, a0 // PANEL_CHUNK).standard_normal(int(boff[b1] - boff[b0]))
+        v *= np.repeat(np.exp(-dist[b0:b1] / pb.decay), sizes_all[b0:b1])
+        for r in range(a0, a1):
+            if not sel_rows[r]:
+                continue
+            p0, p1 = int(row_start[r - c0]), int(row_start[r - c0 + 1])
+            if p0 == p1:
+                continue
+            d0 = int(koff[kidx[p0]])
+            vals[d0:d0 + int(boff[p1] - boff[p0])] = v[boff[p0] - boff[b0]:boff[p1] - boff[b0]]
+
+    nt = threads or min(16, len(os.sched_getaffinity(0)))
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(fill, range(nchunk)))
+    kr, kc = rows[keep_blk] - r0, cols[keep_blk]
+    row_ptr = np.zeros(r1 - r0 + 1, dtype=np.int64)
+    np.cumsum(np.bincount(kr, minlength=r1 - r0), out=row_ptr[1:])
+    m = BlockCSR(pb.sizes[r0:r1].copy(), pb.sizes.copy(), row_ptr, kc.astype(np.int32), vals)
+    m.meta = dict(workload="batching", atoms=n, rows=(r0, r1), cutoff=pb.cutoff, box=pb.box, matrix=matrix)
+    return m
+
+
+def reachable_rows(a_panel: BlockCSR, n: int) -> np.ndarray:
+    """Block rows k of the other operand that some stored block (i, k) of the
+    panel reaches (a mask of n booleans)."""
+    mask = np.zeros(n, dtype=bool)
+    mask[np.asarray(a_panel.col_idx)] = True
+    return mask
+
+
 def symmetric_dft_like(n_atoms: int, config: int = 4, sizes=(5, 13), cutoff: float = 7.0, decay: float = 2.0,
                        gap: float = 10.0, request: int = 0) -> BlockCSR:
     """Symmetric DFT-like start matrix for the sign iteration (Section 1,

@@ -1,0 +1,272 @@
+"""Tile path of the block GEMM (result blocks with edges 17..24, computed in
+2x2 tiles whose operand blocks are staged in LDS) against the CPU oracle,
+through the C ABI.
+
+Bar: the block pattern equals the oracle's exactly, product counts and
+useful flops match exactly, FP64 values agree within relative Frobenius
+error 1e-12 (the tile path sums each result block in ascending k, four k per
+MFMA, against the oracle's plain loop: a different rounding order).  Every
+case checks that the tile path really ran (gemm_path == 2).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_10218_amd import inputs
+from _util import random_bcsr, rel_fro, same_pattern
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+TILE_PATH = 2
+
+
+def _log(msg):
+    sys.stdout.write(msg + "\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1705_10218_amd import bsmm
+    return bsmm
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.Context(0)
+
+
+def _gpu_mul(B, ctx, ta, tb, alpha, a, b, beta=0.0, c=None, eps=0.0, retain=False):
+    A = B.Matrix.from_host(ctx, a)
+    Bm = A if b is a else B.Matrix.from_host(ctx, b)
+    C0 = B.Matrix.from_host(ctx, c) if c is not None else None
+    C, info = B.multiply(ctx, ta, tb, alpha, A, Bm, beta, C0, eps, retain)
+    host = C.to_host()
+    for m in (C, A, None if Bm is A else Bm, C0):
+        if m is not None:
+            m.close()
+    return host, info
+
+
+def _check(host, info, ref, tol=TOL, path=TILE_PATH):
+    assert info.gemm_path == path, f"GEMM path {info.gemm_path}, expected {path}"
+    assert np.array_equal(host.row_ptr, ref.row_ptr), "row_ptr differs"
+    assert np.array_equal(host.col_idx, ref.col_idx), "col_idx differs"
+    assert info.n_products == ref.n_products
+    assert info.useful_flops == ref.useful_flops
+    if ref.values.size:
+        err = rel_fro(host.values, ref.values)
+        _log(f"  rel err {err:.2e}")
+        assert err <= tol
+    else:
+        assert host.values.size == 0
+
+
+def _sizes(rng, n, lo=17, hi=24):
+    return rng.integers(lo, hi + 1, n).astype(np.int32)
+
+
+def _operands(rng, ta, tb, nbr, nk, nbc, p, kmax=24, empty_rows=()):
+    rbs, kbs, cbs = _sizes(rng, nbr), _sizes(rng, nk, 1, kmax), _sizes(rng, nbc)
+    a = random_bcsr(rng, nbr, nk, rbs, kbs, p, empty_rows=empty_rows) if ta == "N" else \
+        random_bcsr(rng, nk, nbr, kbs, rbs, p)
+    b = random_bcsr(rng, nk, nbc, kbs, cbs, p) if tb == "N" else random_bcsr(rng, nbc, nk, cbs, kbs, p)
+    return a, b, rbs, cbs
+
+
+SHAPES = [(2, 2), (2, 4), (4, 2), (4, 4), (4, 8), (8, 4)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("ta", ["N", "T"])
+@pytest.mark.parametrize("tb", ["N", "T"])
+def test_tiles_shapes(B, shape, ta, tb):
+    """Every tile shape, every transpose pair, odd grids (tiles with missing
+    rows and columns), against the oracle."""
+    rng = np.random.default_rng([709, shape[0], shape[1], ord(ta), ord(tb)])
+    nbr, nk, nbc = (int(x) for x in rng.integers(5, 30, 3))
+    a, b, _, _ = _operands(rng, ta, tb, nbr, nk, nbc, 0.35, empty_rows=(1,))
+    c2 = B.Context(0)
+    c2.set_tile_shape(*shape)
+    _log(f"tile shape {shape} {ta}{tb} grid={nbr}x{nk}x{nbc}")
+    host, info = _gpu_mul(B, c2, ta, tb, 1.0, a, b)
+    c2.close()
+    _check(host, info, oracle.multiply(ta, tb, 1.0, a, b))
+
+
+def test_tiles_shapes_bitwise_equal(B):
+    """Each result block sums its products in ascending k whatever the tile
+    shape, so every shape gives the same bits."""
+    rng = np.random.default_rng(710)
+    a, b, rbs, cbs = _operands(rng, "N", "N", 23, 19, 21, 0.3)
+    c = random_bcsr(rng, 23, 21, rbs, cbs, 0.3)
+    ref = None
+    for shape in SHAPES:
+        c2 = B.Context(0)
+        c2.set_tile_shape(*shape)
+        host, info = _gpu_mul(B, c2, "N", "N", 0.5, a, b, 1.5, c)
+        c2.close()
+        assert info.gemm_path == TILE_PATH
+        if ref is None:
+            ref = host
+            _check(host, info, oracle.multiply("N", "N", 0.5, a, b, 1.5, c))
+        else:
+            assert same_pattern(host, ref)
+            assert np.array_equal(host.values.view(np.uint64), ref.values.view(np.uint64)), f"shape {shape}"
+
+
+def test_tile_shape_rejected(B):
+    c2 = B.Context(0)
+    for bad in ((3, 3), (8, 8), (1, 2), (2, 8)):
+        with pytest.raises(B.BsmmError):
+            c2.set_tile_shape(*bad)
+    c2.close()
+
+
+@pytest.mark.parametrize("ta", ["N", "T"])
+@pytest.mark.parametrize("tb", ["N", "T"])
+@pytest.mark.parametrize("seed", range(3))
+def test_tiles_random(B, ctx, ta, tb, seed):
+    rng = np.random.default_rng([700, seed])
+    nbr, nk, nbc = (int(x) for x in rng.integers(1, 36, 3))   # odd and even counts: tiles of one row / column
+    a, b, _, _ = _operands(rng, ta, tb, nbr, nk, nbc, 0.3, empty_rows=(0, nbr // 2))
+    _log(f"tiles random {ta}{tb} seed={seed} grid={nbr}x{nk}x{nbc}")
+    host, info = _gpu_mul(B, ctx, ta, tb, 1.0, a, b)
+    _check(host, info, oracle.multiply(ta, tb, 1.0, a, b))
+
+
+@pytest.mark.parametrize("alpha,beta", [(1.0, 1.0), (-0.5, 2.0), (0.0, 1.5), (2.0, 0.0)])
+def test_tiles_alpha_beta(B, ctx, alpha, beta):
+    rng = np.random.default_rng(701)
+    a, b, rbs, cbs = _operands(rng, "N", "N", 27, 21, 25, 0.25)
+    c = random_bcsr(rng, 27, 25, rbs, cbs, 0.3)
+    _log(f"tiles alpha={alpha} beta={beta}")
+    host, info = _gpu_mul(B, ctx, "N", "N", alpha, a, b, beta, c)
+    _check(host, info, oracle.multiply("N", "N", alpha, a, b, beta, c))
+
+
+def test_tiles_beta_zero_ignores_nan_c_old(B, ctx):
+    rng = np.random.default_rng(702)
+    a, b, rbs, cbs = _operands(rng, "N", "N", 14, 12, 15, 0.35)
+    c = random_bcsr(rng, 14, 15, rbs, cbs, 0.5)
+    c.values[:] = np.nan
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, 0.0, c)
+    assert np.all(np.isfinite(host.values))
+    _check(host, info, oracle.multiply("N", "N", 1.0, a, b))
+
+
+def test_tiles_retain_sparsity(B, ctx):
+    rng = np.random.default_rng(703)
+    a, b, rbs, cbs = _operands(rng, "N", "N", 22, 19, 23, 0.3)
+    c = random_bcsr(rng, 22, 23, rbs, cbs, 0.2)
+    for beta in (0.0, 0.5):
+        _log(f"tiles retain beta={beta}")
+        host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, beta, c, retain=True)
+        _check(host, info, oracle.multiply("N", "N", 1.0, a, b, beta, c, retain_sparsity=True))
+        assert same_pattern(host, c)
+
+
+def test_tiles_filters_drop(B, ctx):
+    """A threshold between two norm products, so that the on-the-fly filter
+    drops some products and the post-filter some blocks, with no product or
+    block norm within 1e-9 relative of it."""
+    rng = np.random.default_rng(704)
+    a, b, _, _ = _operands(rng, "N", "N", 30, 26, 28, 0.3)
+    # scale rows so norms spread over decades
+    off = a.block_offsets()
+    rows = a.block_rows()
+    for p in range(a.nnzb):
+        a.values[off[p]:off[p + 1]] *= 10.0 ** (-(rows[p] % 7))
+    na, nb = oracle.block_norms(a), oracle.block_norms(b)
+    prods = np.sort(np.outer(na, nb).ravel())
+    eps = float(0.5 * (prods[len(prods) // 3] + prods[len(prods) // 3 + 1]))
+    assert np.min(np.abs(prods - eps)) > 1e-9 * eps
+    ref = oracle.multiply("N", "N", 1.0, a, b, eps=eps)
+    full = oracle.multiply("N", "N", 1.0, a, b)
+    assert ref.n_products < full.n_products, "the filter should drop products"
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=eps)
+    _check(host, info, ref)
+
+
+def test_tiles_square_same_handle(B, ctx):
+    rng = np.random.default_rng(705)
+    s = _sizes(rng, 33)
+    a = random_bcsr(rng, 33, 33, s, s, 0.25)
+    A = B.Matrix.from_host(ctx, a)
+    C, info = B.multiply(ctx, "N", "N", 1.0, A, A)
+    host = C.to_host()
+    C.close()
+    A.close()
+    _check(host, info, oracle.multiply("N", "N", 1.0, a, a))
+
+
+def test_tiles_dft_like_23(B, ctx):
+    """23x23 blocks on the DFT-like generator (Table 1's H2O block size) at
+    300 atoms, cutoff 6.5 A, filter 1e-10 in both phases; large enough for
+    the locality order (square product over 64+ rows) and the column ranks."""
+    a, b, _ = inputs.dft_like_pair(300, config=3, sizes=(23,), cutoff=6.5)
+    _log(f"tiles dft-like 23: nnzb {a.nnzb}")
+    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=1e-10)
+    _check(host, info, oracle.multiply("N", "N", 1.0, a, b, eps=1e-10))
+
+
+def test_tiles_deterministic_and_against_packed_path(B, ctx):
+    rng = np.random.default_rng(706)
+    a, b, _, _ = _operands(rng, "N", "N", 40, 37, 39, 0.2, kmax=24)
+    h1, i1 = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
+    h2, _ = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
+    assert i1.gemm_path == TILE_PATH
+    assert np.array_equal(h1.values.view(np.uint64), h2.values.view(np.uint64)), "two runs differ"
+    ctx2 = B.Context(0)
+    ctx2.set_gemm_variant(23, 23, 4)   # the packed-operand path for the same class
+    h3, i3 = _gpu_mul(B, ctx2, "N", "N", 1.0, a, b)
+    ctx2.close()
+    assert i3.gemm_path in (0, 1)   # packed path, or the walker past 8 distinct k sizes
+    assert same_pattern(h1, h3) and rel_fro(h1.values, h3.values) <= TOL
+
+
+def test_tiles_plan_and_graph(B, ctx):
+    import torch
+    rng = np.random.default_rng(707)
+    a, b, rbs, cbs = _operands(rng, "N", "N", 26, 22, 24, 0.3)
+    stream = torch.cuda.Stream()
+    c2 = B.Context(0, stream=stream)
+    A = B.Matrix.from_host(c2, a)
+    Bm = B.Matrix.from_host(c2, b)
+    one, _ = B.multiply(c2, "N", "N", 1.0, A, Bm)
+    ref = one.to_host()
+    one.close()
+    P = B.Plan(c2, "N", "N", 1.0, A, Bm)
+    assert P.info.gemm_path == TILE_PATH
+    P.execute()
+    r = P.result()
+    h = r.to_host()
+    r.close()
+    assert same_pattern(h, ref) and np.array_equal(h.values.view(np.uint64), ref.values.view(np.uint64))
+    P.capture()
+    for rep in range(3):
+        P.execute()
+        torch.cuda.synchronize()
+        r = P.result()
+        h = r.to_host()
+        r.close()
+        assert np.array_equal(h.values.view(np.uint64), ref.values.view(np.uint64)), f"replay {rep}"
+    P.close()
+    A.close()
+    Bm.close()
+    c2.close()
+
+
+def test_tiles_single_row_and_column(B, ctx):
+    rng = np.random.default_rng(708)
+    for nbr, nk, nbc in ((1, 5, 1), (1, 1, 7), (5, 3, 1), (2, 1, 2)):
+        a, b, _, _ = _operands(rng, "N", "N", nbr, nk, nbc, 0.9)
+        _log(f"tiles grid {nbr}x{nk}x{nbc}")
+        host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
+        _check(host, info, oracle.multiply("N", "N", 1.0, a, b))
