@@ -31,7 +31,8 @@ FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 SIGN_ATOMS, SIGN_EPS, SIGN_TOL, SIGN_MAX_ITER = 1000, 1e-6, 1e-4, 20
 SERVE_ATOMS, SERVE_BUDGET_GB = (200, 1500), 64
-BATCH_ATOMS = 3500   # 23x23 blocks at 3 % occupancy: the packed operands just fit 32-bit offsets
+BATCH_ATOMS, BATCH_OCC, BATCH_PANEL = 20000, 0.03, 2500   # batching workload: one process's panel of C rows
+PANEL_SAMPLE = 0.01   # fraction of the panel's rows the oracle checks
 HBM_PEAK_GBS = 8000.0
 METRIC = "useful FP64 GFLOP/s of block-sparse C+=A·B, % MFMA peak; p99 serve latency"
 
@@ -51,11 +52,13 @@ def workload(name: str):
     if name == "tiny":
         a, b = inputs.config_tiny(0), inputs.config_tiny(1)
         return a, b, 0.0, {"workload": "tiny_100x100_blocks_5", "filter_eps": 0.0}
-    if name == "blocks23":   # the batching section's 23x23 workload, as the timed step (profiling)
-        a, b, atoms = inputs.config_big23(BATCH_ATOMS, 0.03, sizes=(23,))
-        return a, b, 1e-10, {"workload": f"dft_like_{BATCH_ATOMS}_atoms_blocks_23_occupancy_3pct",
-                             "atoms": BATCH_ATOMS, "block_sizes": [23], "filter_eps": 1e-10,
-                             "box_A": round(atoms.box, 3)}
+    if name == "panel23":   # the batching workload's 23x23 panel, as the timed step (profiling)
+        pb = inputs.batching_problem(BATCH_ATOMS, BATCH_OCC, sizes=(23,))
+        a = inputs.batching_matrix(pb, 1, (0, BATCH_PANEL))
+        b = inputs.batching_matrix(pb, 2)
+        return a, b, 1e-10, {"workload": f"batching_{BATCH_ATOMS}_atoms_blocks_23_panel_{BATCH_PANEL}_rows",
+                             "atoms": BATCH_ATOMS, "block_sizes": [23], "panel_rows": [0, BATCH_PANEL],
+                             "filter_eps": 1e-10, "box_A": round(pb.box, 3), "cutoff_A": round(pb.cutoff, 3)}
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -147,26 +150,101 @@ def sample_parity(gpu_host, r, rows):
 
 
 def time_mode(bsmm, ctx, A, Bm, eps, steps, warmup):
-    """Warm-up, then `steps` whole multiplies timed with events on the stream."""
+    """Warm-up, then `steps` whole multiplies, each bracketed by HIP events on
+    the stream; returns the mean, the per-step times, the infos and the last
+    result."""
     import torch
     for _ in range(warmup):
         C, info = bsmm.multiply(ctx, "N", "N", 1.0, A, Bm, filter_eps=eps)
         C.close()
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     infos = []
     torch.cuda.synchronize()
-    ev0.record(stream)
+    evs[0].record(stream)
     last = None
-    for _ in range(steps):
+    for t in range(steps):
         C, info = bsmm.multiply(ctx, "N", "N", 1.0, A, Bm, filter_eps=eps)
+        evs[t + 1].record(stream)
         infos.append(info)
         if last is not None:
             last.close()
         last = C
-    ev1.record(stream)
     torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / steps, infos, last
+    per = [evs[t].elapsed_time(evs[t + 1]) for t in range(steps)]
+    return sum(per) / steps, per, infos, last
+
+
+def step_stats(per) -> dict:
+    import statistics
+    return {"ms_per_step_median": round(statistics.median(per), 4), "ms_per_step_min": round(min(per), 4),
+            "ms_per_step_max": round(max(per), 4)}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def panel_leg(bsmm, ctx, sizes, rows, steps: int, threads: int, variants: str) -> dict:
+    """The batching workload at its real shape: a panel of C block rows of
+    the 20,000-atom matrices against all of B, parity-checked against the
+    oracle on a seeded sample of the panel's rows."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1705_10218_amd import inputs
+    t0 = time.perf_counter()
+    pb = inputs.batching_problem(BATCH_ATOMS, BATCH_OCC, sizes=sizes)
+    a = inputs.batching_matrix(pb, 1, rows)
+    b = inputs.batching_matrix(pb, 2)
+    gen_s = time.perf_counter() - t0
+    _log(f"batching {sizes}: generated A panel {a.nnzb} blocks, B {b.nnzb} blocks "
+         f"({(a.values.nbytes + b.values.nbytes) / 1e9:.1f} GB) in {gen_s:.1f} s")
+    A, Bm = bsmm.Matrix.from_host(ctx, a), bsmm.Matrix.from_host(ctx, b)
+    torch.cuda.synchronize()
+    ms, per, infos, last = time_mode(bsmm, ctx, A, Bm, 1e-10, steps, 1)
+    info = infos[-1]
+    fl = info.useful_flops
+    g = sorted(i.ms_gemm for i in infos)
+    gemm_ms = g[len(g) // 2]
+    # sampled parity: the oracle on a seeded 1 % of the panel's rows
+    rng = np.random.default_rng(2024)
+    n_s = max(1, int(round(PANEL_SAMPLE * a.nbr)))
+    sample = np.sort(rng.choice(a.nbr, n_s, replace=False)).astype(np.int32)
+    gpu_host = last.to_host()
+    last.close()
+    t1 = time.perf_counter()
+    r = oracle.multiply("N", "N", 1.0, a, b, eps=1e-10, nthreads=threads, rows=sample)
+    oracle_s = time.perf_counter() - t1
+    parity = sample_parity(gpu_host, r, sample)
+    A.close()
+    Bm.close()
+    ctx.trim()
+    out = {"atoms": BATCH_ATOMS, "block_sizes": list(sizes), "occupancy_target": BATCH_OCC,
+           "cutoff_A": round(pb.cutoff, 3), "box_A": round(pb.box, 3), "panel_rows": [int(rows[0]), int(rows[1])],
+           "a_panel_nnzb": int(a.nnzb), "b_nnzb": int(b.nnzb), "b_gb": round(b.values.nbytes / 1e9, 2),
+           "c_nnzb": int(info.c_nnzb), "n_products": int(info.n_products), "useful_flops": fl,
+           "ms_per_step": round(ms, 3), **step_stats(per), "gemm_ms": round(gemm_ms, 3),
+           "value": round(fl / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+           "gemm_tflops": round(fl / (gemm_ms * 1e-3) / 1e12, 3),
+           "gemm_frac_of_fp64_mfma_peak": round(fl / (gemm_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+           "gemm_path": {0: "packed", 1: "walker", 2: "tile", 3: "lowp"}.get(info.gemm_path, "?"),
+           "gemm_variants": variants, "generation_s": round(gen_s, 1),
+           "sample_parity": parity,
+           "oracle": {"rows": int(n_s), "threads": threads, "s": round(oracle_s, 2),
+                      "gflops": round(r.useful_flops / oracle_s / 1e9, 3),
+                      "extrapolated_panel_s": round(oracle_s * a.nbr / n_s, 1),
+                      "note": "linear extrapolation from the sampled rows to the whole panel"}}
+    _log(f"batching {sizes}: {ms:.1f} ms/step, GEMM {gemm_ms:.1f} ms ({out['gemm_tflops']} TF/s), "
+         f"parity {parity}")
+    return out
 
 
 def tiny_latency(bsmm, torch, reps: int = 50) -> dict:
@@ -240,12 +318,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dft4000", choices=["dft4000", "tiny", "blocks23"])
+    ap.add_argument("--workload", default="dft4000", choices=["dft4000", "tiny", "panel23"])
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--fp64-only", action="store_true",
                     help="only the headline FP64 workload (no precision, batching or sign-iteration legs)")
     ap.add_argument("--no-tuning", action="store_true", help="default GEMM kernel variants instead of the tuned table")
     ap.add_argument("--serve-requests", type=int, default=40, help="requests of the serving leg (0: skip it)")
+    ap.add_argument("--no-batching", dest="batching", action="store_false",
+                    help="skip the 20,000-atom batching legs (about 70 GB of host data)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run plain device copies of this size (HBM counter calibration)")
@@ -287,9 +367,7 @@ def main():
     ctx.set_timing(True)
 
     _log(f"warmup {args.warmup}, timing {args.steps} steps")
-    t0 = time.perf_counter()
-    ms_step, infos, last = time_mode(bsmm, ctx, A, Bm, eps, args.steps, args.warmup)
-    wall = time.perf_counter() - t0
+    ms_step, per_step, infos, last = time_mode(bsmm, ctx, A, Bm, eps, args.steps, args.warmup)
     _log(f"{ms_step:.3f} ms/step")
 
     flops = infos[-1].useful_flops
@@ -313,6 +391,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        **step_stats(per_step),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -343,7 +422,7 @@ def main():
         prec = {}
         for name, mode in (("fp32", 1), ("split", 2)):
             ctx.set_compute_mode(mode)
-            ms_m, inf_m, last_m = time_mode(bsmm, ctx, A, Bm, eps, args.steps, 1)
+            ms_m, _, inf_m, last_m = time_mode(bsmm, ctx, A, Bm, eps, args.steps, 1)
             ctx.set_compute_mode(0)
             g_m = sum(i.ms_gemm for i in inf_m) / len(inf_m)
             prec[name] = {"value": round(inf_m[-1].useful_flops / (ms_m * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
@@ -356,28 +435,22 @@ def main():
             lowp_hosts[name] = last_m.to_host()
             last_m.close()
         out["precision"] = prec
-    # batching workloads: 23x23 blocks at 3 % occupancy, and sizes {5, 13, 23}
-    if not args.fp64_only:
+    # batching workloads at their real shape: a panel of 2,500 C block rows of
+    # the 20,000-atom matrices (23x23 blocks, and sizes {5, 13, 23}) against
+    # all of B, each parity-checked on a seeded sample of its rows
+    threads = len(os.sched_getaffinity(0))
+    if not args.fp64_only and args.batching:
+        A.close()
+        Bm.close()
+        ctx.trim()
+        torch.cuda.empty_cache()
         batching = {}
         for name, sizes in (("blocks_23", (23,)), ("blocks_5_13_23", (5, 13, 23))):
-            ab, bb, atb = inputs.config_big23(BATCH_ATOMS, 0.03, sizes=sizes)
-            variants = tune_for(sizes)
-            Ab, Bb = bsmm.Matrix.from_host(ctx, ab), bsmm.Matrix.from_host(ctx, bb)
-            ms_b, inf_b, last_b = time_mode(bsmm, ctx, Ab, Bb, 1e-10, 3, 1)
-            last_b.close()
-            g_b = sum(i.ms_gemm for i in inf_b) / len(inf_b)
-            fl = inf_b[-1].useful_flops
-            batching[name] = {"atoms": BATCH_ATOMS, "occupancy": round(ab.nnzb / ab.nbr ** 2, 4),
-                              "c_nnzb": int(inf_b[-1].c_nnzb), "n_products": int(inf_b[-1].n_products),
-                              "useful_flops": fl, "ms_per_step": round(ms_b, 3), "gemm_ms": round(g_b, 3),
-                              "value": round(fl / (ms_b * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
-                              "gemm_tflops": round(fl / (g_b * 1e-3) / 1e12, 3),
-                              "gemm_frac_of_fp64_mfma_peak": round(fl / (g_b * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
-                              "gemm_variants": variants}
-            _log(f"batching {name}: {ms_b:.3f} ms/step, GEMM {g_b:.3f} ms")
-            Ab.close()
-            Bb.close()
+            batching[name] = panel_leg(bsmm, ctx, sizes, (0, BATCH_PANEL), 2, threads, tune_for(sizes))
+            torch.cuda.empty_cache()
         out["batching"] = batching
+        A = bsmm.Matrix.from_host(ctx, a)
+        Bm = bsmm.Matrix.from_host(ctx, b)
     # latency of the tiny multiply (100x100 blocks of 5): one-shot multiply,
     # re-execution of its plan's numeric part, and the same part replayed
     # from a HIP graph (fixed pattern, values changing between calls)
@@ -411,13 +484,13 @@ def main():
         Y.close()
         X0.close()
     if not args.no_cpu_baseline:
-        threads = min(len(os.sched_getaffinity(0)), 16)
         _log(f"cpu baseline on {threads} threads")
         r, rows, dt = oracle_sample(a, b, eps, args.cpu_seconds, threads)
         out["cpu_baseline"] = {
             "value": round(r.useful_flops / dt / 1e9, 3),
             "unit": "GFLOP/s",
             "cores": threads,
+            "cpu_model": cpu_model(),
             "kind": "oracle",
             "sample": (f"{len(rows)} of {a.nbr} seeded block rows of C ({r.useful_flops:.3e} useful flops, "
                        f"{100.0 * len(rows) / a.nbr:.1f}% of rows), {dt:.2f} s wall"),

@@ -314,32 +314,41 @@ static void plan_build(Plan &P, char transa, char transb) {
     for (int32_t v = 1; v <= MAX_BLOCK; v++)
       if (seen[v]) ksizes.push_back(v);
   }
-  // tile path of the GEMM (operand blocks staged in LDS per 2x2 tile of
-  // result blocks, read from the stored values): FP64, every result block
-  // edge in 17..24 and every contraction extent up to 24, unless another
-  // variant is requested for that size class
-  bool tiles = false;
-  if (ctx->mode == BSMM_COMPUTE_FP64 && nbr > 0 && nbc > 0 && !ksizes.empty()) {
-    const uint8_t v = ctx->gemm_variant[10];   // class of edges 17..24 x 17..24
-    tiles = v == 0 || v == 5;
-    for (int32_t x : opa_r) tiles = tiles && x >= 17 && x <= 24;
-    for (int32_t x : opb_c) tiles = tiles && x >= 17 && x <= 24;
-    tiles = tiles && ksizes.back() <= 24 &&
-            tile_path_fits(nbc, (int32_t)opa_c.size(), TileShape{ctx->tile_ti, ctx->tile_tj});
-  }
-  P.tiles = tiles;
-  const uint64_t two_gb = 1ull << 31;
-  // quad path of the GEMM: packed operand copies below 2 GB (32-bit byte
-  // offsets in the stack entries), at most 8 distinct k sizes.  A packed
-  // block pads its contraction extent k to a multiple of 2 (FP64) or 4
-  // (FP32 / split, half the bytes), so it holds at most (k + 1) / k or
+  // tile path of the GEMM (operand blocks staged in LDS per tile of result
+  // blocks, read from the stored values): FP64, every edge and contraction
+  // extent up to 24, and either every result block edge in 17..24 (its
+  // preferred shape, unless another variant is requested for that class) or
+  // operands the packed-operand path cannot take (copies of 2 GB or more, or
+  // more than 8 distinct k sizes), where it replaces the pointer walker
+  // The quad (packed-operand) path needs packed copies below 2 GB (32-bit
+  // byte offsets in the stack entries) and at most 8 distinct k sizes.  A
+  // packed block pads its contraction extent k to a multiple of 2 (FP64) or
+  // 4 (FP32 / split, half the bytes), so it holds at most (k + 1) / k or
   // (k + 3) / k times the values of the stored block; kmin bounds both.
+  const uint64_t two_gb = 1ull << 31;
   const bool lowp = P.lowp = ctx->mode != BSMM_COMPUTE_FP64;
   const double kmin = ksizes.empty() ? 1.0 : (double)ksizes.front();
   const double grow = lowp ? 0.5 * (kmin + 3.0) / kmin : (kmin + 1.0) / kmin;
-  const bool quads = P.quads = !tiles && !ksizes.empty() && ksizes.size() <= 8 &&
-                               (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
-                               (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
+  const bool pack_ok = !ksizes.empty() && ksizes.size() <= 8 &&
+                       (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
+                       (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
+  bool tiles = false;
+  if (!lowp && nbr > 0 && nbc > 0 && !ksizes.empty() && ksizes.back() <= 24 &&
+      tile_path_fits(nbc, (int32_t)opa_c.size(), TileShape{ctx->tile_ti, ctx->tile_tj})) {
+    bool all24 = true, big = true;
+    for (int32_t x : opa_r) {
+      all24 = all24 && x <= 24;
+      big = big && x >= 17;
+    }
+    for (int32_t x : opb_c) {
+      all24 = all24 && x <= 24;
+      big = big && x >= 17;
+    }
+    const uint8_t v = ctx->gemm_variant[10];   // class of edges 17..24 x 17..24
+    tiles = all24 && ((big && (v == 0 || v == 5)) || !pack_ok);
+  }
+  P.tiles = tiles;
+  const bool quads = P.quads = !tiles && pack_ok;
   // ------------------------------------------------------- a1: norms
   // A one-shot FP64 product on the packed path reads A and B once: the
   // packing kernel computes the block norms as well (after the symbolic

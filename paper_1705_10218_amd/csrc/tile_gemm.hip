@@ -17,11 +17,13 @@
 // written to the other of two LDS buffers) while the products of step k run;
 // one barrier per step separates them.
 //
-// The tile path serves result blocks whose edges are all in 17..24 (and
-// contraction extents up to 24): one V_MFMA_F64_16X16X4F64 tile covers rows
-// and columns 0..15, V_MFMA_F64_4X4X4F64 subtiles the edge rows and columns
-// 16..23 (the edge-subtile layout of the quad path, checked element by
-// element on the device).  The four k-groups of an MFMA take four
+// The tile path serves result blocks with edges up to 24 (and contraction
+// extents up to 24): one V_MFMA_F64_16X16X4F64 tile covers rows and columns
+// 0..15, V_MFMA_F64_4X4X4F64 subtiles the edge rows and columns 16..23 of
+// blocks that reach them (the edge-subtile layout of the quad path, checked
+// element by element on the device).  It is the preferred path for blocks
+// with both edges in 17..24 and the path for operands too large for packed
+// 32-bit-offset copies; smaller blocks use a fraction of the 16 x 16 tile.  The four k-groups of an MFMA take four
 // consecutive k of one block product; K is padded to a multiple of 4 with
 // exact zeros.  Stored blocks are read as they are (column-major), so
 // transposed operands only change the LDS strides, and 64-bit element
@@ -349,12 +351,18 @@ __global__ __launch_bounds__((64 * Shape<TI, TJ>::NW)) void k_tile_gemm(TileP P,
       for (int x = 0; x < 4; x++) {
         const int r = x >> 1, c = x & 1;
         if ((mine >> x) & 1u) {
+          // edge subtiles only where the block reaches past 16 rows / columns
           acc16[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(fc.am[r], fc.bm[c], acc16[x], 0, 0, 0);
-          acc4[x][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(fc.am[r], fc.be[c], acc4[x][0], 0, 0, 0);
-          acc4[x][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(fc.am[r], ber[c], acc4[x][1], 0, 0, 0);
-          acc4[x][2] = __builtin_amdgcn_mfma_f64_4x4x4f64(fc.ae[r], fc.bm[c], acc4[x][2], 0, 0, 0);
-          acc4[x][3] = __builtin_amdgcn_mfma_f64_4x4x4f64(aer[r], fc.bm[c], acc4[x][3], 0, 0, 0);
-          acc4[x][4] = __builtin_amdgcn_mfma_f64_4x4x4f64(fc.ae[r], bes[c], acc4[x][4], 0, 0, 0);
+          if (nw[c] > 16) {
+            acc4[x][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(fc.am[r], fc.be[c], acc4[x][0], 0, 0, 0);
+            acc4[x][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(fc.am[r], ber[c], acc4[x][1], 0, 0, 0);
+          }
+          if (mw[r] > 16) {
+            acc4[x][2] = __builtin_amdgcn_mfma_f64_4x4x4f64(fc.ae[r], fc.bm[c], acc4[x][2], 0, 0, 0);
+            acc4[x][3] = __builtin_amdgcn_mfma_f64_4x4x4f64(aer[r], fc.bm[c], acc4[x][3], 0, 0, 0);
+          }
+          if (mw[r] > 16 && nw[c] > 16)
+            acc4[x][4] = __builtin_amdgcn_mfma_f64_4x4x4f64(fc.ae[r], bes[c], acc4[x][4], 0, 0, 0);
         }
       }
       fc = fn;

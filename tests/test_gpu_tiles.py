@@ -219,6 +219,11 @@ def test_tiles_dft_like_23(B, ctx):
 def test_tiles_deterministic_and_against_packed_path(B, ctx):
     rng = np.random.default_rng(706)
     a, b, _, _ = _operands(rng, "N", "N", 40, 37, 39, 0.2, kmax=24)
+    # at most 8 distinct contraction sizes, so that the packed path can take them
+    kset = np.array([5, 13, 17, 19, 21, 22, 23, 24], np.int32)
+    kbs = kset[rng.integers(0, 8, 37)]
+    a = random_bcsr(rng, 40, 37, a.rbs, kbs, 0.2)
+    b = random_bcsr(rng, 37, 39, kbs, b.cbs, 0.2)
     h1, i1 = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
     h2, _ = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
     assert i1.gemm_path == TILE_PATH
@@ -227,7 +232,7 @@ def test_tiles_deterministic_and_against_packed_path(B, ctx):
     ctx2.set_gemm_variant(23, 23, 4)   # the packed-operand path for the same class
     h3, i3 = _gpu_mul(B, ctx2, "N", "N", 1.0, a, b)
     ctx2.close()
-    assert i3.gemm_path in (0, 1)   # packed path, or the walker past 8 distinct k sizes
+    assert i3.gemm_path == 0
     assert same_pattern(h1, h3) and rel_fro(h1.values, h3.values) <= TOL
 
 
@@ -261,6 +266,25 @@ def test_tiles_plan_and_graph(B, ctx):
     A.close()
     Bm.close()
     c2.close()
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (4, 4)])
+def test_tiles_small_blocks_when_packing_is_impossible(B, shape):
+    """Blocks of any edge up to 24 with more than 8 distinct contraction
+    sizes: the packed path cannot take them, so the tile path does (edge
+    subtiles only for blocks past 16)."""
+    rng = np.random.default_rng([711, shape[0]])
+    rbs = rng.integers(1, 25, 31).astype(np.int32)
+    kbs = rng.integers(1, 25, 27).astype(np.int32)
+    cbs = rng.integers(1, 25, 29).astype(np.int32)
+    assert len(set(kbs.tolist())) > 8
+    a = random_bcsr(rng, 31, 27, rbs, kbs, 0.3)
+    b = random_bcsr(rng, 27, 29, kbs, cbs, 0.3)
+    c2 = B.Context(0)
+    c2.set_tile_shape(*shape)
+    host, info = _gpu_mul(B, c2, "N", "N", 1.0, a, b)
+    c2.close()
+    _check(host, info, oracle.multiply("N", "N", 1.0, a, b))
 
 
 def test_tiles_single_row_and_column(B, ctx):
