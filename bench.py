@@ -478,6 +478,7 @@ def main():
             "ms_total": round(sinfo.ms_total, 3), "ms_per_iteration": round(sinfo.ms_total / max(sinfo.iterations, 1), 3),
             "value": round(sinfo.useful_flops / (sinfo.ms_total * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
             "x0_nnzb": int(x0.nnzb), "nnzb_trace": [int(v) for v in snnz],
+            "plan_reuses": int(sinfo.plan_reuses),
             "residual_trace": [float(f"{v:.4g}") for v in sres],
         }
         _log(f"sign iteration: {sinfo.iterations} steps, {sinfo.ms_total:.1f} ms")

@@ -273,6 +273,9 @@ typedef struct {
   double useful_flops;    /* sum over all multiplications (2*m*k*n per kept
                              block product)                                   */
   float ms_total;         /* device time when timing is enabled, else 0      */
+  int32_t plan_reuses;    /* multiplications that re-executed the previous
+                             step's plan (same operand patterns, filter
+                             decisions provably unchanged)                    */
 } bsmm_sign_info;
 
 /* Newton-Schulz iteration for the matrix sign function (Section 1, eq. (3)
@@ -283,7 +286,13 @@ typedef struct {
  * Each iteration is two filtered multiplications on the device: T = 3I - X X
  * (beta = 3 with the block-diagonal identity as C_old, so the pattern is the
  * union) and X = 0.5 X T, both with filter_eps for the on-the-fly and post
- * filters, so the pattern of X evolves from iteration to iteration.
+ * filters, so the pattern of X evolves from iteration to iteration.  Once it
+ * settles, each multiplication re-executes the previous iteration's plan
+ * (numeric part only) when the operand patterns are the plan's and every
+ * on-the-fly filter decision provably stays the same under the new block
+ * norms (the smallest kept and largest dropped norm products of the plan,
+ * scaled by the extreme per-block norm ratios, stay on their sides of
+ * filter_eps); the results are those of planning afresh.
  * The residual ||X_n^2 - I||_F / sqrt(N) comes from T.  The loop stops after
  * max_iter iterations, or as soon as the residual of the current iterate is
  * below tol (tol <= 0: never); the current iterate is then returned as is.

@@ -62,7 +62,7 @@ class SignInfo(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("residual", ctypes.c_double),
         ("nnzb", ctypes.c_int64), ("nnzb_max", ctypes.c_int64), ("useful_flops", ctypes.c_double),
-        ("ms_total", ctypes.c_float), ("gemm_path", ctypes.c_int32),
+        ("ms_total", ctypes.c_float), ("plan_reuses", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

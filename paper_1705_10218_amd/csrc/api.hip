@@ -251,6 +251,9 @@ struct Plan {
   DBuf<int2> stack;
   DBuf<double> a_pack, b_pack, a_lo, b_lo, a_t, b_t, c_norm, c_values;
   GemmArgs ga;
+  // filter decisions of a reusable plan: the block norms they were taken
+  // on and the smallest kept / largest dropped norm product (device)
+  DBuf<double> na_plan, nb_plan, margin;
   // tile path: tiles of result blocks and their per-k step records
   TilePlan tp;
   TileArgs targs;
@@ -492,6 +495,11 @@ static void plan_build(Plan &P, char transa, char transb) {
   fa.bent = bent.p;
   fa.eps = eps;
   fa.max_row = max_row;
+  if (filt && !P.one_shot) {   // a plan records what its filter decisions rest on
+    P.margin = DBuf<double>(al, 2);
+    set_pairs(P.margin.p, 2, INFINITY, 0.0, s);
+    fa.margin = P.margin.p;
+  }
   symbolic_fill(fa, s);
   // column windows of the stack generator (bounds of C's and op(B)'s rows)
   const StackWindows sw = quads ? stack_windows(nbc, max_row, (int)ksizes.size()) : StackWindows{};
@@ -631,6 +639,10 @@ static void plan_build(Plan &P, char transa, char transb) {
       build_desc_by_block(nnzb_c, wl_pos.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, P.desc.p, s);
     else
       build_desc(nnzb_c, P.c_list.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, P.desc.p, s);
+  }
+  if (filt && !P.one_shot) {
+    P.na_plan = std::move(na);
+    P.nb_plan = std::move(nb);
   }
   // ------------------------------------- buffers of the numeric part
   P.post = filt && !retain;
@@ -850,6 +862,148 @@ static bsmm_mat_s *multiply_impl(bsmm_ctx ctx, char transa, char transb, double 
   return R;
 }
 
+// Deep copy of a matrix (owned index and values), ordered on the stream.
+static bsmm_mat_s *copy_matrix(bsmm_ctx ctx, const bsmm_mat_s *x) {
+  hipStream_t s = ctx->stream;
+  Allocator &al = ctx->alloc;
+  bsmm_mat_s *m = new_result(ctx, x->nbr, x->nbc, x->h_rbs, x->h_cbs);
+  try {
+    const size_t nb1 = (size_t)std::max<int64_t>(x->nnzb, 1);
+    m->d_row_ptr = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * ((size_t)x->nbr + 1)));
+    m->d_col_idx = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nb1));
+    m->d_blk_off = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * (nb1 + 1)));
+    m->d_values = static_cast<double *>(al.alloc(sizeof(double) * (size_t)std::max<int64_t>(x->n_values, 1)));
+    m->nnzb = x->nnzb;
+    m->n_values = x->n_values;
+    HIPCHECK(hipMemcpyAsync(m->d_row_ptr, x->d_row_ptr, sizeof(int64_t) * ((size_t)x->nbr + 1),
+                            hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemcpyAsync(m->d_blk_off, x->d_blk_off, sizeof(int64_t) * ((size_t)x->nnzb + 1),
+                            hipMemcpyDeviceToDevice, s));
+    if (x->nnzb)
+      HIPCHECK(hipMemcpyAsync(m->d_col_idx, x->d_col_idx, sizeof(int32_t) * (size_t)x->nnzb, hipMemcpyDeviceToDevice, s));
+    if (x->n_values)
+      HIPCHECK(hipMemcpyAsync(m->d_values, x->d_values, sizeof(double) * (size_t)x->n_values, hipMemcpyDeviceToDevice, s));
+  } catch (...) {
+    free_mat(m);
+    throw;
+  }
+  return m;
+}
+
+// Whether x and y have the same block sizes and block pattern (one
+// synchronisation when the sizes agree).
+static bool same_pattern(bsmm_ctx ctx, const bsmm_mat_s *x, const bsmm_mat_s *y) {
+  if (x == y) return true;
+  if (x->nbr != y->nbr || x->nbc != y->nbc || x->nnzb != y->nnzb || x->h_rbs != y->h_rbs || x->h_cbs != y->h_cbs)
+    return false;
+  hipStream_t s = ctx->stream;
+  DBuf<int32_t> flag(ctx->alloc, 1);
+  HIPCHECK(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+  differs_i64(x->d_row_ptr, y->d_row_ptr, (int64_t)x->nbr + 1, flag.p, s);
+  differs_i32(x->d_col_idx, y->d_col_idx, x->nnzb, flag.p, s);
+  HIPCHECK(hipMemcpyAsync(ctx->pinned, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  return *reinterpret_cast<int32_t *>(ctx->pinned) == 0;
+}
+
+// Whether every on-the-fly filter decision of plan P stays the same when its
+// operands take the values of A and B (same patterns as the plan's).  Each
+// norm product of the plan moves by a factor within [fa_lo fb_lo, fa_hi fb_hi]
+// (the ranges of the per-block norm ratios now / then); the decisions hold
+// when the smallest kept product stays >= eps and the largest dropped one
+// stays < eps under those factors, with a relative slack of 1e-12 for the
+// rounding of the products.
+static bool filter_decisions_hold(Plan &P, const bsmm_mat_s *A, const bsmm_mat_s *B) {
+  if (!P.filt) return true;
+  bsmm_ctx ctx = P.ctx;
+  hipStream_t s = ctx->stream;
+  Allocator &al = ctx->alloc;
+  DBuf<double> na(al, (size_t)std::max<int64_t>(A->nnzb, 1)), nb(al, (size_t)std::max<int64_t>(B->nnzb, 1));
+  DBuf<double> rb(al, 4);
+  set_pairs(rb.p, 4, INFINITY, 0.0, s);
+  block_norms(*A, na.p, s);
+  ratio_bounds(P.na_plan.p, na.p, A->nnzb, rb.p, s);
+  block_norms(*B, nb.p, s);
+  ratio_bounds(P.nb_plan.p, nb.p, B->nnzb, rb.p + 2, s);
+  double h[6];
+  HIPCHECK(hipMemcpyAsync(ctx->pinned, rb.p, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(ctx->pinned + 4, P.margin.p, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  std::memcpy(h, ctx->pinned, sizeof h);
+  const double fa_lo = h[0], fa_hi = h[1], fb_lo = h[2], fb_hi = h[3], kept_min = h[4], drop_max = h[5];
+  const double eps = P.eps, slack = 1e-12;
+  const bool kept_ok = kept_min == INFINITY || kept_min * fa_lo * fb_lo >= eps * (1.0 + slack);
+  const bool drop_ok = drop_max == 0.0 || drop_max * fa_hi * fb_hi <= eps * (1.0 - slack);
+  return kept_ok && drop_ok && fa_hi < INFINITY && fb_hi < INFINITY;
+}
+
+// One multiplication of a loop whose operand patterns settle (the sign
+// iteration): the plan of the previous call is re-executed on the new values
+// when the patterns of A and B are those it was built on and its filter
+// decisions provably stay the same; otherwise a new plan is built.  The plan
+// reads deep copies of A and B held by the cache, so the caller may free its
+// matrices; the result is a new matrix either way, equal to bsmm_multiply's.
+struct MulCache {
+  Plan *P = nullptr;
+  bsmm_mat_s *a = nullptr, *b = nullptr;   // copies the plan reads (b == a for A == B)
+  bool same = false;
+  int32_t reuses = 0;
+  void clear() {
+    delete P;
+    P = nullptr;
+    if (b && b != a) free_mat(b);
+    if (a) free_mat(a);
+    a = b = nullptr;
+  }
+  ~MulCache() { clear(); }
+};
+
+static bsmm_mat_s *multiply_cached(bsmm_ctx ctx, MulCache &mc, double alpha, bsmm_mat_s *A, bsmm_mat_s *B,
+                                   double beta, bsmm_mat_s *C0, double eps, bsmm_multiply_info *info) {
+  hipStream_t s = ctx->stream;
+  const bool same = A == B;
+  bool reuse = mc.P && mc.same == same && same_pattern(ctx, A, mc.a) && (same || same_pattern(ctx, B, mc.b));
+  if (reuse) reuse = filter_decisions_hold(*mc.P, A, B);
+  if (reuse) {
+    if (A != mc.a && A->n_values)
+      HIPCHECK(hipMemcpyAsync(mc.a->d_values, A->d_values, sizeof(double) * (size_t)A->n_values,
+                              hipMemcpyDeviceToDevice, s));
+    if (!same && B != mc.b && B->n_values)
+      HIPCHECK(hipMemcpyAsync(mc.b->d_values, B->d_values, sizeof(double) * (size_t)B->n_values,
+                              hipMemcpyDeviceToDevice, s));
+    mc.reuses++;
+  } else {
+    mc.clear();
+    mc.a = copy_matrix(ctx, A);
+    mc.b = same ? mc.a : copy_matrix(ctx, B);
+    mc.same = same;
+    mc.P = new Plan(ctx);
+    Plan &P = *mc.P;
+    P.A = mc.a;
+    P.B = mc.b;
+    P.C0 = C0;
+    P.alpha = alpha;
+    P.beta = beta;
+    P.eps = eps;
+    P.retain = 0;
+    plan_build(P, 'N', 'N');
+  }
+  Plan &P = *mc.P;
+  plan_numeric(P, false);
+  bsmm_mat_s *R = plan_finish(P, false);
+  if (info) {
+    *info = bsmm_multiply_info{};
+    info->c_nnzb_symbolic = P.nnzb_c;
+    info->c_nnzb = R->nnzb;
+    info->c_n_values = R->n_values;
+    info->n_products = P.nprod;
+    info->n_candidates = P.ncand;
+    info->useful_flops = 2.0 * (double)P.kmn_total;
+    info->gemm_path = gemm_path(P);
+  }
+  return R;
+}
+
 // Block-diagonal identity with the given block sizes (owned values).
 static bsmm_mat_s *make_identity(bsmm_ctx ctx, const std::vector<int32_t> &sizes) {
   const int32_t n = (int32_t)sizes.size();
@@ -914,6 +1068,9 @@ static bsmm_mat_s *sign_impl(bsmm_ctx ctx, bsmm_mat_s *X0, int32_t max_iter, dou
   }
   bsmm_mat_s *I = make_identity(ctx, X0->h_rbs);
   bsmm_mat_s *X = X0;   // borrowed until the first update
+  // plans of the two multiplications, re-executed while the patterns of X
+  // and T stay put and the filter decisions provably do not change
+  MulCache m1, m2;
   bsmm_sign_info st{};
   st.nnzb_max = X0->nnzb;
   st.residual = -1.0;
@@ -921,7 +1078,7 @@ static bsmm_mat_s *sign_impl(bsmm_ctx ctx, bsmm_mat_s *X0, int32_t max_iter, dou
     for (int32_t it = 0; it < max_iter; it++) {
       bsmm_multiply_info mi{};
       // T = 3I - X X  (beta = 3, C_old = I: the pattern is the union)
-      bsmm_mat_s *T = multiply_impl(ctx, 'N', 'N', -1.0, X, X, 3.0, I, eps, 0, &mi);
+      bsmm_mat_s *T = multiply_cached(ctx, m1, -1.0, X, X, 3.0, I, eps, &mi);
       st.useful_flops += mi.useful_flops;
       st.nnzb_max = std::max(st.nnzb_max, T->nnzb);
       double res;
@@ -942,7 +1099,7 @@ static bsmm_mat_s *sign_impl(bsmm_ctx ctx, bsmm_mat_s *X0, int32_t max_iter, dou
       }
       bsmm_mat_s *Xn;
       try {
-        Xn = multiply_impl(ctx, 'N', 'N', 0.5, X, T, 0.0, nullptr, eps, 0, &mi);
+        Xn = multiply_cached(ctx, m2, 0.5, X, T, 0.0, nullptr, eps, &mi);
       } catch (...) {
         free_mat(T);
         throw;
@@ -965,6 +1122,9 @@ static bsmm_mat_s *sign_impl(bsmm_ctx ctx, bsmm_mat_s *X0, int32_t max_iter, dou
     if (e1) (void)hipEventDestroy(e1);
     throw;
   }
+  st.plan_reuses = m1.reuses + m2.reuses;
+  m1.clear();
+  m2.clear();
   free_mat(I);
   st.nnzb = X->nnzb;
   if (ctx->timing) {

@@ -466,6 +466,81 @@ __global__ __launch_bounds__(64) void k_shift_dist_rows(const int64_t *rp, const
 
 }  // namespace
 
+namespace {
+
+// flag[0] stays 0 while x[t] == y[t] for every t < n.
+template <typename T>
+__global__ void k_differs(const T *x, const T *y, int64_t n, int32_t *flag) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    if (x[t] != y[t]) {
+      atomicOr(flag, 1);
+      return;
+    }
+}
+
+// Bounds of the ratios now[t] / then[t] over t < n (both non-negative):
+// atomic min into out[0], max into out[1] on the bit patterns (non-negative
+// doubles order like them).  Equal values give 1 (also 0 == 0); a ratio that
+// is not finite (then == 0 < now, or a NaN) forces the bounds to 0 and +inf.
+__global__ void k_ratio_bounds(const double *then, const double *now, int64_t n, unsigned long long *out) {
+  double lo = INFINITY, hi = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const double a = then[t], b = now[t];
+    double r;
+    if (a == b) r = 1.0;
+    else if (a > 0.0 && b >= 0.0 && b < INFINITY) r = b / a;
+    else r = NAN;
+    if (r == r && r < INFINITY) {
+      lo = fmin(lo, r);
+      hi = fmax(hi, r);
+    } else {
+      lo = 0.0;
+      hi = INFINITY;
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, d, 64));
+    hi = fmax(hi, __shfl_xor(hi, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&out[0], (unsigned long long)__double_as_longlong(lo));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(hi));
+  }
+}
+
+__global__ void k_set_u64(unsigned long long *p, int n, unsigned long long a, unsigned long long b) {
+  const int t = threadIdx.x;
+  if (t < n) p[t] = (t & 1) ? b : a;
+}
+
+}  // namespace
+
+void differs_i64(const int64_t *x, const int64_t *y, int64_t n, int32_t *flag, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_differs<int64_t>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, x, y, n, flag);
+  HIPCHECK(hipGetLastError());
+}
+
+void differs_i32(const int32_t *x, const int32_t *y, int64_t n, int32_t *flag, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_differs<int32_t>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, x, y, n, flag);
+  HIPCHECK(hipGetLastError());
+}
+
+void set_pairs(double *p, int n, double a, double b, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long *>(p), n,
+                     (unsigned long long)__builtin_bit_cast(uint64_t, a), (unsigned long long)__builtin_bit_cast(uint64_t, b));
+  HIPCHECK(hipGetLastError());
+}
+
+void ratio_bounds(const double *then, const double *now, int64_t n, double *out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_ratio_bounds, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, then, now, n,
+                     reinterpret_cast<unsigned long long *>(out));
+  HIPCHECK(hipGetLastError());
+}
+
 void identity_values(const int32_t *d_sizes, const int64_t *d_off, int32_t n, double *values, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_identity_values, dim3(n), dim3(256), 0, s, d_sizes, d_off, n, values);

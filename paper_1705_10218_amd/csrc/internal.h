@@ -207,6 +207,9 @@ struct FillArgs {
   const int4 *bent = nullptr;      // product records of op(B) (product_records)
   double eps = 0.0;
   int32_t max_row = 0;
+  // out (optional, 2 doubles preset to +inf and 0): the smallest kept and the
+  // largest dropped norm product of the on-the-fly filter
+  double *margin = nullptr;
 };
 
 // a2 (fill) + a4 (count): C col_idx, block sizes, product counts.
@@ -330,6 +333,15 @@ struct GemmArgs {
   uint8_t variant[16] = {};          // GEMM kernel variant per (m, n) size class
   const double *zeros = nullptr;     // >= 4 KB of zeros
 };
+
+// *flag |= 1 when x and y differ somewhere in their first n entries.
+void differs_i64(const int64_t *x, const int64_t *y, int64_t n, int32_t *flag, hipStream_t s);
+void differs_i32(const int32_t *x, const int32_t *y, int64_t n, int32_t *flag, hipStream_t s);
+// p[t] = a for even t, b for odd t, t < n <= 64.
+void set_pairs(double *p, int n, double a, double b, hipStream_t s);
+// out[0] = min(out[0], now[t] / then[t]), out[1] = max(out[1], ...) over t < n
+// (out preset to +inf, 0); a ratio that is not finite gives 0 and +inf.
+void ratio_bounds(const double *then, const double *now, int64_t n, double *out, hipStream_t s);
 
 // Block-diagonal identity values (block i of size sizes[i] at off[i]).
 void identity_values(const int32_t *d_sizes, const int64_t *d_off, int32_t n, double *values, hipStream_t s);

@@ -303,7 +303,8 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
                                                           const BEnt *bent, const double *na, double eps,
                                                           int32_t cnt_cap, KSizes ksz, int nkp, int32_t *cnt_g,
                                                           int32_t *kofs, int32_t nbr, const int32_t *ord,
-                                                          int64_t per_xcd, const uint32_t *gbits, int diag8) {
+                                                          int64_t per_xcd, const uint32_t *gbits, int diag8,
+                                                          unsigned long long *margin) {
   extern __shared__ uint32_t sm[];
   __shared__ int32_t shi[SYM_THREADS / 64];
   __shared__ int64_t shl[SYM_THREADS / 64];
@@ -370,6 +371,8 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
   __syncthreads();
   const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int64_t kmn = 0, cand = 0;
+  // filter margins: the smallest kept and the largest dropped norm product
+  double kept_min = INFINITY, drop_max = 0.0;
   {
     AOpen &st = stage[wv];
     const int64_t pa1 = A.rp[i + 1];
@@ -379,7 +382,14 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
       auto walk = [&](auto fast) {
         constexpr bool FAST = decltype(fast)::value;
         chunk_walk<BEnt>(st.qb, st.nq, ne, [&](int64_t q) { return bent[q]; }, [&](int e, const BEnt &v) {
-          if (na && (st.na[e] * v.nb < eps)) return;
+          if (na) {
+            const double pr = st.na[e] * v.nb;
+            if (pr < eps) {
+              drop_max = fmax(drop_max, pr);
+              return;
+            }
+            kept_min = fmin(kept_min, pr);
+          }
           if constexpr (FAST) {
             if (!bm_test(bm, v.j)) return;   // only under retain_sparsity
             atomicAdd(&cnt[bm_slot(bm, pre, v.j) * nk1 + st.kx[e]], 1);
@@ -422,6 +432,17 @@ __global__ __launch_bounds__(SYM_THREADS) void k_sym_fill(OpView A, OpView B, co
     c_cnt[cbase + t] = tot_pad;
     real += tot_real;
     if (nkp > 0) kmn += ksum * B.cbs[c_ci[cbase + t]];
+  }
+  if (margin && na) {   // non-negative doubles order like their bit patterns
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      kept_min = fmin(kept_min, __shfl_xor(kept_min, d, 64));
+      drop_max = fmax(drop_max, __shfl_xor(drop_max, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(&margin[0], (unsigned long long)__double_as_longlong(kept_min));
+      atomicMax(&margin[1], (unsigned long long)__double_as_longlong(drop_max));
+    }
   }
   int64_t tot = block_sum<int64_t>(kmn, shl);
   int64_t tcand = block_sum<int64_t>(cand, shl);
@@ -847,7 +868,7 @@ void symbolic_fill(const FillArgs &f, hipStream_t s) {
                      reinterpret_cast<const BEnt *>(f.bent), f.na, f.eps, cap, ks, nkp, f.cnt_g,
                      nkp > 0 ? f.kofs : nullptr, nbr, f.sym.ord, px,
                      (words_total <= MAX_WORDS && !f.sym.retain) ? f.sym.bits : nullptr,
-                     (f.diag8 && nkp > 0) ? 1 : 0);
+                     (f.diag8 && nkp > 0) ? 1 : 0, reinterpret_cast<unsigned long long *>(f.margin));
   HIPCHECK(hipGetLastError());
 }
 

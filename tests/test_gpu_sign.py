@@ -62,10 +62,32 @@ def test_matches_oracle_iteration(B, ctx, case):
     assert np.max(np.abs(res - rres) / np.maximum(rres, 1e-300)) <= 1e-9
     assert np.array_equal(host.row_ptr, ref.row_ptr) and np.array_equal(host.col_idx, ref.col_idx)
     err = rel_fro(host.values, ref.values)
-    _log(f"  iterations {info.iterations} residual {info.residual:.3e} rel err {err:.2e} nnzb {nnz.tolist()}")
+    _log(f"  iterations {info.iterations} residual {info.residual:.3e} rel err {err:.2e} nnzb {nnz.tolist()} "
+         f"plan reuses {info.plan_reuses}")
     assert err <= 1e-11
     assert info.useful_flops == rflops
     assert info.nnzb == host.row_ptr[-1]
+
+
+@pytest.mark.parametrize("eps,reuse", [(0.0, True), (1e-8, True), (1e-4, False)])
+def test_plan_reuse_on_settled_pattern(B, ctx, eps, reuse):
+    """Once the pattern of X settles, the multiplications re-execute the
+    previous step's plans (eps > 0: only where every filter decision provably
+    holds -- at 1e-4 norm products lie too close to the threshold for the
+    bound, and every step plans afresh); the iteration equals the oracle's,
+    step by step, either way."""
+    x = inputs.symmetric_dft_like(120, config=6, sizes=(5, 13), cutoff=5.0, request=2)
+    n = 10
+    ref, rres, rnnz, rconv, rflops = oracle.newton_schulz(x, n, eps=eps, tol=0.0, nthreads=8)
+    host, info, res, nnz = _run(B, ctx, x, n, eps, 0.0)
+    _log(f"  eps {eps}: plan reuses {info.plan_reuses} of {2 * info.iterations}, nnzb {nnz.tolist()}")
+    if reuse:
+        assert info.plan_reuses > 0, "the pattern settles: the plans should be re-executed"
+    assert np.array_equal(nnz, rnnz)
+    assert np.max(np.abs(res - rres) / np.maximum(rres, 1e-300)) <= 1e-9
+    assert np.array_equal(host.row_ptr, ref.row_ptr) and np.array_equal(host.col_idx, ref.col_idx)
+    assert rel_fro(host.values, ref.values) <= 1e-11
+    assert info.useful_flops == rflops
 
 
 def test_zero_iterations_copy(B, ctx):
