@@ -223,8 +223,16 @@ bsmm_status bsmm_filter_noalloc(bsmm_mat m, double eps, int64_t *row_ptr_out, in
  * A plan splits one multiplication (same arguments as bsmm_multiply) into
  *   - bsmm_plan_create: the structural part, run once -- validation, index
  *     views, block norms, symbolic phase, stacks with the on-the-fly filter
- *     decisions taken on the values A and B have now, and every buffer of
- *     the numeric part (synchronises the stream);
+ *     decisions taken on the values A and B have now (synchronises the
+ *     stream).  It allocates no buffer of the numeric part: the result
+ *     values and the workspace are either allocated by the first
+ *     bsmm_plan_execute (library-owned, within the context budget, before
+ *     any kernel of that call) or supplied by the caller
+ *     (bsmm_plan_sizes / bsmm_plan_execute_into).  Budget: the sizes of the
+ *     result pattern, and then of the stacks, are checked against the
+ *     context budget as soon as the symbolic phase has produced them and
+ *     before any kernel that fills them is launched; on any failure the
+ *     stream is left idle and *out untouched;
  *   - bsmm_plan_execute: the numeric part -- packed operand copies and the
  *     block GEMM -- on the context's stream, asynchronous, reading the
  *     *current* values of A, B and C_old (the matrices must stay alive and
@@ -243,6 +251,26 @@ bsmm_status bsmm_filter_noalloc(bsmm_mat m, double eps, int64_t *row_ptr_out, in
 bsmm_status bsmm_plan_create(bsmm_ctx ctx, char transa, char transb, double alpha, bsmm_mat a, bsmm_mat b,
                              double beta, bsmm_mat c_old, double filter_eps, int retain_sparsity, bsmm_plan *out,
                              bsmm_multiply_info *info);
+/* Sizes of a plan's numeric part, known once bsmm_plan_create returns and
+ * before anything of the result is allocated: c_nnzb and c_n_values are the
+ * result's blocks and FP64 values before the post-filter (upper bounds of the
+ * final result), workspace_bytes the scratch of bsmm_plan_execute_into
+ * (packed operand copies, result-block norms and, with a post-filter, a copy
+ * of the result values for its compaction).  Any output may be NULL. */
+bsmm_status bsmm_plan_sizes(bsmm_plan plan, int64_t *c_nnzb, int64_t *c_n_values, size_t *workspace_bytes);
+/* The numeric part and the post-filter in caller-owned device buffers (e.g.
+ * torch tensors): c_values_dev has room for c_n_values doubles (8-byte
+ * aligned), workspace_dev for workspace_bytes (256-byte aligned); neither
+ * may overlap the other or the values of A, B or C_old.  *c_out receives a
+ * new matrix whose index belongs to the library and whose values are
+ * c_values_dev itself (borrowed: bsmm_mat_destroy leaves them alone; the
+ * post-filter compacts the kept blocks to its front).  The library allocates
+ * only the result's index and the post-filter's counters.  Runs eagerly (a
+ * captured graph keeps the library-owned buffers); synchronises the stream
+ * only to size the post-filter's result.  Same results as bsmm_plan_execute
+ * followed by bsmm_plan_result, bitwise.
+ * Errors: BSMM_ERR_INVALID_ARG (NULL or misaligned buffer), BSMM_ERR_ALIAS. */
+bsmm_status bsmm_plan_execute_into(bsmm_plan plan, double *c_values_dev, void *workspace_dev, bsmm_mat *c_out);
 bsmm_status bsmm_plan_execute(bsmm_plan plan);
 bsmm_status bsmm_plan_capture(bsmm_plan plan);
 bsmm_status bsmm_plan_result(bsmm_plan plan, bsmm_mat *c_out);

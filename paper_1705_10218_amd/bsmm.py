@@ -35,7 +35,8 @@ SYMBOLS = (
     "bsmm_mat_get_index", "bsmm_mat_get_block_sizes", "bsmm_mat_values", "bsmm_mat_copy_values",
     "bsmm_mat_destroy", "bsmm_block_norms", "bsmm_multiply", "bsmm_filter", "bsmm_sign_newton_schulz",
     "bsmm_plan_create", "bsmm_plan_execute", "bsmm_plan_capture", "bsmm_plan_result", "bsmm_plan_destroy",
-    "bsmm_plans_execute", "bsmm_filter_noalloc", "bsmm_ctx_set_tile_shape",
+    "bsmm_plans_execute", "bsmm_filter_noalloc", "bsmm_ctx_set_tile_shape", "bsmm_plan_sizes",
+    "bsmm_plan_execute_into",
 )
 
 
@@ -117,6 +118,8 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_double, _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(_vp),
                                        ctypes.POINTER(MultiplyInfo)]
         L.bsmm_plan_execute.argtypes = [_vp]
+        L.bsmm_plan_sizes.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_size_t)]
+        L.bsmm_plan_execute_into.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_vp)]
         L.bsmm_plan_capture.argtypes = [_vp]
         L.bsmm_plan_result.argtypes = [_vp, ctypes.POINTER(_vp)]
         L.bsmm_plan_destroy.argtypes = [_vp]
@@ -349,6 +352,21 @@ class Plan:
 
     def capture(self):
         _check(lib().bsmm_plan_capture(self.handle))
+
+    def sizes(self):
+        """bsmm_plan_sizes: (c_nnzb, c_n_values, workspace_bytes) before the post-filter."""
+        nb, nv, ws = _i64(), _i64(), ctypes.c_size_t()
+        _check(lib().bsmm_plan_sizes(self.handle, ctypes.byref(nb), ctypes.byref(nv), ctypes.byref(ws)))
+        return nb.value, nv.value, ws.value
+
+    def execute_into(self, c_values, workspace) -> Matrix:
+        """bsmm_plan_execute_into: numeric part and post-filter in caller
+        tensors (float64 with room for c_n_values; a byte tensor of
+        workspace_bytes, 256-byte aligned).  The result matrix borrows c_values."""
+        out = _vp()
+        _check(lib().bsmm_plan_execute_into(self.handle, _vp(c_values.data_ptr() if c_values.numel() else 0),
+                                            _vp(workspace.data_ptr() if workspace.numel() else 0), ctypes.byref(out)))
+        return Matrix(self.ctx, out, c_values)
 
     def result(self) -> Matrix:
         out = _vp()

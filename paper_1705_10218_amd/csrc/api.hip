@@ -44,6 +44,7 @@ void *Allocator::alloc(size_t bytes) {
     void *p = it->second;
     size_t have = it->first;
     free_.erase(it);
+    cached_ -= have;
     live_[p] = have;
     return p;
   }
@@ -80,6 +81,7 @@ void Allocator::release(void *p) {
   auto it = live_.find(p);
   if (it == live_.end()) return;
   free_.emplace(it->second, p);
+  cached_ += it->second;
   live_.erase(it);
 }
 
@@ -92,6 +94,18 @@ void Allocator::trim() {
     held_ -= kv.first;
   }
   free_.clear();
+  cached_ = 0;
+}
+
+void Allocator::check(size_t bytes, const char *what) const {
+  if (!budget_) return;
+  const size_t live = held_ - cached_;
+  if (live + bytes > budget_) {
+    std::ostringstream os;
+    os << what << " needs " << bytes << " bytes beyond the " << live << " in use; the context budget is " << budget_
+       << " bytes";
+    fail(BSMM_ERR_OUT_OF_MEMORY, os.str());
+  }
 }
 
 Allocator::~Allocator() {
@@ -251,6 +265,23 @@ struct Plan {
   DBuf<int2> stack;
   DBuf<double> a_pack, b_pack, a_lo, b_lo, a_t, b_t, c_norm, c_values;
   GemmArgs ga;
+  // Buffers of the numeric part.  A plan computes their layout; they are
+  // either library-owned (own_cval, own_ws: allocated by the first execution)
+  // or the caller's (bsmm_plan_execute_into).  Workspace regions, byte
+  // offsets from its start, 256-byte aligned: packed op(A) and op(B) (and
+  // their low parts in split mode), transposed operand copies of the walker
+  // path, result-block norms and, with a post-filter, a copy of the result
+  // values the compaction reads from.
+  struct Ws {
+    size_t apack = 0, bpack = 0, alo = 0, blo = 0, at = 0, bt = 0, cnorm = 0, stash = 0, total = 0;
+    size_t core = 0;   // bytes before the stash (all a library-owned execution needs)
+    bool has_apack = false, has_alo = false, has_at = false, has_bt = false, has_cnorm = false;
+  } ws;
+  DBuf<double> own_cval;
+  DBuf<uint8_t> own_ws;
+  double *cval = nullptr;     // bound result values (nval_c)
+  uint8_t *wsp = nullptr;     // bound workspace
+  bool bound = false, caller_bound = false;
   // filter decisions of a reusable plan: the block norms they were taken
   // on and the smallest kept / largest dropped norm product (device)
   DBuf<double> na_plan, nb_plan, margin;
@@ -266,6 +297,66 @@ struct Plan {
     if (graph) (void)hipGraphDestroy(graph);
   }
 };
+
+// Points the numeric part at result values cval (nval_c doubles) and the
+// workspace wsp (P.ws.total bytes, 256-byte aligned).
+static void bind_numeric(Plan &P, double *cval, uint8_t *wsp) {
+  const Plan::Ws &w = P.ws;
+  auto at = [&](size_t o, bool has) { return has ? reinterpret_cast<double *>(wsp + o) : nullptr; };
+  double *apack = at(w.apack, w.has_apack), *bpack = at(w.bpack, w.has_apack);
+  double *alo = at(w.alo, w.has_alo), *blo = at(w.blo, w.has_alo);
+  double *a_t = at(w.at, w.has_at), *b_t = at(w.bt, w.has_bt);
+  double *cnorm = at(w.cnorm, w.has_cnorm);
+  GemmArgs &ga = P.ga;
+  ga.c_values = cval;
+  ga.c_norm = cnorm;
+  // operand layouts: packed copies (quad path), or op(A) column-major and
+  // op(B) row-major (walker path)
+  ga.a_cm = P.ta ? a_t : P.A->d_values;
+  ga.b_rm = P.tb ? P.B->d_values : b_t;
+  ga.a_pack = apack;
+  ga.b_pack = bpack;
+  ga.a_hi = reinterpret_cast<const float *>(apack);
+  ga.b_hi = reinterpret_cast<const float *>(bpack);
+  ga.a_lo = reinterpret_cast<const float *>(alo);
+  ga.b_lo = reinterpret_cast<const float *>(blo);
+  P.targs.c_val = cval;
+  P.targs.c_norm = cnorm;
+  P.cval = cval;
+  P.wsp = wsp;
+  P.bound = true;
+}
+
+// One-shot product whose packing kernel already wrote the packed copies
+// (with the norms) into P.a_pack / P.b_pack.
+static void bind_packed(Plan &P) {
+  GemmArgs &ga = P.ga;
+  ga.c_values = P.c_values.p;
+  ga.c_norm = P.post ? P.c_norm.p : nullptr;
+  ga.a_cm = P.A->d_values;
+  ga.b_rm = P.B->d_values;
+  ga.a_pack = P.a_pack.p;
+  ga.b_pack = P.b_pack.p;
+  ga.a_hi = reinterpret_cast<const float *>(P.a_pack.p);
+  ga.b_hi = reinterpret_cast<const float *>(P.b_pack.p);
+  ga.a_lo = ga.b_lo = nullptr;
+  P.targs.c_val = P.c_values.p;
+  P.targs.c_norm = ga.c_norm;
+  P.cval = P.c_values.p;
+  P.bound = true;
+}
+
+// Library-owned buffers of the numeric part, allocated (within the budget,
+// before any kernel of the calling operation) the first time a plan runs
+// without caller buffers.
+static void ensure_own_buffers(Plan &P) {
+  if (P.bound && !P.caller_bound) return;
+  Allocator &al = P.ctx->alloc;
+  if (!P.own_cval.p) P.own_cval = DBuf<double>(al, (size_t)std::max<int64_t>(P.nval_c, 1));
+  if (!P.own_ws.p) P.own_ws = DBuf<uint8_t>(al, std::max<size_t>(P.ws.core, 256));
+  bind_numeric(P, P.own_cval.p, P.own_ws.p);
+  P.caller_bound = false;
+}
 
 static void plan_build(Plan &P, char transa, char transb) {
   bsmm_ctx ctx = P.ctx;
@@ -457,6 +548,12 @@ static void plan_build(Plan &P, char transa, char transb) {
   if (nnzb_c > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "more than 2^31 result blocks");
   if (A->nnzb > INT32_MAX || B->nnzb > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "more than 2^31 operand blocks");
   const size_t nc1 = (size_t)std::max<int64_t>(nnzb_c, 1);
+  // budget of the result pattern's phase, checked before any of its launches:
+  // C's index and offsets, per-block counters and run starts, per-row sums
+  {
+    const size_t nks = quads ? ksizes.size() : 1;
+    al.check(nc1 * (4 + 4 + 4 + 8 + 8 + 8 + 8 * nks) + 32 * ((size_t)nbr + 1) + 4096, "the result pattern");
+  }
   P.c_ci = DBuf<int32_t>(al, nc1);
   P.c_row = DBuf<int32_t>(al, nc1);
   DBuf<int32_t> c_cnt(al, nc1);
@@ -552,6 +649,15 @@ static void plan_build(Plan &P, char transa, char transb) {
     old_block_map(C0->d_row_ptr, C0->d_col_idx, nbr, P.c_rp.p, P.c_ci.p, P.old_blk.p, s);
   }
   tm.mark();  // 3
+  // budget of the stacks, the work list and (one-shot) the numeric buffers,
+  // checked before any of their launches
+  {
+    size_t need = 8 * (size_t)std::max<int64_t>(P.nstack, 1) + nc1 * (4 + 4 + 4 + 32) + 4096;
+    if (P.one_shot)
+      need += 8 * (size_t)std::max<int64_t>(P.nval_c, 1) + 8 * nc1 +
+              (quads ? 8 * (size_t)(std::max<int64_t>(P.a_pack_n, 2) + std::max<int64_t>(P.b_pack_n, 2)) : 0);
+    al.check(need, "the stacks and the numeric part");
+  }
   // ------------------------------------------------------- a4: stacks
   P.stack = DBuf<int2>(al, (size_t)std::max<int64_t>(P.nstack, 1));
   {
@@ -646,20 +752,49 @@ static void plan_build(Plan &P, char transa, char transb) {
   }
   // ------------------------------------- buffers of the numeric part
   P.post = filt && !retain;
-  if (P.post) P.c_norm = DBuf<double>(al, nc1);
-  P.c_values = DBuf<double>(al, (size_t)std::max<int64_t>(P.nval_c, 1));
-  if (quads && P.nprod > 0) {   // packed copies (sizes in units of 8 bytes)
-    if (!P.packed) {
-      P.a_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.a_pack_n, 2));
-      P.b_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
+  {
+    Plan::Ws &w = P.ws;
+    size_t at = 0;
+    auto region = [&](size_t bytes) {
+      const size_t o = at;
+      at += (std::max<size_t>(bytes, 16) + 255) / 256 * 256;
+      return o;
+    };
+    if (quads && P.nprod > 0) {   // packed copies (sizes in units of 8 bytes)
+      w.has_apack = true;
+      w.apack = region(8 * (size_t)std::max<int64_t>(P.a_pack_n, 2));
+      w.bpack = region(8 * (size_t)std::max<int64_t>(P.b_pack_n, 2));
+      if (ctx->mode == BSMM_COMPUTE_SPLIT) {
+        w.has_alo = true;
+        w.alo = region(8 * (size_t)std::max<int64_t>(P.a_pack_n, 2));
+        w.blo = region(8 * (size_t)std::max<int64_t>(P.b_pack_n, 2));
+      }
     }
-    if (ctx->mode == BSMM_COMPUTE_SPLIT) {
-      P.a_lo = DBuf<double>(al, (size_t)std::max<int64_t>(P.a_pack_n, 2));
-      P.b_lo = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
+    if (!quads && !tiles && ta && P.nprod > 0) {
+      w.has_at = true;
+      w.at = region(8 * (size_t)std::max<int64_t>(A->n_values, 1));
+    }
+    if (!quads && !tiles && !tb && P.nprod > 0) {
+      w.has_bt = true;
+      w.bt = region(8 * (size_t)std::max<int64_t>(B->n_values, 1));
+    }
+    if (P.post) {
+      w.has_cnorm = true;
+      w.cnorm = region(8 * nc1);
+    }
+    w.core = at;
+    if (P.post) w.stash = region(8 * (size_t)std::max<int64_t>(P.nval_c, 1));
+    w.total = at;
+  }
+  if (P.one_shot) {   // the one-shot product's buffers come from the library (C values become the result)
+    if (P.packed) {   // fused packing already wrote the packed copies
+      P.c_values = DBuf<double>(al, (size_t)std::max<int64_t>(P.nval_c, 1));
+      if (P.post) P.c_norm = DBuf<double>(al, nc1);
+    } else {
+      P.c_values = DBuf<double>(al, (size_t)std::max<int64_t>(P.nval_c, 1));
+      P.own_ws = DBuf<uint8_t>(al, std::max<size_t>(P.ws.core, 256));
     }
   }
-  if (!quads && !tiles && ta && P.nprod > 0) P.a_t = DBuf<double>(al, (size_t)std::max<int64_t>(A->n_values, 1));
-  if (!quads && !tiles && !tb && P.nprod > 0) P.b_t = DBuf<double>(al, (size_t)std::max<int64_t>(B->n_values, 1));
   if (!ctx->zeros) {
     ctx->zeros = static_cast<double *>(al.alloc(4096));
     HIPCHECK(hipMemsetAsync(ctx->zeros, 0, 4096, s));
@@ -677,21 +812,9 @@ static void plan_build(Plan &P, char transa, char transb) {
   ga.c_old_blk = P.old_blk.p;
   ga.old_off = C0 ? C0->d_blk_off : nullptr;
   ga.old_values = C0 ? C0->d_values : nullptr;
-  ga.c_values = P.c_values.p;
-  ga.c_norm = P.post ? P.c_norm.p : nullptr;
   ga.alpha = P.alpha;
   ga.beta = P.beta;
   ga.mode = ctx->mode;
-  // operand layouts: packed copies (quad path), or op(A) column-major and
-  // op(B) row-major (walker path)
-  ga.a_cm = ta ? P.a_t.p : A->d_values;
-  ga.b_rm = tb ? B->d_values : P.b_t.p;
-  ga.a_pack = P.a_pack.p;
-  ga.b_pack = P.b_pack.p;
-  ga.a_hi = reinterpret_cast<const float *>(P.a_pack.p);
-  ga.b_hi = reinterpret_cast<const float *>(P.b_pack.p);
-  ga.a_lo = reinterpret_cast<const float *>(P.a_lo.p);
-  ga.b_lo = reinterpret_cast<const float *>(P.b_lo.p);
   ga.a_bytes = (uint64_t)(quads ? P.a_pack_n : A->n_values) * sizeof(double);
   ga.b_bytes = (uint64_t)(quads ? P.b_pack_n : B->n_values) * sizeof(double);
   ga.zeros = ctx->zeros;
@@ -710,13 +833,15 @@ static void plan_build(Plan &P, char transa, char transb) {
   tg.old_blk = P.old_blk.p;
   tg.old_off = C0 ? C0->d_blk_off : nullptr;
   tg.old_val = C0 ? C0->d_values : nullptr;
-  tg.c_val = P.c_values.p;
-  tg.c_norm = P.post ? P.c_norm.p : nullptr;
   tg.alpha = P.alpha;
   tg.beta = P.beta;
   P.max_edge = 1;
   for (int32_t v : opa_r) P.max_edge = std::max(P.max_edge, v);
   for (int32_t v : opb_c) P.max_edge = std::max(P.max_edge, v);
+  if (P.one_shot) {
+    if (P.packed) bind_packed(P);
+    else bind_numeric(P, P.c_values.p, P.own_ws.p);
+  }
   tm.mark();  // 4
 }
 
@@ -731,15 +856,18 @@ static void plan_numeric(Plan &P, bool marks) {
     return;
   }
   if (P.nprod > 0) {
+    GemmArgs &ga = P.ga;
     if (P.quads && P.lowp) {
-      pack32_values(*P.A, ta, P.a_poff.p, reinterpret_cast<float *>(P.a_pack.p), reinterpret_cast<float *>(P.a_lo.p), s);
-      pack32_values(*P.B, !tb, P.b_poff.p, reinterpret_cast<float *>(P.b_pack.p), reinterpret_cast<float *>(P.b_lo.p), s);
+      pack32_values(*P.A, ta, P.a_poff.p, const_cast<float *>(ga.a_hi), const_cast<float *>(ga.a_lo), s);
+      pack32_values(*P.B, !tb, P.b_poff.p, const_cast<float *>(ga.b_hi), const_cast<float *>(ga.b_lo), s);
     } else if (P.quads) {
-      if (!P.packed) pack_values(*P.A, ta, P.a_poff.p, P.a_pack.p, *P.B, !tb, P.b_poff.p, P.b_pack.p, s);
+      if (!P.packed)
+        pack_values(*P.A, ta, P.a_poff.p, const_cast<double *>(ga.a_pack), *P.B, !tb, P.b_poff.p,
+                    const_cast<double *>(ga.b_pack), s);
       P.packed = false;   // a later execution packs the values it finds
     } else {
-      if (ta) transpose_blocks(*P.A, P.a_t.p, s);
-      if (!tb) transpose_blocks(*P.B, P.b_t.p, s);
+      if (ta) transpose_blocks(*P.A, const_cast<double *>(ga.a_cm), s);
+      if (!tb) transpose_blocks(*P.B, const_cast<double *>(ga.b_rm), s);
     }
   }
   if (marks) P.tm.mark();  // 5
@@ -768,8 +896,8 @@ static bsmm_mat_s *plan_finish(Plan &P, bool consume) {
       ca.rp = P.c_rp.p;
       ca.ci = P.c_ci.p;
       ca.off = P.c_off.p;
-      ca.values = P.c_values.p;
-      ca.norm = P.c_norm.p;
+      ca.values = P.cval;
+      ca.norm = P.ga.c_norm;
       ca.eps = P.eps;
       DBuf<int32_t> flags(al, (size_t)std::max<int64_t>(nnzb_c, 1));
       kept = count_kept(al, ca, flags.p, ctx->pinned, s, rank);
@@ -802,7 +930,7 @@ static bsmm_mat_s *plan_finish(Plan &P, bool consume) {
         HIPCHECK(hipMemcpyAsync(R->d_row_ptr, P.c_rp.p, sizeof(int64_t) * ((size_t)P.nbr + 1), hipMemcpyDeviceToDevice, s));
         if (nnzb_c) {
           HIPCHECK(hipMemcpyAsync(R->d_col_idx, P.c_ci.p, sizeof(int32_t) * (size_t)nnzb_c, hipMemcpyDeviceToDevice, s));
-          HIPCHECK(hipMemcpyAsync(R->d_values, P.c_values.p, sizeof(double) * (size_t)P.nval_c, hipMemcpyDeviceToDevice, s));
+          HIPCHECK(hipMemcpyAsync(R->d_values, P.cval, sizeof(double) * (size_t)P.nval_c, hipMemcpyDeviceToDevice, s));
         }
         HIPCHECK(hipMemcpyAsync(R->d_blk_off, P.c_off.p, sizeof(int64_t) * ((size_t)nnzb_c + 1), hipMemcpyDeviceToDevice, s));
       }
@@ -817,6 +945,69 @@ static bsmm_mat_s *plan_finish(Plan &P, bool consume) {
 }
 
 static int32_t gemm_path(const Plan &P) { return P.tiles ? 2 : P.lowp ? 3 : P.quads ? 0 : 1; }
+
+// Post-filter and the result matrix of an execution into caller buffers:
+// the result's index belongs to the library, its values are the caller's
+// (borrowed).  When the post-filter drops blocks, the values are copied to
+// the workspace's stash and compacted back into the caller's buffer.
+static bsmm_mat_s *plan_finish_into(Plan &P) {
+  bsmm_ctx ctx = P.ctx;
+  hipStream_t s = ctx->stream;
+  Allocator &al = ctx->alloc;
+  const int64_t nnzb_c = P.nnzb_c;
+  bsmm_mat_s *R = new_result(ctx, P.nbr, P.nbc, P.opa_r, P.opb_c);
+  R->owns_values = false;
+  try {
+    int64_t kept = nnzb_c;
+    if (P.post && nnzb_c > 0) {
+      CompactArgs ca;
+      ca.nbr = P.nbr;
+      ca.nnzb = nnzb_c;
+      ca.rp = P.c_rp.p;
+      ca.ci = P.c_ci.p;
+      ca.off = P.c_off.p;
+      ca.values = P.cval;
+      ca.norm = P.ga.c_norm;
+      ca.eps = P.eps;
+      DBuf<int32_t> flags(al, (size_t)std::max<int64_t>(nnzb_c, 1));
+      DBuf<int64_t> rank;
+      kept = count_kept(al, ca, flags.p, ctx->pinned, s, rank);
+      if (kept < nnzb_c) {
+        double *stash = reinterpret_cast<double *>(P.wsp + P.ws.stash);
+        HIPCHECK(hipMemcpyAsync(stash, P.cval, sizeof(double) * (size_t)P.nval_c, hipMemcpyDeviceToDevice, s));
+        ca.values = stash;
+        DBuf<int64_t> nrp(al, (size_t)P.nbr + 1), noff(al, (size_t)std::max<int64_t>(kept, 1) + 1);
+        DBuf<int32_t> nci(al, (size_t)std::max<int64_t>(kept, 1));
+        double *nv = P.cval;
+        int64_t nval = 0;
+        compact(al, ca, rank.p, P.oa.rbs, P.ob.cbs, nrp.p, nci.p, noff.p, ctx->pinned, &nv, &nval, s, P.cval);
+        R->d_row_ptr = nrp.release_ownership();
+        R->d_col_idx = nci.release_ownership();
+        R->d_blk_off = noff.release_ownership();
+        R->d_values = P.cval;
+        R->nnzb = kept;
+        R->n_values = nval;
+      }
+    }
+    if (kept == nnzb_c) {
+      const size_t nc1 = (size_t)std::max<int64_t>(nnzb_c, 1);
+      R->d_row_ptr = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * ((size_t)P.nbr + 1)));
+      R->d_col_idx = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nc1));
+      R->d_blk_off = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * (nc1 + 1)));
+      HIPCHECK(hipMemcpyAsync(R->d_row_ptr, P.c_rp.p, sizeof(int64_t) * ((size_t)P.nbr + 1), hipMemcpyDeviceToDevice, s));
+      if (nnzb_c)
+        HIPCHECK(hipMemcpyAsync(R->d_col_idx, P.c_ci.p, sizeof(int32_t) * (size_t)nnzb_c, hipMemcpyDeviceToDevice, s));
+      HIPCHECK(hipMemcpyAsync(R->d_blk_off, P.c_off.p, sizeof(int64_t) * ((size_t)nnzb_c + 1), hipMemcpyDeviceToDevice, s));
+      R->d_values = P.cval;
+      R->nnzb = nnzb_c;
+      R->n_values = P.nval_c;
+    }
+  } catch (...) {
+    free_mat(R);
+    throw;
+  }
+  return R;
+}
 
 static void plan_info(Plan &P, const bsmm_mat_s *R, bsmm_multiply_info *info) {
   if (!info) return;
@@ -989,6 +1180,7 @@ static bsmm_mat_s *multiply_cached(bsmm_ctx ctx, MulCache &mc, double alpha, bsm
     plan_build(P, 'N', 'N');
   }
   Plan &P = *mc.P;
+  ensure_own_buffers(P);
   plan_numeric(P, false);
   bsmm_mat_s *R = plan_finish(P, false);
   if (info) {
@@ -1461,6 +1653,8 @@ bsmm_status bsmm_plan_create(bsmm_ctx ctx, char transa, char transb, double alph
       info->gemm_path = gemm_path(P);
     }
   } catch (...) {
+    // leave the stream idle: nothing the failed plan queued is still running
+    (void)hipStreamSynchronize(ctx->stream);
     delete pl;
     throw;
   }
@@ -1469,11 +1663,53 @@ bsmm_status bsmm_plan_create(bsmm_ctx ctx, char transa, char transb, double alph
   ABI_END
 }
 
+bsmm_status bsmm_plan_sizes(bsmm_plan plan, int64_t *c_nnzb, int64_t *c_n_values, size_t *workspace_bytes) {
+  ABI_BEGIN
+  if (!plan) fail(BSMM_ERR_INVALID_ARG, "plan is NULL");
+  const Plan &P = plan->plan;
+  if (c_nnzb) *c_nnzb = P.nnzb_c;
+  if (c_n_values) *c_n_values = P.nval_c;
+  if (workspace_bytes) *workspace_bytes = P.ws.total;
+  ABI_END
+}
+
+bsmm_status bsmm_plan_execute_into(bsmm_plan plan, double *c_values_dev, void *workspace_dev, bsmm_mat *c_out) {
+  ABI_BEGIN
+  if (!plan || !c_out) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  Plan &P = plan->plan;
+  if (P.nval_c > 0 && !c_values_dev) fail(BSMM_ERR_INVALID_ARG, "c_values_dev is NULL");
+  if (P.ws.total > 0 && !workspace_dev) fail(BSMM_ERR_INVALID_ARG, "workspace_dev is NULL");
+  if (((uintptr_t)workspace_dev & 255u) != 0) fail(BSMM_ERR_INVALID_ARG, "workspace_dev is not 256-byte aligned");
+  if (((uintptr_t)c_values_dev & 7u) != 0) fail(BSMM_ERR_INVALID_ARG, "c_values_dev is not 8-byte aligned");
+  auto overlaps = [](const void *x, size_t nx, const void *y, size_t ny) {
+    const char *a = static_cast<const char *>(x), *b = static_cast<const char *>(y);
+    return x && y && nx && ny && a < b + ny && b < a + nx;
+  };
+  const size_t cb = 8 * (size_t)P.nval_c;
+  for (const bsmm_mat_s *m : {P.A, P.B, P.C0}) {
+    if (!m) continue;
+    if (overlaps(c_values_dev, cb, m->d_values, 8 * (size_t)m->n_values) ||
+        overlaps(workspace_dev, P.ws.total, m->d_values, 8 * (size_t)m->n_values))
+      fail(BSMM_ERR_ALIAS, "a caller buffer overlaps the values of an operand");
+  }
+  if (overlaps(c_values_dev, cb, workspace_dev, P.ws.total))
+    fail(BSMM_ERR_ALIAS, "c_values_dev overlaps workspace_dev");
+  DeviceGuard g(P.ctx->device);
+  bind_numeric(P, c_values_dev, static_cast<uint8_t *>(workspace_dev));
+  P.caller_bound = true;
+  plan_numeric(P, false);
+  bsmm_mat_s *R = plan_finish_into(P);
+  P.ctx->live_mats++;
+  *c_out = R;
+  ABI_END
+}
+
 bsmm_status bsmm_plan_execute(bsmm_plan plan) {
   ABI_BEGIN
   if (!plan) fail(BSMM_ERR_INVALID_ARG, "plan is NULL");
   Plan &P = plan->plan;
   DeviceGuard g(P.ctx->device);
+  ensure_own_buffers(P);   // allocates before any launch of this call
   if (P.exec)
     HIPCHECK(hipGraphLaunch(P.exec, P.ctx->stream));
   else
@@ -1488,6 +1724,7 @@ bsmm_status bsmm_plan_capture(bsmm_plan plan) {
   if (P.exec) return BSMM_OK;   // already captured
   if (P.ctx->stream == nullptr) fail(BSMM_ERR_UNSUPPORTED, "graph capture needs a non-default stream");
   DeviceGuard g(P.ctx->device);
+  ensure_own_buffers(P);   // no allocation under capture
   HIPCHECK(hipStreamBeginCapture(P.ctx->stream, hipStreamCaptureModeThreadLocal));
   try {
     plan_numeric(P, false);
@@ -1519,6 +1756,7 @@ bsmm_status bsmm_plans_execute(int32_t n, bsmm_plan *plans) {
   bool batched = true;
   for (int32_t r = 0; r < n; r++) batched = batched && plans[r]->plan.quads && !plans[r]->plan.lowp;
   if (!batched) {   // one after another, as bsmm_plan_execute
+    for (int32_t r = 0; r < n; r++) ensure_own_buffers(plans[r]->plan);
     for (int32_t r = 0; r < n; r++) {
       Plan &P = plans[r]->plan;
       if (P.exec) HIPCHECK(hipGraphLaunch(P.exec, s));
@@ -1529,9 +1767,12 @@ bsmm_status bsmm_plans_execute(int32_t n, bsmm_plan *plans) {
   std::vector<const GemmArgs *> gs;
   std::vector<int64_t> nnzb;
   int max_edge = 1;
+  for (int32_t r = 0; r < n; r++) ensure_own_buffers(plans[r]->plan);   // every allocation before any launch
   for (int32_t r = 0; r < n; r++) {
     Plan &P = plans[r]->plan;
-    if (P.nprod > 0) pack_values(*P.A, P.ta, P.a_poff.p, P.a_pack.p, *P.B, !P.tb, P.b_poff.p, P.b_pack.p, s);
+    if (P.nprod > 0)
+      pack_values(*P.A, P.ta, P.a_poff.p, const_cast<double *>(P.ga.a_pack), *P.B, !P.tb, P.b_poff.p,
+                  const_cast<double *>(P.ga.b_pack), s);
     gs.push_back(&P.ga);
     nnzb.push_back(P.nnzb_c);
     max_edge = std::max(max_edge, P.max_edge);

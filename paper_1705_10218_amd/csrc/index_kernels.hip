@@ -570,7 +570,7 @@ int64_t count_kept(Allocator &al, const CompactArgs &c, int32_t *keep_tmp, int64
 
 void compact(Allocator &al, const CompactArgs &c, const int64_t *rank, const int32_t *d_rbs,
              const int32_t *d_cbs, int64_t *new_rp, int32_t *new_ci, int64_t *new_off, int64_t *pinned,
-             double **new_values, int64_t *new_nval, hipStream_t s) {
+             double **new_values, int64_t *new_nval, hipStream_t s, double *dst) {
   hipLaunchKernelGGL(k_new_rowptr, dim3((c.nbr + 1 + 255) / 256), dim3(256), 0, s, c.rp, c.nbr, rank, new_rp);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipMemcpyAsync(pinned, rank + c.nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -586,7 +586,7 @@ void compact(Allocator &al, const CompactArgs &c, const int64_t *rank, const int
   HIPCHECK(hipMemcpyAsync(pinned, new_off + kept, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
   *new_nval = pinned[0];
-  double *nv = static_cast<double *>(al.alloc(sizeof(double) * (size_t)std::max<int64_t>(*new_nval, 1)));
+  double *nv = dst ? dst : static_cast<double *>(al.alloc(sizeof(double) * (size_t)std::max<int64_t>(*new_nval, 1)));
   if (c.nnzb > 0) {
     hipLaunchKernelGGL(k_compact_values, dim3(grid_for(c.nnzb * 64, 256)), dim3(256), 0, s, rank, c.nnzb, c.off,
                        c.values, (const int64_t *)new_off, nv);

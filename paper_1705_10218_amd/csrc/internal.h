@@ -36,12 +36,16 @@ class Allocator {
   void trim();             // return cached free blocks to HIP
   size_t held() const { return held_; }
   size_t peak() const { return peak_; }
+  // Fails with BSMM_ERR_OUT_OF_MEMORY when `bytes` more in live buffers
+  // would exceed the budget (cached free blocks count as available).
+  void check(size_t bytes, const char *what) const;
   ~Allocator();
 
  private:
   int device_ = 0;
   size_t budget_ = 0;      // 0 = no cap
   size_t held_ = 0, peak_ = 0;
+  size_t cached_ = 0;      // bytes of the free blocks in the cache
   std::multimap<size_t, void *> free_;   // size -> ptr
   std::map<void *, size_t> live_;        // ptr -> size
 };
@@ -472,8 +476,10 @@ struct CompactArgs {
 // every block is kept nothing is written and the caller keeps its arrays.
 int64_t count_kept(Allocator &al, const CompactArgs &c, int32_t *keep_prefix_tmp, int64_t *pinned,
                    hipStream_t s, DBuf<int64_t> &new_rank);
+// Values go to dst when given (room for the kept values; it must not overlap
+// c.values), else to a new allocation.
 void compact(Allocator &al, const CompactArgs &c, const int64_t *new_rank, const int32_t *d_rbs,
              const int32_t *d_cbs, int64_t *new_rp, int32_t *new_ci, int64_t *new_off,
-             int64_t *pinned, double **new_values, int64_t *new_nval, hipStream_t s);
+             int64_t *pinned, double **new_values, int64_t *new_nval, hipStream_t s, double *dst = nullptr);
 
 }  // namespace bsmm
