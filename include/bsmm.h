@@ -280,9 +280,10 @@ bsmm_status bsmm_plan_result(bsmm_plan plan, bsmm_mat *c_out);
  * block of one plan), so the requests' work shares the device.  Every
  * result block is computed exactly as in a launch of its own plan, so each
  * plan's result is bitwise the one it gets alone.  Plans outside the FP64
- * packed-operand path run one after another instead.  Asynchronous; waits
- * only for the previous batched launch of the context to have read its
- * staging buffer.  The batching of stacks across independent requests is
+ * packed-operand path run one after another instead.  Asynchronous: the
+ * launch parameters go through a ring of four pinned staging slots, and the
+ * host waits only when the copy out of the slot it reuses (four batched
+ * launches back) has not run yet.  The batching of stacks across independent requests is
  * what a serving loop uses (admit requests, build their plans, execute them
  * together). */
 bsmm_status bsmm_plans_execute(int32_t n, bsmm_plan *plans);

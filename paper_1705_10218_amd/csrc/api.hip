@@ -1457,7 +1457,10 @@ bsmm_status bsmm_ctx_destroy(bsmm_ctx ctx) {
   DeviceGuard g(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipHostFree(ctx->pinned);
-  if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
+  for (int t = 0; t < bsmm_ctx_s::NSTAGE; t++) {
+    if (ctx->stage_host[t]) (void)hipHostFree(ctx->stage_host[t]);
+    if (ctx->stage_ev[t]) (void)hipEventDestroy(ctx->stage_ev[t]);
+  }
   delete ctx;
   ABI_END
 }
@@ -1777,25 +1780,35 @@ bsmm_status bsmm_plans_execute(int32_t n, bsmm_plan *plans) {
     nnzb.push_back(P.nnzb_c);
     max_edge = std::max(max_edge, P.max_edge);
   }
-  // the staging buffers are reused: wait until the previous batched launch
-  // on this stream has read them
-  HIPCHECK(hipStreamSynchronize(s));
+  // launch parameters go through a ring of pinned host slots: a slot is
+  // rewritten once the copy out of it has run (its event), so the host never
+  // waits for the GEMM itself; the device buffer is reused in stream order
   const size_t need = gemm_multi_stage_bytes(n);
   if (need > ctx->batch_bytes) {
-    if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
+    (void)hipStreamSynchronize(s);   // no copy from the old slots is pending
+    for (int t = 0; t < bsmm_ctx_s::NSTAGE; t++) {
+      if (ctx->stage_host[t]) (void)hipHostFree(ctx->stage_host[t]);
+      ctx->stage_host[t] = nullptr;
+    }
     ctx->alloc.release(ctx->batch_dev);
-    ctx->batch_host = nullptr;
     ctx->batch_dev = nullptr;
     ctx->batch_bytes = 0;
     const size_t cap = std::max<size_t>(need, 64 * 1024);
-    if (hipHostMalloc(&ctx->batch_host, cap, hipHostMallocDefault) != hipSuccess) {
-      ctx->batch_host = nullptr;
-      fail(BSMM_ERR_OUT_OF_MEMORY, "pinned staging buffer");
+    for (int t = 0; t < bsmm_ctx_s::NSTAGE; t++) {
+      if (hipHostMalloc(&ctx->stage_host[t], cap, hipHostMallocDefault) != hipSuccess) {
+        ctx->stage_host[t] = nullptr;
+        fail(BSMM_ERR_OUT_OF_MEMORY, "pinned staging buffer");
+      }
+      if (!ctx->stage_ev[t]) HIPCHECK(hipEventCreateWithFlags(&ctx->stage_ev[t], hipEventDisableTiming));
     }
     ctx->batch_dev = ctx->alloc.alloc(cap);
     ctx->batch_bytes = cap;
   }
-  gemm_launch_multi(ctx->alloc, gs, nnzb, max_edge, ctx->batch_host, ctx->batch_bytes, ctx->batch_dev, s);
+  const int slot = ctx->stage_next;
+  HIPCHECK(hipEventSynchronize(ctx->stage_ev[slot]));   // the copy out of this slot has run
+  gemm_launch_multi(ctx->alloc, gs, nnzb, max_edge, ctx->stage_host[slot], ctx->batch_bytes, ctx->batch_dev, s);
+  HIPCHECK(hipEventRecord(ctx->stage_ev[slot], s));
+  ctx->stage_next = (slot + 1) % bsmm_ctx_s::NSTAGE;
   ABI_END
 }
 

@@ -79,8 +79,14 @@ struct bsmm_ctx_s {
   int64_t *pinned = nullptr;   // small host buffer for size read-backs
   uint8_t gemm_variant[16] = {};   // GEMM kernel variant per (m, n) size class
   int tile_ti = 2, tile_tj = 2;    // result-block tile of the tile path
-  void *batch_host = nullptr;      // pinned staging of batched launch parameters
-  void *batch_dev = nullptr;       // device copy (reused once the stream has passed the last launch)
+  // Staging of batched launch parameters: a ring of pinned host slots, each
+  // reused once the copy from it has run (its event), and one device buffer
+  // (every copy into it is ordered after the previous launch on the stream).
+  static constexpr int NSTAGE = 4;
+  void *stage_host[NSTAGE] = {};
+  hipEvent_t stage_ev[NSTAGE] = {};
+  int stage_next = 0;
+  void *batch_dev = nullptr;
   size_t batch_bytes = 0;
   double *zeros = nullptr;     // 4 KB zero page on the device
   int live_mats = 0;

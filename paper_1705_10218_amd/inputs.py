@@ -371,19 +371,28 @@ def symmetric_dft_like(n_atoms: int, config: int = 4, sizes=(5, 13), cutoff: flo
     return m
 
 
+def serving_request_params(n: int, atoms=(200, 8000), occupancy=(0.02, 0.20), seed: int = 0, config: int = 5):
+    """(atoms, occupancy, cutoff) of the n requests of serving_requests, from
+    the same draws, without building the matrices."""
+    rng = np.random.default_rng([config, 99, seed])
+    out = []
+    for _ in range(n):
+        na = int(round(math.exp(rng.uniform(math.log(atoms[0]), math.log(atoms[1])))))
+        occ = float(rng.uniform(occupancy[0], occupancy[1]))
+        box = (na / DENSITY) ** (1.0 / 3.0)
+        rc = min(cutoff_for_occupancy(na, occ), 0.49 * box)
+        out.append((na, occ, rc))
+    return out
+
+
 def serving_requests(n: int, atoms=(200, 8000), occupancy=(0.02, 0.20), sizes=(5, 13, 23), config: int = 5,
                      seed: int = 0):
     """Independent multiplication requests: atom count log-uniform in atoms,
     block sizes uniform over sizes, cutoff giving an occupancy uniform in
     occupancy (capped below half the box edge), DFT-like A and B from
     default_rng([config, matrix, request])."""
-    rng = np.random.default_rng([config, 99, seed])
     out = []
-    for rid in range(n):
-        na = int(round(math.exp(rng.uniform(math.log(atoms[0]), math.log(atoms[1])))))
-        occ = float(rng.uniform(occupancy[0], occupancy[1]))
-        box = (na / DENSITY) ** (1.0 / 3.0)
-        rc = min(cutoff_for_occupancy(na, occ), 0.49 * box)
+    for rid, (na, occ, rc) in enumerate(serving_request_params(n, atoms, occupancy, seed, config)):
         a, b, _ = dft_like_pair(na, config=config, sizes=sizes, cutoff=rc, request=seed * 100000 + rid)
         out.append((a, b, {"atoms": na, "occupancy": occ, "cutoff": rc}))
     return out

@@ -1,20 +1,33 @@
 """Continuous-batching loop for independent block-sparse multiplications on one GPU.
 
-Requests (C = A*B with a filter threshold) arrive over time.  The loop keeps
-admitting arrived requests while their estimated device footprint fits the
-HBM budget, uploads their matrices and builds their plans (the structural
-part of the multiplication), then runs the numeric parts of every admitted
-request as ONE batch -- a single block-GEMM launch over the result blocks of
-all of them (bsmm_plans_execute) -- and returns each result as soon as its
-batch is done.  Requests that arrive while a batch is on the GPU join the
-next batch as memory frees up, so the device keeps working on a changing
-mix of requests.  Each result is bitwise the one the request gets alone: a
-result block is computed by one wavefront in a fixed order whatever else
-shares the launch.
+Requests (C = A*B with a filter threshold) arrive over time.  The loop works
+on two lanes, each a library context with a stream of its own:
 
-Latency of a request = completion time of its result on the device (read
-back to the host) minus its arrival time; it includes waiting for admission,
-the host-to-device upload of A and B, planning and execution.
+* admission -- an arrived request is admitted while the device memory of the
+  requests in flight stays within the HBM budget.  Before the upload the
+  request is counted with its operand bytes times the largest footprint /
+  operand ratio seen so far; once its plan exists (the structural part of the
+  multiplication: symbolic phase, stacks) it is counted with the sizes the
+  library reports (bsmm_plan_sizes: result values and workspace, plus the
+  stacks and the result index of its product counts);
+* planning -- admitted requests are uploaded and planned on the lane that is
+  not executing, so planning and uploads overlap the other lane's batch on
+  the device;
+* execution -- the planned requests of a lane run as ONE batch: a single
+  block-GEMM launch over the result blocks of all of them
+  (bsmm_plans_execute).  A lane launches when no batch is running, when its
+  batch is full, or when its oldest request has waited max_wait_s; so the
+  two lanes' batches can run on the device at the same time;
+* completion -- an event per batch is polled; a finished batch's results are
+  returned (post-filter, read back) and its memory is released, which lets
+  waiting requests in.
+
+Every result is bitwise the one the request gets alone: a result block is
+computed by one wavefront in a fixed order whatever else shares the launch.
+
+Latency of a request = the time its result is available on the host minus
+its arrival time; it includes waiting for admission, the host-to-device
+upload of A and B, planning, execution and the result's read-back.
 """
 from __future__ import annotations
 
@@ -34,10 +47,12 @@ class Request:
     eps: float = 0.0
     arrival: float = 0.0      # seconds after the start of the run
     admitted: float = math.nan
+    planned: float = math.nan
+    launched: float = math.nan
     done: float = math.nan
     flops: float = 0.0
     batch: int = -1
-    nbytes: int = 0
+    nbytes: int = 0           # device bytes counted against the budget
     result: object = None     # host copy of C when keep_results
     _dev: tuple = field(default=(), repr=False)
 
@@ -55,78 +70,189 @@ def percentiles(x, qs=(50, 99)) -> dict:
     return {f"p{q}": float(np.percentile(x, q)) for q in qs} if x.size else {f"p{q}": math.nan for q in qs}
 
 
-def footprint_bytes(a, b) -> int:
-    """Device bytes one request needs while it is in flight: its operands,
-    their packed copies, the result (values, index, offsets, norms, work
-    list) and the stacks -- from the symbolic product of the two patterns."""
-    import scipy.sparse as sp
-    pa = sp.csr_matrix((np.ones(a.nnzb, dtype=np.int8), a.col_idx, a.row_ptr), shape=(a.nbr, a.nbc))
-    pb = sp.csr_matrix((np.ones(b.nnzb, dtype=np.int8), b.col_idx, b.row_ptr), shape=(b.nbr, b.nbc))
-    pc = (pa.astype(np.int64) @ pb.astype(np.int64)).tocoo()
-    c_vals = int(np.sum(a.rbs[pc.row].astype(np.int64) * b.cbs[pc.col].astype(np.int64)))
-    n_prod = int(np.sum(np.diff(b.row_ptr)[a.col_idx]))
-    ab = 8 * (a.n_values() + b.n_values())
-    return int(ab + 1.2 * ab + 8 * c_vals + 40 * pc.nnz + 8 * n_prod + (1 << 20))
+def operand_bytes(a, b) -> int:
+    """Device bytes of a request's operands: FP64 values and the block index."""
+    return int(8 * (a.n_values() + b.n_values()) + 16 * (a.nnzb + b.nnzb) + 8 * (a.nbr + b.nbr) + 4096)
+
+
+def plan_bytes(n_products: int, c_nnzb: int, c_n_values: int, workspace: int) -> int:
+    """Device bytes of a planned request beyond its operands: stacks (8 bytes
+    a product), the result's index, offsets, counts and work list (48 bytes a
+    block), its values and the numeric part's workspace."""
+    return int(8 * n_products + 48 * c_nnzb + 8 * c_n_values + workspace)
+
+
+@dataclass
+class _Batch:
+    reqs: list
+    event: object
+    launched: float
+    index: int
+
+
+class Lane:
+    """A library context with its own stream; requests planned on it run in
+    its batches."""
+
+    def __init__(self, device: int):
+        from . import bsmm
+        torch = bsmm._torch()
+        self.stream = torch.cuda.Stream(device)
+        self.ctx = bsmm.Context(device, stream=self.stream)
+        self.planned = []
+        self.inflight: _Batch | None = None
+
+    def close(self):
+        self.ctx.close()
 
 
 class Server:
-    """The request loop on one context (one device, one stream)."""
+    """The request loop on one device.  The engine hooks (_new_lane, _plan,
+    _launch, _finished, _complete) are the only places that touch the
+    library; tests substitute them."""
 
-    def __init__(self, ctx, budget_bytes: int, max_batch: int = 64, keep_results: bool = False):
-        self.ctx = ctx
+    def __init__(self, device: int, budget_bytes: int, max_batch: int = 64, keep_results: bool = False,
+                 max_wait_s: float = 0.002, poll_s: float = 0.0002):
+        self.device = device
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
         self.keep = keep_results
-        self.batches = []      # number of requests per batch
+        self.max_wait = float(max_wait_s)
+        self.poll = float(poll_s)
+        self.batches = []          # requests per batch
+        self.batch_times = []      # (launched, completed) per batch, seconds after the start
+        self.expansion = 4.0       # largest footprint / operand bytes seen
+        self.peak_used = 0
 
-    def run(self, requests) -> list:
+    # ------------------------------------------------------------ engine
+    def _new_lane(self):
+        return Lane(self.device)
+
+    def _plan(self, lane, r) -> int:
+        """Upload and plan r on the lane; returns its planned device bytes."""
         from . import bsmm
         torch = bsmm._torch()
-        queue = deque(sorted(requests, key=lambda r: r.arrival))
-        for r in queue:
-            r.nbytes = footprint_bytes(r.a, r.b)
-            if r.nbytes > self.budget:
-                raise ValueError(f"request {r.rid} needs {r.nbytes} bytes, above the budget {self.budget}")
+        with torch.cuda.stream(lane.stream):   # the uploads are ordered before the planning on the lane
+            A = bsmm.Matrix.from_host(lane.ctx, r.a)
+            B = bsmm.Matrix.from_host(lane.ctx, r.b)
+        plan = bsmm.Plan(lane.ctx, "N", "N", 1.0, A, B, filter_eps=r.eps)
+        nb, nv, ws = plan.sizes()
+        r.flops = plan.info.useful_flops
+        r._dev = (A, B, plan)
+        return operand_bytes(r.a, r.b) + plan_bytes(plan.info.n_products, nb, nv, ws)
+
+    def _launch(self, lane, reqs):
+        from . import bsmm
+        torch = bsmm._torch()
+        bsmm.plans_execute([r._dev[2] for r in reqs])
+        ev = torch.cuda.Event()
+        ev.record(lane.stream)
+        return ev
+
+    def _finished(self, lane, event) -> bool:
+        return bool(event.query())
+
+    def _complete(self, lane, r):
+        A, B, plan = r._dev
+        C = plan.result()              # post-filter; the batch is done, so this waits for nothing else
+        if self.keep:
+            r.result = C.to_host()
+        C.close()
+        plan.close()
+        A.close()
+        B.close()
+        r._dev = ()
+
+    # -------------------------------------------------------------- loop
+    def run(self, requests) -> list:
+        lanes = [self._new_lane(), self._new_lane()]
+        try:
+            return self._run(lanes, requests)
+        finally:
+            for ln in lanes:
+                if hasattr(ln, "close"):
+                    ln.close()
+
+    def _run(self, lanes, requests) -> list:
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        for r in pending:
+            if operand_bytes(r.a, r.b) > self.budget:
+                raise ValueError(f"request {r.rid}: its operands alone exceed the budget {self.budget}")
         t0 = time.perf_counter()
-        done = []
-        while queue:
-            now = time.perf_counter() - t0
-            if queue[0].arrival > now:
-                time.sleep(min(queue[0].arrival - now, 0.05))
-                continue
-            # admit arrived requests while they fit the budget
-            batch, used = [], 0
-            while queue and queue[0].arrival <= time.perf_counter() - t0 and len(batch) < self.max_batch:
-                r = queue[0]
-                if used + r.nbytes > self.budget:
-                    break
-                queue.popleft()
-                used += r.nbytes
-                r.admitted = time.perf_counter() - t0
-                A = bsmm.Matrix.from_host(self.ctx, r.a)
-                B = bsmm.Matrix.from_host(self.ctx, r.b)
-                plan = bsmm.Plan(self.ctx, "N", "N", 1.0, A, B, filter_eps=r.eps)
-                r.flops = plan.info.useful_flops
-                r._dev = (A, B, plan)
-                batch.append(r)
-            # one batched execution of every admitted request
-            bsmm.plans_execute([r._dev[2] for r in batch])
-            self.batches.append(len(batch))
-            for r in batch:
-                A, B, plan = r._dev
-                C = plan.result()           # post filter, synchronises the stream
-                if self.keep:
-                    r.result = C.to_host()
-                r.done = time.perf_counter() - t0
-                r.batch = len(self.batches) - 1
-                C.close()
-                plan.close()
-                A.close()
-                B.close()
-                r._dev = ()
-                done.append(r)
-            torch.cuda.synchronize()
+        clock = lambda: time.perf_counter() - t0   # noqa: E731
+        done, used, plan_lane = [], 0, 0
+        while pending or any(ln.planned or ln.inflight for ln in lanes):
+            progressed = False
+            # completions
+            for ln in lanes:
+                b = ln.inflight
+                if b is not None and self._finished(ln, b.event):
+                    for r in b.reqs:
+                        self._complete(ln, r)
+                        r.done = clock()
+                        used -= r.nbytes
+                        done.append(r)
+                    self.batch_times[b.index] = (b.launched, clock())
+                    ln.inflight = None
+                    progressed = True
+            # admission and planning on the lane that is not executing
+            # (planning synchronises the lane's stream)
+            ln = lanes[plan_lane]
+            if ln.inflight is None:
+                while pending and pending[0].arrival <= clock() and len(ln.planned) < self.max_batch:
+                    r = pending[0]
+                    est = int(self.expansion * operand_bytes(r.a, r.b))
+                    busy = any(x.planned or x.inflight for x in lanes)
+                    if busy and used + est > self.budget:
+                        break
+                    pending.popleft()
+                    r.admitted = clock()
+                    used += est
+                    r.nbytes = est
+                    real = self._plan(ln, r)
+                    used += real - est
+                    r.nbytes = real
+                    self.expansion = max(self.expansion, real / max(operand_bytes(r.a, r.b), 1))
+                    self.peak_used = max(self.peak_used, used)
+                    r.planned = clock()
+                    ln.planned.append(r)
+                    progressed = True
+            # launch: a lane with planned requests and no batch running goes
+            # when nothing else runs, its batch is full, or it waited enough
+            for k in (plan_lane, 1 - plan_lane):
+                ln = lanes[k]
+                if not ln.planned or ln.inflight is not None:
+                    continue
+                others = any(x.inflight is not None for x in lanes)
+                waited = clock() - min(r.planned for r in ln.planned)
+                arrived = bool(pending) and pending[0].arrival <= clock()
+                if others and len(ln.planned) < self.max_batch and waited < self.max_wait and arrived:
+                    continue
+                now = clock()
+                for r in ln.planned:
+                    r.launched = now
+                    r.batch = len(self.batches)
+                ev = self._launch(ln, ln.planned)
+                ln.inflight = _Batch(ln.planned, ev, now, len(self.batches))
+                self.batches.append(len(ln.planned))
+                self.batch_times.append((now, math.nan))
+                ln.planned = []
+                plan_lane = 1 - k
+                progressed = True
+            if not progressed:
+                wait = self.poll
+                if pending and not any(x.planned or x.inflight for x in lanes):
+                    wait = max(0.0, min(pending[0].arrival - clock(), 0.05))
+                time.sleep(wait)
         return done
+
+    def overlapping_batches(self) -> int:
+        """Batches launched while another batch was still running on the device."""
+        n = 0
+        for k, (l, _) in enumerate(self.batch_times):
+            if any(j != k and a < l < c for j, (a, c) in enumerate(self.batch_times)):
+                n += 1
+        return n
 
 
 def summary(done, makespan: float | None = None) -> dict:

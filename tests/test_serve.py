@@ -1,4 +1,5 @@
 """Serving loop: arrival process, statistics and admission logic (CPU, fake engine)."""
+import time
 import types
 
 import numpy as np
@@ -21,65 +22,79 @@ def test_percentiles():
     assert p["p50"] == pytest.approx(50.5) and p["p99"] == pytest.approx(99.01)
 
 
-def test_footprint_counts_result_blocks():
+def test_footprint_terms():
     a, b, _ = inputs.dft_like_pair(150, config=97, sizes=(5, 13), cutoff=5.0)
-    small = serve.footprint_bytes(a, b)
-    assert small > 8 * (a.n_values() + b.n_values())
+    ob = serve.operand_bytes(a, b)
+    assert ob >= 8 * (a.n_values() + b.n_values())
     a2, b2, _ = inputs.dft_like_pair(150, config=97, sizes=(5, 13), cutoff=5.5)
-    assert serve.footprint_bytes(a2, b2) > small
+    assert serve.operand_bytes(a2, b2) > ob
+    assert serve.plan_bytes(10, 2, 30, 256) == 8 * 10 + 48 * 2 + 8 * 30 + 256
 
 
-class _FakeBsmm(types.SimpleNamespace):
-    pass
+class _FakeServer(serve.Server):
+    """The loop with a fake engine: a batch 'runs' for a fixed time after its
+    launch; planned bytes are the operand bytes times a per-request factor."""
+
+    def __init__(self, *a, run_s=0.01, factor=None, **k):
+        super().__init__(0, *a, **k)
+        self.run_s = run_s
+        self.factor = factor or {}
+        self.launches = []
+
+    def _new_lane(self):
+        return types.SimpleNamespace(planned=[], inflight=None)
+
+    def _plan(self, lane, r):
+        r.flops = 1.0
+        return int(self.factor.get(r.rid, 2.0) * serve.operand_bytes(r.a, r.b))
+
+    def _launch(self, lane, reqs):
+        self.launches.append([r.rid for r in reqs])
+        return time.perf_counter() + self.run_s
+
+    def _finished(self, lane, event):
+        return time.perf_counter() >= event
+
+    def _complete(self, lane, r):
+        pass
 
 
-def test_admission_respects_budget(monkeypatch):
-    """Drive Server.run with a fake engine: every batch fits the budget, every
-    request completes after it arrived, and arrivals during a batch join a
-    later batch."""
-    import paper_1705_10218_amd as pkg
-    batches = []
+def _reqs(n, arrivals, atoms=60):
+    out = []
+    for i in range(n):
+        a, b, _ = inputs.dft_like_pair(atoms, config=98, sizes=(5,), cutoff=4.0, request=i)
+        out.append(serve.Request(rid=i, a=a, b=b, arrival=arrivals[i]))
+    return out
 
-    class M:
-        def __init__(self, *a, **k):
-            pass
 
-        @classmethod
-        def from_host(cls, ctx, m):
-            return cls()
-
-        def close(self):
-            pass
-
-        def to_host(self):
-            return None
-
-    class P:
-        def __init__(self, ctx, ta, tb, alpha, a, b, beta=0.0, c=None, filter_eps=0.0):
-            self.info = types.SimpleNamespace(useful_flops=1.0)
-
-        def result(self):
-            return M()
-
-        def close(self):
-            pass
-
-    fake = _FakeBsmm(Matrix=M, Plan=P, plans_execute=lambda plans: batches.append(len(plans)),
-                     _torch=lambda: types.SimpleNamespace(cuda=types.SimpleNamespace(synchronize=lambda: None)))
-    monkeypatch.setattr(pkg, "bsmm", fake, raising=False)
-    monkeypatch.setitem(__import__("sys").modules, "paper_1705_10218_amd.bsmm", fake)
-    sizes = {}
-    monkeypatch.setattr(serve, "footprint_bytes", lambda a, b: sizes[id(a)])
-    reqs = []
-    for i in range(12):
-        a = object()
-        sizes[id(a)] = 10 if i % 3 else 25
-        reqs.append(serve.Request(rid=i, a=a, b=None, arrival=0.0 if i < 8 else 0.02 * (i - 7)))
-    srv = serve.Server(ctx=None, budget_bytes=40, max_batch=4)
+def test_loop_batches_overlap_and_respect_the_budget():
+    """Requests arriving while a batch runs are planned on the other lane and
+    launched before the running batch ends; every request completes after
+    its arrival; the planned bytes in flight never exceed the budget once
+    more than one request is in flight."""
+    arrivals = [0.0] * 4 + [0.002 * k for k in range(1, 13)]
+    reqs = _reqs(16, arrivals)
+    ob = serve.operand_bytes(reqs[0].a, reqs[0].b)
+    srv = _FakeServer(budget_bytes=20 * ob, max_batch=4, run_s=0.01, max_wait_s=0.001)
     done = srv.run(reqs)
-    assert len(done) == 12 and sorted(r.rid for r in done) == list(range(12))
-    assert all(r.done >= r.arrival for r in done)
+    assert len(done) == 16 and sorted(r.rid for r in done) == list(range(16))
+    assert all(r.done >= r.launched >= r.planned >= r.admitted >= r.arrival for r in done)
+    assert max(srv.batches) <= 4 and len(srv.batches) >= 4
+    assert srv.overlapping_batches() > 0, srv.batch_times
+    assert srv.peak_used <= 20 * ob
+
+
+def test_loop_admits_by_planned_size():
+    """A request whose plan turns out large keeps later ones waiting until
+    memory frees up: no two large requests are in flight together."""
+    reqs = _reqs(6, [0.0] * 6)
+    ob = serve.operand_bytes(reqs[0].a, reqs[0].b)
+    factor = {0: 9.0, 3: 9.0}
+    srv = _FakeServer(budget_bytes=12 * ob, max_batch=8, run_s=0.005, factor=factor)
+    done = srv.run(reqs)
+    assert len(done) == 6
     for k in range(len(srv.batches)):
-        members = [r for r in done if r.batch == k]
-        assert sum(sizes[id(r.a)] for r in members) <= 40 and len(members) <= 4
-    assert max(batches) > 1
+        members = {r.rid for r in done if r.batch == k}
+        assert not {0, 3} <= members
+    t = {r.rid: r for r in done}
+    assert t[3].launched >= t[0].done or t[0].launched >= t[3].done
