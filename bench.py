@@ -62,34 +62,64 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-GEMM_SOURCE = os.path.join(ROOT, "paper_1705_10218_amd", "csrc", "gemm_kernels.hip")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_gemm_f64_dft4000_traffic.md")
+CSRC = os.path.join(ROOT, "paper_1705_10218_amd", "csrc")
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+# block-GEMM kernels: (source file, counter summaries per workload under profiles/)
+GEMM_KERNELS = {
+    "packed": ("k_gemm_f64 (batched block GEMM, all size classes in one launch)", "gemm_kernels.hip", "k_gemm_f64"),
+    "tile": ("k_tile_gemm<2,2> (block GEMM over tiles of C blocks, operands staged in LDS)", "tile_gemm.hip",
+             "k_tile_gemm"),
+    "tile_uniform": ("k_tile_uni<23> (tile GEMM, every block 23x23, sizes fixed at compile time)", "tile_gemm.hip",
+                     "k_tile_uni"),
+}
 
 
-def gemm_source_digest() -> str:
-    with open(GEMM_SOURCE, "rb") as f:
+def source_digest(name: str) -> str:
+    with open(os.path.join(CSRC, name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per GEMM launch from the committed counter summary.
+def profile_values(path_name: str, workload: str, what: str) -> dict:
+    """Values of a committed counter summary (profiles/<kernel>_<workload>_<what>.md).
 
-    The summary holds FETCH_SIZE and WRITE_SIZE of the block-GEMM kernel on
-    this workload, each divided by the factor the same counter reads for a
-    plain copy of known size.  It is used only while the kernel source is the
-    one the counters were taken on (digest match); otherwise None.
+    A summary lists its figures as "- key: `value`" lines, among them the
+    digest of the kernel's source file it was taken on; the values are used
+    only while that source is unchanged, otherwise {} (the counters would
+    describe another kernel).
     """
+    _, src, kname = GEMM_KERNELS[path_name]
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(os.path.join(PROFILE_DIR, f"{kname}_{workload}_{what}.md")).read()
     except OSError:
-        return None
+        return {}
     kv = dict(re.findall(r"^- ([a-z_0-9]+): `([^`]*)`", text, re.M))
-    if kv.get("gemm_source_sha256_16") != gemm_source_digest():
-        return None
-    try:
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    if kv.get("source_sha256_16") != source_digest(src):
+        return {}
+    out = {}
+    for k, v in kv.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
+
+
+def roofline(path_name: str, workload: str, flops: float, gemm_ms: float, compulsory: int) -> dict:
+    """Roofline of the dominant kernel: useful flops per launch over its
+    measured launch time against the FP64 MFMA peak, with the HBM traffic
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated) and the matrix-core counters
+    of the committed summaries for this kernel and workload (null when the
+    kernel changed since they were taken)."""
+    tr = profile_values(path_name, workload, "traffic")
+    mf = profile_values(path_name, workload, "mfma")
+    tflops = flops / (gemm_ms * 1e-3) / 1e12
+    issued = mf.get("mfma_f64_flops_per_launch")
+    return {"bound": "mfma", "kernel": GEMM_KERNELS[path_name][0], "achieved": round(tflops, 3),
+            "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+            "traffic": tr.get("hbm_bytes_per_launch"), "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
+            "compulsory_bytes": compulsory, "ms_per_launch": round(gemm_ms, 4),
+            "mfma_busy": mf.get("mfma_busy_frac"),
+            "mfma_issued_over_useful_flops": round(issued / flops, 4) if issued else None}
 
 
 def copy_calibration(mib: int, reps: int):
@@ -235,7 +265,11 @@ def panel_leg(bsmm, ctx, sizes, rows, steps: int, threads: int, variants: str) -
            "value": round(fl / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
            "gemm_tflops": round(fl / (gemm_ms * 1e-3) / 1e12, 3),
            "gemm_frac_of_fp64_mfma_peak": round(fl / (gemm_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
-           "gemm_path": {0: "packed", 1: "walker", 2: "tile", 3: "lowp"}.get(info.gemm_path, "?"),
+           "gemm_path": {0: "packed", 1: "walker", 2: "tile", 3: "lowp", 4: "tile_uniform"}.get(info.gemm_path, "?"),
+           "roofline": (roofline({2: "tile", 4: "tile_uniform"}[info.gemm_path],
+                                 "panel23" if tuple(sizes) == (23,) else "panel_mixed", fl, gemm_ms,
+                                 int(8 * (a.n_values() + b.n_values() + info.c_n_values)))
+                        if info.gemm_path in (2, 4) else None),
            "gemm_variants": variants, "generation_s": round(gen_s, 1),
            "sample_parity": parity,
            "oracle": {"rows": int(n_s), "threads": threads, "s": round(oracle_s, 2),
@@ -410,8 +444,7 @@ def main():
     last.close()
     # compulsory HBM bytes of the GEMM launch: A and B values once, C values once
     compulsory = int(8 * (a.n_values() + b.n_values() + infos[-1].c_n_values))
-    # the counter summary is of the dft4000 GEMM
-    traffic = measured_traffic() if args.workload == "dft4000" else None
+    path_name = {0: "packed", 2: "tile", 4: "tile_uniform"}.get(infos[-1].gemm_path, "packed")
 
     out = {
         "metric": METRIC,
@@ -433,18 +466,7 @@ def main():
         "c_nnzb": int(infos[-1].c_nnzb),
         "n_products": int(infos[-1].n_products),
         "phases_ms": phases,
-        "roofline": {
-            "bound": "mfma",
-            "kernel": "k_gemm_f64 (batched block GEMM, all size classes in one launch)",
-            "achieved": round(gemm_tflops, 3),
-            "peak": FP64_MFMA_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(gemm_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
-            "traffic": traffic,
-            "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
-            "compulsory_bytes": compulsory,
-            "ms_per_launch": round(gemm_ms, 4),
-        },
+        "roofline": roofline(path_name, args.workload, flops, gemm_ms, compulsory),
     }
     # FP32 and split-FP32 modes on the same matrices (norms and filters FP64)
     lowp_hosts = {}

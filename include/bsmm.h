@@ -84,7 +84,8 @@ typedef struct {
   float ms_index, ms_norms, ms_symbolic, ms_stacks, ms_gemm, ms_filter, ms_total;
   /* block-GEMM path: 0 = packed operand copies (k-pair slabs, one wavefront
      per result block), 1 = 64-bit pointer walker, 2 = tile path (2x2 tiles
-     of result blocks, operands staged in LDS), 3 = FP32 / split packed path */
+     of result blocks, operands staged in LDS), 3 = FP32 / split packed path,
+     4 = tile path with the uniform-size kernel (every block S x S)          */
   int32_t gemm_path;
 } bsmm_multiply_info;
 
@@ -114,17 +115,21 @@ bsmm_status bsmm_ctx_set_compute_mode(bsmm_ctx ctx, bsmm_compute_mode mode);
  *       result blocks stages the operand blocks the tile uses at each k in
  *       LDS, read straight from the stored values (no packed copies, no
  *       2 GB limit), and runs the tile's products at that k from LDS with
- *       the MFMA layout of variant 4.
+ *       the MFMA layout of variant 4.  When every block of op(A), op(B)
+ *       and C has the same size S and a kernel for S is built (S = 23) and
+ *       the tile shape is 2x2, a kernel with S fixed at compile time runs it,
+ *   6 = the tile path with the general kernel only (as 5 otherwise).
  * For the class of edges 17..24 x 17..24, variant 0 selects the tile path
- * when every result block of the product is in that class and every
- * contraction extent is at most 24 (else the packed-operand path).
+ * (as variant 5) when every result block of the product is in that class
+ * and every contraction extent is at most 24 (else the packed-operand
+ * path).  Variants 5 and 6 give bitwise the same results.
  * The variant in force when a product is planned is the one it runs with.
  * All variants give results within FP64 rounding of each other; the choice
  * only changes speed (an autotuner picks it per size class).  Applies to the
  * packed-operand path (packed copies of op(A) and op(B) below 2 GB each, at
  * most 8 distinct k sizes).
  * Errors: BSMM_ERR_INVALID_ARG for edges outside 1..32, another variant,
- * variant 3 with an edge above 8, or variant 4 or 5 outside its edges. */
+ * variant 3 with an edge above 8, or variant 4, 5 or 6 outside its edges. */
 bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_t variant);
 /* Result-block tile of the tile path (variant 5): ti x tj result blocks per
  * workgroup, each of its (ti/2)(tj/2) wavefronts owning a 2 x 2 part; an

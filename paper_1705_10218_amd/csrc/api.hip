@@ -248,6 +248,7 @@ struct Plan {
   bsmm_ctx ctx = nullptr;
   bsmm_mat_s *A = nullptr, *B = nullptr, *C0 = nullptr;
   bool ta = false, tb = false, filt = false, post = false, quads = false, lowp = false, tiles = false;
+  int32_t uni = 0;   // block size of the uniform-size tile kernel (0: the general one)
   // one_shot: built, executed once and consumed (bsmm_multiply); packed:
   // plan_build already made the packed operand copies of the current values
   bool one_shot = false, packed = false;
@@ -439,7 +440,16 @@ static void plan_build(Plan &P, char transa, char transb) {
       big = big && x >= 17;
     }
     const uint8_t v = ctx->gemm_variant[10];   // class of edges 17..24 x 17..24
-    tiles = all24 && ((big && (v == 0 || v == 5)) || !pack_ok);
+    tiles = all24 && ((big && (v == 0 || v == 5 || v == 6)) || !pack_ok);
+    // every block of op(A), op(B) and C S x S: the uniform-size kernel for S
+    // (2 x 2 tiles), unless variant 6 asks for the general one
+    if (tiles && v != 6 && ksizes.size() == 1 && ctx->tile_ti == 2 && ctx->tile_tj == 2 &&
+        tile_uni_size(ksizes[0])) {
+      bool uni = true;
+      for (int32_t x : opa_r) uni = uni && x == ksizes[0];
+      for (int32_t x : opb_c) uni = uni && x == ksizes[0];
+      P.uni = uni ? ksizes[0] : 0;
+    }
   }
   P.tiles = tiles;
   const bool quads = P.quads = !tiles && pack_ok;
@@ -835,6 +845,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   tg.old_val = C0 ? C0->d_values : nullptr;
   tg.alpha = P.alpha;
   tg.beta = P.beta;
+  tg.uni = P.uni;
   P.max_edge = 1;
   for (int32_t v : opa_r) P.max_edge = std::max(P.max_edge, v);
   for (int32_t v : opb_c) P.max_edge = std::max(P.max_edge, v);
@@ -944,7 +955,7 @@ static bsmm_mat_s *plan_finish(Plan &P, bool consume) {
   return R;
 }
 
-static int32_t gemm_path(const Plan &P) { return P.tiles ? 2 : P.lowp ? 3 : P.quads ? 0 : 1; }
+static int32_t gemm_path(const Plan &P) { return P.tiles ? (P.uni ? 4 : 2) : P.lowp ? 3 : P.quads ? 0 : 1; }
 
 // Post-filter and the result matrix of an execution into caller buffers:
 // the result's index belongs to the library, its values are the caller's
@@ -1407,9 +1418,9 @@ bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_
   ABI_BEGIN
   if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
   if (m < 1 || m > MAX_BLOCK || n < 1 || n > MAX_BLOCK) fail(BSMM_ERR_INVALID_ARG, "block edge outside 1..32");
-  if (variant < 0 || variant > 5) fail(BSMM_ERR_INVALID_ARG, "variant must be 0, 1, 2, 3, 4 or 5");
-  if (variant == 5 && (m < 17 || n < 17 || m > 24 || n > 24))
-    fail(BSMM_ERR_INVALID_ARG, "variant 5 needs both block edges in 17..24");
+  if (variant < 0 || variant > 6) fail(BSMM_ERR_INVALID_ARG, "variant must be 0, 1, 2, 3, 4, 5 or 6");
+  if ((variant == 5 || variant == 6) && (m < 17 || n < 17 || m > 24 || n > 24))
+    fail(BSMM_ERR_INVALID_ARG, "variants 5 and 6 need both block edges in 17..24");
   if (variant == 3 && (m > 8 || n > 8)) fail(BSMM_ERR_INVALID_ARG, "variant 3 needs both block edges <= 8");
   if (variant == 4 && (m < 9 || n < 9 || m > 24 || n > 24 || (m <= 16 && n <= 16)))
     fail(BSMM_ERR_INVALID_ARG, "variant 4 needs both block edges in 9..24 and one above 16");

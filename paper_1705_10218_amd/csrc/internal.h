@@ -441,9 +441,12 @@ struct TileArgs {
   double *c_val = nullptr;
   double *c_norm = nullptr;
   double alpha = 1.0, beta = 0.0;
+  int32_t uni = 0;   // S when every block of op(A), op(B) and C is S x S and a kernel for S exists (2 x 2 tiles)
 };
 // Tile shapes the kernels are built for.
 bool tile_shape_valid(int ti, int tj);
+// Whether a uniform-size tile kernel exists for S x S blocks.
+bool tile_uni_size(int32_t sz);
 // Whether the tile plan's LDS bitmaps hold a product with nbc block columns
 // of C and nbk contraction blocks.
 bool tile_path_fits(int32_t nbc, int32_t nbk, TileShape sh);

@@ -698,11 +698,253 @@ void launch_t(const TilePlan &tp, const TileP &p, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
+
+// ------------------------------------------------ uniform block size
+// Every block of op(A), op(B) and C is S x S (S fixed at compile time, 17..24:
+// the uniform-size case, e.g. one basis size per atom).  One wavefront owns a
+// 2 x 2 tile as above, but with every extent known the step needs no size
+// decoding, the LDS fragment offsets are immediates, and each of the 24
+// MFMAs of a k-slice is issued without a branch when all four result blocks
+// have a product at the step's k (with per-product branches otherwise).
+// A block is copied as NP = ceil(S^2 / 2) 16-byte pieces read from its
+// first value on (8-byte aligned loads); when S^2 is odd the last piece is
+// read one value earlier, so no load leaves the block, and its upper value
+// is moved down.  Slots then start on a 16-byte boundary (no shift).
+template <int S>
+struct Uni {
+  static constexpr int NV = S * S;
+  static constexpr int NP = (NV + 1) / 2;      // 16-byte pieces of a block
+  static constexpr int NL = (NP + 63) / 64;    // pieces per lane
+  static constexpr int NKS = (S + 3) / 4;      // k-slices
+  static constexpr int KT = S - 4 * (NKS - 1); // k-groups of the last slice that hold a k
+  static constexpr int SLOT = 2 * NP;          // doubles of an LDS slot
+};
+
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+
+template <int S, bool TA, bool TB>
+__global__ __launch_bounds__(64) void k_tile_uni(TileP P, int64_t ntile, int64_t chunk) {
+  using SH = Shape<2, 2>;
+  using U = Uni<S>;
+  static_assert(S >= 17 && S <= 24, "the edge subtiles cover rows and columns 16..23");
+  __shared__ __attribute__((aligned(16))) double slot[4][U::SLOT];
+  const int64_t w = xcd_logical(blockIdx.x, chunk);
+  if (w >= ntile) return;
+  const int lane = threadIdx.x;
+  const int32_t *td = reinterpret_cast<const int32_t *>(P.tiles + w * (SH::DESC_BYTES / 16));
+  const int64_t s0 = sread64(reinterpret_cast<const int64_t *>(reinterpret_cast<const char *>(td) + SH::S0_OFF));
+  const int32_t ns = sread32(reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(td) + SH::S0_OFF + 8));
+
+  // element (i, k) of op(A) and (k, j) of op(B) within a slot
+  auto ao = [](int i, int k) { return TA ? k + i * S : i + k * S; };
+  auto bo = [](int k, int j) { return TB ? j + k * S : k + j * S; };
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int e8 = min(16 + (lane & 7), S - 1);   // rows / columns >= S are computed and discarded
+  const int am0 = ao(i16, kq), ae0 = ao(e8, kq), bm0 = bo(kq, i16), be0 = bo(kq, e8);
+  // the last slice: k-groups past S read k = S - 1 and take zeros
+  const int kl = min(4 * (U::NKS - 1) + kq, S - 1);
+  const int aml = ao(i16, kl), ael = ao(e8, kl), bml = bo(kl, i16), bel = bo(kl, e8);
+  const bool kval = kq < U::KT;
+
+  d4 acc16[4];
+  double acc4[4][5];
+#pragma unroll
+  for (int x = 0; x < 4; x++) {
+    acc16[x] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 5; t++) acc4[x][t] = 0.0;
+  }
+
+  d2 pre[4][U::NL];
+  auto need = [](uint32_t mask, int o) { return o < 2 ? SH::need_a(mask, o) : SH::need_b(mask, o - 2); };
+  auto fetch = [&](const Rec<SH> &R, uint32_t mask) {
+#pragma unroll
+    for (int o = 0; o < 4; o++) {
+      if (need(mask, o)) {
+        const double *first = (o < 2 ? P.a_val : P.b_val) + R.off(o);
+#pragma unroll
+        for (int x = 0; x < U::NL; x++) {
+          const int p = 64 * x + lane;
+          if (x < U::NL - 1 || p < U::NP) {
+            const int e = ((U::NV & 1) && p == U::NP - 1) ? U::NV - 2 : 2 * p;
+            const d2u v = *reinterpret_cast<const d2u *>(first + e);
+            pre[o][x] = d2{v.x, v.y};
+          }
+        }
+      }
+    }
+  };
+  auto stage = [&](uint32_t mask) {
+#pragma unroll
+    for (int o = 0; o < 4; o++) {
+      if (need(mask, o)) {
+#pragma unroll
+        for (int x = 0; x < U::NL; x++) {
+          const int p = 64 * x + lane;
+          if (x < U::NL - 1 || p < U::NP) {
+            d2 v = pre[o][x];
+            if ((U::NV & 1) && p == U::NP - 1) v = d2{v.y, 0.0};
+            *reinterpret_cast<d2 *>(&slot[o][2 * p]) = v;
+          }
+        }
+      }
+    }
+  };
+
+  struct Frag {
+    double am[2], ae[2], bm[2], be[2];
+  };
+  // fragments of k-slice ks (compile-time after unrolling)
+  auto frag = [&](int ks) {
+    Frag f;
+    const bool last = ks == U::NKS - 1;
+    const int da = last ? 0 : ao(0, 4 * ks), db = last ? 0 : bo(4 * ks, 0);
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      f.am[r] = slot[r][(last ? aml : am0) + da];
+      f.ae[r] = slot[r][(last ? ael : ae0) + da];
+      f.bm[r] = slot[2 + r][(last ? bml : bm0) + db];
+      f.be[r] = slot[2 + r][(last ? bel : be0) + db];
+      if (last && U::KT < 4) {
+        f.am[r] = kval ? f.am[r] : 0.0;
+        f.ae[r] = kval ? f.ae[r] : 0.0;
+        f.bm[r] = kval ? f.bm[r] : 0.0;
+        f.be[r] = kval ? f.be[r] : 0.0;
+      }
+    }
+    return f;
+  };
+  // the six MFMAs of result block x = 2r + c at one k-slice
+  auto mma = [&](const Frag &f, const double (&aer)[2], const double (&ber)[2], const double (&bes)[2], int x) {
+    const int r = x >> 1, c = x & 1;
+    acc16[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.am[r], f.bm[c], acc16[x], 0, 0, 0);
+    acc4[x][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(f.am[r], f.be[c], acc4[x][0], 0, 0, 0);
+    acc4[x][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(f.am[r], ber[c], acc4[x][1], 0, 0, 0);
+    acc4[x][2] = __builtin_amdgcn_mfma_f64_4x4x4f64(f.ae[r], f.bm[c], acc4[x][2], 0, 0, 0);
+    acc4[x][3] = __builtin_amdgcn_mfma_f64_4x4x4f64(aer[r], f.bm[c], acc4[x][3], 0, 0, 0);
+    acc4[x][4] = __builtin_amdgcn_mfma_f64_4x4x4f64(f.ae[r], bes[c], acc4[x][4], 0, 0, 0);
+  };
+  auto products = [&](uint32_t mine, bool all) {
+    Frag fc = frag(0);
+#pragma unroll
+    for (int ks = 0; ks < U::NKS; ks++) {
+      Frag fn;
+      if (ks + 1 < U::NKS) fn = frag(ks + 1);
+      double aer[2], ber[2], bes[2];
+#pragma unroll
+      for (int d = 0; d < 2; d++) {
+        aer[d] = dpp_f64<DPP_ROW_ROR4>(fc.ae[d]);
+        ber[d] = dpp_f64<DPP_ROW_ROR4>(fc.be[d]);
+        bes[d] = dpp_f64<DPP_ROW_SHR4, 0x6>(fc.be[d]);
+      }
+#pragma unroll
+      for (int x = 0; x < 4; x++)
+        if (all || ((mine >> x) & 1u)) mma(fc, aer, ber, bes, x);
+      if (ks + 1 < U::NKS) fc = fn;
+    }
+  };
+
+  int4 bcur = int4{0, 0, 0, 0}, bnxt = int4{0, 0, 0, 0};
+  Rec<SH> R;
+  uint32_t mask = 0u;
+  if (ns > 0) {
+    bcur = load_batch<SH>(P.steps, s0, lane);
+    if (ns > SH::RB) bnxt = load_batch<SH>(P.steps, s0 + SH::RB, lane);
+    R.at(bcur, 0);
+    mask = R.mask();
+    fetch(R, mask);
+    stage(mask);
+  }
+  for (int32_t s = 0; s < ns; s++) {
+    const uint32_t cur = mask;
+    const bool more = s + 1 < ns;
+    if (more) {   // the next step's blocks go in flight
+      const int t = (s + 1) % SH::RB;
+      if (t == 0) {
+        bcur = bnxt;
+        if (s + 1 + SH::RB < ns) bnxt = load_batch<SH>(P.steps, s0 + s + 1 + SH::RB, lane);
+      }
+      R.at(bcur, t);
+      mask = R.mask();
+      fetch(R, mask);
+    }
+    products(cur, false);
+    // this step's fragments were read from LDS before the copies below
+    // (one wavefront: LDS operations complete in order)
+    if (more) stage(mask);
+  }
+
+  // epilogue: C = alpha * acc + beta * C_old, and the Frobenius norm
+  const int i4 = lane >> 4, j4 = lane & 3, b4 = (lane >> 2) & 3, lo = b4 & 1;
+#pragma unroll
+  for (int x = 0; x < 4; x++) {
+    const int r = x >> 1, c = x & 1;
+    const int32_t cb = sread32(td + 4 + 2 * r + c);
+    if (cb < 0) continue;
+    const int64_t co = sread64(P.c_off + cb);
+    const double *old = nullptr;
+    if (P.beta != 0.0 && P.old_blk) {
+      const int32_t ob = sread32(P.old_blk + cb);
+      if (ob >= 0) old = P.old_val + sread64(P.old_off + ob);
+    }
+    double ss = 0.0;
+    auto put = [&](int row, int col, double v) {
+      if (row < S && col < S) {
+        double y = P.alpha * v;
+        if (old) y += P.beta * old[row + col * S];
+        P.c_val[co + row + col * S] = y;
+        ss += y * y;
+      }
+    };
+#pragma unroll
+    for (int t = 0; t < 4; t++) put(4 * t + kq, i16, acc16[x][t]);
+    put(4 * b4 + i4, 16 + 4 * lo + j4, acc4[x][0]);
+    put(4 * b4 + i4, 16 + 4 * (lo ^ 1) + j4, acc4[x][1]);
+    put(16 + 4 * lo + i4, 4 * b4 + j4, acc4[x][2]);
+    put(16 + 4 * (lo ^ 1) + i4, 4 * b4 + j4, acc4[x][3]);
+    put(16 + 4 * lo + i4, 16 + 4 * (b4 >> 1) + j4, acc4[x][4]);
+    if (P.c_norm) {
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) ss += __shfl_xor(ss, d, 64);
+      if (lane == 0) P.c_norm[cb] = sqrt(ss);
+    }
+  }
+}
+
+template <int S>
+void launch_uni(const TilePlan &tp, const TileP &p, hipStream_t s) {
+  const XcdMap xm = xcd_map(tp.ntile);
+  const int64_t grid = xm.per_xcd * 8;
+  if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many result tiles for one launch");
+#define BSMM_UNI_LAUNCH(TA, TB)                                                                          \
+  if (p.ta == TA && p.tb == TB) {                                                                        \
+    hipLaunchKernelGGL((k_tile_uni<S, TA, TB>), dim3((unsigned)grid), dim3(64), 0, s, p, tp.ntile, xm.chunk); \
+    HIPCHECK(hipGetLastError());                                                                         \
+    return;                                                                                              \
+  }
+  BSMM_UNI_LAUNCH(0, 0)
+  BSMM_UNI_LAUNCH(0, 1)
+  BSMM_UNI_LAUNCH(1, 0)
+  BSMM_UNI_LAUNCH(1, 1)
+#undef BSMM_UNI_LAUNCH
+}
+
+// Block sizes with a uniform-size kernel.
+#define BSMM_UNI_SIZES(X) X(23)
+
 }  // namespace
 
 bool tile_shape_valid(int ti, int tj) {
   return (ti == 2 && tj == 2) || (ti == 2 && tj == 4) || (ti == 4 && tj == 2) || (ti == 4 && tj == 4) ||
          (ti == 4 && tj == 8) || (ti == 8 && tj == 4);
+}
+
+bool tile_uni_size(int32_t sz) {
+#define BSMM_UNI_HAS(S) \
+  if (sz == S) return true;
+  BSMM_UNI_SIZES(BSMM_UNI_HAS)
+#undef BSMM_UNI_HAS
+  return false;
 }
 
 bool tile_path_fits(int32_t nbc, int32_t nbk, TileShape sh) {
@@ -758,6 +1000,14 @@ void tile_gemm_launch(const TilePlan &tp, const TileArgs &g, hipStream_t s) {
   p.c_norm = g.c_norm;
   p.alpha = g.alpha;
   p.beta = g.beta;
+  if (g.uni > 0) {
+    if (tp.sh.ti != 2 || tp.sh.tj != 2) fail(BSMM_ERR_INVALID_ARG, "the uniform-size kernels take 2 x 2 tiles");
+#define BSMM_UNI_GO(S) \
+  if (g.uni == S) return launch_uni<S>(tp, p, s);
+    BSMM_UNI_SIZES(BSMM_UNI_GO)
+#undef BSMM_UNI_GO
+    fail(BSMM_ERR_INVALID_ARG, "no uniform-size kernel for this block size");
+  }
 #define BSMM_LAUNCH(A, B) \
   if (tp.sh.ti == A && tp.sh.tj == B) return launch_t<A, B>(tp, p, s);
   BSMM_TILE_SHAPES(BSMM_LAUNCH)

@@ -1,5 +1,5 @@
 """Host-side logic of bench.py (CPU): the one-GPU contract, the digest gate
-on the committed HBM-traffic figure, and the workload configurations."""
+on the committed counter figures, and the workload configurations."""
 import os
 import subprocess
 import sys
@@ -20,24 +20,36 @@ def test_more_than_one_gpu_is_refused(n):
     assert not r.stdout.strip().startswith("{")   # no result line
 
 
-def _profile(tmp_path, digest, value="123456789"):
-    p = tmp_path / "traffic.md"
-    p.write_text("# summary\n\n- gemm_source_sha256_16: `%s`\n- hbm_bytes_per_launch: `%s`\n" % (digest, value))
-    return str(p)
+def _profile(tmp_path, digest, value="123456789", name="k_gemm_f64_dft4000_traffic.md"):
+    (tmp_path / name).write_text("# summary\n\n- source_sha256_16: `%s`\n- hbm_bytes_per_launch: `%s`\n"
+                                 "- mfma_busy_frac: `0.25`\n" % (digest, value))
+    return str(tmp_path)
 
 
-def test_traffic_read_while_the_gemm_source_matches(tmp_path, monkeypatch):
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _profile(tmp_path, bench.gemm_source_digest()))
-    assert bench.measured_traffic() == 123456789.0
+def test_counters_read_while_the_kernel_source_matches(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PROFILE_DIR", _profile(tmp_path, bench.source_digest("gemm_kernels.hip")))
+    assert bench.profile_values("packed", "dft4000", "traffic")["hbm_bytes_per_launch"] == 123456789.0
+    r = bench.roofline("packed", "dft4000", 1e12, 10.0, 1000)
+    assert r["traffic"] == 123456789.0 and r["frac"] == round(100.0 / bench.FP64_MFMA_PEAK_TFLOPS, 4)
+    assert r["mfma_busy"] is None   # no mfma summary in this folder
+    # the tile kernel's summaries are keyed to its own source
+    _profile(tmp_path, bench.source_digest("tile_gemm.hip"), name="k_tile_gemm_panel23_mfma.md")
+    assert bench.roofline("tile", "panel23", 1e12, 10.0, 1000)["mfma_busy"] == 0.25
 
 
-def test_traffic_null_once_the_gemm_source_changed(tmp_path, monkeypatch):
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _profile(tmp_path, "0000000000000000"))
-    assert bench.measured_traffic() is None
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
-    assert bench.measured_traffic() is None
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _profile(tmp_path, bench.gemm_source_digest(), "n/a"))
-    assert bench.measured_traffic() is None
+def test_counters_null_once_the_kernel_source_changed(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PROFILE_DIR", _profile(tmp_path, "0000000000000000"))
+    assert bench.profile_values("packed", "dft4000", "traffic") == {}
+    assert bench.roofline("packed", "dft4000", 1e12, 10.0, 1000)["traffic"] is None
+    monkeypatch.setattr(bench, "PROFILE_DIR", str(tmp_path / "missing"))
+    assert bench.profile_values("packed", "dft4000", "traffic") == {}
+    monkeypatch.setattr(bench, "PROFILE_DIR",
+                        _profile(tmp_path, bench.source_digest("gemm_kernels.hip"), "n/a"))
+    assert "hbm_bytes_per_launch" not in bench.profile_values("packed", "dft4000", "traffic")
+    # a summary of another kernel's source does not count for this one
+    monkeypatch.setattr(bench, "PROFILE_DIR",
+                        _profile(tmp_path, bench.source_digest("tile_gemm.hip")))
+    assert bench.profile_values("packed", "dft4000", "traffic") == {}
 
 
 def test_workload_configs():

@@ -6,7 +6,8 @@ Bar: the block pattern equals the oracle's exactly, product counts and
 useful flops match exactly, FP64 values agree within relative Frobenius
 error 1e-12 (the tile path sums each result block in ascending k, four k per
 MFMA, against the oracle's plain loop: a different rounding order).  Every
-case checks that the tile path really ran (gemm_path == 2).
+case checks that the tile path really ran (gemm_path 2, or 4 for the
+uniform-size kernel, which must also match the general kernel bit for bit).
 """
 import sys
 
@@ -21,6 +22,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 TILE_PATH = 2
+UNI_PATH = 4   # the tile path with the uniform-size kernel (every block S x S)
 
 
 def _log(msg):
@@ -209,11 +211,101 @@ def test_tiles_square_same_handle(B, ctx):
 def test_tiles_dft_like_23(B, ctx):
     """23x23 blocks on the DFT-like generator (Table 1's H2O block size) at
     300 atoms, cutoff 6.5 A, filter 1e-10 in both phases; large enough for
-    the locality order (square product over 64+ rows) and the column ranks."""
+    the locality order (square product over 64+ rows) and the column ranks.
+    Every block is 23x23, so the uniform-size kernel runs; the general tile
+    kernel (variant 6) gives the same bits."""
     a, b, _ = inputs.dft_like_pair(300, config=3, sizes=(23,), cutoff=6.5)
     _log(f"tiles dft-like 23: nnzb {a.nnzb}")
     host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=1e-10)
-    _check(host, info, oracle.multiply("N", "N", 1.0, a, b, eps=1e-10))
+    _check(host, info, oracle.multiply("N", "N", 1.0, a, b, eps=1e-10), path=UNI_PATH)
+    c2 = B.Context(0)
+    c2.set_gemm_variant(23, 23, 6)
+    h6, i6 = _gpu_mul(B, c2, "N", "N", 1.0, a, b, eps=1e-10)
+    c2.close()
+    assert i6.gemm_path == TILE_PATH
+    assert same_pattern(h6, host) and np.array_equal(h6.values.view(np.uint64), host.values.view(np.uint64))
+
+
+def _uniform(rng, ta, tb, nbr, nk, nbc, p, s=23, empty_rows=()):
+    r, k, c = (np.full(x, s, np.int32) for x in (nbr, nk, nbc))
+    a = random_bcsr(rng, nbr, nk, r, k, p, empty_rows=empty_rows) if ta == "N" else random_bcsr(rng, nk, nbr, k, r, p)
+    b = random_bcsr(rng, nk, nbc, k, c, p) if tb == "N" else random_bcsr(rng, nbc, nk, c, k, p)
+    return a, b
+
+
+def _both_kernels(B, ta, tb, alpha, a, b, beta=0.0, c=None, eps=0.0, retain=False):
+    """The product with the uniform-size kernel and with the general tile
+    kernel (variant 6); asserts both ran and gave the same bits."""
+    c1 = B.Context(0)
+    h, info = _gpu_mul(B, c1, ta, tb, alpha, a, b, beta, c, eps, retain)
+    c1.close()
+    c2 = B.Context(0)
+    c2.set_gemm_variant(23, 23, 6)
+    h6, i6 = _gpu_mul(B, c2, ta, tb, alpha, a, b, beta, c, eps, retain)
+    c2.close()
+    assert info.gemm_path == UNI_PATH and i6.gemm_path == TILE_PATH
+    assert same_pattern(h, h6)
+    assert np.array_equal(h.values.view(np.uint64), h6.values.view(np.uint64)), "uniform and general kernels differ"
+    return h, info
+
+
+@pytest.mark.parametrize("ta", ["N", "T"])
+@pytest.mark.parametrize("tb", ["N", "T"])
+@pytest.mark.parametrize("seed", range(2))
+def test_uniform_23_against_oracle_and_general_kernel(B, ta, tb, seed):
+    """Every block 23x23: the uniform-size kernel against the oracle and
+    bitwise against the general tile kernel, every transpose pair, odd grids
+    (tiles missing a row or column), empty rows."""
+    rng = np.random.default_rng([712, seed, ord(ta), ord(tb)])
+    nbr, nk, nbc = (int(x) for x in rng.integers(3, 34, 3))
+    a, b = _uniform(rng, ta, tb, nbr, nk, nbc, 0.3, empty_rows=(0,) if ta == "N" else ())
+    _log(f"uniform 23 {ta}{tb} seed={seed} grid={nbr}x{nk}x{nbc}")
+    host, info = _both_kernels(B, ta, tb, 1.0, a, b)
+    _check(host, info, oracle.multiply(ta, tb, 1.0, a, b), path=UNI_PATH)
+
+
+@pytest.mark.parametrize("alpha,beta", [(1.0, 1.0), (-0.5, 2.0), (0.0, 1.5), (2.0, 0.0)])
+def test_uniform_23_alpha_beta(B, alpha, beta):
+    rng = np.random.default_rng(713)
+    a, b = _uniform(rng, "N", "N", 21, 17, 19, 0.3)
+    s = np.full(21, 23, np.int32)
+    c = random_bcsr(rng, 21, 19, s, np.full(19, 23, np.int32), 0.3)
+    if beta == 0.0:
+        c.values[:] = np.nan   # beta 0 must not read C_old
+    _log(f"uniform 23 alpha={alpha} beta={beta}")
+    host, info = _both_kernels(B, "N", "N", alpha, a, b, beta, c)
+    assert np.all(np.isfinite(host.values))
+    _check(host, info, oracle.multiply("N", "N", alpha, a, b, beta, None if beta == 0.0 else c), path=UNI_PATH)
+
+
+def test_uniform_23_filters_and_retain(B):
+    rng = np.random.default_rng(714)
+    a, b = _uniform(rng, "N", "N", 26, 24, 25, 0.3)
+    off = a.block_offsets()
+    rows = a.block_rows()
+    for p in range(a.nnzb):
+        a.values[off[p]:off[p + 1]] *= 10.0 ** (-(rows[p] % 6))
+    na, nb = oracle.block_norms(a), oracle.block_norms(b)
+    prods = np.sort(np.outer(na, nb).ravel())
+    eps = float(0.5 * (prods[len(prods) // 3] + prods[len(prods) // 3 + 1]))
+    assert np.min(np.abs(prods - eps)) > 1e-9 * eps
+    ref = oracle.multiply("N", "N", 1.0, a, b, eps=eps)
+    assert ref.n_products < oracle.multiply("N", "N", 1.0, a, b).n_products
+    host, info = _both_kernels(B, "N", "N", 1.0, a, b, eps=eps)
+    _check(host, info, ref, path=UNI_PATH)
+    s = np.full(26, 23, np.int32)
+    c = random_bcsr(rng, 26, 25, s, np.full(25, 23, np.int32), 0.2)
+    host, info = _both_kernels(B, "N", "N", 1.0, a, b, 0.5, c, retain=True)
+    _check(host, info, oracle.multiply("N", "N", 1.0, a, b, 0.5, c, retain_sparsity=True), path=UNI_PATH)
+
+
+def test_uniform_23_single_rows_and_columns(B):
+    rng = np.random.default_rng(715)
+    for nbr, nk, nbc in ((1, 5, 1), (1, 1, 7), (5, 3, 1), (2, 1, 2), (1, 1, 1)):
+        a, b = _uniform(rng, "N", "N", nbr, nk, nbc, 0.9)
+        _log(f"uniform 23 grid {nbr}x{nk}x{nbc}")
+        host, info = _both_kernels(B, "N", "N", 1.0, a, b)
+        _check(host, info, oracle.multiply("N", "N", 1.0, a, b), path=UNI_PATH)
 
 
 def test_tiles_deterministic_and_against_packed_path(B, ctx):
