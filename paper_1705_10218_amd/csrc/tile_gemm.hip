@@ -103,6 +103,14 @@ __device__ __forceinline__ double dpp_f64(double x) {
 }
 constexpr int DPP_ROW_SHR4 = 0x114;   // lane l takes lane l - 4 of its row
 constexpr int DPP_ROW_ROR4 = 0x124;   // lane l takes lane (l - 4) mod 16 of its row
+// row_ror:4 of a double: every lane is written, so no old value is kept
+__device__ __forceinline__ double ror4_f64(double x) {
+  const int2 v = __builtin_bit_cast(int2, x);
+  int2 r;
+  r.x = __builtin_amdgcn_mov_dpp(v.x, DPP_ROW_ROR4, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_mov_dpp(v.y, DPP_ROW_ROR4, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
 
 __device__ __forceinline__ int64_t sread64(const int64_t *p) {
   const int64_t v = *p;
@@ -766,7 +774,8 @@ __global__ __launch_bounds__(64) void k_tile_uni(TileP P, int64_t ntile, int64_t
         for (int x = 0; x < U::NL; x++) {
           const int p = 64 * x + lane;
           if (x < U::NL - 1 || p < U::NP) {
-            const int e = ((U::NV & 1) && p == U::NP - 1) ? U::NV - 2 : 2 * p;
+            // only the last piece of a block of odd size is read one value early
+            const int e = (x == U::NL - 1 && (U::NV & 1) && p == U::NP - 1) ? U::NV - 2 : 2 * p;
             const d2u v = *reinterpret_cast<const d2u *>(first + e);
             pre[o][x] = d2{v.x, v.y};
           }
@@ -783,7 +792,7 @@ __global__ __launch_bounds__(64) void k_tile_uni(TileP P, int64_t ntile, int64_t
           const int p = 64 * x + lane;
           if (x < U::NL - 1 || p < U::NP) {
             d2 v = pre[o][x];
-            if ((U::NV & 1) && p == U::NP - 1) v = d2{v.y, 0.0};
+            if (x == U::NL - 1 && (U::NV & 1) && p == U::NP - 1) v = d2{v.y, 0.0};
             *reinterpret_cast<d2 *>(&slot[o][2 * p]) = v;
           }
         }
@@ -824,7 +833,8 @@ __global__ __launch_bounds__(64) void k_tile_uni(TileP P, int64_t ntile, int64_t
     acc4[x][3] = __builtin_amdgcn_mfma_f64_4x4x4f64(aer[r], f.bm[c], acc4[x][3], 0, 0, 0);
     acc4[x][4] = __builtin_amdgcn_mfma_f64_4x4x4f64(f.ae[r], bes[c], acc4[x][4], 0, 0, 0);
   };
-  auto products = [&](uint32_t mine, bool all) {
+  auto products = [&](uint32_t mine_v) {
+    const uint32_t mine = (uint32_t)__builtin_amdgcn_readfirstlane((int)mine_v);   // uniform: scalar branches
     Frag fc = frag(0);
 #pragma unroll
     for (int ks = 0; ks < U::NKS; ks++) {
@@ -833,24 +843,27 @@ __global__ __launch_bounds__(64) void k_tile_uni(TileP P, int64_t ntile, int64_t
       double aer[2], ber[2], bes[2];
 #pragma unroll
       for (int d = 0; d < 2; d++) {
-        aer[d] = dpp_f64<DPP_ROW_ROR4>(fc.ae[d]);
-        ber[d] = dpp_f64<DPP_ROW_ROR4>(fc.be[d]);
+        aer[d] = ror4_f64(fc.ae[d]);
+        ber[d] = ror4_f64(fc.be[d]);
         bes[d] = dpp_f64<DPP_ROW_SHR4, 0x6>(fc.be[d]);
       }
 #pragma unroll
       for (int x = 0; x < 4; x++)
-        if (all || ((mine >> x) & 1u)) mma(fc, aer, ber, bes, x);
+        if ((mine >> x) & 1u) mma(fc, aer, ber, bes, x);
       if (ks + 1 < U::NKS) fc = fn;
     }
   };
 
-  int4 bcur = int4{0, 0, 0, 0}, bnxt = int4{0, 0, 0, 0};
+  // step records one at a time (lanes 0..LPR-1 hold one), the record of
+  // step s + 2 in flight while step s runs: it has arrived when the blocks
+  // of step s + 1 are staged, so decoding never waits for memory
+  auto load_rec = [&](int64_t step) { return P.steps[step * SH::LPR + min(lane, SH::LPR - 1)]; };
+  int4 rnext = int4{0, 0, 0, 0};
   Rec<SH> R;
   uint32_t mask = 0u;
   if (ns > 0) {
-    bcur = load_batch<SH>(P.steps, s0, lane);
-    if (ns > SH::RB) bnxt = load_batch<SH>(P.steps, s0 + SH::RB, lane);
-    R.at(bcur, 0);
+    R.at(load_rec(s0), 0);
+    if (ns > 1) rnext = load_rec(s0 + 1);
     mask = R.mask();
     fetch(R, mask);
     stage(mask);
@@ -859,16 +872,12 @@ __global__ __launch_bounds__(64) void k_tile_uni(TileP P, int64_t ntile, int64_t
     const uint32_t cur = mask;
     const bool more = s + 1 < ns;
     if (more) {   // the next step's blocks go in flight
-      const int t = (s + 1) % SH::RB;
-      if (t == 0) {
-        bcur = bnxt;
-        if (s + 1 + SH::RB < ns) bnxt = load_batch<SH>(P.steps, s0 + s + 1 + SH::RB, lane);
-      }
-      R.at(bcur, t);
+      R.at(rnext, 0);
+      if (s + 2 < ns) rnext = load_rec(s0 + s + 2);
       mask = R.mask();
       fetch(R, mask);
     }
-    products(cur, false);
+    products(cur);
     // this step's fragments were read from LDS before the copies below
     // (one wavefront: LDS operations complete in order)
     if (more) stage(mask);
