@@ -69,7 +69,8 @@ GEMM_KERNELS = {
     "packed": ("k_gemm_f64 (batched block GEMM, all size classes in one launch)", "gemm_kernels.hip", "k_gemm_f64"),
     "tile": ("k_tile_gemm<2,2> (block GEMM over tiles of C blocks, operands staged in LDS)", "tile_gemm.hip",
              "k_tile_gemm"),
-    "tile_uniform": ("k_tile_uni<23> (tile GEMM, every block 23x23, sizes fixed at compile time)", "tile_gemm.hip",
+    "tile_uniform": ("k_tile_uni<23,false,false> (tile GEMM, every block 23x23, sizes fixed at compile time)",
+                     "tile_gemm.hip",
                      "k_tile_uni"),
 }
 
@@ -119,7 +120,8 @@ def roofline(path_name: str, workload: str, flops: float, gemm_ms: float, compul
             "traffic": tr.get("hbm_bytes_per_launch"), "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
             "compulsory_bytes": compulsory, "ms_per_launch": round(gemm_ms, 4),
             "mfma_busy": mf.get("mfma_busy_frac"),
-            "mfma_issued_over_useful_flops": round(issued / flops, 4) if issued else None}
+            "padding_ratio": round(issued / flops, 4) if issued else None,
+            "clock_ghz_under_load": mf.get("clock_ghz")}
 
 
 def copy_calibration(mib: int, reps: int):
