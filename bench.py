@@ -72,6 +72,7 @@ GEMM_KERNELS = {
     "tile_uniform": ("k_tile_uni<23,false,false> (tile GEMM, every block 23x23, sizes fixed at compile time)",
                      "tile_gemm.hip",
                      "k_tile_uni"),
+    "lowp": ("k_gemm_lowp (FP32 / split-FP32 block GEMM, packed FP32 operands)", "gemm_lowp.hip", "k_gemm_lowp"),
 }
 
 
@@ -114,9 +115,10 @@ def roofline(path_name: str, workload: str, flops: float, gemm_ms: float, compul
     tr = profile_values(path_name, workload, "traffic")
     mf = profile_values(path_name, workload, "mfma")
     tflops = flops / (gemm_ms * 1e-3) / 1e12
-    issued = mf.get("mfma_f64_flops_per_launch")
+    issued = mf.get("mfma_f64_flops_per_launch") or mf.get("mfma_f32_flops_per_launch")
+    peak = FP32_MFMA_PEAK_TFLOPS if path_name == "lowp" else FP64_MFMA_PEAK_TFLOPS
     return {"bound": "mfma", "kernel": GEMM_KERNELS[path_name][0], "achieved": round(tflops, 3),
-            "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(tflops / peak, 4),
             "traffic": tr.get("hbm_bytes_per_launch"), "traffic_unit": "bytes per launch (HBM, counter-calibrated)",
             "compulsory_bytes": compulsory, "ms_per_launch": round(gemm_ms, 4),
             "mfma_busy": mf.get("mfma_busy_frac"),
@@ -393,6 +395,9 @@ def main():
     ap.add_argument("--no-batching", dest="batching", action="store_false",
                     help="skip the 20,000-atom batching legs (about 70 GB of host data)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--compute-mode", choices=["fp64", "fp32", "split"], default="fp64",
+                    help="arithmetic of the timed workload's block products (profiling the FP32 and split "
+                         "paths; with fp32 or split only that workload runs, as with --fp64-only)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run plain device copies of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -432,7 +437,11 @@ def main():
     torch.cuda.synchronize()
     ctx.set_timing(True)
 
-    _log(f"warmup {args.warmup}, timing {args.steps} steps")
+    mode = {"fp64": 0, "fp32": 1, "split": 2}[args.compute_mode]
+    if mode:
+        args.fp64_only = True   # the other legs measure FP64 (and the precision leg both modes)
+        ctx.set_compute_mode(mode)
+    _log(f"warmup {args.warmup}, timing {args.steps} steps ({args.compute_mode})")
     ms_step, per_step, infos, last = time_mode(bsmm, ctx, A, Bm, eps, args.steps, args.warmup)
     _log(f"{ms_step:.3f} ms/step")
 
@@ -446,7 +455,7 @@ def main():
     last.close()
     # compulsory HBM bytes of the GEMM launch: A and B values once, C values once
     compulsory = int(8 * (a.n_values() + b.n_values() + infos[-1].c_n_values))
-    path_name = {0: "packed", 2: "tile", 4: "tile_uniform"}.get(infos[-1].gemm_path, "packed")
+    path_name = {0: "packed", 2: "tile", 3: "lowp", 4: "tile_uniform"}.get(infos[-1].gemm_path, "packed")
 
     out = {
         "metric": METRIC,
@@ -460,7 +469,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32", "split": "f32x2 (split FP64)"}[args.compute_mode],
         "data": "synthetic (seeded generator, DFT-like block pattern)",
         "config": cfg,
         "pct_fp64_mfma_peak": round(100.0 * value / (FP64_MFMA_PEAK_TFLOPS * 1e3), 2),
@@ -468,7 +477,8 @@ def main():
         "c_nnzb": int(infos[-1].c_nnzb),
         "n_products": int(infos[-1].n_products),
         "phases_ms": phases,
-        "roofline": roofline(path_name, args.workload, flops, gemm_ms, compulsory),
+        "roofline": roofline(path_name, args.workload if not mode else f"{args.workload}_{args.compute_mode}", flops,
+                             gemm_ms, compulsory),
     }
     # FP32 and split-FP32 modes on the same matrices (norms and filters FP64)
     lowp_hosts = {}
