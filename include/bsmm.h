@@ -140,6 +140,15 @@ bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_
  * result block sums its products in ascending k).
  * Errors: BSMM_ERR_INVALID_ARG for another shape. */
 bsmm_status bsmm_ctx_set_tile_shape(bsmm_ctx ctx, int32_t ti, int32_t tj);
+/* Schedule of the tile path's GEMM launch (products planned afterwards):
+ * xcd_chunk = consecutive tiles handed to one XCD at a time (0 = 8192; the
+ * 8 XCDs take chunks in turn, so each XCD's L2 stays on neighbouring tiles).
+ * Results are bitwise the same for every chunk.  persistent must be 0: a
+ * persistent launch (resident workgroups taking tiles from device ticket
+ * counters) is not available.
+ * Errors: BSMM_ERR_INVALID_ARG for xcd_chunk outside 0..2^30,
+ * BSMM_ERR_UNSUPPORTED for persistent != 0. */
+bsmm_status bsmm_ctx_set_tile_schedule(bsmm_ctx ctx, int32_t persistent, int64_t xcd_chunk);
 /* Bytes of device memory the library currently holds for this context
  * (live buffers plus its cache of freed ones). */
 bsmm_status bsmm_ctx_memory(bsmm_ctx ctx, size_t *held_bytes, size_t *peak_bytes);

@@ -846,6 +846,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   tg.alpha = P.alpha;
   tg.beta = P.beta;
   tg.uni = P.uni;
+  tg.xcd_chunk = ctx->tile_chunk;
   P.max_edge = 1;
   for (int32_t v : opa_r) P.max_edge = std::max(P.max_edge, v);
   for (int32_t v : opb_c) P.max_edge = std::max(P.max_edge, v);
@@ -1434,6 +1435,15 @@ bsmm_status bsmm_ctx_set_tile_shape(bsmm_ctx ctx, int32_t ti, int32_t tj) {
   if (!tile_shape_valid(ti, tj)) fail(BSMM_ERR_INVALID_ARG, "tile shape must be 2x2, 2x4, 4x2, 4x4, 4x8 or 8x4");
   ctx->tile_ti = ti;
   ctx->tile_tj = tj;
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_set_tile_schedule(bsmm_ctx ctx, int32_t persistent, int64_t xcd_chunk) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  if (xcd_chunk < 0 || xcd_chunk > (1ll << 30)) fail(BSMM_ERR_INVALID_ARG, "xcd_chunk must be in 0..2^30");
+  if (persistent != 0) fail(BSMM_ERR_UNSUPPORTED, "the persistent tile launch is disabled");
+  ctx->tile_chunk = xcd_chunk;
   ABI_END
 }
 

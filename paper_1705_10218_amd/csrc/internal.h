@@ -79,6 +79,7 @@ struct bsmm_ctx_s {
   int64_t *pinned = nullptr;   // small host buffer for size read-backs
   uint8_t gemm_variant[16] = {};   // GEMM kernel variant per (m, n) size class
   int tile_ti = 2, tile_tj = 2;    // result-block tile of the tile path
+  int64_t tile_chunk = 0;          // tiles per XCD chunk of the tile path (0: 8192)
   // Staging of batched launch parameters: a ring of pinned host slots, each
   // reused once the copy from it has run (its event), and one device buffer
   // (every copy into it is ordered after the previous launch on the stream).
@@ -442,6 +443,7 @@ struct TileArgs {
   double *c_norm = nullptr;
   double alpha = 1.0, beta = 0.0;
   int32_t uni = 0;   // S when every block of op(A), op(B) and C is S x S and a kernel for S exists (2 x 2 tiles)
+  int64_t xcd_chunk = 0;   // tiles per XCD chunk (0: 8192)
 };
 // Tile shapes the kernels are built for.
 bool tile_shape_valid(int ti, int tj);

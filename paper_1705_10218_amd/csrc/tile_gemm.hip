@@ -697,9 +697,9 @@ void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const
 }
 
 template <int TI, int TJ>
-void launch_t(const TilePlan &tp, const TileP &p, hipStream_t s) {
+void launch_t(const TilePlan &tp, const TileP &p, int64_t max_chunk, hipStream_t s) {
   using S = Shape<TI, TJ>;
-  const XcdMap xm = xcd_map(tp.ntile);
+  const XcdMap xm = xcd_map(tp.ntile, max_chunk);
   const int64_t grid = xm.per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many result tiles for one launch");
   hipLaunchKernelGGL((k_tile_gemm<TI, TJ>), dim3((unsigned)grid), dim3(64 * S::NW), 0, s, p, tp.ntile, xm.chunk);
@@ -730,14 +730,12 @@ struct Uni {
 
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
+// One tile w of the uniform-size kernel (slot: the wavefront's LDS).
 template <int S, bool TA, bool TB>
-__global__ __launch_bounds__(64) void k_tile_uni(TileP P, int64_t ntile, int64_t chunk) {
+__device__ __forceinline__ void tile_uni(const TileP &P, int64_t w, double (&slot)[4][Uni<S>::SLOT]) {
   using SH = Shape<2, 2>;
   using U = Uni<S>;
   static_assert(S >= 17 && S <= 24, "the edge subtiles cover rows and columns 16..23");
-  __shared__ __attribute__((aligned(16))) double slot[4][U::SLOT];
-  const int64_t w = xcd_logical(blockIdx.x, chunk);
-  if (w >= ntile) return;
   const int lane = threadIdx.x;
   const int32_t *td = reinterpret_cast<const int32_t *>(P.tiles + w * (SH::DESC_BYTES / 16));
   const int64_t s0 = sread64(reinterpret_cast<const int64_t *>(reinterpret_cast<const char *>(td) + SH::S0_OFF));
@@ -920,22 +918,31 @@ __global__ __launch_bounds__(64) void k_tile_uni(TileP P, int64_t ntile, int64_t
   }
 }
 
-template <int S>
-void launch_uni(const TilePlan &tp, const TileP &p, hipStream_t s) {
-  const XcdMap xm = xcd_map(tp.ntile);
+// One workgroup per tile, tiles handed to the XCDs in chunks of `chunk`
+// consecutive tiles (the XCDs take chunks in turn).
+template <int S, bool TA, bool TB>
+__global__ __launch_bounds__(64, 2) void k_tile_uni(TileP P, int64_t ntile, int64_t chunk) {   // two waves per SIMD
+  __shared__ __attribute__((aligned(16))) double slot[4][Uni<S>::SLOT];
+  const int64_t w = xcd_logical(blockIdx.x, chunk);
+  if (w >= ntile) return;   // uniform over the workgroup
+  tile_uni<S, TA, TB>(P, w, slot);
+}
+
+template <int S, bool TA, bool TB>
+void launch_uni_t(const TilePlan &tp, const TileP &p, int64_t max_chunk, hipStream_t s) {
+  const XcdMap xm = xcd_map(tp.ntile, max_chunk);
   const int64_t grid = xm.per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many result tiles for one launch");
-#define BSMM_UNI_LAUNCH(TA, TB)                                                                          \
-  if (p.ta == TA && p.tb == TB) {                                                                        \
-    hipLaunchKernelGGL((k_tile_uni<S, TA, TB>), dim3((unsigned)grid), dim3(64), 0, s, p, tp.ntile, xm.chunk); \
-    HIPCHECK(hipGetLastError());                                                                         \
-    return;                                                                                              \
-  }
-  BSMM_UNI_LAUNCH(0, 0)
-  BSMM_UNI_LAUNCH(0, 1)
-  BSMM_UNI_LAUNCH(1, 0)
-  BSMM_UNI_LAUNCH(1, 1)
-#undef BSMM_UNI_LAUNCH
+  hipLaunchKernelGGL((k_tile_uni<S, TA, TB>), dim3((unsigned)grid), dim3(64), 0, s, p, tp.ntile, xm.chunk);
+  HIPCHECK(hipGetLastError());
+}
+
+template <int S>
+void launch_uni(const TilePlan &tp, const TileP &p, int64_t max_chunk, hipStream_t s) {
+  if (p.ta == 0 && p.tb == 0) return launch_uni_t<S, false, false>(tp, p, max_chunk, s);
+  if (p.ta == 0 && p.tb == 1) return launch_uni_t<S, false, true>(tp, p, max_chunk, s);
+  if (p.ta == 1 && p.tb == 0) return launch_uni_t<S, true, false>(tp, p, max_chunk, s);
+  return launch_uni_t<S, true, true>(tp, p, max_chunk, s);
 }
 
 // Block sizes with a uniform-size kernel.
@@ -1009,16 +1016,17 @@ void tile_gemm_launch(const TilePlan &tp, const TileArgs &g, hipStream_t s) {
   p.c_norm = g.c_norm;
   p.alpha = g.alpha;
   p.beta = g.beta;
+  const int64_t chunk = g.xcd_chunk > 0 ? g.xcd_chunk : 8192;
   if (g.uni > 0) {
     if (tp.sh.ti != 2 || tp.sh.tj != 2) fail(BSMM_ERR_INVALID_ARG, "the uniform-size kernels take 2 x 2 tiles");
 #define BSMM_UNI_GO(S) \
-  if (g.uni == S) return launch_uni<S>(tp, p, s);
+  if (g.uni == S) return launch_uni<S>(tp, p, chunk, s);
     BSMM_UNI_SIZES(BSMM_UNI_GO)
 #undef BSMM_UNI_GO
     fail(BSMM_ERR_INVALID_ARG, "no uniform-size kernel for this block size");
   }
 #define BSMM_LAUNCH(A, B) \
-  if (tp.sh.ti == A && tp.sh.tj == B) return launch_t<A, B>(tp, p, s);
+  if (tp.sh.ti == A && tp.sh.tj == B) return launch_t<A, B>(tp, p, chunk, s);
   BSMM_TILE_SHAPES(BSMM_LAUNCH)
 #undef BSMM_LAUNCH
   fail(BSMM_ERR_INVALID_ARG, "unsupported tile shape");

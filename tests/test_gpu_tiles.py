@@ -386,3 +386,56 @@ def test_tiles_single_row_and_column(B, ctx):
         _log(f"tiles grid {nbr}x{nk}x{nbc}")
         host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)
         _check(host, info, oracle.multiply("N", "N", 1.0, a, b))
+
+
+@pytest.mark.skip(reason="the persistent launch faulted the GPU on the 2,500-row 23x23 panel (memory aperture "
+                         "violation in the persistent kernel) with no cause found; the launch is disabled and "
+                         "bsmm_ctx_set_tile_schedule rejects persistent != 0")
+@pytest.mark.parametrize("chunk", [0, 1, 3, 64])
+def test_uniform_23_persistent_launch_same_bits(B, chunk):
+    """The persistent launch of the uniform-size kernel (resident workgroups
+    taking their XCD's tiles from ticket counters) gives the grid launch's
+    bits, for chunk sizes that give every XCD many rounds, one, or tiles
+    fewer than workgroups."""
+    rng = np.random.default_rng([716, chunk])
+    for nbr, nk, nbc in ((24, 19, 27), (3, 2, 3)):
+        a, b = _uniform(rng, "N", "N", nbr, nk, nbc, 0.35)
+        c1 = B.Context(0)
+        c1.set_tile_schedule(False, chunk)
+        h1, i1 = _gpu_mul(B, c1, "N", "N", 1.0, a, b)
+        c1.close()
+        c2 = B.Context(0)
+        c2.set_tile_schedule(True, chunk)
+        h2, i2 = _gpu_mul(B, c2, "N", "N", 1.0, a, b)
+        c2.close()
+        _log(f"persistent chunk={chunk} grid {nbr}x{nk}x{nbc}")
+        assert i1.gemm_path == UNI_PATH and i2.gemm_path == UNI_PATH
+        assert same_pattern(h1, h2) and np.array_equal(h1.values.view(np.uint64), h2.values.view(np.uint64))
+        _check(h2, i2, oracle.multiply("N", "N", 1.0, a, b), path=UNI_PATH)
+
+
+def test_tile_schedule_rejected(B):
+    c2 = B.Context(0)
+    with pytest.raises(B.BsmmError) as e:
+        c2.set_tile_schedule(False, -1)
+    assert e.value.status == 1
+    with pytest.raises(B.BsmmError) as e:   # the persistent launch is disabled
+        c2.set_tile_schedule(True, 0)
+    assert e.value.status == 7
+    c2.close()
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 64, 32768])
+def test_uniform_23_xcd_chunk_same_bits(B, chunk):
+    """Every XCD chunk size of the tile launch gives the same bits."""
+    rng = np.random.default_rng([717, chunk])
+    a, b = _uniform(rng, "N", "N", 24, 19, 27, 0.35)
+    c1 = B.Context(0)
+    h1, i1 = _gpu_mul(B, c1, "N", "N", 1.0, a, b)
+    c1.close()
+    c2 = B.Context(0)
+    c2.set_tile_schedule(False, chunk)
+    h2, i2 = _gpu_mul(B, c2, "N", "N", 1.0, a, b)
+    c2.close()
+    assert i1.gemm_path == UNI_PATH and i2.gemm_path == UNI_PATH
+    assert same_pattern(h1, h2) and np.array_equal(h1.values.view(np.uint64), h2.values.view(np.uint64))
