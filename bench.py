@@ -340,7 +340,7 @@ def config5_estimate(n: int = 512, atoms=(200, 8000), sizes=(5, 13, 23)) -> dict
             "input_bytes_estimate": round(8.0 * vals), "useful_flops_estimate": float(f"{flops:.3e}")}
 
 
-def serving_leg(bsmm, n: int) -> dict:
+def serving_leg(bsmm, n: int, configure=None) -> dict:
     import numpy as np
 
     from paper_1705_10218_amd import inputs, serve
@@ -353,10 +353,10 @@ def serving_leg(bsmm, n: int) -> dict:
         return [serve.Request(rid=i, a=a, b=b, eps=1e-10, arrival=float(t)) for i, ((a, b, _), t) in
                 enumerate(zip(gen, arrivals))]
 
-    srv = serve.Server(0, budget, max_batch=64)
+    srv = serve.Server(0, budget, max_batch=64, configure=configure)
     sat = serve.summary(srv.run(requests(np.zeros(n))))
     rate = 0.7 * sat["requests_per_s"]
-    srv2 = serve.Server(0, budget, max_batch=64)
+    srv2 = serve.Server(0, budget, max_batch=64, configure=configure)
     done = srv2.run(requests(serve.poisson_arrivals(n, rate, np.random.default_rng(5))))
     st = serve.summary(done)
     _log(f"serving: saturation {sat['requests_per_s']:.1f} req/s, at 0.7x: p50 {st['latency_p50_ms']:.1f} ms "
@@ -421,15 +421,19 @@ def main():
     ctx = bsmm.Context(0)
     from paper_1705_10218_amd import autotune
     def tune_for(sizes):
-        """Tuned GEMM variants of this block-size set, if the table has them."""
+        """Tuned GEMM variants and tile-path schedule of this block-size set,
+        if the table has them; returns what was set."""
         for m in (5, 13, 23, 32):
             for n in (5, 13, 23, 32):
                 ctx.set_gemm_variant(m, n, 0)
+        ctx.set_tile_shape(2, 2)
+        ctx.set_tile_schedule(False, 0)
         if args.no_tuning or not os.path.exists(autotune.DEFAULT_TABLE):
             return "default"
         if autotune.apply(ctx, autotune.DEFAULT_TABLE, sizes) == 0:
             return "default (no tuned table for these block sizes)"
-        return "autotuned per size class (" + os.path.relpath(autotune.DEFAULT_TABLE, ROOT) + ")"
+        return (f"autotuned ({os.path.relpath(autotune.DEFAULT_TABLE, ROOT)}): "
+                + autotune.describe(autotune.DEFAULT_TABLE, sizes))
 
     cfg["gemm_variants"] = tune_for(cfg.get("block_sizes", [5]))
     A = bsmm.Matrix.from_host(ctx, a)
@@ -525,7 +529,10 @@ def main():
     # (saturation throughput), then Poisson arrivals at 0.7 of that rate
     if not args.fp64_only and args.serve_requests > 0:
         variants = tune_for((5, 13, 23))
-        out["serving"] = serving_leg(bsmm, args.serve_requests)
+        tuned = not (args.no_tuning or not os.path.exists(autotune.DEFAULT_TABLE))
+        out["serving"] = serving_leg(
+            bsmm, args.serve_requests,
+            configure=(lambda c: autotune.apply(c, autotune.DEFAULT_TABLE, (5, 13, 23))) if tuned else None)
         out["serving"]["gemm_variants"] = variants
     # second workload: Newton-Schulz sign iteration (two filtered multiplies
     # per step, pattern evolving then stabilising)

@@ -1,4 +1,5 @@
-"""Autotuner for the block GEMM's kernel variant per (m, n) size class.
+"""Autotuner for the block GEMM's kernel variant per (m, n) size class and
+the tile path's schedule.
 
 The FP64 block GEMM has several ways to cover a result block on the matrix
 cores: 16x16x4 MFMA tiles (few loads per k-step, padding to 16), 4x4x4
@@ -12,7 +13,12 @@ workload whose result blocks all have that shape (contraction sizes drawn
 from the same set) is multiplied with each variant, and the fastest GEMM
 time wins.  The best variant depends on the contraction-size mix as well,
 so the JSON file holds one table per block-size set and :func:`apply` picks
-the table of the workload's set.
+the table of the workload's set.  A wavefront (packed path) or a tile (tile
+path) owns result blocks whose products have every k size of the set, so the
+choice is made per (m, n) class with the set's k mix, not per (m, n, k).
+For sets whose sizes all lie in 17..24 the tile path is a candidate too, and
+when it wins, its tile shape and the number of consecutive tiles per XCD
+chunk are tuned as well.
 
 Usage::
 
@@ -29,16 +35,23 @@ import sys
 import numpy as np
 
 VARIANTS = {1: "mfma16x16x4_tiles", 2: "mfma4x4x4_subtiles", 3: "mfma16x16x4_diagonal_pairs",
-            4: "mfma16x16x4_with_4x4x4_edges"}
+            4: "mfma16x16x4_with_4x4x4_edges", 5: "tile_path_lds_staged", 6: "tile_path_general_kernel"}
+TILE_SHAPES = ((2, 2), (2, 4), (4, 2), (4, 4))
+XCD_CHUNKS = (2048, 8192, 32768)
 
 
-def applies(v: int, m: int, n: int) -> bool:
+def applies(v: int, m: int, n: int, sizes=None) -> bool:
     """Variant 3 exists for blocks with both edges at most 8, variant 4 for
-    both edges in 9..24 with one above 16."""
+    both edges in 9..24 with one above 16.  The tile-path variants 5 and 6
+    take a whole product or none of it: they are tried only for block-size
+    sets whose sizes all lie in 17..24 (in a mixed set they would never
+    run)."""
     if v == 3:
         return m <= 8 and n <= 8
     if v == 4:
         return 9 <= m <= 24 and 9 <= n <= 24 and max(m, n) > 16
+    if v in (5, 6):
+        return sizes is not None and all(17 <= x <= 24 for x in sizes)
     return True
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.json")
 
@@ -85,6 +98,7 @@ def tune(sizes=(5, 13, 23), atoms: int = 1500, reps: int = 3, log=None) -> dict:
     ctx = bsmm.Context(0)
     ctx.set_timing(True)
     entries = {}
+    tile = None
     for m in sizes:
         for n in sizes:
             key = (size_class(m), size_class(n))
@@ -93,24 +107,52 @@ def tune(sizes=(5, 13, 23), atoms: int = 1500, reps: int = 3, log=None) -> dict:
             B = bsmm.Matrix.from_host(ctx, b)
             times = {}
             for v in VARIANTS:
-                if not applies(v, m, n):
+                if not applies(v, m, n, sizes):
                     continue
                 ctx.set_gemm_variant(m, n, v)
                 times[v] = time_gemm(bsmm, ctx, A, B, reps)
-            ctx.set_gemm_variant(m, n, 0)
             best = min(times, key=times.get)
             entries[key] = {"m_class": key[0], "n_class": key[1], "m": m, "n": n, "variant": best,
                             "variant_name": VARIANTS[best], "gemm_ms": {VARIANTS[v]: round(t, 4) for v, t in times.items()}}
             if log:
                 log(f"m={m} n={n}: " + ", ".join(f"{VARIANTS[v]} {t:.3f} ms" for v, t in times.items())
                     + f" -> {VARIANTS[best]}")
+            if best in (5, 6) and tile is None:
+                ctx.set_gemm_variant(m, n, best)
+                tile = tune_tile(bsmm, ctx, A, B, m, n, best, reps, log)
+            ctx.set_gemm_variant(m, n, 0)
             A.close()
             B.close()
             torch.cuda.synchronize()
     ctx.close()
-    return {"device": torch.cuda.get_device_name(0), "sizes": sorted(set(sizes)),
-            "workload": f"dft-like {atoms} atoms, block sizes {list(sizes)}",
-            "classes": sorted(entries.values(), key=lambda e: (e["m_class"], e["n_class"]))}
+    out = {"device": torch.cuda.get_device_name(0), "sizes": sorted(set(sizes)),
+           "workload": f"dft-like {atoms} atoms, block sizes {list(sizes)}",
+           "classes": sorted(entries.values(), key=lambda e: (e["m_class"], e["n_class"]))}
+    if tile is not None:
+        out["tile"] = tile
+    return out
+
+
+def tune_tile(bsmm, ctx, A, B, m: int, n: int, variant: int, reps: int, log=None) -> dict:
+    """Schedule of the tile path for the class (m, n) with the chosen tile
+    variant: the result-block tile shape (the general kernel takes 2x2 to
+    4x4; the uniform-size kernel 2x2 only) and the number of consecutive
+    tiles handed to one XCD at a time."""
+    shapes = TILE_SHAPES if variant == 6 else ((2, 2),)
+    times = {}
+    for sh in shapes:
+        ctx.set_tile_shape(*sh)
+        for ch in XCD_CHUNKS:
+            ctx.set_tile_schedule(False, ch)
+            times[(sh, ch)] = time_gemm(bsmm, ctx, A, B, reps)
+    ctx.set_tile_shape(2, 2)
+    ctx.set_tile_schedule(False, 0)
+    (sh, ch) = min(times, key=times.get)
+    if log:
+        log(f"tile schedule m={m} n={n}: " + ", ".join(f"{s[0]}x{s[1]}/{c} {t:.3f} ms" for (s, c), t in times.items())
+            + f" -> {sh[0]}x{sh[1]}, chunk {ch}")
+    return {"m": m, "n": n, "variant": variant, "shape": list(sh), "xcd_chunk": ch,
+            "gemm_ms": {f"{s[0]}x{s[1]}/{c}": round(t, 4) for (s, c), t in times.items()}}
 
 
 def pick(doc: dict, sizes) -> dict | None:
@@ -136,7 +178,26 @@ def apply(ctx, table, sizes=None) -> int:
     for e in table["classes"]:
         edge = lambda cls: 8 * cls + 1   # noqa: E731 - any edge of the class
         ctx.set_gemm_variant(edge(e["m_class"]), edge(e["n_class"]), int(e["variant"]))
+    t = table.get("tile")
+    ctx.set_tile_shape(*(t["shape"] if t else (2, 2)))
+    ctx.set_tile_schedule(False, int(t["xcd_chunk"]) if t else 0)
     return len(table["classes"])
+
+
+def describe(table, sizes=None) -> str:
+    """The tuned choices of the table of `sizes` in one line (for reports)."""
+    if isinstance(table, (str, os.PathLike)):
+        with open(table) as f:
+            table = json.load(f)
+    if "tables" in table:
+        table = pick(table, sizes or ())
+        if table is None:
+            return "default (no tuned table for these block sizes)"
+    parts = [f"{e['m']}x{e['n']}: {e['variant_name']}" for e in table["classes"]]
+    t = table.get("tile")
+    if t:
+        parts.append(f"tile path {t['shape'][0]}x{t['shape'][1]} tiles, {t['xcd_chunk']} tiles per XCD chunk")
+    return "; ".join(parts)
 
 
 def main(argv=None):

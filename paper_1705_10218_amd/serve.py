@@ -94,11 +94,13 @@ class Lane:
     """A library context with its own stream; requests planned on it run in
     its batches."""
 
-    def __init__(self, device: int):
+    def __init__(self, device: int, configure=None):
         from . import bsmm
         torch = bsmm._torch()
         self.stream = torch.cuda.Stream(device)
         self.ctx = bsmm.Context(device, stream=self.stream)
+        if configure is not None:   # e.g. tuned kernel variants
+            configure(self.ctx)
         self.planned = []
         self.inflight: _Batch | None = None
 
@@ -112,8 +114,9 @@ class Server:
     library; tests substitute them."""
 
     def __init__(self, device: int, budget_bytes: int, max_batch: int = 64, keep_results: bool = False,
-                 max_wait_s: float = 0.002, poll_s: float = 0.0002):
+                 max_wait_s: float = 0.002, poll_s: float = 0.0002, configure=None):
         self.device = device
+        self.configure = configure   # called with each lane's context
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
         self.keep = keep_results
@@ -126,7 +129,7 @@ class Server:
 
     # ------------------------------------------------------------ engine
     def _new_lane(self):
-        return Lane(self.device)
+        return Lane(self.device, self.configure)
 
     def _plan(self, lane, r) -> int:
         """Upload and plan r on the lane; returns its planned device bytes."""

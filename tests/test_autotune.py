@@ -22,15 +22,46 @@ def test_apply_sets_every_class(tmp_path):
         def set_gemm_variant(self, m, n, v):
             calls.append((autotune.size_class(m), autotune.size_class(n), v))
 
+        def set_tile_shape(self, ti, tj):
+            calls.append(("shape", ti, tj))
+
+        def set_tile_schedule(self, persistent, chunk):
+            calls.append(("chunk", persistent, chunk))
+
     t1 = {"sizes": [5, 23], "classes": [{"m_class": 0, "n_class": 2, "variant": 1},
                                         {"m_class": 2, "n_class": 2, "variant": 2}]}
     t2 = {"sizes": [13], "classes": [{"m_class": 1, "n_class": 1, "variant": 2}]}
     p = tmp_path / "t.json"
     p.write_text(json.dumps({"tables": [t2, t1]}))
     assert autotune.apply(FakeCtx(), str(p), sizes=(23, 5)) == 2
-    assert calls == [(0, 2, 1), (2, 2, 2)]
+    assert calls == [(0, 2, 1), (2, 2, 2), ("shape", 2, 2), ("chunk", False, 0)]   # no tile entry: defaults
+    calls.clear()
     assert autotune.apply(FakeCtx(), str(p), sizes=(5, 13)) == 0   # no table for that set
-    assert autotune.apply(FakeCtx(), t2) == 1 and calls[-1] == (1, 1, 2)
+    assert calls == []
+    assert autotune.apply(FakeCtx(), t2) == 1 and calls[0] == (1, 1, 2)
+
+
+def test_apply_sets_the_tile_schedule():
+    calls = []
+
+    class FakeCtx:
+        def set_gemm_variant(self, m, n, v):
+            calls.append(("variant", m, n, v))
+
+        def set_tile_shape(self, ti, tj):
+            calls.append(("shape", ti, tj))
+
+        def set_tile_schedule(self, persistent, chunk):
+            calls.append(("chunk", persistent, chunk))
+
+    t = {"sizes": [23], "classes": [{"m_class": 2, "n_class": 2, "m": 23, "n": 23, "variant": 5,
+                                     "variant_name": "tile_path_lds_staged"}],
+         "tile": {"m": 23, "n": 23, "variant": 5, "shape": [2, 2], "xcd_chunk": 2048}}
+    assert autotune.apply(FakeCtx(), t) == 1
+    assert calls == [("variant", 17, 17, 5), ("shape", 2, 2), ("chunk", False, 2048)]
+    d = autotune.describe({"tables": [t]}, (23,))
+    assert "23x23: tile_path_lds_staged" in d and "2048 tiles per XCD chunk" in d
+    assert autotune.describe({"tables": [t]}, (5,)).startswith("default")
 
 
 def test_class_workload_shapes():
@@ -45,6 +76,9 @@ def test_variant_edges():
     assert autotune.applies(4, 13, 23) and autotune.applies(4, 24, 9) and autotune.applies(4, 17, 17)
     assert not autotune.applies(4, 16, 16) and not autotune.applies(4, 5, 23) and not autotune.applies(4, 25, 23)
     assert all(autotune.applies(v, m, n) for v in (1, 2) for m in (1, 32) for n in (1, 32))
+    # the tile-path variants only for sets whose sizes all lie in 17..24
+    assert autotune.applies(5, 23, 23, (23,)) and autotune.applies(6, 17, 24, (17, 24))
+    assert not autotune.applies(5, 23, 23, (5, 13, 23)) and not autotune.applies(6, 23, 23)
 
 
 @pytest.mark.gpu
