@@ -832,10 +832,14 @@ __device__ __forceinline__ void tile_uni(const TileP &P, int64_t w, double (&slo
     acc4[x][4] = __builtin_amdgcn_mfma_f64_4x4x4f64(f.ae[r], bes[c], acc4[x][4], 0, 0, 0);
   };
   auto products = [&](uint32_t mine_v) {
-    const uint32_t mine = (uint32_t)__builtin_amdgcn_readfirstlane((int)mine_v);   // uniform: scalar branches
+    uint32_t mine = (uint32_t)__builtin_amdgcn_readfirstlane((int)mine_v);   // uniform: scalar branches
     Frag fc = frag(0);
 #pragma unroll
     for (int ks = 0; ks < U::NKS; ks++) {
+      // the product mask stays a scalar register tested per slice, so the
+      // branches below are scalar-compare branches, not lane-mask values
+      // carried across the slices
+      asm volatile("" : "+s"(mine));
       Frag fn;
       if (ks + 1 < U::NKS) fn = frag(ks + 1);
       double aer[2], ber[2], bes[2];
