@@ -1110,12 +1110,14 @@ static bool same_pattern(bsmm_ctx ctx, const bsmm_mat_s *x, const bsmm_mat_s *y)
 }
 
 // Whether every on-the-fly filter decision of plan P stays the same when its
-// operands take the values of A and B (same patterns as the plan's).  Each
-// norm product of the plan moves by a factor within [fa_lo fb_lo, fa_hi fb_hi]
-// (the ranges of the per-block norm ratios now / then); the decisions hold
-// when the smallest kept product stays >= eps and the largest dropped one
-// stays < eps under those factors, with a relative slack of 1e-12 for the
-// rounding of the products.
+// operands take the values of A and B (same patterns as the plan's).  First
+// a bound: each norm product of the plan moves by a factor within
+// [fa_lo fb_lo, fa_hi fb_hi] (the ranges of the per-block norm ratios now /
+// then); the decisions hold when the smallest kept product stays >= eps and
+// the largest dropped one stays < eps under those factors, with a relative
+// slack of 1e-12 for the rounding of the products.  When the bound is
+// inconclusive, every candidate's decision is recomputed under both sets of
+// norms and compared exactly.
 static bool filter_decisions_hold(Plan &P, const bsmm_mat_s *A, const bsmm_mat_s *B) {
   if (!P.filt) return true;
   bsmm_ctx ctx = P.ctx;
@@ -1137,7 +1139,15 @@ static bool filter_decisions_hold(Plan &P, const bsmm_mat_s *A, const bsmm_mat_s
   const double eps = P.eps, slack = 1e-12;
   const bool kept_ok = kept_min == INFINITY || kept_min * fa_lo * fb_lo >= eps * (1.0 + slack);
   const bool drop_ok = drop_max == 0.0 || drop_max * fa_hi * fb_hi <= eps * (1.0 - slack);
-  return kept_ok && drop_ok && fa_hi < INFINITY && fb_hi < INFINITY;
+  if (kept_ok && drop_ok && fa_hi < INFINITY && fb_hi < INFINITY) return true;
+  // the bound is inconclusive: decide every candidate product under both
+  // sets of norms and compare (a pass over the candidates, no stacks)
+  DBuf<int32_t> flag(al, 1);
+  HIPCHECK(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+  decisions_differ(P.oa, P.ob, P.na_plan.p, P.nb_plan.p, na.p, nb.p, eps, flag.p, s);
+  HIPCHECK(hipMemcpyAsync(ctx->pinned, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  return *reinterpret_cast<int32_t *>(ctx->pinned) == 0;
 }
 
 // One multiplication of a loop whose operand patterns settle (the sign

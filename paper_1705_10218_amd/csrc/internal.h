@@ -275,6 +275,12 @@ struct StackArgs {
 // the block norm (0 when nb is null).
 void product_records(const OpIndex &b, const double *nb, const int64_t *b_poff, int4 *out, hipStream_t s);
 
+// Sets *flag (preset to 0) when some candidate product of op(A) x op(B) is
+// kept under one set of block norms and dropped under the other (norms
+// indexed by stored block id).
+void decisions_differ(const OpIndex &a, const OpIndex &b, const double *na0, const double *nb0, const double *na1,
+                      const double *nb1, double eps, int32_t *flag, hipStream_t s);
+
 // a4: stack entries, grouped by C block, ascending k inside a block.  `run`
 // (nnzb of C, zeroed) serves rows too wide for the LDS cursors.
 void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s);

@@ -823,7 +823,43 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
   }
 }
 
+// Whether the on-the-fly filter decision of any candidate product changes
+// between two sets of block norms (na0, nb0: those a plan was built with;
+// na1, nb1: the current ones): for every row i of op(A), entry (i, k) and
+// entry (k, j) of op(B), kept iff !(||A_ik|| ||B_kj|| < eps) under each
+// set, the same expression as the stack generator's.  One workgroup per
+// row; a difference sets *flag, after which remaining rows return at once.
+__global__ __launch_bounds__(256) void k_decisions_differ(OpView A, OpView B, int32_t nbr, const double *na0,
+                                                          const double *nb0, const double *na1, const double *nb1,
+                                                          double eps, int32_t *flag) {
+  const int32_t i = blockIdx.x;
+  if (i >= nbr || __atomic_load_n(flag, __ATOMIC_RELAXED)) return;   // uniform over the workgroup
+  for (int64_t pa = A.rp[i]; pa < A.rp[i + 1]; pa++) {
+    const int32_t k = A.ci[pa];
+    const int32_t a = A.blk ? A.blk[pa] : (int32_t)pa;
+    const double x0 = na0[a], x1 = na1[a];
+    int diff = 0;
+    for (int64_t q = B.rp[k] + threadIdx.x; q < B.rp[k + 1]; q += blockDim.x) {
+      const int32_t b = B.blk ? B.blk[q] : (int32_t)q;
+      const bool keep0 = !(x0 * nb0[b] < eps), keep1 = !(x1 * nb1[b] < eps);
+      diff |= keep0 != keep1;
+    }
+    if (__syncthreads_or(diff)) {
+      if (threadIdx.x == 0) atomicOr(flag, 1);
+      return;
+    }
+  }
+}
+
 }  // namespace
+
+void decisions_differ(const OpIndex &a, const OpIndex &b, const double *na0, const double *nb0, const double *na1,
+                      const double *nb1, double eps, int32_t *flag, hipStream_t s) {
+  if (a.nbr == 0) return;
+  hipLaunchKernelGGL(k_decisions_differ, dim3((unsigned)a.nbr), dim3(256), 0, s, view(a), view(b), a.nbr, na0, nb0,
+                     na1, nb1, eps, flag);
+  HIPCHECK(hipGetLastError());
+}
 
 size_t symbolic_bits_words(int32_t nbr, int32_t nbc) {
   const int64_t words_total = ((int64_t)nbc + 31) >> 5;
