@@ -272,6 +272,16 @@ bsmm_status bsmm_plan_create(bsmm_ctx ctx, char transa, char transb, double alph
  * (packed operand copies, result-block norms and, with a post-filter, a copy
  * of the result values for its compaction).  Any output may be NULL. */
 bsmm_status bsmm_plan_sizes(bsmm_plan plan, int64_t *c_nnzb, int64_t *c_n_values, size_t *workspace_bytes);
+/* Whether the plan's on-the-fly filter decisions (taken on the values A and
+ * B had at bsmm_plan_create) are still those a new plan would take on their
+ * current values (Section 1: the filter is part of each multiplication):
+ * *holds = 1 when every candidate product is kept or dropped as before, so
+ * bsmm_plan_execute gives bitwise what a fresh bsmm_multiply would; 0
+ * otherwise.  First a bound from the smallest kept and largest dropped norm
+ * product and the range of block-norm ratios now / then; if inconclusive,
+ * every candidate is decided again and compared.  Always 1 without a filter
+ * (filter_eps 0).  Synchronises the context's stream. */
+bsmm_status bsmm_plan_filter_holds(bsmm_plan plan, int32_t *holds);
 /* The numeric part and the post-filter in caller-owned device buffers (e.g.
  * torch tensors): c_values_dev has room for c_n_values doubles (8-byte
  * aligned), workspace_dev for workspace_bytes (256-byte aligned); neither

@@ -36,7 +36,7 @@ SYMBOLS = (
     "bsmm_mat_destroy", "bsmm_block_norms", "bsmm_multiply", "bsmm_filter", "bsmm_sign_newton_schulz",
     "bsmm_plan_create", "bsmm_plan_execute", "bsmm_plan_capture", "bsmm_plan_result", "bsmm_plan_destroy",
     "bsmm_plans_execute", "bsmm_filter_noalloc", "bsmm_ctx_set_tile_shape", "bsmm_plan_sizes",
-    "bsmm_plan_execute_into", "bsmm_ctx_set_tile_schedule",
+    "bsmm_plan_execute_into", "bsmm_ctx_set_tile_schedule", "bsmm_plan_filter_holds",
 )
 
 
@@ -120,6 +120,7 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(MultiplyInfo)]
         L.bsmm_plan_execute.argtypes = [_vp]
         L.bsmm_plan_sizes.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_size_t)]
+        L.bsmm_plan_filter_holds.argtypes = [_vp, ctypes.POINTER(_i32)]
         L.bsmm_plan_execute_into.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_vp)]
         L.bsmm_plan_capture.argtypes = [_vp]
         L.bsmm_plan_result.argtypes = [_vp, ctypes.POINTER(_vp)]
@@ -362,6 +363,13 @@ class Plan:
         nb, nv, ws = _i64(), _i64(), ctypes.c_size_t()
         _check(lib().bsmm_plan_sizes(self.handle, ctypes.byref(nb), ctypes.byref(nv), ctypes.byref(ws)))
         return nb.value, nv.value, ws.value
+
+    def filter_holds(self) -> bool:
+        """bsmm_plan_filter_holds: the plan's filter decisions equal those a
+        new plan would take on the operands' current values."""
+        h = _i32()
+        _check(lib().bsmm_plan_filter_holds(self.handle, ctypes.byref(h)))
+        return bool(h.value)
 
     def execute_into(self, c_values, workspace) -> Matrix:
         """bsmm_plan_execute_into: numeric part and post-filter in caller

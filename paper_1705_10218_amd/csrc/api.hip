@@ -1707,6 +1707,14 @@ bsmm_status bsmm_plan_sizes(bsmm_plan plan, int64_t *c_nnzb, int64_t *c_n_values
   ABI_END
 }
 
+bsmm_status bsmm_plan_filter_holds(bsmm_plan plan, int32_t *holds) {
+  ABI_BEGIN
+  if (!plan || !holds) fail(BSMM_ERR_INVALID_ARG, "NULL argument");
+  Plan &P = plan->plan;
+  *holds = filter_decisions_hold(P, P.A, P.B) ? 1 : 0;
+  ABI_END
+}
+
 bsmm_status bsmm_plan_execute_into(bsmm_plan plan, double *c_values_dev, void *workspace_dev, bsmm_mat *c_out) {
   ABI_BEGIN
   if (!plan || !c_out) fail(BSMM_ERR_INVALID_ARG, "NULL argument");

@@ -131,3 +131,62 @@ def test_capture_needs_a_stream(B):
     A.close()
     Bm.close()
     ctx.close()
+
+
+def test_plan_filter_holds(B, torch_mod):
+    """bsmm_plan_filter_holds against fresh multiplies: unchanged values;
+    blocks scaled by 1e3 and 1e-3 where every product stays on its side of
+    the threshold (the norm-ratio bound is then inconclusive and every
+    candidate is decided again: the decisions hold, and re-executing the
+    plan gives a fresh multiply's bits); and a block scaled so that one of
+    its products crosses the threshold (the decisions do not hold)."""
+    from _util import random_bcsr
+    torch = torch_mod
+    rng = np.random.default_rng(730)
+    a = random_bcsr(rng, 30, 26, p=0.3, max_bs=6)
+    b = random_bcsr(rng, 26, 28, a.cbs, None, p=0.3, max_bs=6)
+    off, rows = a.block_offsets(), a.block_rows()
+    for p in range(a.nnzb):
+        a.values[off[p]:off[p + 1]] *= 10.0 ** (-(rows[p] % 7))
+    na, nb = oracle.block_norms(a), oracle.block_norms(b)
+    # products per A block (stored id) through its column k
+    a_col, b_rows = a.col_idx, b.block_rows()
+    prod = {p: na[p] * nb[b_rows == a_col[p]] for p in range(a.nnzb)}
+    allp = np.sort(np.concatenate([v for v in prod.values() if v.size]))
+    eps = float(0.5 * (allp[len(allp) // 2] + allp[len(allp) // 2 + 1]))
+    assert np.min(np.abs(allp - eps)) > 1e-6 * eps
+    hi = [p for p, v in prod.items() if v.size and v.min() >= eps]     # every product kept: stays kept when scaled up
+    lo = [p for p, v in prod.items() if v.size and v.max() < eps]      # every product dropped: stays dropped when scaled down
+    near = [p for p, v in prod.items() if v.size and np.any((v >= eps) & (v < 1.5 * eps))]
+    assert hi and lo and near, (len(hi), len(lo), len(near))
+    ctx = B.Context(0)
+    A, Bm = B.Matrix.from_host(ctx, a), B.Matrix.from_host(ctx, b)
+    plan = B.Plan(ctx, "N", "N", 1.0, A, Bm, filter_eps=eps)
+    assert plan.filter_holds()   # values as planned
+
+    def block(p):
+        return A._values[int(off[p]):int(off[p + 1])]
+
+    # kept products scaled up and dropped ones scaled down: same decisions
+    block(hi[0]).mul_(1e3)
+    block(lo[0]).mul_(1e-3)
+    torch.cuda.synchronize()
+    assert plan.filter_holds()
+    plan.execute()
+    got = plan.result()
+    want, winfo = B.multiply(ctx, "N", "N", 1.0, A, Bm, filter_eps=eps)
+    assert _same(got.to_host(), want.to_host())
+    assert winfo.n_products == plan.info.n_products
+    got.close()
+    want.close()
+    # a product just above the threshold falls below it
+    block(near[0]).mul_(0.5)
+    torch.cuda.synchronize()
+    assert not plan.filter_holds()
+    want, winfo = B.multiply(ctx, "N", "N", 1.0, A, Bm, filter_eps=eps)
+    assert winfo.n_products < plan.info.n_products
+    want.close()
+    plan.close()
+    A.close()
+    Bm.close()
+    ctx.close()
