@@ -356,9 +356,25 @@ def serving_leg(bsmm, n: int, configure=None) -> dict:
     srv = serve.Server(0, budget, max_batch=64, configure=configure)
     sat = serve.summary(srv.run(requests(np.zeros(n))))
     rate = 0.7 * sat["requests_per_s"]
-    srv2 = serve.Server(0, budget, max_batch=64, configure=configure)
+    srv2 = serve.Server(0, budget, max_batch=64, configure=configure, keep_results=True)
     done = srv2.run(requests(serve.poisson_arrivals(n, rate, np.random.default_rng(5))))
     st = serve.summary(done)
+    # a seeded subset of the requests (among those under 2e10 useful flops, so
+    # that the oracle takes seconds) against the oracle
+    import oracle
+    small = sorted(r.rid for r in done if r.flops < 2e10)
+    pick = np.random.default_rng(7).choice(small, size=min(3, len(small)), replace=False) if small else []
+    checks = []
+    byid = {r.rid: r for r in done}
+    for rid in sorted(int(x) for x in pick):
+        r = byid[rid]
+        ref = oracle.multiply("N", "N", 1.0, r.a, r.b, eps=r.eps, nthreads=len(os.sched_getaffinity(0)))
+        same = bool(np.array_equal(ref.row_ptr, r.result.row_ptr) and np.array_equal(ref.col_idx, r.result.col_idx))
+        err = float(np.linalg.norm(r.result.values - ref.values) / max(np.linalg.norm(ref.values), 1e-300)) \
+            if same else None
+        checks.append({"request": rid, "atoms": int(r.a.nbr), "pattern_equal": same, "rel_fro_err": err})
+    for r in done:
+        r.result = None
     _log(f"serving: saturation {sat['requests_per_s']:.1f} req/s, at 0.7x: p50 {st['latency_p50_ms']:.1f} ms "
          f"p99 {st['latency_p99_ms']:.1f} ms, {len(srv2.batches)} batches, {srv2.overlapping_batches()} overlapping")
     full = config5_estimate()
@@ -373,6 +389,7 @@ def serving_leg(bsmm, n: int, configure=None) -> dict:
             "throughput_gflops": round(st["throughput_gflops"], 2), "batches": len(srv2.batches),
             "overlapping_batches": srv2.overlapping_batches(),
             "mean_batch": round(float(np.mean(srv2.batches)), 2), "useful_flops": st["useful_flops"],
+            "sample_parity": checks,
             "full_configuration": dict(full, run=False,
                                        reason="512 requests up to 8,000 atoms need about "
                                               f"{full['input_bytes_estimate'] / 1e12:.1f} TB of generated input and "
@@ -514,7 +531,7 @@ def main():
         torch.cuda.empty_cache()
         batching = {}
         for name, sizes in (("blocks_23", (23,)), ("blocks_5_13_23", (5, 13, 23))):
-            batching[name] = panel_leg(bsmm, ctx, sizes, (0, BATCH_PANEL), 2, threads, tune_for(sizes))
+            batching[name] = panel_leg(bsmm, ctx, sizes, (0, BATCH_PANEL), 5, threads, tune_for(sizes))
             torch.cuda.empty_cache()
         out["batching"] = batching
         A = bsmm.Matrix.from_host(ctx, a)

@@ -25,9 +25,10 @@ on two lanes, each a library context with a stream of its own:
 Every result is bitwise the one the request gets alone: a result block is
 computed by one wavefront in a fixed order whatever else shares the launch.
 
-Latency of a request = the time its result is available on the host minus
-its arrival time; it includes waiting for admission, the host-to-device
-upload of A and B, planning, execution and the result's read-back.
+Latency of a request = the time its result is ready on the device (after
+the post-filter) minus its arrival time; it includes waiting for admission,
+the host-to-device upload of A and B, planning and execution.  With
+keep_results the result is then also read back to the host (not counted).
 """
 from __future__ import annotations
 
@@ -158,6 +159,7 @@ class Server:
     def _complete(self, lane, r):
         A, B, plan = r._dev
         C = plan.result()              # post-filter; the batch is done, so this waits for nothing else
+        r.done = self._clock()         # the result is ready on the device
         if self.keep:
             r.result = C.to_host()
         C.close()
@@ -183,6 +185,7 @@ class Server:
                 raise ValueError(f"request {r.rid}: its operands alone exceed the budget {self.budget}")
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0   # noqa: E731
+        self._clock = clock
         done, used, plan_lane = [], 0, 0
         while pending or any(ln.planned or ln.inflight for ln in lanes):
             progressed = False
@@ -192,7 +195,8 @@ class Server:
                 if b is not None and self._finished(ln, b.event):
                     for r in b.reqs:
                         self._complete(ln, r)
-                        r.done = clock()
+                        if math.isnan(r.done):
+                            r.done = clock()
                         used -= r.nbytes
                         done.append(r)
                     self.batch_times[b.index] = (b.launched, clock())
