@@ -356,17 +356,19 @@ def serving_leg(bsmm, n: int, configure=None) -> dict:
     srv = serve.Server(0, budget, max_batch=64, configure=configure)
     sat = serve.summary(srv.run(requests(np.zeros(n))))
     rate = 0.7 * sat["requests_per_s"]
-    srv2 = serve.Server(0, budget, max_batch=64, configure=configure, keep_results=True)
+    # a seeded three of the requests (among those of at most 500 atoms, so
+    # that the oracle takes seconds) are read back and checked against the
+    # oracle; only those are read back inside the loop
+    small = [i for i, (a, _, _) in enumerate(gen) if a.nbr <= 500]
+    pick = sorted(int(x) for x in np.random.default_rng(7).choice(small, size=min(3, len(small)), replace=False)) \
+        if small else []
+    srv2 = serve.Server(0, budget, max_batch=64, configure=configure, keep_results=pick)
     done = srv2.run(requests(serve.poisson_arrivals(n, rate, np.random.default_rng(5))))
     st = serve.summary(done)
-    # a seeded subset of the requests (among those under 2e10 useful flops, so
-    # that the oracle takes seconds) against the oracle
     import oracle
-    small = sorted(r.rid for r in done if r.flops < 2e10)
-    pick = np.random.default_rng(7).choice(small, size=min(3, len(small)), replace=False) if small else []
     checks = []
     byid = {r.rid: r for r in done}
-    for rid in sorted(int(x) for x in pick):
+    for rid in pick:
         r = byid[rid]
         ref = oracle.multiply("N", "N", 1.0, r.a, r.b, eps=r.eps, nthreads=len(os.sched_getaffinity(0)))
         same = bool(np.array_equal(ref.row_ptr, r.result.row_ptr) and np.array_equal(ref.col_idx, r.result.col_idx))

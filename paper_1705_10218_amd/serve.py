@@ -114,13 +114,13 @@ class Server:
     _launch, _finished, _complete) are the only places that touch the
     library; tests substitute them."""
 
-    def __init__(self, device: int, budget_bytes: int, max_batch: int = 64, keep_results: bool = False,
+    def __init__(self, device: int, budget_bytes: int, max_batch: int = 64, keep_results=False,
                  max_wait_s: float = 0.002, poll_s: float = 0.0002, configure=None):
         self.device = device
         self.configure = configure   # called with each lane's context
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
-        self.keep = keep_results
+        self.keep = keep_results if keep_results is True else set(keep_results or ())   # True, or rids to keep
         self.max_wait = float(max_wait_s)
         self.poll = float(poll_s)
         self.batches = []          # requests per batch
@@ -160,7 +160,7 @@ class Server:
         A, B, plan = r._dev
         C = plan.result()              # post-filter; the batch is done, so this waits for nothing else
         r.done = self._clock()         # the result is ready on the device
-        if self.keep:
+        if self.keep is True or (self.keep and r.rid in self.keep):
             r.result = C.to_host()
         C.close()
         plan.close()
