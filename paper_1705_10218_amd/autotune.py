@@ -133,6 +133,21 @@ def tune(sizes=(5, 13, 23), atoms: int = 1500, reps: int = 3, log=None) -> dict:
     return out
 
 
+DEFAULT_SCHEDULE = ((2, 2), 8192)
+MARGIN = 0.02   # a schedule replaces the default only when this much faster
+
+
+def pick_schedule(times: dict):
+    """The fastest (shape, chunk), unless the default is within MARGIN of it:
+    timings on the small tuning workload differ by about 1-2 % between runs,
+    and larger workloads need not follow such small differences."""
+    best = min(times, key=times.get)
+    base = times.get(DEFAULT_SCHEDULE)
+    if base is not None and times[best] > (1.0 - MARGIN) * base:
+        return DEFAULT_SCHEDULE
+    return best
+
+
 def tune_tile(bsmm, ctx, A, B, m: int, n: int, variant: int, reps: int, log=None) -> dict:
     """Schedule of the tile path for the class (m, n) with the chosen tile
     variant: the result-block tile shape (the general kernel takes 2x2 to
@@ -147,7 +162,7 @@ def tune_tile(bsmm, ctx, A, B, m: int, n: int, variant: int, reps: int, log=None
             times[(sh, ch)] = time_gemm(bsmm, ctx, A, B, reps)
     ctx.set_tile_shape(2, 2)
     ctx.set_tile_schedule(False, 0)
-    (sh, ch) = min(times, key=times.get)
+    (sh, ch) = pick_schedule(times)
     if log:
         log(f"tile schedule m={m} n={n}: " + ", ".join(f"{s[0]}x{s[1]}/{c} {t:.3f} ms" for (s, c), t in times.items())
             + f" -> {sh[0]}x{sh[1]}, chunk {ch}")

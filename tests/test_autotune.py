@@ -108,3 +108,10 @@ def test_variants_agree_with_oracle():
     A.close()
     B.close()
     ctx.close()
+
+
+def test_schedule_keeps_the_default_within_the_margin():
+    d = autotune.DEFAULT_SCHEDULE
+    assert autotune.pick_schedule({d: 10.0, ((2, 2), 2048): 9.9}) == d          # 1 % faster: noise
+    assert autotune.pick_schedule({d: 10.0, ((2, 2), 2048): 9.5}) == ((2, 2), 2048)
+    assert autotune.pick_schedule({((2, 4), 2048): 9.0, ((4, 4), 8192): 8.0}) == ((4, 4), 8192)
