@@ -62,6 +62,11 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+# block-GEMM path (bsmm_multiply_info.gemm_path) -> name, and the kernel
+# whose roofline a path reports
+PATH_NAMES = {0: "packed", 1: "walker", 2: "tile", 3: "lowp", 4: "tile_uniform", 5: "packed_per_unit"}
+ROOFLINE_KERNEL = {0: "packed", 2: "tile", 4: "tile_uniform", 5: "packed"}
+
 CSRC = os.path.join(ROOT, "paper_1705_10218_amd", "csrc")
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 # block-GEMM kernels: (source file, counter summaries per workload under profiles/)
@@ -269,11 +274,11 @@ def panel_leg(bsmm, ctx, sizes, rows, steps: int, threads: int, variants: str) -
            "value": round(fl / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
            "gemm_tflops": round(fl / (gemm_ms * 1e-3) / 1e12, 3),
            "gemm_frac_of_fp64_mfma_peak": round(fl / (gemm_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
-           "gemm_path": {0: "packed", 1: "walker", 2: "tile", 3: "lowp", 4: "tile_uniform"}.get(info.gemm_path, "?"),
-           "roofline": (roofline({2: "tile", 4: "tile_uniform"}[info.gemm_path],
+           "gemm_path": PATH_NAMES.get(info.gemm_path, "?"),
+           "roofline": (roofline(ROOFLINE_KERNEL[info.gemm_path],
                                  "panel23" if tuple(sizes) == (23,) else "panel_mixed", fl, gemm_ms,
                                  int(8 * (a.n_values() + b.n_values() + info.c_n_values)))
-                        if info.gemm_path in (2, 4) else None),
+                        if info.gemm_path in ROOFLINE_KERNEL else None),
            "gemm_variants": variants, "generation_s": round(gen_s, 1),
            "sample_parity": parity,
            "oracle": {"rows": int(n_s), "threads": threads, "s": round(oracle_s, 2),
@@ -478,7 +483,7 @@ def main():
     last.close()
     # compulsory HBM bytes of the GEMM launch: A and B values once, C values once
     compulsory = int(8 * (a.n_values() + b.n_values() + infos[-1].c_n_values))
-    path_name = {0: "packed", 2: "tile", 3: "lowp", 4: "tile_uniform"}.get(infos[-1].gemm_path, "packed")
+    path_name = {**ROOFLINE_KERNEL, 3: "lowp"}.get(infos[-1].gemm_path, "packed")
 
     out = {
         "metric": METRIC,

@@ -85,7 +85,10 @@ typedef struct {
   /* block-GEMM path: 0 = packed operand copies (k-pair slabs, one wavefront
      per result block), 1 = 64-bit pointer walker, 2 = tile path (2x2 tiles
      of result blocks, operands staged in LDS), 3 = FP32 / split packed path,
-     4 = tile path with the uniform-size kernel (every block S x S)          */
+     4 = tile path with the uniform-size kernel (every block S x S),
+     5 = packed operand copies addressed per unit (as 0, the stack entries
+         holding offsets from the start of their op(A) row's and op(B)
+         column's packed blocks: copies of 2 GB and more)                    */
   int32_t gemm_path;
 } bsmm_multiply_info;
 
@@ -126,8 +129,8 @@ bsmm_status bsmm_ctx_set_compute_mode(bsmm_ctx ctx, bsmm_compute_mode mode);
  * The variant in force when a product is planned is the one it runs with.
  * All variants give results within FP64 rounding of each other; the choice
  * only changes speed (an autotuner picks it per size class).  Applies to the
- * packed-operand path (packed copies of op(A) and op(B) below 2 GB each, at
- * most 8 distinct k sizes).
+ * packed-operand path (at most 8 distinct k sizes; copies of 2 GB or more
+ * are addressed per unit, see bsmm_ctx_set_packed_addressing).
  * Errors: BSMM_ERR_INVALID_ARG for edges outside 1..32, another variant,
  * variant 3 with an edge above 8, or variant 4, 5 or 6 outside its edges. */
 bsmm_status bsmm_ctx_set_gemm_variant(bsmm_ctx ctx, int32_t m, int32_t n, int32_t variant);
@@ -149,6 +152,20 @@ bsmm_status bsmm_ctx_set_tile_shape(bsmm_ctx ctx, int32_t ti, int32_t tj);
  * Errors: BSMM_ERR_INVALID_ARG for xcd_chunk outside 0..2^30,
  * BSMM_ERR_UNSUPPORTED for persistent != 0. */
 bsmm_status bsmm_ctx_set_tile_schedule(bsmm_ctx ctx, int32_t persistent, int64_t xcd_chunk);
+/* Addressing of the packed operand copies (FP64, products planned
+ * afterwards).  The packed path reads operand blocks through 32-bit byte
+ * offsets held in the stack entries.  mode 0 (default): offsets from the
+ * start of each copy while both copies stay below 2 GB, else per unit;
+ * mode 1: always per unit.  Per unit, the packed blocks of every row of
+ * op(A) and of every column of op(B) are laid out contiguously (op(B) = B
+ * takes an index transpose of B to find its columns) and an entry's offsets
+ * start at its row's and column's first block, which lifts the 2 GB limit
+ * of the copies (each row or column must pack below 2 GB: its edge times
+ * the sum of the padded contraction extents, times 8 bytes).  Results are
+ * bitwise the same in both modes: the same products are summed in the same
+ * order.
+ * Errors: BSMM_ERR_INVALID_ARG for another mode. */
+bsmm_status bsmm_ctx_set_packed_addressing(bsmm_ctx ctx, int32_t mode);
 /* Bytes of device memory the library currently holds for this context
  * (live buffers plus its cache of freed ones). */
 bsmm_status bsmm_ctx_memory(bsmm_ctx ctx, size_t *held_bytes, size_t *peak_bytes);

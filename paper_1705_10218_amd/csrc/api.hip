@@ -248,6 +248,10 @@ struct Plan {
   bsmm_ctx ctx = nullptr;
   bsmm_mat_s *A = nullptr, *B = nullptr, *C0 = nullptr;
   bool ta = false, tb = false, filt = false, post = false, quads = false, lowp = false, tiles = false;
+  // packed path with per-unit addressing: stack entries hold offsets from
+  // the start of their op(A) row's / op(B) column's packed blocks (a_base,
+  // b_base), so the copies may exceed 2 GB
+  bool units = false;
   int32_t uni = 0;   // block size of the uniform-size tile kernel (0: the general one)
   // one_shot: built, executed once and consumed (bsmm_multiply); packed:
   // plan_build already made the packed operand copies of the current values
@@ -260,7 +264,7 @@ struct Plan {
   int64_t nnzb_c = 0, nval_c = 0, nstack = 0, nprod = 0, kmn_total = 0, ncand = 0;
   int64_t a_pack_n = 0, b_pack_n = 0;
   OpIndex oa, ob;
-  DBuf<int64_t> c_rp, c_off, seg_off, a_poff, b_poff;
+  DBuf<int64_t> c_rp, c_off, seg_off, a_poff, b_poff, a_base, b_base;
   DBuf<int32_t> c_ci, c_row, old_blk, c_list;
   DBuf<BlkDesc> desc;
   DBuf<int2> stack;
@@ -413,13 +417,15 @@ static void plan_build(Plan &P, char transa, char transb) {
   // blocks, read from the stored values): FP64, every edge and contraction
   // extent up to 24, and either every result block edge in 17..24 (its
   // preferred shape, unless another variant is requested for that class) or
-  // operands the packed-operand path cannot take (copies of 2 GB or more, or
-  // more than 8 distinct k sizes), where it replaces the pointer walker
-  // The quad (packed-operand) path needs packed copies below 2 GB (32-bit
-  // byte offsets in the stack entries) and at most 8 distinct k sizes.  A
-  // packed block pads its contraction extent k to a multiple of 2 (FP64) or
-  // 4 (FP32 / split, half the bytes), so it holds at most (k + 1) / k or
-  // (k + 3) / k times the values of the stored block; kmin bounds both.
+  // operands the packed-operand path cannot take (more than 8 distinct k
+  // sizes), where it replaces the pointer walker.
+  // The quad (packed-operand) path takes at most 8 distinct k sizes.  Its
+  // stack entries hold 32-bit byte offsets: from the start of each packed
+  // copy while both copies stay below 2 GB, else (FP64) from the start of
+  // their op(A) row's / op(B) column's packed blocks.  A packed block pads
+  // its contraction extent k to a multiple of 2 (FP64) or 4 (FP32 / split,
+  // half the bytes), so it holds at most (k + 1) / k or (k + 3) / k times the
+  // values of the stored block; kmin bounds both.
   const uint64_t two_gb = 1ull << 31;
   const bool lowp = P.lowp = ctx->mode != BSMM_COMPUTE_FP64;
   const double kmin = ksizes.empty() ? 1.0 : (double)ksizes.front();
@@ -427,6 +433,19 @@ static void plan_build(Plan &P, char transa, char transb) {
   const bool pack_ok = !ksizes.empty() && ksizes.size() <= 8 &&
                        (double)A->n_values * 8.0 * grow + 64.0 < (double)two_gb &&
                        (double)B->n_values * 8.0 * grow + 64.0 < (double)two_gb;
+  // Per-unit addressing (FP64): the packed blocks of every row of op(A) and
+  // every column of op(B) are contiguous and the stack entries hold offsets
+  // from their start, which must stay below the 2 GB buffer range.  A unit
+  // packs at most (its edge) x (sum of the padded k extents) values.
+  bool units_ok = false;
+  if (!lowp && !ksizes.empty() && ksizes.size() <= 8) {
+    double kp = 0.0;
+    for (int32_t v : opa_c) kp += (double)(v + (v & 1));
+    int32_t edge = 1;
+    for (int32_t v : opa_r) edge = std::max(edge, v);
+    for (int32_t v : opb_c) edge = std::max(edge, v);
+    units_ok = 8.0 * kp * (double)edge < (double)0x7FFFFFF0u;
+  }
   bool tiles = false;
   if (!lowp && nbr > 0 && nbc > 0 && !ksizes.empty() && ksizes.back() <= 24 &&
       tile_path_fits(nbc, (int32_t)opa_c.size(), TileShape{ctx->tile_ti, ctx->tile_tj})) {
@@ -440,7 +459,7 @@ static void plan_build(Plan &P, char transa, char transb) {
       big = big && x >= 17;
     }
     const uint8_t v = ctx->gemm_variant[10];   // class of edges 17..24 x 17..24
-    tiles = all24 && ((big && (v == 0 || v == 5 || v == 6)) || !pack_ok);
+    tiles = all24 && ((big && (v == 0 || v == 5 || v == 6)) || !(pack_ok || units_ok));
     // every block of op(A), op(B) and C S x S: the uniform-size kernel for S
     // (2 x 2 tiles), unless variant 6 asks for the general one
     if (tiles && v != 6 && ksizes.size() == 1 && ctx->tile_ti == 2 && ctx->tile_tj == 2 &&
@@ -452,7 +471,8 @@ static void plan_build(Plan &P, char transa, char transb) {
     }
   }
   P.tiles = tiles;
-  const bool quads = P.quads = !tiles && pack_ok;
+  const bool quads = P.quads = !tiles && (pack_ok || units_ok);
+  const bool units = P.units = quads && units_ok && (!pack_ok || ctx->pack_addr == 1);
   // ------------------------------------------------------- a1: norms
   // A one-shot FP64 product on the packed path reads A and B once: the
   // packing kernel computes the block norms as well (after the symbolic
@@ -479,13 +499,22 @@ static void plan_build(Plan &P, char transa, char transb) {
     if (lowp) {   // FP32 k-quad slabs
       pack32_offsets(al, *A, ta, P.a_poff.p, s);
       pack32_offsets(al, *B, !tb, P.b_poff.p, s);
+    } else if (units) {   // FP64 k-pair slabs, unit by unit
+      // units of op(A): its rows (oa); of op(B): its columns, the stored
+      // rows of B when op(B) = B^T, else the rows of B's transposed index
+      P.a_base = DBuf<int64_t>(al, (size_t)std::max<int32_t>(nbr, 1));
+      P.b_base = DBuf<int64_t>(al, (size_t)std::max<int32_t>(nbc, 1));
+      pack_offsets_units(al, *A, ta, oa, P.a_poff.p, P.a_base.p, s);
+      OpIndex bu;
+      make_op(ctx, B, !tb, bu);
+      pack_offsets_units(al, *B, !tb, bu, P.b_poff.p, P.b_base.p, s);
     } else {      // FP64 k-pair slabs
       pack_offsets(al, *A, ta, P.a_poff.p, s);
       pack_offsets(al, *B, !tb, P.b_poff.p, s);
     }
   }
   DBuf<int4> bent(al, (size_t)std::max<int64_t>(ob.nnzb, 1));
-  if (!fuse) product_records(ob, filt ? nb.p : nullptr, quads ? P.b_poff.p : nullptr, bent.p, s);
+  if (!fuse) product_records(ob, filt ? nb.p : nullptr, quads ? P.b_poff.p : nullptr, P.b_base.p, bent.p, s);
   // ------------------------------------------------------- a2: symbolic
   SymArgs sym;
   sym.a = &oa;
@@ -548,7 +577,7 @@ static void plan_build(Plan &P, char transa, char transb) {
         P.b_pack = DBuf<double>(al, (size_t)std::max<int64_t>(P.b_pack_n, 2));
         pack_values(*A, ta, P.a_poff.p, P.a_pack.p, *B, !tb, P.b_poff.p, P.b_pack.p, s, na.p, nb.p);
         P.packed = true;
-        product_records(ob, nb.p, P.b_poff.p, bent.p, s);
+        product_records(ob, nb.p, P.b_poff.p, P.b_base.p, bent.p, s);
       }
       nnzb_c = ctx->pinned[0];
       max_row = (int32_t)ctx->pinned[7];
@@ -696,6 +725,7 @@ static void plan_build(Plan &P, char transa, char transb) {
     sa.encode = quads;
     sa.kofs = kofs.p;
     sa.a_poff = P.a_poff.p;
+    sa.a_base = P.a_base.p;
     sa.bent = bent.p;
     sa.ord = sym.ord;
     sa.diag8 = diag8;
@@ -751,10 +781,13 @@ static void plan_build(Plan &P, char transa, char transb) {
   // work-item descriptors of the quad path
   if (quads && nnzb_c > 0) {
     P.desc = DBuf<BlkDesc>(al, nc1);
+    const DescBases bases{P.a_base.p, P.b_base.p};
     if (wl_pos.p)   // C blocks read in storage order, records written at their places
-      build_desc_by_block(nnzb_c, wl_pos.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, P.desc.p, s);
+      build_desc_by_block(nnzb_c, wl_pos.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, bases,
+                          P.desc.p, s);
     else
-      build_desc(nnzb_c, P.c_list.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, P.desc.p, s);
+      build_desc(nnzb_c, P.c_list.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, bases, P.desc.p,
+                 s);
   }
   if (filt && !P.one_shot) {
     P.na_plan = std::move(na);
@@ -956,7 +989,9 @@ static bsmm_mat_s *plan_finish(Plan &P, bool consume) {
   return R;
 }
 
-static int32_t gemm_path(const Plan &P) { return P.tiles ? (P.uni ? 4 : 2) : P.lowp ? 3 : P.quads ? 0 : 1; }
+static int32_t gemm_path(const Plan &P) {
+  return P.tiles ? (P.uni ? 4 : 2) : P.lowp ? 3 : P.quads ? (P.units ? 5 : 0) : 1;
+}
 
 // Post-filter and the result matrix of an execution into caller buffers:
 // the result's index belongs to the library, its values are the caller's
@@ -1454,6 +1489,14 @@ bsmm_status bsmm_ctx_set_tile_schedule(bsmm_ctx ctx, int32_t persistent, int64_t
   if (xcd_chunk < 0 || xcd_chunk > (1ll << 30)) fail(BSMM_ERR_INVALID_ARG, "xcd_chunk must be in 0..2^30");
   if (persistent != 0) fail(BSMM_ERR_UNSUPPORTED, "the persistent tile launch is disabled");
   ctx->tile_chunk = xcd_chunk;
+  ABI_END
+}
+
+bsmm_status bsmm_ctx_set_packed_addressing(bsmm_ctx ctx, int32_t mode) {
+  ABI_BEGIN
+  if (!ctx) fail(BSMM_ERR_INVALID_ARG, "ctx is NULL");
+  if (mode != 0 && mode != 1) fail(BSMM_ERR_INVALID_ARG, "addressing mode must be 0 (automatic) or 1 (per unit)");
+  ctx->pack_addr = mode;
   ABI_END
 }
 

@@ -54,7 +54,7 @@ struct GemmP {
   double *c_val;
   double *c_norm;
   double alpha, beta;
-  uint32_t a_bytes, b_bytes;   // buffer extents (BUF path)
+  uint64_t a_len, b_len;       // bytes of the packed copies (BUF path)
   const double *zeros;         // zero page (pointer path)
   uint8_t variant[16];         // kernel variant per (m, n) size class (BUF path)
 };
@@ -244,8 +244,8 @@ __device__ __forceinline__ void gemm_block_16(const GemmP &P, int32_t c, ParamLd
   const int i16 = lane & 15;
   const int kq = lane >> 4;
   const int arow[1] = {i16}, bcol[1] = {i16};
-  const __amdgpu_buffer_rsrc_t ra_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rb_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ra_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, (int)P.a_len, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, (int)P.b_len, 0x00020000);
   d4 acc = {0.0, 0.0, 0.0, 0.0};
   const int64_t s0 = P.seg[c], s1 = P.seg[c + 1];
   for (int64_t rb = s0; rb < s1; rb += ROUND) {
@@ -304,8 +304,8 @@ __device__ __forceinline__ void gemm_block_44(const GemmP &P, int32_t c, ParamLd
   for (int u = 0; u < HM; u++) arow[u] = 4 * (Pq * HM + u) + L4;
 #pragma unroll
   for (int v = 0; v < HN; v++) bcol[v] = 4 * (Qq * HN + v) + L4;
-  const __amdgpu_buffer_rsrc_t ra_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rb_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ra_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, (int)P.a_len, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb_ = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, (int)P.b_len, 0x00020000);
   double acc[HM * HN];
 #pragma unroll
   for (int t = 0; t < HM * HN; t++) acc[t] = 0.0;
@@ -461,6 +461,15 @@ __device__ __forceinline__ d2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 // Four operand loads per k-pair cover 24 x 24, against six for 4x4
 // subtiles; the matrix cores do 1 + 5 narrow instructions instead of four
 // 16x16 tiles.
+// Buffer resource over a packed copy (len bytes) from value offset `base`
+// on (uniform): at most 2 GB - 16 bytes, so the null offset QOOB and
+// everything past the copy's end read zeros.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const double *v, uint64_t len, int64_t base) {
+  const uint64_t rest = len - 8ull * (uint64_t)base;
+  const uint32_t ext = rest < 0x7FFFFFF0ull ? (uint32_t)rest : 0x7FFFFFF0u;
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(v + base), (short)0, (int)ext, 0x00020000);
+}
+
 template <bool SIXTEEN, int MT, int NT, bool DIAG = false, int MIX = 0>
 __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql, int pre = 0) {
   static_assert(!DIAG || (SIXTEEN && MT == 1 && NT == 1), "diagonal packing uses one 16x16 tile");
@@ -515,8 +524,8 @@ __device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D
       cb[v] = cc < n ? cc : -1;
     }
   }
-  const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc((void *)P.a_val, (short)0, P.a_bytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)P.b_val, (short)0, P.b_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rsa = packed_rsrc(P.a_val, P.a_len, D.ab);
+  const __amdgpu_buffer_rsrc_t rsb = packed_rsrc(P.b_val, P.b_len, D.bb);
   constexpr int TA = MIX ? (NX > 0 ? NX : 1) : (SIXTEEN ? 1 : HM * HN);   // 4x4 accumulators
   double acc[NC][TA];
   d4 acc16[NC][T16];
@@ -753,6 +762,10 @@ __device__ __forceinline__ BlkDesc load_desc(const BlkDesc *desc, int64_t w) {
          (uint32_t)__builtin_amdgcn_readfirstlane((int)d->co);
   r.ns = __builtin_amdgcn_readfirstlane(d->ns);
   r.pad = 0;
+  r.ab = ((int64_t)__builtin_amdgcn_readfirstlane((int)(d->ab >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)d->ab);
+  r.bb = ((int64_t)__builtin_amdgcn_readfirstlane((int)(d->bb >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)d->bb);
   return r;
 }
 
@@ -992,7 +1005,7 @@ __global__ __launch_bounds__(256) void k_transpose_blocks(const int64_t *rp, con
 // each XCD's L2 holds the index data of its own tiles only.
 __global__ void k_build_desc(int64_t n, const int32_t *c_list, const int32_t *c_row, const int32_t *c_ci,
                              const int32_t *rbs, const int32_t *cbs, const int64_t *seg, const int64_t *c_off,
-                             BlkDesc *desc, int64_t per_xcd) {
+                             DescBases bases, BlkDesc *desc, int64_t per_xcd) {
   const int64_t b = blockIdx.x;
   const int64_t w = ((b & 7) * per_xcd + (b >> 3)) * blockDim.x + threadIdx.x;
   if (w >= n) return;
@@ -1004,17 +1017,20 @@ __global__ void k_build_desc(int64_t n, const int32_t *c_list, const int32_t *c_
   d.ns = (int32_t)(seg[c + 1] - seg[c]);
   d.co = c_off[c];
   d.pad = 0;
+  d.ab = bases.a ? bases.a[c_row[c]] : 0;
+  d.bb = bases.b ? bases.b[c_ci[c]] : 0;
   desc[w] = d;
 }
 
 }  // namespace
 
 void build_desc(int64_t n, const int32_t *c_list, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
-                const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s) {
+                const int32_t *cbs, const int64_t *seg, const int64_t *c_off, DescBases bases, BlkDesc *desc,
+                hipStream_t s) {
   if (n <= 0) return;
   const int64_t per_xcd = ((n + 255) / 256 + 7) / 8;
   hipLaunchKernelGGL(k_build_desc, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s, n, c_list, c_row, c_ci, rbs, cbs,
-                     seg, c_off, desc, per_xcd);
+                     seg, c_off, bases, desc, per_xcd);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1069,8 +1085,8 @@ static GemmP make_params(const GemmArgs &g) {
     p.a_val = g.a_pack;
     p.b_val = g.b_pack;
   }
-  p.a_bytes = buf ? (uint32_t)g.a_bytes : 0u;
-  p.b_bytes = buf ? (uint32_t)g.b_bytes : 0u;
+  p.a_len = buf ? g.a_bytes : 0u;
+  p.b_len = buf ? g.b_bytes : 0u;
   p.zeros = g.zeros;
   for (int t = 0; t < 16; t++) p.variant[t] = g.variant[t];
   return p;

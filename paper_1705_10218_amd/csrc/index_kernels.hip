@@ -317,7 +317,8 @@ namespace {
 // reads), each 32-byte record written at its place in the work list.
 __global__ __launch_bounds__(256) void k_desc_by_block(int64_t n, const int32_t *pos, const int32_t *c_row,
                                                        const int32_t *c_ci, const int32_t *rbs, const int32_t *cbs,
-                                                       const int64_t *seg, const int64_t *c_off, BlkDesc *desc) {
+                                                       const int64_t *seg, const int64_t *c_off, DescBases bases,
+                                                       BlkDesc *desc) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   BlkDesc d;
@@ -327,15 +328,18 @@ __global__ __launch_bounds__(256) void k_desc_by_block(int64_t n, const int32_t 
   d.ns = (int32_t)(seg[c + 1] - d.s0);
   d.co = c_off[c];
   d.pad = 0;
+  d.ab = bases.a ? bases.a[c_row[c]] : 0;
+  d.bb = bases.b ? bases.b[c_ci[c]] : 0;
   desc[pos[c]] = d;
 }
 }  // namespace
 
 void build_desc_by_block(int64_t n, const int32_t *pos, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
-                         const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s) {
+                         const int32_t *cbs, const int64_t *seg, const int64_t *c_off, DescBases bases,
+                         BlkDesc *desc, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_desc_by_block, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, pos, c_row, c_ci, rbs,
-                     cbs, seg, c_off, desc);
+                     cbs, seg, c_off, bases, desc);
   HIPCHECK(hipGetLastError());
 }
 

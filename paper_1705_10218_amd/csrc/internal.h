@@ -80,6 +80,7 @@ struct bsmm_ctx_s {
   uint8_t gemm_variant[16] = {};   // GEMM kernel variant per (m, n) size class
   int tile_ti = 2, tile_tj = 2;    // result-block tile of the tile path
   int64_t tile_chunk = 0;          // tiles per XCD chunk of the tile path (0: 8192)
+  int32_t pack_addr = 0;           // packed-operand addressing: 0 = automatic, 1 = per row / column
   // Staging of batched launch parameters: a ring of pinned host slots, each
   // reused once the copy from it has run (its event), and one device buffer
   // (every copy into it is ordered after the previous launch on the stream).
@@ -260,6 +261,7 @@ struct StackArgs {
   bool encode = false;               // entries = byte offsets | (k-1) bits (quad path), null = 0x80000000
   const int32_t *kofs = nullptr;     // k-size run starts inside each segment (pad4)
   const int64_t *a_poff = nullptr;   // packed block offsets of A used by the encoded entries
+  const int64_t *a_base = nullptr;   // per row of op(A): offset the encoded A offsets are taken from (null: 0)
   const int4 *bent = nullptr;        // product records of op(B) (product_records)
   StackWindows win;                  // windowed generation when win.nwin > 0:
   const int64_t *wslot = nullptr;    //   window bounds of C's rows
@@ -271,9 +273,11 @@ struct StackArgs {
 
 // Per entry of op(B), one 16-byte record read by the symbolic fill and the
 // stack generator: block column, the B half of a stack entry (byte offset
-// into the packed copy of op(B) when b_poff is given, else the block id) and
-// the block norm (0 when nb is null).
-void product_records(const OpIndex &b, const double *nb, const int64_t *b_poff, int4 *out, hipStream_t s);
+// into the packed copy of op(B) when b_poff is given -- from the start of
+// its column's packed blocks when b_base is given too -- else the block id)
+// and the block norm (0 when nb is null).
+void product_records(const OpIndex &b, const double *nb, const int64_t *b_poff, const int64_t *b_base, int4 *out,
+                     hipStream_t s);
 
 // Sets *flag (preset to 0) when some candidate product of op(A) x op(B) is
 // kept under one set of block norms and dropped under the other (norms
@@ -291,14 +295,18 @@ void old_block_map(const int64_t *cold_rp, const int32_t *cold_ci, int32_t nbr, 
                    const int32_t *c_ci, int32_t *old_blk, hipStream_t s);
 
 // Per work item of the GEMM (one C block, in work-list order): everything a
-// wavefront needs before its first stack round, in one 32-byte record.
-struct alignas(32) BlkDesc {
+// wavefront needs before its first stack round, in one 48-byte record.
+struct alignas(16) BlkDesc {
   int32_t c;    // C block id
   int32_t mn;   // m | n << 16 (block edges)
   int64_t s0;   // first stack entry of the block's segment
   int64_t co;   // value offset of the C block
   int32_t ns;   // stack entries of the segment
   int32_t pad;
+  // where the stack entries' operand offsets start (values into the packed
+  // copies): the packed blocks of the block's row of op(A) and of its column
+  // of op(B), or 0 when the offsets are taken from the start of each copy
+  int64_t ab, bb;
 };
 
 // Workgroups of a GEMM launch to XCDs.  The hardware deals workgroup ids to
@@ -370,6 +378,14 @@ void shift_dist_rows(const bsmm_mat_s &x, double shift, double *row_out, hipStre
 // row count is the contraction extent (op(A) = A^T or op(B) = B).
 // pack_offsets writes nnzb + 1 offsets (exclusive scan, total last).
 void pack_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_poff, hipStream_t s);
+// The same offsets laid out unit by unit: the rows of `units` are the units
+// (the rows of op(A), or the columns of op(B)), each listing the positions
+// of its blocks in x's storage (units.blk; identity when null), and every
+// unit's packed blocks are contiguous.  base[r] (units.nbr entries) is the
+// offset of unit r's first block, so a block's offset minus its unit's base
+// stays below the unit's packed size.
+void pack_offsets_units(Allocator &al, const bsmm_mat_s &x, bool k_is_row, const OpIndex &units, int64_t *d_poff,
+                        int64_t *d_base, hipStream_t s);
 // Both packed operand copies in one launch; with a_norm / b_norm, the block
 // norms as well, bitwise equal to block_norms (same summation order).
 void pack_values(const bsmm_mat_s &a, bool a_k_is_row, const int64_t *a_poff, double *a_out, const bsmm_mat_s &b,
@@ -397,9 +413,17 @@ void gemm_launch_multi(Allocator &al, const std::vector<const GemmArgs *> &gs, c
                        int max_edge, void *h_stage, size_t stage_bytes, void *d_stage, hipStream_t s);
 size_t gemm_multi_stage_bytes(int n);   // staging bytes for n requests
 
+// Unit bases of the packed operands in the work-item descriptors (null:
+// offsets from the start of each copy).
+struct DescBases {
+  const int64_t *a = nullptr;   // per row of op(A)
+  const int64_t *b = nullptr;   // per column of op(B)
+};
+
 // desc[w] for the work items w < n (C block c_list[w], or w without a list).
 void build_desc(int64_t n, const int32_t *c_list, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
-                const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s);
+                const int32_t *cbs, const int64_t *seg, const int64_t *c_off, DescBases bases, BlkDesc *desc,
+                hipStream_t s);
 
 // c_list = C blocks in tiles of consecutive rows of ord (device), column by
 // column inside a tile.
@@ -419,7 +443,8 @@ void build_work_list_sorted(Allocator &al, const int32_t *ord, const int32_t *cr
 // desc[pos[c]] for every C block c < n (as build_desc, from the inverse of
 // the work list).
 void build_desc_by_block(int64_t n, const int32_t *pos, const int32_t *c_row, const int32_t *c_ci, const int32_t *rbs,
-                         const int32_t *cbs, const int64_t *seg, const int64_t *c_off, BlkDesc *desc, hipStream_t s);
+                         const int32_t *cbs, const int64_t *seg, const int64_t *c_off, DescBases bases,
+                         BlkDesc *desc, hipStream_t s);
 
 // ---------------------------------------------------- tile path of the GEMM
 // Result blocks in tiles of ti x tj (rows adjacent in the locality order,

@@ -160,7 +160,61 @@ __global__ __launch_bounds__(256) void k_pack_blocks(PackSide a, PackSide b) {
   }
 }
 
+// Offsets in unit order: sizes gathered by unit position, and the scanned
+// offsets scattered back to the stored blocks.
+__global__ __launch_bounds__(256) void k_gather_sizes(int64_t n, const int32_t *blk, const int64_t *in, int64_t *out) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    out[t] = in[blk[t]];
+}
+
+__global__ __launch_bounds__(256) void k_scatter_offsets(int64_t n, const int32_t *blk, const int64_t *in,
+                                                         int64_t *out) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t <= n; t += (int64_t)gridDim.x * blockDim.x)
+    out[t < n ? (int64_t)blk[t] : n] = in[t];   // entry n: the total
+}
+
+__global__ __launch_bounds__(256) void k_unit_base(int32_t nunits, const int64_t *rp, const int64_t *off,
+                                                   int64_t *base) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nunits) base[r] = off[rp[r]];
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 65536); }
+
 }  // namespace
+
+void pack_offsets_units(Allocator &al, const bsmm_mat_s &x, bool k_is_row, const OpIndex &units, int64_t *d_poff,
+                        int64_t *d_base, hipStream_t s) {
+  if (x.nnzb == 0) {
+    HIPCHECK(hipMemsetAsync(d_poff, 0, sizeof(int64_t), s));
+    if (units.nbr > 0) HIPCHECK(hipMemsetAsync(d_base, 0, sizeof(int64_t) * (size_t)units.nbr, s));
+    return;
+  }
+  DBuf<int64_t> sizes(al, (size_t)x.nnzb);
+  hipLaunchKernelGGL(k_pack_sizes, dim3(x.nbr), dim3(64), 0, s, x.d_row_ptr, x.d_col_idx, x.d_rbs, x.d_cbs,
+                     k_is_row ? 1 : 0, sizes.p);
+  HIPCHECK(hipGetLastError());
+  const int64_t *off = d_poff;
+  DBuf<int64_t> usz, uoff;
+  if (units.blk) {
+    usz = DBuf<int64_t>(al, (size_t)x.nnzb);
+    uoff = DBuf<int64_t>(al, (size_t)x.nnzb + 1);
+    hipLaunchKernelGGL(k_gather_sizes, dim3(grid_for(x.nnzb)), dim3(256), 0, s, x.nnzb, units.blk, sizes.p, usz.p);
+    HIPCHECK(hipGetLastError());
+    exclusive_scan_i64(al, usz.p, uoff.p, x.nnzb, s);
+    hipLaunchKernelGGL(k_scatter_offsets, dim3(grid_for(x.nnzb + 1)), dim3(256), 0, s, x.nnzb, units.blk, uoff.p,
+                       d_poff);
+    HIPCHECK(hipGetLastError());
+    off = uoff.p;
+  } else {
+    exclusive_scan_i64(al, sizes.p, d_poff, x.nnzb, s);
+  }
+  if (units.nbr > 0) {
+    hipLaunchKernelGGL(k_unit_base, dim3((unsigned)((units.nbr + 255) / 256)), dim3(256), 0, s, units.nbr,
+                       units.row_ptr, off, d_base);
+    HIPCHECK(hipGetLastError());
+  }
+}
 
 void pack_offsets(Allocator &al, const bsmm_mat_s &x, bool k_is_row, int64_t *d_poff, hipStream_t s) {
   if (x.nnzb == 0) {

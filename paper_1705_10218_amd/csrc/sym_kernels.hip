@@ -466,12 +466,13 @@ __global__ void k_old_map(const int64_t *cold_rp, const int32_t *cold_ci, const 
 }
 
 // ------------------------------------------------------ a4: stack fill
-__global__ __launch_bounds__(256) void k_product_records(OpView B, int64_t nq, const double *nb, int enc, BEnt *out) {
+__global__ __launch_bounds__(256) void k_product_records(OpView B, int64_t nq, const double *nb, int enc,
+                                                         const int64_t *b_base, BEnt *out) {
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
     const int32_t bblk = B.blk ? B.blk[q] : (int32_t)q;
     BEnt e;
     e.j = B.ci[q];
-    e.eb = enc ? (uint32_t)(B.off[bblk] * 8) : (uint32_t)bblk;
+    e.eb = enc ? (uint32_t)((B.off[bblk] - (b_base ? b_base[e.j] : 0)) * 8) : (uint32_t)bblk;
     e.nb = nb ? nb[bblk] : 0.0;
     out[q] = e;
   }
@@ -493,7 +494,8 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
                                                    const int32_t *kofs, int2 *stack, const BEnt *bent,
                                                    const double *na, double eps, int32_t cnt_cap, int32_t *run,
                                                    KSizes ksz, int nks, int pad4, int enc, int32_t nbr,
-                                                   const int32_t *ord, int64_t per_xcd, int diag8) {
+                                                   const int32_t *ord, int64_t per_xcd, int diag8,
+                                                   const int64_t *a_base) {
   extern __shared__ uint32_t sm[];
   const RowUnit ru = row_unit(nbr, nks > 0 ? nks : 1, per_xcd, ord);
   if (!ru.ok) return;
@@ -508,6 +510,7 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
   if (R == 0) return;
   const bool lds_cnt = R <= cnt_cap;
   const int nk1 = nks > 0 ? nks : 1;
+  const int64_t abase = a_base ? a_base[i] : 0;   // encoded A offsets start at row i's packed blocks
   // opened A entries (64 at most at a time)
   int64_t *s_qb = reinterpret_cast<int64_t *>(sm);
   double *s_na = reinterpret_cast<double *>(sm + 128);
@@ -565,7 +568,7 @@ __global__ __launch_bounds__(64) void k_stack_fill(OpView A, OpView B, int32_t n
         ok = nq > 0;
         const int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
         nA = na ? na[ablk] : 0.0;
-        ea = enc ? ((uint32_t)(A.off[ablk] * 8) | (uint32_t)((kc - 1) & 7)) : (uint32_t)ablk;
+        ea = enc ? ((uint32_t)((A.off[ablk] - abase) * 8) | (uint32_t)((kc - 1) & 7)) : (uint32_t)ablk;
         kb = enc ? (uint32_t)((kc - 1) >> 3) : 0u;
       }
     }
@@ -683,11 +686,13 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
                                                        const int64_t *seg_off, const int32_t *kofs, int2 *stack,
                                                        const BEnt *bent, const double *na, double eps,
                                                        int32_t buf_cap, KSizes ksz, int nks, int32_t nbr,
-                                                       const int32_t *ord, int64_t per_xcd, int diag8) {
+                                                       const int32_t *ord, int64_t per_xcd, int diag8,
+                                                       const int64_t *a_base) {
   extern __shared__ uint32_t sm[];
   const RowUnit ru = row_unit(nbr, nks * nwin, per_xcd, ord);
   if (!ru.ok) return;
   const int32_t i = ru.row;
+  const int64_t abase = a_base ? a_base[i] : 0;   // encoded A offsets start at row i's packed blocks
   const int pass = ru.unit / nwin, w = ru.unit - pass * nwin;
   const int lane = threadIdx.x;
   const int64_t s0 = wslot[(int64_t)i * (nwin + 1) + w], s1 = wslot[(int64_t)i * (nwin + 1) + w + 1];
@@ -752,7 +757,7 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
         ok = nq > 0;
         const int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
         nA = na ? na[ablk] : 0.0;
-        ea = (uint32_t)(A.off[ablk] * 8) | (uint32_t)((kc - 1) & 7);
+        ea = (uint32_t)((A.off[ablk] - abase) * 8) | (uint32_t)((kc - 1) & 7);
         kb = (uint32_t)((kc - 1) >> 3);
       }
     }
@@ -915,12 +920,13 @@ void old_block_map(const int64_t *cold_rp, const int32_t *cold_ci, int32_t nbr, 
   HIPCHECK(hipGetLastError());
 }
 
-void product_records(const OpIndex &b, const double *nb, const int64_t *b_poff, int4 *out, hipStream_t s) {
+void product_records(const OpIndex &b, const double *nb, const int64_t *b_poff, const int64_t *b_base, int4 *out,
+                     hipStream_t s) {
   if (b.nnzb == 0) return;
   OpView vb = view(b);
   if (b_poff) vb.off = b_poff;   // encoded entries: offsets into the packed copy of op(B)
   hipLaunchKernelGGL(k_product_records, dim3((unsigned)std::min<int64_t>((b.nnzb + 255) / 256, 65536)), dim3(256), 0, s,
-                     vb, b.nnzb, nb, b_poff ? 1 : 0, reinterpret_cast<BEnt *>(out));
+                     vb, b.nnzb, nb, b_poff ? 1 : 0, b_poff ? b_base : nullptr, reinterpret_cast<BEnt *>(out));
   HIPCHECK(hipGetLastError());
 }
 
@@ -977,14 +983,14 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
     const int64_t px = row_units_per_xcd(g.nbr, nks * g.win.nwin);
     hipLaunchKernelGGL(k_stack_fill_win, dim3((unsigned)(px * 8)), dim3(64), lw, s, va, vb, g.wslot, g.bwin,
                        g.win.nwin, g.win.wc, g.c_ci, g.seg_off, g.kofs, g.stack, bent, g.na, g.eps, buf_cap, ks,
-                       nks, g.nbr, g.ord, px, g.diag8 ? 1 : 0);
+                       nks, g.nbr, g.ord, px, g.diag8 ? 1 : 0, g.a_base);
     HIPCHECK(hipGetLastError());
     return;
   }
   const int64_t px = row_units_per_xcd(g.nbr, std::max(nks, 1));
   hipLaunchKernelGGL(k_stack_fill, dim3((unsigned)(px * 8)), dim3(64), lds, s, va, vb, g.nbc, g.c_rp, g.c_ci,
                      g.seg_off, nks > 0 ? g.kofs : nullptr, g.stack, bent, g.na, g.eps, cap, run, ks, nks,
-                     g.pad4 ? 1 : 0, g.encode ? 1 : 0, g.nbr, g.ord, px, g.diag8 ? 1 : 0);
+                     g.pad4 ? 1 : 0, g.encode ? 1 : 0, g.nbr, g.ord, px, g.diag8 ? 1 : 0, g.encode ? g.a_base : nullptr);
   HIPCHECK(hipGetLastError());
 }
 
