@@ -52,12 +52,14 @@ def workload(name: str):
     if name == "tiny":
         a, b = inputs.config_tiny(0), inputs.config_tiny(1)
         return a, b, 0.0, {"workload": "tiny_100x100_blocks_5", "filter_eps": 0.0}
-    if name == "panel23":   # the batching workload's 23x23 panel, as the timed step (profiling)
-        pb = inputs.batching_problem(BATCH_ATOMS, BATCH_OCC, sizes=(23,))
+    if name in ("panel23", "panel_mixed"):   # a batching workload's panel, as the timed step (profiling)
+        sizes = (23,) if name == "panel23" else (5, 13, 23)
+        pb = inputs.batching_problem(BATCH_ATOMS, BATCH_OCC, sizes=sizes)
         a = inputs.batching_matrix(pb, 1, (0, BATCH_PANEL))
         b = inputs.batching_matrix(pb, 2)
-        return a, b, 1e-10, {"workload": f"batching_{BATCH_ATOMS}_atoms_blocks_23_panel_{BATCH_PANEL}_rows",
-                             "atoms": BATCH_ATOMS, "block_sizes": [23], "panel_rows": [0, BATCH_PANEL],
+        tag = "_".join(str(x) for x in sizes)
+        return a, b, 1e-10, {"workload": f"batching_{BATCH_ATOMS}_atoms_blocks_{tag}_panel_{BATCH_PANEL}_rows",
+                             "atoms": BATCH_ATOMS, "block_sizes": list(sizes), "panel_rows": [0, BATCH_PANEL],
                              "filter_eps": 1e-10, "box_A": round(pb.box, 3), "cutoff_A": round(pb.cutoff, 3)}
     raise SystemExit(f"unknown workload {name}")
 
@@ -410,7 +412,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dft4000", choices=["dft4000", "tiny", "panel23"])
+    ap.add_argument("--workload", default="dft4000", choices=["dft4000", "tiny", "panel23", "panel_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--fp64-only", action="store_true",
                     help="only the headline FP64 workload (no precision, batching or sign-iteration legs)")

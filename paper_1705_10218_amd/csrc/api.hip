@@ -759,9 +759,21 @@ static void plan_build(Plan &P, char transa, char transb) {
     P.stack.reset();
   } else if (nnzb_c > 0) {
     const int32_t *ord = row_order(ctx, A);
+    DBuf<int32_t> seq;
+    if (!ord && nbr >= 64 && nbr != A->nbc) {
+      // no locality order of a rectangular A (a panel of rows): its rows in
+      // index order, which the caller's numbering makes local (neighbouring
+      // rows share most of their op(B) rows, so a tile's C blocks of one
+      // column share their B blocks while those are in L2)
+      seq = DBuf<int32_t>(al, (size_t)nbr);
+      fill_sequence(seq.p, nbr, s);
+      ord = seq.p;
+    }
     if (ord) {
       P.c_list = DBuf<int32_t>(al, nc1);
-      const int32_t *rank = (nbc == nbr) ? ord + nbr : nullptr;
+      // columns in the locality order too when C is square over the same
+      // blocks (row_order's second half: the rank of every row)
+      const int32_t *rank = (nbc == nbr && !seq.p) ? ord + nbr : nullptr;
       const double row_bytes = 8.0 * (double)A->n_values / (double)std::max(nbr, 1);
       int32_t big = 16;
       while (big * 2 <= std::min(256, nbr / 16) && 2.0 * big * row_bytes <= 16.0 * (1 << 20)) big *= 2;

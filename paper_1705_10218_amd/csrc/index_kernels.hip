@@ -435,6 +435,11 @@ void block_norms(const bsmm_mat_s &x, double *norms, hipStream_t s) {
 namespace {
 
 // Values of the block-diagonal identity: block i (s_i x s_i) at off[i].
+__global__ __launch_bounds__(256) void k_sequence(int32_t *out, int32_t n) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = t;
+}
+
 __global__ void k_identity_values(const int32_t *sizes, const int64_t *off, int32_t n, double *v) {
   const int32_t i = blockIdx.x;
   if (i >= n) return;
@@ -548,6 +553,12 @@ void ratio_bounds(const double *then, const double *now, int64_t n, double *out,
 void identity_values(const int32_t *d_sizes, const int64_t *d_off, int32_t n, double *values, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_identity_values, dim3(n), dim3(256), 0, s, d_sizes, d_off, n, values);
+  HIPCHECK(hipGetLastError());
+}
+
+void fill_sequence(int32_t *out, int32_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_sequence, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n);
   HIPCHECK(hipGetLastError());
 }
 

@@ -368,6 +368,9 @@ void set_pairs(double *p, int n, double a, double b, hipStream_t s);
 // (out preset to +inf, 0); a ratio that is not finite gives 0 and +inf.
 void ratio_bounds(const double *then, const double *now, int64_t n, double *out, hipStream_t s);
 
+// out[t] = t for t < n.
+void fill_sequence(int32_t *out, int32_t n, hipStream_t s);
+
 // Block-diagonal identity values (block i of size sizes[i] at off[i]).
 void identity_values(const int32_t *d_sizes, const int64_t *d_off, int32_t n, double *values, hipStream_t s);
 // row_out[i] = sum over block row i of ||X_ij - shift * delta_ij I||_F^2 (square x).
