@@ -267,6 +267,7 @@ struct Plan {
   DBuf<int64_t> c_rp, c_off, seg_off, a_poff, b_poff, a_base, b_base;
   DBuf<int32_t> c_ci, c_row, old_blk, c_list;
   DBuf<BlkDesc> desc;
+  DBuf<UnitBases> ubase;   // per work item, per-unit addressing only
   DBuf<int2> stack;
   DBuf<double> a_pack, b_pack, a_lo, b_lo, a_t, b_t, c_norm, c_values;
   GemmArgs ga;
@@ -691,7 +692,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   // budget of the stacks, the work list and (one-shot) the numeric buffers,
   // checked before any of their launches
   {
-    size_t need = 8 * (size_t)std::max<int64_t>(P.nstack, 1) + nc1 * (4 + 4 + 4 + 32) + 4096;
+    size_t need = 8 * (size_t)std::max<int64_t>(P.nstack, 1) + nc1 * (4 + 4 + 4 + 32 + (units ? 16 : 0)) + 4096;
     if (P.one_shot)
       need += 8 * (size_t)std::max<int64_t>(P.nval_c, 1) + 8 * nc1 +
               (quads ? 8 * (size_t)(std::max<int64_t>(P.a_pack_n, 2) + std::max<int64_t>(P.b_pack_n, 2)) : 0);
@@ -793,7 +794,8 @@ static void plan_build(Plan &P, char transa, char transb) {
   // work-item descriptors of the quad path
   if (quads && nnzb_c > 0) {
     P.desc = DBuf<BlkDesc>(al, nc1);
-    const DescBases bases{P.a_base.p, P.b_base.p};
+    if (units) P.ubase = DBuf<UnitBases>(al, nc1);
+    const DescBases bases{P.a_base.p, P.b_base.p, P.ubase.p};
     if (wl_pos.p)   // C blocks read in storage order, records written at their places
       build_desc_by_block(nnzb_c, wl_pos.p, P.c_row.p, P.c_ci.p, oa.rbs, ob.cbs, P.seg_off.p, P.c_off.p, bases,
                           P.desc.p, s);
@@ -859,6 +861,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   ga.b = &ob;
   ga.c_list = P.c_list.p;
   ga.desc = P.desc.p;
+  ga.ubase = P.ubase.p;
   ga.c_row = P.c_row.p;
   ga.c_ci = P.c_ci.p;
   ga.c_off = P.c_off.p;

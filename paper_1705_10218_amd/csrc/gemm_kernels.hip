@@ -37,6 +37,12 @@ namespace bsmm {
 
 namespace {
 
+// A work item's descriptor in scalar registers, with its unit bases
+// (values into the packed copies; 0 without per-unit addressing).
+struct WorkDesc : BlkDesc {
+  int64_t ab, bb;
+};
+
 struct GemmP {
   const int64_t *a_off;
   const double *a_val;   // op(A) blocks column-major
@@ -44,6 +50,7 @@ struct GemmP {
   const double *b_val;   // op(B) blocks row-major
   const int32_t *c_list;
   const BlkDesc *desc;         // work-item descriptors (quad path)
+  const UnitBases *ubase;      // per work item, per-unit addressing only
   const int32_t *c_row, *c_ci;
   const int32_t *rbs, *cbs;   // C block sizes (= op(A) rows, op(B) columns)
   const int64_t *c_off, *seg;
@@ -471,7 +478,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const double *v, u
 }
 
 template <bool SIXTEEN, int MT, int NT, bool DIAG = false, int MIX = 0>
-__device__ __forceinline__ void gemm_block_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql, int pre = 0) {
+__device__ __forceinline__ void gemm_block_quad(const GemmP &P, const WorkDesc &D, QuadLds &ql, int pre = 0) {
   static_assert(!DIAG || (SIXTEEN && MT == 1 && NT == 1), "diagonal packing uses one 16x16 tile");
   static_assert(MIX == 0 || (SIXTEEN && MT == 1 && NT == 1 && !DIAG), "edge subtiles extend one 16x16 tile");
   constexpr bool XM = (MIX & 1) != 0, XN = (MIX & 2) != 0;
@@ -751,9 +758,9 @@ __device__ __forceinline__ int edge_tiles(int e) { return ((((e + 3) >> 2) + 1) 
 // 8,192 10.6 ms, no remap 13.4 ms).
 // MAXT bounds the subtile counts compiled in (4: blocks up to 16).
 // A work item's descriptor in scalar registers (the index is uniform).
-__device__ __forceinline__ BlkDesc load_desc(const BlkDesc *desc, int64_t w) {
-  const BlkDesc *d = desc + __builtin_amdgcn_readfirstlane((int)w);
-  BlkDesc r;
+__device__ __forceinline__ WorkDesc load_desc(const GemmP &P, int64_t w) {
+  const BlkDesc *d = P.desc + __builtin_amdgcn_readfirstlane((int)w);
+  WorkDesc r;
   r.c = __builtin_amdgcn_readfirstlane(d->c);
   r.mn = __builtin_amdgcn_readfirstlane(d->mn);
   r.s0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(d->s0 >> 32)) << 32) |
@@ -762,17 +769,21 @@ __device__ __forceinline__ BlkDesc load_desc(const BlkDesc *desc, int64_t w) {
          (uint32_t)__builtin_amdgcn_readfirstlane((int)d->co);
   r.ns = __builtin_amdgcn_readfirstlane(d->ns);
   r.pad = 0;
-  r.ab = ((int64_t)__builtin_amdgcn_readfirstlane((int)(d->ab >> 32)) << 32) |
-         (uint32_t)__builtin_amdgcn_readfirstlane((int)d->ab);
-  r.bb = ((int64_t)__builtin_amdgcn_readfirstlane((int)(d->bb >> 32)) << 32) |
-         (uint32_t)__builtin_amdgcn_readfirstlane((int)d->bb);
+  r.ab = r.bb = 0;
+  if (P.ubase) {   // uniform: per-unit addressing
+    const UnitBases *u = P.ubase + __builtin_amdgcn_readfirstlane((int)w);
+    r.ab = ((int64_t)__builtin_amdgcn_readfirstlane((int)(u->a >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)u->a);
+    r.bb = ((int64_t)__builtin_amdgcn_readfirstlane((int)(u->b >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)u->b);
+  }
   return r;
 }
 
 // Quad-path dispatch of one C block on its (m, n) class and the class's
 // kernel variant.
 template <int MAXT>
-__device__ __forceinline__ void dispatch_quad(const GemmP &P, const BlkDesc &D, QuadLds &ql, int pre = 0) {
+__device__ __forceinline__ void dispatch_quad(const GemmP &P, const WorkDesc &D, QuadLds &ql, int pre = 0) {
   const int mt = edge_tiles(D.mn & 0xffff);
   const int nt = edge_tiles(D.mn >> 16);
   const int key = mt * 16 + nt;
@@ -849,7 +860,7 @@ __global__ __launch_bounds__(64 * WPG) void k_gemm_f64(GemmP P, int64_t nblk, in
   const int64_t w = lb * WPG + (threadIdx.x >> 6);
   if (w >= nblk) return;   // uniform per wavefront
   if constexpr (BUF) {
-    const BlkDesc D = load_desc(P.desc, w);
+    const WorkDesc D = load_desc(P, w);
     dispatch_quad<MAXT>(P, D, ql);
     return;
   } else {
@@ -904,7 +915,7 @@ __global__ __launch_bounds__(64 * WPG) void k_gemm_f64_multi(const GemmP *ps, co
   r = __builtin_amdgcn_readfirstlane(r);
   const GemmP &P = ps[r];
   const int64_t lw = w - start[r];
-  const BlkDesc D = load_desc(P.desc, lw);
+  const WorkDesc D = load_desc(P, lw);
   dispatch_quad<MAXT>(P, D, ql);
 }
 
@@ -1017,9 +1028,8 @@ __global__ void k_build_desc(int64_t n, const int32_t *c_list, const int32_t *c_
   d.ns = (int32_t)(seg[c + 1] - seg[c]);
   d.co = c_off[c];
   d.pad = 0;
-  d.ab = bases.a ? bases.a[c_row[c]] : 0;
-  d.bb = bases.b ? bases.b[c_ci[c]] : 0;
   desc[w] = d;
+  if (bases.out) bases.out[w] = UnitBases{bases.a[c_row[c]], bases.b[c_ci[c]]};
 }
 
 }  // namespace
@@ -1066,6 +1076,7 @@ static GemmP make_params(const GemmArgs &g) {
   p.b_val = g.b_rm;
   p.c_list = g.c_list;
   p.desc = g.desc;
+  p.ubase = g.ubase;
   p.c_row = g.c_row;
   p.c_ci = g.c_ci;
   p.rbs = g.a->rbs;

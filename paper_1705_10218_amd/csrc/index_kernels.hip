@@ -328,9 +328,8 @@ __global__ __launch_bounds__(256) void k_desc_by_block(int64_t n, const int32_t 
   d.ns = (int32_t)(seg[c + 1] - d.s0);
   d.co = c_off[c];
   d.pad = 0;
-  d.ab = bases.a ? bases.a[c_row[c]] : 0;
-  d.bb = bases.b ? bases.b[c_ci[c]] : 0;
   desc[pos[c]] = d;
+  if (bases.out) bases.out[pos[c]] = UnitBases{bases.a[c_row[c]], bases.b[c_ci[c]]};
 }
 }  // namespace
 

@@ -295,18 +295,21 @@ void old_block_map(const int64_t *cold_rp, const int32_t *cold_ci, int32_t nbr, 
                    const int32_t *c_ci, int32_t *old_blk, hipStream_t s);
 
 // Per work item of the GEMM (one C block, in work-list order): everything a
-// wavefront needs before its first stack round, in one 48-byte record.
-struct alignas(16) BlkDesc {
+// wavefront needs before its first stack round, in one 32-byte record.
+struct alignas(32) BlkDesc {
   int32_t c;    // C block id
   int32_t mn;   // m | n << 16 (block edges)
   int64_t s0;   // first stack entry of the block's segment
   int64_t co;   // value offset of the C block
   int32_t ns;   // stack entries of the segment
   int32_t pad;
-  // where the stack entries' operand offsets start (values into the packed
-  // copies): the packed blocks of the block's row of op(A) and of its column
-  // of op(B), or 0 when the offsets are taken from the start of each copy
-  int64_t ab, bb;
+};
+
+// Per work item, with per-unit addressing of the packed copies only: where
+// the stack entries' operand offsets start (values into the packed copies),
+// the packed blocks of the C block's row of op(A) and of its column of op(B).
+struct alignas(16) UnitBases {
+  int64_t a, b;
 };
 
 // Workgroups of a GEMM launch to XCDs.  The hardware deals workgroup ids to
@@ -335,6 +338,7 @@ struct GemmArgs {
   const OpIndex *a, *b;
   const int32_t *c_list = nullptr;   // C blocks ordered by class
   const BlkDesc *desc = nullptr;     // work-item descriptors (quad path)
+  const UnitBases *ubase = nullptr;  // per work item, per-unit addressing only (else offsets from each copy's start)
   const int32_t *c_row = nullptr;
   const int32_t *c_ci = nullptr;
   const int64_t *c_off = nullptr;    // value offsets of C blocks
@@ -416,11 +420,12 @@ void gemm_launch_multi(Allocator &al, const std::vector<const GemmArgs *> &gs, c
                        int max_edge, void *h_stage, size_t stage_bytes, void *d_stage, hipStream_t s);
 size_t gemm_multi_stage_bytes(int n);   // staging bytes for n requests
 
-// Unit bases of the packed operands in the work-item descriptors (null:
-// offsets from the start of each copy).
+// Unit bases of the packed operands (per-unit addressing): out[w] receives
+// those of work item w's row of op(A) and column of op(B); all null without.
 struct DescBases {
   const int64_t *a = nullptr;   // per row of op(A)
   const int64_t *b = nullptr;   // per column of op(B)
+  UnitBases *out = nullptr;     // per work item
 };
 
 // desc[w] for the work items w < n (C block c_list[w], or w without a list).
