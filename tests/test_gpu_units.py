@@ -182,3 +182,49 @@ def test_units_automatic_past_2gb(B):
         num += float(d @ d)
         den += float(ref.values[ro[r0]:ro[r1]] @ ref.values[ro[r0]:ro[r1]])
     assert den > 0 and (num / den) ** 0.5 <= TOL
+
+
+def test_units_graph_replays(B):
+    """A per-unit plan captured in a HIP graph: every replay, with eager work
+    on the stream between replays, equals a one-shot multiply."""
+    import torch
+    st = torch.cuda.Stream()   # default priority; graphs need a non-default stream
+    with torch.cuda.stream(st):
+        ctx = B.Context(0, stream=st)
+        ctx.set_packed_addressing(1)
+        a, b, _ = inputs.dft_like_pair(250, config=97, sizes=(5, 13), cutoff=6.0)
+        A, Bm = B.Matrix.from_host(ctx, a), B.Matrix.from_host(ctx, b)
+        st.synchronize()
+        plan = B.Plan(ctx, "N", "N", 1.0, A, Bm)
+        assert plan.info.gemm_path == UNITS
+        plan.capture()
+        for rep in range(3):
+            A._values.mul_(1.5).sub_(0.25)
+            plan.execute()   # graph replay
+            got = plan.result().to_host()
+            st.synchronize()
+            want_m, _ = B.multiply(ctx, "N", "N", 1.0, A, Bm)
+            assert _same(got, want_m.to_host()), f"replay {rep}"
+            want_m.close()
+        plan.close()
+        A.close()
+        Bm.close()
+        ctx.close()
+
+
+def test_units_sign_iteration(B):
+    """The sign iteration (eq. (3)) with every product addressed per unit
+    gives the bits of the default addressing."""
+    x = inputs.symmetric_dft_like(200, config=6, sizes=(5, 13), cutoff=5.0)
+    out = []
+    for mode in (0, 1):
+        ctx = B.Context(0)
+        ctx.set_packed_addressing(mode)
+        X = B.Matrix.from_host(ctx, x)
+        Y, info, res, nnz = B.sign_newton_schulz(ctx, X, 6, 1e-8, 0.0)
+        out.append((Y.to_host(), list(res), list(nnz)))
+        Y.close()
+        X.close()
+        ctx.close()
+    (h0, r0, n0), (h1, r1, n1) = out
+    assert n0 == n1 and r0 == r1 and _same(h0, h1)
