@@ -704,7 +704,7 @@ static void plan_build(Plan &P, char transa, char transb) {
     // rows wider than the stack generator's LDS cursors use global cursors,
     // one per (C block, k-size run)
     DBuf<int32_t> run;
-    if (max_row > 4096) {
+    if (max_row > 4096 && !(sw.nwin > 0 && max_ns > 0)) {
       const size_t nr = nc1 * (quads ? ksizes.size() : 1);
       run = DBuf<int32_t>(al, nr);
       HIPCHECK(hipMemsetAsync(run.p, 0, sizeof(int32_t) * nr, s));

@@ -236,7 +236,8 @@ struct StackWindows {
 
 // Windows for a product with nbc block columns whose widest result row has
 // max_row blocks, nks k sizes; nwin = 0 where the windowed generator does
-// not apply (it needs the quad path's k-size runs and LDS-sized rows).
+// not apply (it needs the quad path's k-size runs, a bitmap window and
+// windows whose result blocks fit its LDS).
 StackWindows stack_windows(int32_t nbc, int32_t max_row, int nks);
 
 // out[r*(nwin+1) + w] = first entry of row r with column >= w*wc (the row's

@@ -933,15 +933,21 @@ void product_records(const OpIndex &b, const double *nb, const int64_t *b_poff, 
 StackWindows stack_windows(int32_t nbc, int32_t max_row, int nks) {
   StackWindows sw;
   const int32_t words_total = (nbc + 31) >> 5;
-  if (nks < 1 || nks > MAX_KSIZES || words_total == 0 || words_total > MAX_WORDS || max_row < 1 ||
-      max_row > CNT_CAP / 2)
-    return sw;
+  if (nks < 1 || nks > MAX_KSIZES || words_total == 0 || words_total > MAX_WORDS || max_row < 1) return sw;
   // 32 bytes of LDS per C block of a window for its group of four entries:
   // windows narrow enough that the widest row's share fits
   int nwin = (int)std::min<int64_t>(16, std::max<int64_t>(1, ((int64_t)max_row * 32 + STACK_BUF_BYTES - 1) /
                                                                  STACK_BUF_BYTES));
   const int32_t wc = (int32_t)((((int64_t)nbc + nwin - 1) / nwin + 31) & ~(int64_t)31);
   nwin = (int)(((int64_t)nbc + wc - 1) / wc);
+  // the kernel's LDS for a window of ns C blocks (ns <= min(max_row, wc)):
+  // the opened A entries, groups of four entries (up to the buffer), the
+  // window's bitmap and prefix words, a cursor and a run start per C block;
+  // wider windows go to the unwindowed generator
+  const int64_t ns = std::min<int64_t>(max_row, wc);
+  const int64_t lds = (int64_t)STACK_LDS_HEAD + std::min<int64_t>(ns, STACK_BUF_BYTES / 32) * 32 +
+                      (int64_t)((wc + 31) >> 5) * 8 + ns * 8;
+  if (lds > 65536) return sw;
   sw.nwin = nwin;
   sw.wc = wc;
   return sw;
