@@ -600,7 +600,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   DBuf<int64_t> c_size(al, nc1), row_kmn(al, std::max<int32_t>(nbr, 1)), row_cand(al, std::max<int32_t>(nbr, 1)),
       row_real(al, std::max<int32_t>(nbr, 1));
   DBuf<int32_t> cnt_g;
-  if (quads && (int64_t)max_row * (int64_t)ksizes.size() > 8192) {
+  if (quads && (int64_t)max_row * (int64_t)ksizes.size() > SYM_CNT_CAP) {
     cnt_g = DBuf<int32_t>(al, nc1 * ksizes.size());
     HIPCHECK(hipMemsetAsync(cnt_g.p, 0, sizeof(int32_t) * nc1 * ksizes.size(), s));
   }

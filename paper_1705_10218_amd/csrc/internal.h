@@ -229,6 +229,10 @@ void symbolic_fill(const FillArgs &f, hipStream_t s);
 
 // Column windows of the stack generator: window w holds block columns
 // [w*wc, (w+1)*wc).  nwin = 0: no windows (one pass per row and k size).
+// Per-row counters (result blocks x k sizes) the symbolic fill keeps in LDS;
+// wider rows count in global memory (a zeroed array of that many per block).
+constexpr int32_t SYM_CNT_CAP = 16384;
+
 struct StackWindows {
   int nwin = 0;
   int32_t wc = 0;

@@ -898,7 +898,7 @@ void symbolic_fill(const FillArgs &f, hipStream_t s) {
   KSizes ks;
   const int nkp = f.pad4 ? (int)f.ksizes.size() : 0;
   for (int t = 0; t < nkp; t++) ks.v[t] = f.ksizes[t];
-  int32_t cap = (int32_t)std::min<int64_t>((int64_t)f.max_row * std::max(nkp, 1), CNT_CAP);
+  int32_t cap = (int32_t)std::min<int64_t>((int64_t)f.max_row * std::max(nkp, 1), SYM_CNT_CAP);
   size_t lds = (size_t)W * 8 + (size_t)std::max(cap, 1) * 4;
   if (lds + sizeof(AOpen) * (SYM_THREADS / 64) + 1024 > 65536)
     HIPCHECK(hipFuncSetAttribute((const void *)k_sym_fill, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
