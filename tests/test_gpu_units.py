@@ -228,3 +228,18 @@ def test_units_sign_iteration(B):
         ctx.close()
     (h0, r0, n0), (h1, r1, n1) = out
     assert n0 == n1 and r0 == r1 and _same(h0, h1)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_units_edges_to_32_and_empty_units(B, seed):
+    """Block edges up to 32 (the widest kernel instance), empty rows of
+    op(A) and empty columns of op(B) (units with no packed block), and a
+    transposed op(B)."""
+    rng = np.random.default_rng(620 + seed)
+    nbr, nk, nbc = 30, 26, 34
+    ks = rng.choice(np.array([3, 9, 17, 25, 29, 32], np.int32), nk)   # at most 8 k sizes: the packed path
+    a = random_bcsr(rng, nbr, nk, rng.integers(1, 33, nbr).astype(np.int32), ks, p=0.3, empty_rows=(0, 7, 19))
+    bt = random_bcsr(rng, nbc, nk, rng.integers(1, 33, nbc).astype(np.int32), ks, p=0.3, empty_rows=(3, 11))
+    _log(f"units edges to 32 seed={seed}: {a.nnzb} x {bt.nnzb} blocks")
+    host, info = _both(B, "N", "T", 0.75, a, bt)
+    _check(host, info, oracle.multiply("N", "T", 0.75, a, bt))
