@@ -108,6 +108,12 @@ void Allocator::check(size_t bytes, const char *what) const {
   }
 }
 
+size_t Allocator::room() const {
+  if (!budget_) return SIZE_MAX;
+  const size_t live = held_ - cached_;
+  return live < budget_ ? budget_ - live : 0;
+}
+
 Allocator::~Allocator() {
   (void)hipDeviceSynchronize();
   for (auto &kv : free_) (void)hipFree(kv.second);

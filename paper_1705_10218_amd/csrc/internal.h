@@ -39,6 +39,9 @@ class Allocator {
   // Fails with BSMM_ERR_OUT_OF_MEMORY when `bytes` more in live buffers
   // would exceed the budget (cached free blocks count as available).
   void check(size_t bytes, const char *what) const;
+  // Bytes that live buffers may still grow by under the budget (SIZE_MAX
+  // without one).
+  size_t room() const;
   ~Allocator();
 
  private:

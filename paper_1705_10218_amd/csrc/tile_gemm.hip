@@ -643,6 +643,23 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
   }
 }
 
+// Products of every tile (the sum of its result blocks' stack segments):
+// a bound on its steps, the union of their k.
+template <int TI, int TJ>
+__global__ __launch_bounds__(256) void k_tile_bound(const int4 *tiles, int64_t ntile, const int64_t *seg,
+                                                    int64_t *out) {
+  using S = Shape<TI, TJ>;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntile) return;
+  const int32_t *td = reinterpret_cast<const int32_t *>(tiles + t * (S::DESC_BYTES / 16));
+  int64_t n = 0;
+  for (int x = 0; x < TI * TJ; x++) {
+    const int32_t cb = td[TI + TJ + x];
+    if (cb >= 0) n += seg[cb + 1] - seg[cb];
+  }
+  out[t] = n;
+}
+
 template <int TI, int TJ>
 void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const int32_t *cinv, int32_t nbr,
                   int32_t nbc, const int64_t *c_rp, const int32_t *c_ci, const int64_t *seg, const int2 *stack,
@@ -681,14 +698,27 @@ void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const
   const XcdMap xm = xcd_map(nt);
   const int64_t grid = xm.per_xcd * 8;
   if (grid > INT32_MAX) fail(BSMM_ERR_UNSUPPORTED, "too many result tiles for one launch");
+  // Where the records go: a tile has at most as many steps as products, so
+  // laid out by that bound the records are written in one pass.  When the
+  // bound takes more than 64 GiB or a quarter of what the budget leaves,
+  // the steps are counted first and laid out exactly.
   DBuf<int64_t> tcnt(al, (size_t)nt), toff(al, (size_t)nt + 1);
-  hipLaunchKernelGGL((k_tile_steps<TI, TJ>), dim3((unsigned)grid), dim3(64), lds2, s, tp.tiles.p, nt, seg, stack, kidx,
-                     nbk, ksz, a_off, b_off, tcnt.p, (const int64_t *)nullptr, (int4 *)nullptr, xm.chunk);
+  hipLaunchKernelGGL((k_tile_bound<TI, TJ>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, tp.tiles.p, nt, seg,
+                     tcnt.p);
   HIPCHECK(hipGetLastError());
   exclusive_scan_i64(al, tcnt.p, toff.p, nt, s);
   HIPCHECK(hipMemcpyAsync(pinned, toff.p + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
-  tp.nsteps = pinned[0];
+  const double bound_bytes = (double)pinned[0] * S::LPR * 16.0;
+  if (bound_bytes > 64.0 * (double)(1ull << 30) || bound_bytes > 0.25 * (double)al.room()) {
+    hipLaunchKernelGGL((k_tile_steps<TI, TJ>), dim3((unsigned)grid), dim3(64), lds2, s, tp.tiles.p, nt, seg, stack,
+                       kidx, nbk, ksz, a_off, b_off, tcnt.p, (const int64_t *)nullptr, (int4 *)nullptr, xm.chunk);
+    HIPCHECK(hipGetLastError());
+    exclusive_scan_i64(al, tcnt.p, toff.p, nt, s);
+    HIPCHECK(hipMemcpyAsync(pinned, toff.p + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  tp.nsteps = pinned[0];   // records laid out (steps, or the products bound)
   // RB records of padding: a batch load at a tile's last steps reads past them
   tp.steps = DBuf<int4>(al, ((size_t)std::max<int64_t>(tp.nsteps, 0) + S::RB) * S::LPR);
   hipLaunchKernelGGL((k_tile_steps<TI, TJ>), dim3((unsigned)grid), dim3(64), lds2, s, tp.tiles.p, nt, seg, stack, kidx,
