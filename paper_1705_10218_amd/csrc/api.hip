@@ -645,7 +645,7 @@ static void plan_build(Plan &P, char transa, char transb) {
   }
   symbolic_fill(fa, s);
   // column windows of the stack generator (bounds of C's and op(B)'s rows)
-  const StackWindows sw = quads ? stack_windows(nbc, max_row, (int)ksizes.size()) : StackWindows{};
+  const StackWindows sw = stack_windows(nbc, max_row, quads ? (int)ksizes.size() : 1);
   DBuf<int64_t> wslot, bwin;
   DBuf<int32_t> dmax_ns;
   if (sw.nwin > 0 && nnzb_c > 0) {

@@ -687,7 +687,7 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
                                                        const BEnt *bent, const double *na, double eps,
                                                        int32_t buf_cap, KSizes ksz, int nks, int32_t nbr,
                                                        const int32_t *ord, int64_t per_xcd, int diag8,
-                                                       const int64_t *a_base) {
+                                                       const int64_t *a_base, int plain) {
   extern __shared__ uint32_t sm[];
   const RowUnit ru = row_unit(nbr, nks * nwin, per_xcd, ord);
   if (!ru.ok) return;
@@ -700,7 +700,9 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
   if (ns == 0) return;
   const int32_t j0 = w * wc;
   const int32_t W = (wc + 31) >> 5;
-  const bool buffered = ns <= buf_cap;
+  // plain entries (block ids, every k in one pass, no padding) go straight
+  // to memory: their runs do not start on groups of four
+  const bool buffered = !plain && ns <= buf_cap;
   int64_t *s_qb = reinterpret_cast<int64_t *>(sm);
   double *s_na = reinterpret_cast<double *>(sm + 128);
   int32_t *s_nq = reinterpret_cast<int32_t *>(sm + 256);
@@ -735,7 +737,7 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
   }
   for (int32_t t = lane; t < ns; t += 64) {
     cnt[t] = 0;
-    sbase[t] = (int32_t)(seg_off[s0 + t] - g0) + kofs[(s0 + t) * nks + pass];
+    sbase[t] = (int32_t)(seg_off[s0 + t] - g0) + (plain ? 0 : kofs[(s0 + t) * nks + pass]);
   }
   __syncthreads();
   int2 *base = stack + g0;
@@ -750,15 +752,19 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
     if (p < pa1) {
       const int32_t k = A.ci[p];
       const int32_t kc = A.cbs[k];
-      if (kc == ksz.v[pass]) {
+      if (plain || kc == ksz.v[pass]) {
         const int64_t *bw = bwin + (int64_t)k * (nwin + 1) + w;
         qb = bw[0];
         nq = (int32_t)(bw[1] - qb);
         ok = nq > 0;
         const int32_t ablk = A.blk ? A.blk[p] : (int32_t)p;
         nA = na ? na[ablk] : 0.0;
-        ea = (uint32_t)((A.off[ablk] - abase) * 8) | (uint32_t)((kc - 1) & 7);
-        kb = (uint32_t)((kc - 1) >> 3);
+        if (plain) {
+          ea = (uint32_t)ablk;
+        } else {
+          ea = (uint32_t)((A.off[ablk] - abase) * 8) | (uint32_t)((kc - 1) & 7);
+          kb = (uint32_t)((kc - 1) >> 3);
+        }
       }
     }
     const uint64_t m = __ballot(ok);
@@ -803,6 +809,7 @@ __global__ __launch_bounds__(64) void k_stack_fill_win(OpView A, OpView B, const
     else walk(std::false_type{});
     __syncthreads();   // the opened entries are rewritten by the next batch
   }
+  if (plain) return;   // runs hold exactly their products
   // close every run of this k size: the groups of four from the one holding
   // the last entry up to the padded end (a multiple of four, of eight for
   // the diagonal-packed variant's blocks), null entries past the last
@@ -978,7 +985,10 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
     va.off = g.a_poff;
   }
   const BEnt *bent = reinterpret_cast<const BEnt *>(g.bent);
-  if (g.win.nwin > 0 && g.pad4 && g.encode && nks > 0) {
+  // windowed: encoded entries in padded k-size runs (quad path), or plain
+  // block ids with every k in one pass (tile and pointer paths)
+  const bool plain = !g.pad4 && !g.encode;
+  if (g.win.nwin > 0 && ((g.pad4 && g.encode && nks > 0) || plain)) {
     const int32_t buf_cap = (int32_t)(STACK_BUF_BYTES / 32);
     const int32_t ns = std::max(g.max_ns, 1);
     const int32_t Ww = (g.win.wc + 31) >> 5;
@@ -986,10 +996,12 @@ void stack_fill(const StackArgs &g, int32_t *run, hipStream_t s) {
     if (lw > 65536)
       HIPCHECK(hipFuncSetAttribute((const void *)k_stack_fill_win, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lw));
-    const int64_t px = row_units_per_xcd(g.nbr, nks * g.win.nwin);
+    const int nkw = plain ? 1 : nks;   // k-size passes per row (plain: one for every k)
+    const int64_t px = row_units_per_xcd(g.nbr, nkw * g.win.nwin);
     hipLaunchKernelGGL(k_stack_fill_win, dim3((unsigned)(px * 8)), dim3(64), lw, s, va, vb, g.wslot, g.bwin,
-                       g.win.nwin, g.win.wc, g.c_ci, g.seg_off, g.kofs, g.stack, bent, g.na, g.eps, buf_cap, ks,
-                       nks, g.nbr, g.ord, px, g.diag8 ? 1 : 0, g.a_base);
+                       g.win.nwin, g.win.wc, g.c_ci, g.seg_off, plain ? nullptr : g.kofs, g.stack, bent, g.na,
+                       g.eps, buf_cap, ks, nkw, g.nbr, g.ord, px, (g.diag8 && !plain) ? 1 : 0,
+                       plain ? nullptr : g.a_base, plain ? 1 : 0);
     HIPCHECK(hipGetLastError());
     return;
   }
