@@ -166,6 +166,18 @@ bsmm_status bsmm_ctx_set_tile_schedule(bsmm_ctx ctx, int32_t persistent, int64_t
  * order.
  * Errors: BSMM_ERR_INVALID_ARG for another mode. */
 bsmm_status bsmm_ctx_set_packed_addressing(bsmm_ctx ctx, int32_t mode);
+/* Locality order of the block rows (products planned afterwards).  For a
+ * square op(A) the library can derive an order of its block rows from the
+ * pattern alone (recursive bisection by breadth-first-search distance; the
+ * host computes it once per matrix and keeps it with the matrix): the GEMM
+ * then walks the result in tiles of neighbouring rows and the row-parallel
+ * kernels take rows in that order, for reuse of op(B) blocks in L2.
+ * mode 0 (default): for square operands of at least 2,048 block rows;
+ * mode 1: for square operands of at least 64 block rows; mode 2: never.
+ * Results are bitwise the same in every mode (each result block sums its
+ * products in the same order); only speed and host time change.
+ * Errors: BSMM_ERR_INVALID_ARG for another mode. */
+bsmm_status bsmm_ctx_set_row_order(bsmm_ctx ctx, int32_t mode);
 /* Bytes of device memory the library currently holds for this context
  * (live buffers plus its cache of freed ones). */
 bsmm_status bsmm_ctx_memory(bsmm_ctx ctx, size_t *held_bytes, size_t *peak_bytes);

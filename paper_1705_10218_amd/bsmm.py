@@ -37,7 +37,7 @@ SYMBOLS = (
     "bsmm_plan_create", "bsmm_plan_execute", "bsmm_plan_capture", "bsmm_plan_result", "bsmm_plan_destroy",
     "bsmm_plans_execute", "bsmm_filter_noalloc", "bsmm_ctx_set_tile_shape", "bsmm_plan_sizes",
     "bsmm_plan_execute_into", "bsmm_ctx_set_tile_schedule", "bsmm_plan_filter_holds",
-    "bsmm_ctx_set_packed_addressing",
+    "bsmm_ctx_set_packed_addressing", "bsmm_ctx_set_row_order",
 )
 
 
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
         L.bsmm_ctx_set_tile_shape.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
         L.bsmm_ctx_set_tile_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64]
         L.bsmm_ctx_set_packed_addressing.argtypes = [_vp, ctypes.c_int32]
+        L.bsmm_ctx_set_row_order.argtypes = [_vp, ctypes.c_int32]
         L.bsmm_ctx_memory.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
         L.bsmm_ctx_trim.argtypes = [_vp]
         L.bsmm_ctx_synchronize.argtypes = [_vp]
@@ -180,6 +181,10 @@ class Context:
 
     def set_tile_schedule(self, persistent: bool = False, xcd_chunk: int = 0):
         _check(lib().bsmm_ctx_set_tile_schedule(self.handle, int(bool(persistent)), int(xcd_chunk)))
+
+    def set_row_order(self, mode: int):
+        """0: automatic (square operands of 2,048+ block rows); 1: always (64+ rows); 2: never."""
+        _check(lib().bsmm_ctx_set_row_order(self.handle, int(mode)))
 
     def set_packed_addressing(self, mode: int):
         """0: automatic (per unit only when a packed copy reaches 2 GB); 1: per unit."""

@@ -84,6 +84,7 @@ struct bsmm_ctx_s {
   int tile_ti = 2, tile_tj = 2;    // result-block tile of the tile path
   int64_t tile_chunk = 0;          // tiles per XCD chunk of the tile path (0: 8192)
   int32_t pack_addr = 0;           // packed-operand addressing: 0 = automatic, 1 = per row / column
+  int32_t row_order = 0;           // locality order of square operands: 0 = automatic, 1 = always, 2 = never
   // Staging of batched launch parameters: a ring of pinned host slots, each
   // reused once the copy from it has run (its event), and one device buffer
   // (every copy into it is ordered after the previous launch on the stream).

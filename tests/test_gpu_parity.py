@@ -183,6 +183,29 @@ def test_dft_like_small_full(B, ctx):
         _check_exact(host, info, oracle.multiply("N", "N", 1.0, a, b, eps=eps, nthreads=8))
 
 
+def test_row_order_modes_same_bits(B):
+    """The locality order changes only which result block runs when: the
+    default (no order below 2,048 rows), the order from 64 rows on and no
+    order give the same bits, equal to the oracle; other modes are rejected."""
+    a, b, _ = inputs.dft_like_pair(700, config=95, sizes=(5, 13), cutoff=7.0)
+    out = []
+    for mode in (0, 1, 2):
+        c = B.Context(0)
+        c.set_row_order(mode)
+        out.append(_gpu_mul(B, c, "N", "N", 1.0, a, b, eps=1e-10))
+        c.close()
+    for host, info in out[1:]:
+        assert np.array_equal(host.col_idx, out[0][0].col_idx)
+        assert np.array_equal(host.values.view(np.uint64), out[0][0].values.view(np.uint64))
+    _check_exact(out[1][0], out[1][1], oracle.multiply("N", "N", 1.0, a, b, eps=1e-10, nthreads=8))
+    c = B.Context(0)
+    for mode in (-1, 3):
+        with pytest.raises(B.BsmmError) as e:
+            c.set_row_order(mode)
+        assert e.value.status == 1
+    c.close()
+
+
 def test_dft_like_mixed_23(B, ctx):
     a, b, _ = inputs.dft_like_pair(500, config=96, sizes=(5, 13, 23), cutoff=6.5)
     host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b)

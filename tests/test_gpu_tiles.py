@@ -210,15 +210,20 @@ def test_tiles_square_same_handle(B, ctx):
 
 def test_tiles_dft_like_23(B, ctx):
     """23x23 blocks on the DFT-like generator (Table 1's H2O block size) at
-    300 atoms, cutoff 6.5 A, filter 1e-10 in both phases; large enough for
-    the locality order (square product over 64+ rows) and the column ranks.
+    300 atoms, cutoff 6.5 A, filter 1e-10 in both phases, with the locality
+    order requested from 64 rows on (square product: tiles follow the order
+    and the column ranks).
     Every block is 23x23, so the uniform-size kernel runs; the general tile
     kernel (variant 6) gives the same bits."""
     a, b, _ = inputs.dft_like_pair(300, config=3, sizes=(23,), cutoff=6.5)
     _log(f"tiles dft-like 23: nnzb {a.nnzb}")
-    host, info = _gpu_mul(B, ctx, "N", "N", 1.0, a, b, eps=1e-10)
+    c1 = B.Context(0)
+    c1.set_row_order(1)   # the locality order from 64 rows on (the default starts at 2,048)
+    host, info = _gpu_mul(B, c1, "N", "N", 1.0, a, b, eps=1e-10)
+    c1.close()
     _check(host, info, oracle.multiply("N", "N", 1.0, a, b, eps=1e-10), path=UNI_PATH)
     c2 = B.Context(0)
+    c2.set_row_order(1)
     c2.set_gemm_variant(23, 23, 6)
     h6, i6 = _gpu_mul(B, c2, "N", "N", 1.0, a, b, eps=1e-10)
     c2.close()
