@@ -347,7 +347,7 @@ def config5_estimate(n: int = 512, atoms=(200, 8000), sizes=(5, 13, 23)) -> dict
             "input_bytes_estimate": round(8.0 * vals), "useful_flops_estimate": float(f"{flops:.3e}")}
 
 
-def serving_leg(bsmm, n: int, configure=None) -> dict:
+def serving_leg(bsmm, n: int, configure=None, lanes: int = 2) -> dict:
     import numpy as np
 
     from paper_1705_10218_amd import inputs, serve
@@ -360,7 +360,7 @@ def serving_leg(bsmm, n: int, configure=None) -> dict:
         return [serve.Request(rid=i, a=a, b=b, eps=1e-10, arrival=float(t)) for i, ((a, b, _), t) in
                 enumerate(zip(gen, arrivals))]
 
-    srv = serve.Server(0, budget, max_batch=64, configure=configure)
+    srv = serve.Server(0, budget, max_batch=64, configure=configure, lanes=lanes)
     sat = serve.summary(srv.run(requests(np.zeros(n))))
     rate = 0.7 * sat["requests_per_s"]
     # a seeded three of the requests (among those of at most 500 atoms, so
@@ -369,7 +369,7 @@ def serving_leg(bsmm, n: int, configure=None) -> dict:
     small = [i for i, (a, _, _) in enumerate(gen) if a.nbr <= 500]
     pick = sorted(int(x) for x in np.random.default_rng(7).choice(small, size=min(3, len(small)), replace=False)) \
         if small else []
-    srv2 = serve.Server(0, budget, max_batch=64, configure=configure, keep_results=pick)
+    srv2 = serve.Server(0, budget, max_batch=64, configure=configure, keep_results=pick, lanes=lanes)
     done = srv2.run(requests(serve.poisson_arrivals(n, rate, np.random.default_rng(5))))
     st = serve.summary(done)
     import oracle
@@ -389,12 +389,13 @@ def serving_leg(bsmm, n: int, configure=None) -> dict:
     full = config5_estimate()
     return {"workload": "stand-in for the serving configuration (fewer, smaller requests)",
             "requests": n, "atoms_log_uniform": list(SERVE_ATOMS), "occupancy_uniform": [0.02, 0.20],
-            "block_sizes": [5, 13, 23], "filter_eps": 1e-10, "hbm_budget_gb": SERVE_BUDGET_GB,
+            "block_sizes": [5, 13, 23], "filter_eps": 1e-10, "hbm_budget_gb": SERVE_BUDGET_GB, "lanes": lanes,
             "generation_s": round(gen_s, 1),
             "saturation": {"requests_per_s": round(sat["requests_per_s"], 3),
                            "gflops": round(sat["throughput_gflops"], 2), "batches": len(srv.batches)},
             "arrival_rate_per_s": round(rate, 3), "arrival_rate_rule": "0.7 x measured saturation",
             "latency_p50_ms": round(st["latency_p50_ms"], 3), "latency_p99_ms": round(st["latency_p99_ms"], 3),
+            "latency_parts_ms": st["latency_parts_ms"],
             "throughput_gflops": round(st["throughput_gflops"], 2), "batches": len(srv2.batches),
             "overlapping_batches": srv2.overlapping_batches(),
             "mean_batch": round(float(np.mean(srv2.batches)), 2), "useful_flops": st["useful_flops"],

@@ -115,8 +115,11 @@ class Server:
     library; tests substitute them."""
 
     def __init__(self, device: int, budget_bytes: int, max_batch: int = 64, keep_results=False,
-                 max_wait_s: float = 0.002, poll_s: float = 0.0002, configure=None):
+                 max_wait_s: float = 0.002, poll_s: float = 0.0002, configure=None, lanes: int = 2):
+        if lanes < 2:
+            raise ValueError("the loop needs at least two lanes (one plans while another executes)")
         self.device = device
+        self.n_lanes = int(lanes)
         self.configure = configure   # called with each lane's context
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
@@ -170,7 +173,7 @@ class Server:
 
     # -------------------------------------------------------------- loop
     def run(self, requests) -> list:
-        lanes = [self._new_lane(), self._new_lane()]
+        lanes = [self._new_lane() for _ in range(self.n_lanes)]
         try:
             return self._run(lanes, requests)
         finally:
@@ -202,8 +205,10 @@ class Server:
                     self.batch_times[b.index] = (b.launched, clock())
                     ln.inflight = None
                     progressed = True
-            # admission and planning on the lane that is not executing
+            # admission and planning on a lane that is not executing
             # (planning synchronises the lane's stream)
+            if lanes[plan_lane].inflight is not None:
+                plan_lane = next((k for k, x in enumerate(lanes) if x.inflight is None), plan_lane)
             ln = lanes[plan_lane]
             if ln.inflight is None:
                 while pending and pending[0].arrival <= clock() and len(ln.planned) < self.max_batch:
@@ -226,7 +231,7 @@ class Server:
                     progressed = True
             # launch: a lane with planned requests and no batch running goes
             # when nothing else runs, its batch is full, or it waited enough
-            for k in (plan_lane, 1 - plan_lane):
+            for k in [plan_lane] + [j for j in range(len(lanes)) if j != plan_lane]:
                 ln = lanes[k]
                 if not ln.planned or ln.inflight is not None:
                     continue
@@ -244,7 +249,8 @@ class Server:
                 self.batches.append(len(ln.planned))
                 self.batch_times.append((now, math.nan))
                 ln.planned = []
-                plan_lane = 1 - k
+                # plan next on another lane that is not executing
+                plan_lane = next((j for j in range(len(lanes)) if lanes[j].inflight is None), plan_lane)
                 progressed = True
             if not progressed:
                 wait = self.poll
@@ -270,4 +276,10 @@ def summary(done, makespan: float | None = None) -> dict:
            "throughput_gflops": flops / span / 1e9 if span > 0 else math.nan,
            "requests_per_s": len(done) / span if span > 0 else math.nan}
     out.update({f"latency_{k}_ms": v * 1e3 for k, v in percentiles(lat).items()})
+    # where the latency goes: waiting for admission, upload and planning,
+    # waiting for the launch, and the batch on the device up to the result
+    parts = {"admission": [r.admitted - r.arrival for r in done], "upload_plan": [r.planned - r.admitted for r in done],
+             "launch_wait": [r.launched - r.planned for r in done], "device": [r.done - r.launched for r in done]}
+    out["latency_parts_ms"] = {name: {k: round(v * 1e3, 3) for k, v in percentiles(x).items()}
+                               for name, x in parts.items()}
     return out

@@ -98,3 +98,21 @@ def test_loop_admits_by_planned_size():
         assert not {0, 3} <= members
     t = {r.rid: r for r in done}
     assert t[3].launched >= t[0].done or t[0].launched >= t[3].done
+
+
+def test_three_lanes_run_three_batches_at_once():
+    """With three lanes, requests arriving while two batches run are planned
+    on the third and launched before either ends; every request completes;
+    fewer than two lanes are rejected."""
+    arrivals = [0.0] * 2 + [0.003] * 2 + [0.006] * 2
+    reqs = _reqs(6, arrivals)
+    ob = serve.operand_bytes(reqs[0].a, reqs[0].b)
+    srv = _FakeServer(budget_bytes=100 * ob, max_batch=2, run_s=0.05, max_wait_s=0.001, lanes=3)
+    done = srv.run(reqs)
+    assert sorted(r.rid for r in done) == list(range(6))
+    assert all(r.done >= r.arrival for r in done)
+    # some batch launched while two others were still running
+    bt = srv.batch_times
+    assert any(sum(1 for j, (a, c) in enumerate(bt) if j != k and a < l < c) >= 2 for k, (l, _) in enumerate(bt))
+    with pytest.raises(ValueError):
+        _FakeServer(budget_bytes=ob, lanes=1)
