@@ -764,13 +764,16 @@ static void plan_build(Plan &P, char transa, char transb) {
   if (tiles && nnzb_c > 0) {
     // tiles of the result pattern and their step records; the per-block
     // stacks are not needed once merged into the steps
-    DBuf<int32_t> kidx(al, (size_t)std::max<int64_t>(A->nnzb, 1));
-    block_k_index(oa, kidx.p, s);
     const int32_t *ord = sym.ord;
     const int32_t *crank = (ord && nbc == nbr) ? ord + nbr : nullptr;
+    OpRows ar;
+    ar.rp = oa.row_ptr;
+    ar.ci = oa.col_idx;
+    ar.blk = oa.blk;
+    ar.nnzb = oa.nnzb;
     build_tile_plan(al, TileShape{ctx->tile_ti, ctx->tile_tj}, ord, crank, crank ? ord : nullptr, nbr, nbc, P.c_rp.p,
-                    P.c_ci.p, P.seg_off.p, P.stack.p, kidx.p, (int32_t)opa_c.size(), oa.cbs, A->d_blk_off,
-                    B->d_blk_off, ctx->pinned, P.tp, s);
+                    P.c_ci.p, P.seg_off.p, P.stack.p, ar, (int32_t)opa_c.size(), oa.cbs, A->d_blk_off, B->d_blk_off,
+                    ctx->pinned, P.tp, s);
     P.stack.reset();
   } else if (nnzb_c > 0) {
     const int32_t *ord = row_order(ctx, A);

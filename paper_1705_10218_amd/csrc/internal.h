@@ -500,15 +500,22 @@ bool tile_uni_size(int32_t sz);
 // Whether the tile plan's LDS bitmaps hold a product with nbc block columns
 // of C and nbk contraction blocks.
 bool tile_path_fits(int32_t nbc, int32_t nbk, TileShape sh);
-// kidx[stored block id of A] = its k (block column of op(A)).
-void block_k_index(const OpIndex &a, int32_t *kidx, hipStream_t s);
+// The rows of op(A): row pointers, block columns (k) and stored block ids
+// (null: the positions) of its entries.
+struct OpRows {
+  const int64_t *rp = nullptr;
+  const int32_t *ci = nullptr;
+  const int32_t *blk = nullptr;
+  int64_t nnzb = 0;
+};
 // Tiles of the result pattern (rows grouped in the order ord, null =
 // natural; columns by crank, null = natural, cinv its inverse) and their step
 // records from the per-result-block stacks (entries = stored A and B block
-// ids, ascending k): two host synchronisations for the sizes.
+// ids, ascending k; ar: the rows of op(A), nbk its block columns): two host
+// synchronisations for the sizes.
 void build_tile_plan(Allocator &al, TileShape sh, const int32_t *ord, const int32_t *crank, const int32_t *cinv,
                      int32_t nbr, int32_t nbc, const int64_t *c_rp, const int32_t *c_ci, const int64_t *seg,
-                     const int2 *stack, const int32_t *kidx, int32_t nbk, const int32_t *ksz, const int64_t *a_off,
+                     const int2 *stack, const OpRows &ar, int32_t nbk, const int32_t *ksz, const int64_t *a_off,
                      const int64_t *b_off, int64_t *pinned, TilePlan &tp, hipStream_t s);
 // a5 on the tile path.
 void tile_gemm_launch(const TilePlan &tp, const TileArgs &g, hipStream_t s);

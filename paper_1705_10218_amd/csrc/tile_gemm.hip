@@ -435,10 +435,94 @@ __device__ inline int32_t bsearch_pos(const int32_t *ci, int64_t lo, int64_t hi,
   return -1;
 }
 
-// k of every stored block of op(A): its block column in the op(A) view.
-__global__ void k_block_k(const int32_t *ci, const int32_t *blk, int64_t n, int32_t *kidx) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) kidx[blk ? blk[p] : (int32_t)p] = ci[p];
+// Row groups of the tile plan: group g holds the TI rows x = TI g .. of the
+// order ord (the rows of its tiles).  k_group_len: the number of op(A)
+// entries of each group's rows, and the largest such number.
+template <int TI>
+__global__ __launch_bounds__(256) void k_group_len(const int32_t *ord, int32_t nbr, int32_t ngroup, const int64_t *arp,
+                                                   int64_t *glen, unsigned long long *gmax) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroup) return;
+  int64_t n = 0;
+  for (int r = 0; r < TI; r++) {
+    const int32_t x = TI * g + r;
+    if (x >= nbr) break;
+    const int32_t row = ord ? ord[x] : x;
+    n += arp[row + 1] - arp[row];
+  }
+  glen[g] = n;
+  atomicMax(gmax, (unsigned long long)n);
+}
+
+// The k of a row group's op(A) entries in compact form: ukey[gbase[g] + u]
+// is the u-th smallest of them, ucount[g] their number, and upos[a] = u for
+// every stored A block a of the group's rows.  The step builder then keeps
+// its bitmaps over a group's u (about a row's length) instead of over every
+// k.  One workgroup per group: a bitmap over k in LDS and its prefix
+// popcounts.
+template <int TI>
+__global__ __launch_bounds__(256) void k_group_union(const int32_t *ord, int32_t nbr, const int64_t *arp,
+                                                     const int32_t *aci, const int32_t *ablk, int32_t nbk,
+                                                     const int64_t *gbase, int32_t *ukey, int32_t *upos,
+                                                     int32_t *ucount) {
+  extern __shared__ uint32_t sm[];
+  __shared__ int32_t wsum[4];
+  const int32_t g = blockIdx.x;
+  const int32_t W = (nbk + 31) >> 5;
+  uint32_t *bm = sm;
+  int32_t *pre = reinterpret_cast<int32_t *>(sm + W);
+  for (int32_t t = threadIdx.x; t < W; t += blockDim.x) bm[t] = 0u;
+  __syncthreads();
+  for (int r = 0; r < TI; r++) {
+    const int32_t x = TI * g + r;
+    if (x >= nbr) break;
+    const int32_t row = ord ? ord[x] : x;
+    for (int64_t p = arp[row] + threadIdx.x; p < arp[row + 1]; p += blockDim.x) {
+      const int32_t k = aci[p];
+      atomicOr(&bm[k >> 5], 1u << (k & 31));
+    }
+  }
+  __syncthreads();
+  // exclusive prefix of the words' popcounts (contiguous words per thread)
+  const int32_t per = (W + blockDim.x - 1) / blockDim.x;
+  const int32_t w0 = min(W, (int32_t)threadIdx.x * per), w1 = min(W, w0 + per);
+  int32_t loc = 0;
+  for (int32_t t = w0; t < w1; t++) loc += __popc(bm[t]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t inc = loc;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  int32_t run = inc - loc, total = 0;
+  for (int x = 0; x < (int)(blockDim.x >> 6); x++) {
+    if (x < wv) run += wsum[x];
+    total += wsum[x];
+  }
+  const int64_t base = gbase[g];
+  for (int32_t t = w0; t < w1; t++) {
+    pre[t] = run;
+    uint32_t word = bm[t];
+    while (word) {
+      ukey[base + run] = 32 * t + __builtin_ctz(word);
+      word &= word - 1;
+      run++;
+    }
+  }
+  if (threadIdx.x == 0) ucount[g] = total;
+  __syncthreads();
+  for (int r = 0; r < TI; r++) {
+    const int32_t x = TI * g + r;
+    if (x >= nbr) break;
+    const int32_t row = ord ? ord[x] : x;
+    for (int64_t p = arp[row] + threadIdx.x; p < arp[row + 1]; p += blockDim.x) {
+      const int32_t k = aci[p];
+      upos[ablk ? ablk[p] : (int32_t)p] = pre[k >> 5] + __popc(bm[k >> 5] & ((1u << (k & 31)) - 1u));
+    }
+  }
 }
 
 // Tiles of row block q: RG consecutive row groups of TI rows of the order
@@ -519,6 +603,7 @@ __global__ __launch_bounds__(256) void k_tile_groups(const int32_t *ord, int32_t
       for (int g = 0; g < RG; g++) {
         if (!((bm[g * W + t] >> b) & 1u)) continue;
         int32_t *d = reinterpret_cast<int32_t *>(tiles + (base + run) * (S::DESC_BYTES / 16));
+        d[(S::S0_OFF + 12) / 4] = RG * q + g;   // the tile's row group (after s0 and the step count)
 #pragma unroll
         for (int c = 0; c < TJ; c++) d[TI + c] = cols[c];
 #pragma unroll
@@ -539,14 +624,16 @@ __global__ __launch_bounds__(256) void k_tile_groups(const int32_t *ord, int32_t
 }
 
 // Union of the k of a tile's product lists: per result block x of the tile a
-// bitmap over k in LDS, their union, and the union's prefix popcounts.  One
-// wavefront per tile.  count mode: the number of steps into count[t].  fill
-// mode: the step records from the tile's s0 -- for step s (the s-th k of the
-// union): the element offsets of the A and B blocks the tile's products use
-// at that k, K and the mask of result blocks with a product at this k.
+// bitmap over the compact k of its row group (k_group_union) in LDS, their
+// union, and the union's prefix popcounts.  One wavefront per tile.  count
+// mode: the number of steps into count[t].  fill mode: the step records from
+// the tile's s0 -- for step s (the s-th k of the union): the element offsets
+// of the A and B blocks the tile's products use at that k, K and the mask of
+// result blocks with a product at this k.
 template <int TI, int TJ>
 __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, const int64_t *seg,
-                                                   const int2 *stack, const int32_t *kidx, int32_t nbk,
+                                                   const int2 *stack, const int32_t *upos, const int32_t *ukey,
+                                                   const int32_t *ucount, const int64_t *gbase,
                                                    const int32_t *ksz, const int64_t *a_off, const int64_t *b_off,
                                                    int64_t *count, const int64_t *step_off, int4 *steps,
                                                    int64_t chunk) {
@@ -556,19 +643,21 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
   const int64_t t = xcd_logical(blockIdx.x, chunk);
   if (t >= ntile) return;
   const int lane = threadIdx.x;
-  const int32_t W = (nbk + 31) >> 5;
+  int32_t *td = reinterpret_cast<int32_t *>(tiles + t * (S::DESC_BYTES / 16));
+  const int32_t grp = td[(S::S0_OFF + 12) / 4];   // the tile's row group
+  const int32_t W = (ucount[grp] + 31) >> 5;       // words over the group's compact k
+  const int32_t *gkey = ukey + gbase[grp];
   const bool fill = count == nullptr;
   uint32_t *bmx = sm;                 // NX x W
   uint32_t *un = sm + NX * W;         // W
   int32_t *pre = reinterpret_cast<int32_t *>(sm + (NX + 1) * W);   // W
-  int32_t *td = reinterpret_cast<int32_t *>(tiles + t * (S::DESC_BYTES / 16));
   for (int32_t u = lane; u < NX * W; u += 64) bmx[u] = 0u;
   __syncthreads();
   for (int x = 0; x < NX; x++) {
     const int32_t cb = td[TI + TJ + x];
     if (cb < 0) continue;
     for (int64_t e = seg[cb] + lane; e < seg[cb + 1]; e += 64) {
-      const int32_t k = kidx[stack[e].x];
+      const int32_t k = upos[stack[e].x];
       atomicOr(&bmx[x * W + (k >> 5)], 1u << (k & 31));
     }
   }
@@ -616,7 +705,7 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
       for (int x = 0; x < NX; x++) mask |= ((bmx[x * W + u] >> b) & 1u) << x;
       int64_t *r = reinterpret_cast<int64_t *>(steps + (base + s) * S::LPR);
       int32_t *tail = reinterpret_cast<int32_t *>(r + S::NS);
-      tail[0] = ksz[k];
+      tail[0] = ksz[gkey[k]];
       tail[1] = (int32_t)mask;
       tail[2] = tail[3] = 0;
 #pragma unroll
@@ -633,7 +722,7 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
     const int r = x / TJ, c = x % TJ;
     for (int64_t e = seg[cb] + lane; e < seg[cb + 1]; e += 64) {
       const int2 pr = stack[e];
-      const int32_t k = kidx[pr.x];
+      const int32_t k = upos[pr.x];
       const int32_t u = k >> 5;
       const int32_t s = pre[u] + __popc(un[u] & ((1u << (k & 31)) - 1u));
       int64_t *rr = reinterpret_cast<int64_t *>(steps + (base + s) * S::LPR);
@@ -663,7 +752,7 @@ __global__ __launch_bounds__(256) void k_tile_bound(const int4 *tiles, int64_t n
 template <int TI, int TJ>
 void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const int32_t *cinv, int32_t nbr,
                   int32_t nbc, const int64_t *c_rp, const int32_t *c_ci, const int64_t *seg, const int2 *stack,
-                  const int32_t *kidx, int32_t nbk, const int32_t *ksz, const int64_t *a_off, const int64_t *b_off,
+                  const OpRows &ar, int32_t nbk, const int32_t *ksz, const int64_t *a_off, const int64_t *b_off,
                   int64_t *pinned, TilePlan &tp, hipStream_t s) {
   using S = Shape<TI, TJ>;
   const int32_t ngroup = (nbr + TI * RG - 1) / (TI * RG);   // row blocks
@@ -680,9 +769,28 @@ void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const
                      nbc, cnt.p, (const int64_t *)nullptr, (int4 *)nullptr);
   HIPCHECK(hipGetLastError());
   exclusive_scan_i64(al, cnt.p, off.p, ngroup, s);
+  // the compact k of every row group (its rows' op(A) entries, at most)
+  DBuf<int64_t> glen(al, ngroup), gbase(al, (size_t)ngroup + 1);
+  DBuf<unsigned long long> gmax(al, 1);
+  HIPCHECK(hipMemsetAsync(gmax.p, 0, sizeof(unsigned long long), s));
+  hipLaunchKernelGGL((k_group_len<TI>), dim3((unsigned)((ngroup + 255) / 256)), dim3(256), 0, s, ord, nbr, ngroup,
+                     ar.rp, glen.p, gmax.p);
+  HIPCHECK(hipGetLastError());
+  exclusive_scan_i64(al, glen.p, gbase.p, ngroup, s);
+  const size_t lds_u = sizeof(uint32_t) * 2 * (size_t)std::max((nbk + 31) >> 5, 1);
+  if (lds_u > 65536)
+    HIPCHECK(hipFuncSetAttribute((const void *)k_group_union<TI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds_u));
+  DBuf<int32_t> ukey(al, (size_t)std::max<int64_t>(ar.nnzb, 1)), upos(al, (size_t)std::max<int64_t>(ar.nnzb, 1)),
+      ucount(al, ngroup);
+  hipLaunchKernelGGL((k_group_union<TI>), dim3(ngroup), dim3(256), lds_u, s, ord, nbr, ar.rp, ar.ci, ar.blk, nbk,
+                     gbase.p, ukey.p, upos.p, ucount.p);
+  HIPCHECK(hipGetLastError());
   HIPCHECK(hipMemcpyAsync(pinned, off.p + ngroup, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(pinned + 1, gmax.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
   const int64_t nt = pinned[0];
+  const int64_t wgroup = std::min<int64_t>((nbk + 31) >> 5, (pinned[1] + 31) >> 5);   // words of the widest group
   tp.ntile = nt;
   tp.tiles = DBuf<int4>(al, (size_t)std::max<int64_t>(nt, 1) * (S::DESC_BYTES / 16));
   if (nt <= 0) return;
@@ -690,8 +798,7 @@ void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const
                      nbc, (int64_t *)nullptr, (const int64_t *)off.p, tp.tiles.p);
   HIPCHECK(hipGetLastError());
   // step records
-  const int32_t W = (nbk + 31) >> 5;
-  const size_t lds2 = sizeof(uint32_t) * (TI * TJ + 2) * (size_t)std::max(W, 1);
+  const size_t lds2 = sizeof(uint32_t) * (TI * TJ + 2) * (size_t)std::max<int64_t>(wgroup, 1);
   if (lds2 > 65536)
     HIPCHECK(hipFuncSetAttribute((const void *)k_tile_steps<TI, TJ>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds2));
@@ -712,7 +819,8 @@ void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const
   const double bound_bytes = (double)pinned[0] * S::LPR * 16.0;
   if (bound_bytes > 64.0 * (double)(1ull << 30) || bound_bytes > 0.25 * (double)al.room()) {
     hipLaunchKernelGGL((k_tile_steps<TI, TJ>), dim3((unsigned)grid), dim3(64), lds2, s, tp.tiles.p, nt, seg, stack,
-                       kidx, nbk, ksz, a_off, b_off, tcnt.p, (const int64_t *)nullptr, (int4 *)nullptr, xm.chunk);
+                       upos.p, ukey.p, ucount.p, gbase.p, ksz, a_off, b_off, tcnt.p, (const int64_t *)nullptr,
+                       (int4 *)nullptr, xm.chunk);
     HIPCHECK(hipGetLastError());
     exclusive_scan_i64(al, tcnt.p, toff.p, nt, s);
     HIPCHECK(hipMemcpyAsync(pinned, toff.p + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -721,8 +829,9 @@ void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const
   tp.nsteps = pinned[0];   // records laid out (steps, or the products bound)
   // RB records of padding: a batch load at a tile's last steps reads past them
   tp.steps = DBuf<int4>(al, ((size_t)std::max<int64_t>(tp.nsteps, 0) + S::RB) * S::LPR);
-  hipLaunchKernelGGL((k_tile_steps<TI, TJ>), dim3((unsigned)grid), dim3(64), lds2, s, tp.tiles.p, nt, seg, stack, kidx,
-                     nbk, ksz, a_off, b_off, (int64_t *)nullptr, (const int64_t *)toff.p, tp.steps.p, xm.chunk);
+  hipLaunchKernelGGL((k_tile_steps<TI, TJ>), dim3((unsigned)grid), dim3(64), lds2, s, tp.tiles.p, nt, seg, stack,
+                     upos.p, ukey.p, ucount.p, gbase.p, ksz, a_off, b_off, (int64_t *)nullptr, (const int64_t *)toff.p,
+                     tp.steps.p, xm.chunk);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1006,23 +1115,17 @@ bool tile_path_fits(int32_t nbc, int32_t nbk, TileShape sh) {
   return 4 * w * (size_t)(sh.ti * sh.tj + 2) <= 150 * 1024 && 4 * wc * RG <= 150 * 1024;
 }
 
-void block_k_index(const OpIndex &a, int32_t *kidx, hipStream_t s) {
-  if (a.nnzb == 0) return;
-  hipLaunchKernelGGL(k_block_k, dim3((unsigned)((a.nnzb + 255) / 256)), dim3(256), 0, s, a.col_idx, a.blk, a.nnzb,
-                     kidx);
-  HIPCHECK(hipGetLastError());
-}
 
 #define BSMM_TILE_SHAPES(X) X(2, 2) X(2, 4) X(4, 2) X(4, 4) X(4, 8) X(8, 4)
 
 void build_tile_plan(Allocator &al, TileShape sh, const int32_t *ord, const int32_t *crank, const int32_t *cinv,
                      int32_t nbr, int32_t nbc, const int64_t *c_rp, const int32_t *c_ci, const int64_t *seg,
-                     const int2 *stack, const int32_t *kidx, int32_t nbk, const int32_t *ksz, const int64_t *a_off,
+                     const int2 *stack, const OpRows &ar, int32_t nbk, const int32_t *ksz, const int64_t *a_off,
                      const int64_t *b_off, int64_t *pinned, TilePlan &tp, hipStream_t s) {
   tp.sh = sh;
 #define BSMM_BUILD(A, B)                                                                                          \
   if (sh.ti == A && sh.tj == B)                                                                                  \
-    return build_plan_t<A, B>(al, ord, crank, cinv, nbr, nbc, c_rp, c_ci, seg, stack, kidx, nbk, ksz, a_off, b_off, \
+    return build_plan_t<A, B>(al, ord, crank, cinv, nbr, nbc, c_rp, c_ci, seg, stack, ar, nbk, ksz, a_off, b_off, \
                               pinned, tp, s);
   BSMM_TILE_SHAPES(BSMM_BUILD)
 #undef BSMM_BUILD
