@@ -207,6 +207,17 @@ static const int32_t *row_order(bsmm_ctx ctx, bsmm_mat_s *x) {
   return x->d_order;
 }
 
+// The area of x's blocks when they all have one (every row and every column
+// block size the same), else 0.
+static int64_t one_block_area(const bsmm_mat_s *x) {
+  if (x->h_rbs.empty() || x->h_cbs.empty()) return 0;
+  for (int32_t r : x->h_rbs)
+    if (r != x->h_rbs[0]) return 0;
+  for (int32_t c : x->h_cbs)
+    if (c != x->h_cbs[0]) return 0;
+  return (int64_t)x->h_rbs[0] * x->h_cbs[0];
+}
+
 static void make_op(bsmm_ctx ctx, bsmm_mat_s *x, bool trans, OpIndex &op) {
   op.blk_off = x->d_blk_off;
   op.values = x->d_values;
@@ -771,9 +782,14 @@ static void plan_build(Plan &P, char transa, char transb) {
     ar.ci = oa.col_idx;
     ar.blk = oa.blk;
     ar.nnzb = oa.nnzb;
+    OffsetAreas ob;
+    ob.a_area = one_block_area(A);
+    ob.b_area = one_block_area(B);
+    ob.a_n = A->nnzb;
+    ob.b_n = B->nnzb;
     build_tile_plan(al, TileShape{ctx->tile_ti, ctx->tile_tj}, ord, crank, crank ? ord : nullptr, nbr, nbc, P.c_rp.p,
                     P.c_ci.p, P.seg_off.p, P.stack.p, ar, (int32_t)opa_c.size(), oa.cbs, A->d_blk_off, B->d_blk_off,
-                    ctx->pinned, P.tp, s);
+                    ob, ctx->pinned, P.tp, s);
     P.stack.reset();
   } else if (nnzb_c > 0) {
     const int32_t *ord = row_order(ctx, A);

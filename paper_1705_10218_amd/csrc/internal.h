@@ -106,7 +106,7 @@ struct bsmm_mat_s {
   int32_t *d_rbs = nullptr, *d_cbs = nullptr;
   int64_t *d_row_ptr = nullptr;        // nbr+1
   int32_t *d_col_idx = nullptr;        // nnzb
-  int64_t *d_blk_off = nullptr;        // nnzb+1 element offsets
+  int64_t *d_blk_off = nullptr;        // nnzb+1 element offsets (the prefix of the block areas)
   double *d_values = nullptr;
   bool owns_values = false;
   // planner cache: locality order of the block rows (host and device copy)
@@ -508,6 +508,13 @@ struct OpRows {
   const int32_t *blk = nullptr;
   int64_t nnzb = 0;
 };
+// The one block area of A and of B (0: blocks of several areas) and their
+// numbers of stored blocks: with one area, block p starts at p times it
+// (blocks are stored in order), which the tile plan checks and then uses.
+struct OffsetAreas {
+  int64_t a_area = 0, b_area = 0;
+  int64_t a_n = 0, b_n = 0;
+};
 // Tiles of the result pattern (rows grouped in the order ord, null =
 // natural; columns by crank, null = natural, cinv its inverse) and their step
 // records from the per-result-block stacks (entries = stored A and B block
@@ -516,7 +523,7 @@ struct OpRows {
 void build_tile_plan(Allocator &al, TileShape sh, const int32_t *ord, const int32_t *crank, const int32_t *cinv,
                      int32_t nbr, int32_t nbc, const int64_t *c_rp, const int32_t *c_ci, const int64_t *seg,
                      const int2 *stack, const OpRows &ar, int32_t nbk, const int32_t *ksz, const int64_t *a_off,
-                     const int64_t *b_off, int64_t *pinned, TilePlan &tp, hipStream_t s);
+                     const int64_t *b_off, OffsetAreas ob, int64_t *pinned, TilePlan &tp, hipStream_t s);
 // a5 on the tile path.
 void tile_gemm_launch(const TilePlan &tp, const TileArgs &g, hipStream_t s);
 

@@ -32,6 +32,7 @@
 // Each result block keeps a single owner and its accumulators stay in
 // registers: no atomics; its products are added in ascending k, identically
 // on every run.
+#include <cstring>
 #include "internal.h"
 
 namespace bsmm {
@@ -435,6 +436,13 @@ __device__ inline int32_t bsearch_pos(const int32_t *ci, int64_t lo, int64_t hi,
   return -1;
 }
 
+// flag = 1 if some block p of an array does not start at element p * area
+// (stored blocks all of one area, in storage order: it starts there).
+__global__ __launch_bounds__(256) void k_off_irregular(const int64_t *off, int64_t n, int64_t area, int32_t *flag) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+    if (off[p] != area * p) *flag = 1;
+}
+
 // Row groups of the tile plan: group g holds the TI rows x = TI g .. of the
 // order ord (the rows of its tiles).  k_group_len: the number of op(A)
 // entries of each group's rows, and the largest such number.
@@ -629,14 +637,16 @@ __global__ __launch_bounds__(256) void k_tile_groups(const int32_t *ord, int32_t
 // mode: the number of steps into count[t].  fill mode: the step records from
 // the tile's s0 -- for step s (the s-th k of the union): the element offsets
 // of the A and B blocks the tile's products use at that k, K and the mask of
-// result blocks with a product at this k.
+// result blocks with a product at this k.  a_area / b_area: the one block area
+// of A / B when block p starts at p times it (checked when the plan is built),
+// else 0 and the offsets are read from a_off / b_off.
 template <int TI, int TJ>
 __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, const int64_t *seg,
                                                    const int2 *stack, const int32_t *upos, const int32_t *ukey,
                                                    const int32_t *ucount, const int64_t *gbase,
                                                    const int32_t *ksz, const int64_t *a_off, const int64_t *b_off,
-                                                   int64_t *count, const int64_t *step_off, int4 *steps,
-                                                   int64_t chunk) {
+                                                   int64_t a_area, int64_t b_area, int64_t *count,
+                                                   const int64_t *step_off, int4 *steps, int64_t chunk) {
   using S = Shape<TI, TJ>;
   constexpr int NX = TI * TJ;
   extern __shared__ uint32_t sm[];
@@ -726,8 +736,8 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
       const int32_t u = k >> 5;
       const int32_t s = pre[u] + __popc(un[u] & ((1u << (k & 31)) - 1u));
       int64_t *rr = reinterpret_cast<int64_t *>(steps + (base + s) * S::LPR);
-      rr[r] = a_off[pr.x];
-      rr[TI + c] = b_off[pr.y];
+      rr[r] = a_area ? a_area * pr.x : a_off[pr.x];
+      rr[TI + c] = b_area ? b_area * pr.y : b_off[pr.y];
     }
   }
 }
@@ -753,7 +763,7 @@ template <int TI, int TJ>
 void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const int32_t *cinv, int32_t nbr,
                   int32_t nbc, const int64_t *c_rp, const int32_t *c_ci, const int64_t *seg, const int2 *stack,
                   const OpRows &ar, int32_t nbk, const int32_t *ksz, const int64_t *a_off, const int64_t *b_off,
-                  int64_t *pinned, TilePlan &tp, hipStream_t s) {
+                  OffsetAreas ob, int64_t *pinned, TilePlan &tp, hipStream_t s) {
   using S = Shape<TI, TJ>;
   const int32_t ngroup = (nbr + TI * RG - 1) / (TI * RG);   // row blocks
   tp.ntile = tp.nsteps = 0;
@@ -786,9 +796,25 @@ void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const
   hipLaunchKernelGGL((k_group_union<TI>), dim3(ngroup), dim3(256), lds_u, s, ord, nbr, ar.rp, ar.ci, ar.blk, nbk,
                      gbase.p, ukey.p, upos.p, ucount.p);
   HIPCHECK(hipGetLastError());
+  // A and B blocks of one area each: do their offsets follow from it?
+  DBuf<int32_t> irregular(al, 2);
+  HIPCHECK(hipMemsetAsync(irregular.p, 0, 2 * sizeof(int32_t), s));
+  const int64_t areas[2] = {ob.a_area, ob.b_area}, nblk[2] = {ob.a_n, ob.b_n};
+  const int64_t *offs[2] = {a_off, b_off};
+  for (int x = 0; x < 2; x++)
+    if (areas[x] > 0 && nblk[x] > 0) {
+      hipLaunchKernelGGL(k_off_irregular, dim3((unsigned)std::min<int64_t>((nblk[x] + 255) / 256, 8192)), dim3(256), 0,
+                         s, offs[x], nblk[x], areas[x], irregular.p + x);
+      HIPCHECK(hipGetLastError());
+    }
   HIPCHECK(hipMemcpyAsync(pinned, off.p + ngroup, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(pinned + 1, gmax.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(pinned + 2, irregular.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
+  int32_t irr[2];
+  std::memcpy(irr, pinned + 2, sizeof(irr));
+  const int64_t a_area = (ob.a_area > 0 && !irr[0]) ? ob.a_area : 0;
+  const int64_t b_area = (ob.b_area > 0 && !irr[1]) ? ob.b_area : 0;
   const int64_t nt = pinned[0];
   const int64_t wgroup = std::min<int64_t>((nbk + 31) >> 5, (pinned[1] + 31) >> 5);   // words of the widest group
   tp.ntile = nt;
@@ -819,8 +845,8 @@ void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const
   const double bound_bytes = (double)pinned[0] * S::LPR * 16.0;
   if (bound_bytes > 64.0 * (double)(1ull << 30) || bound_bytes > 0.25 * (double)al.room()) {
     hipLaunchKernelGGL((k_tile_steps<TI, TJ>), dim3((unsigned)grid), dim3(64), lds2, s, tp.tiles.p, nt, seg, stack,
-                       upos.p, ukey.p, ucount.p, gbase.p, ksz, a_off, b_off, tcnt.p, (const int64_t *)nullptr,
-                       (int4 *)nullptr, xm.chunk);
+                       upos.p, ukey.p, ucount.p, gbase.p, ksz, a_off, b_off, a_area, b_area, tcnt.p,
+                       (const int64_t *)nullptr, (int4 *)nullptr, xm.chunk);
     HIPCHECK(hipGetLastError());
     exclusive_scan_i64(al, tcnt.p, toff.p, nt, s);
     HIPCHECK(hipMemcpyAsync(pinned, toff.p + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -830,8 +856,8 @@ void build_plan_t(Allocator &al, const int32_t *ord, const int32_t *crank, const
   // RB records of padding: a batch load at a tile's last steps reads past them
   tp.steps = DBuf<int4>(al, ((size_t)std::max<int64_t>(tp.nsteps, 0) + S::RB) * S::LPR);
   hipLaunchKernelGGL((k_tile_steps<TI, TJ>), dim3((unsigned)grid), dim3(64), lds2, s, tp.tiles.p, nt, seg, stack,
-                     upos.p, ukey.p, ucount.p, gbase.p, ksz, a_off, b_off, (int64_t *)nullptr, (const int64_t *)toff.p,
-                     tp.steps.p, xm.chunk);
+                     upos.p, ukey.p, ucount.p, gbase.p, ksz, a_off, b_off, a_area, b_area, (int64_t *)nullptr,
+                     (const int64_t *)toff.p, tp.steps.p, xm.chunk);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1121,12 +1147,12 @@ bool tile_path_fits(int32_t nbc, int32_t nbk, TileShape sh) {
 void build_tile_plan(Allocator &al, TileShape sh, const int32_t *ord, const int32_t *crank, const int32_t *cinv,
                      int32_t nbr, int32_t nbc, const int64_t *c_rp, const int32_t *c_ci, const int64_t *seg,
                      const int2 *stack, const OpRows &ar, int32_t nbk, const int32_t *ksz, const int64_t *a_off,
-                     const int64_t *b_off, int64_t *pinned, TilePlan &tp, hipStream_t s) {
+                     const int64_t *b_off, OffsetAreas ob, int64_t *pinned, TilePlan &tp, hipStream_t s) {
   tp.sh = sh;
 #define BSMM_BUILD(A, B)                                                                                          \
   if (sh.ti == A && sh.tj == B)                                                                                  \
     return build_plan_t<A, B>(al, ord, crank, cinv, nbr, nbc, c_rp, c_ci, seg, stack, ar, nbk, ksz, a_off, b_off, \
-                              pinned, tp, s);
+                              ob, pinned, tp, s);
   BSMM_TILE_SHAPES(BSMM_BUILD)
 #undef BSMM_BUILD
   fail(BSMM_ERR_INVALID_ARG, "unsupported tile shape");
