@@ -662,14 +662,58 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
   uint32_t *un = sm + NX * W;         // W
   int32_t *pre = reinterpret_cast<int32_t *>(sm + (NX + 1) * W);   // W
   for (int32_t u = lane; u < NX * W; u += 64) bmx[u] = 0u;
-  __syncthreads();
+  // the tile's product lists as one index range: entry i (0 <= i < tot) is
+  // stack entry sb[x] + i - lo[x] of result block x, lo[x] <= i < lo[x + 1];
+  // each lane takes CH entries at a time, so their loads are in flight together
+  constexpr int CH = 4;
+  int64_t sb[NX];
+  int32_t lo[NX + 1];
+  lo[0] = 0;
+#pragma unroll
   for (int x = 0; x < NX; x++) {
     const int32_t cb = td[TI + TJ + x];
-    if (cb < 0) continue;
-    for (int64_t e = seg[cb] + lane; e < seg[cb + 1]; e += 64) {
-      const int32_t k = upos[stack[e].x];
-      atomicOr(&bmx[x * W + (k >> 5)], 1u << (k & 31));
+    int64_t b0 = 0, b1 = 0;
+    if (cb >= 0) {
+      b0 = seg[cb];
+      b1 = seg[cb + 1];
     }
+    sb[x] = b0;
+    lo[x + 1] = lo[x] + (int32_t)(b1 - b0);
+  }
+  const int32_t tot = lo[NX];
+  auto locate = [&](int32_t i, int &x) {   // the last x with lo[x] <= i: the one holding i
+    int64_t e = sb[0] + i;
+    x = 0;
+#pragma unroll
+    for (int y = 1; y < NX; y++)
+      if (i >= lo[y]) {
+        x = y;
+        e = sb[y] + (i - lo[y]);
+      }
+    return e;
+  };
+  // entries i0, i0 + 64, ...: stored A and B block of each, its result block
+  // (-1 past the end) and its compact k
+  auto gather = [&](int32_t i0, int2 (&pr)[CH], int (&xs)[CH], int32_t (&kk)[CH]) {
+#pragma unroll
+    for (int u = 0; u < CH; u++) {
+      const int32_t i = i0 + 64 * u;
+      xs[u] = -1;
+      if (i < tot) pr[u] = stack[locate(i, xs[u])];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; u++)
+      if (xs[u] >= 0) kk[u] = upos[pr[u].x];
+  };
+  __syncthreads();
+  for (int32_t i0 = lane; i0 < tot; i0 += CH * 64) {
+    int2 pr[CH];
+    int xs[CH];
+    int32_t kk[CH];
+    gather(i0, pr, xs, kk);
+#pragma unroll
+    for (int u = 0; u < CH; u++)
+      if (xs[u] >= 0) atomicOr(&bmx[xs[u] * W + (kk[u] >> 5)], 1u << (kk[u] & 31));
   }
   __syncthreads();
   const int32_t per = (W + 63) / 64;
@@ -726,18 +770,20 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
   }
   // the blocks the steps use (result blocks of one row or column write the
   // same offset)
-  for (int x = 0; x < NX; x++) {
-    const int32_t cb = td[TI + TJ + x];
-    if (cb < 0) continue;
-    const int r = x / TJ, c = x % TJ;
-    for (int64_t e = seg[cb] + lane; e < seg[cb + 1]; e += 64) {
-      const int2 pr = stack[e];
-      const int32_t k = upos[pr.x];
-      const int32_t u = k >> 5;
-      const int32_t s = pre[u] + __popc(un[u] & ((1u << (k & 31)) - 1u));
+  for (int32_t i0 = lane; i0 < tot; i0 += CH * 64) {
+    int2 pr[CH];
+    int xs[CH];
+    int32_t kk[CH];
+    gather(i0, pr, xs, kk);
+#pragma unroll
+    for (int u = 0; u < CH; u++) {
+      if (xs[u] < 0) continue;
+      const int r = xs[u] / TJ, c = xs[u] % TJ;
+      const int32_t k = kk[u], w = k >> 5;
+      const int32_t s = pre[w] + __popc(un[w] & ((1u << (k & 31)) - 1u));
       int64_t *rr = reinterpret_cast<int64_t *>(steps + (base + s) * S::LPR);
-      rr[r] = a_area ? a_area * pr.x : a_off[pr.x];
-      rr[TI + c] = b_area ? b_area * pr.y : b_off[pr.y];
+      rr[r] = a_area ? a_area * pr[u].x : a_off[pr[u].x];
+      rr[TI + c] = b_area ? b_area * pr[u].y : b_off[pr[u].y];
     }
   }
 }
