@@ -665,7 +665,7 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
   // the tile's product lists as one index range: entry i (0 <= i < tot) is
   // stack entry sb[x] + i - lo[x] of result block x, lo[x] <= i < lo[x + 1];
   // each lane takes CH entries at a time, so their loads are in flight together
-  constexpr int CH = 4;
+  constexpr int CH = 8;
   int64_t sb[NX];
   int32_t lo[NX + 1];
   lo[0] = 0;
