@@ -269,6 +269,26 @@ def test_uniform_23_against_oracle_and_general_kernel(B, ta, tb, seed):
     _check(host, info, oracle.multiply(ta, tb, 1.0, a, b), path=UNI_PATH)
 
 
+@pytest.mark.parametrize("uniform", ["A", "B"])
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
+def test_tiles_one_operand_of_one_block_area(B, ctx, uniform, ta, tb):
+    """One operand with every block 23x23, the other with column (or row)
+    sizes 17..24: the step records take the first operand's block offsets
+    from its one area and gather the other's (general tile kernel)."""
+    rng = np.random.default_rng([730, ord(uniform), ord(ta)])
+    nbr, nk, nbc = 21, 19, 23
+    n23 = lambda n: np.full(n, 23, np.int32)
+    rbs = n23(nbr) if uniform == "A" else _sizes(rng, nbr)
+    cbs = n23(nbc) if uniform == "B" else _sizes(rng, nbc)
+    kbs = n23(nk)
+    a = random_bcsr(rng, nbr, nk, rbs, kbs, 0.3, empty_rows=(2,)) if ta == "N" else \
+        random_bcsr(rng, nk, nbr, kbs, rbs, 0.3)
+    b = random_bcsr(rng, nk, nbc, kbs, cbs, 0.3) if tb == "N" else random_bcsr(rng, nbc, nk, cbs, kbs, 0.3)
+    _log(f"one area ({uniform}) {ta}{tb}: {a.nnzb} x {b.nnzb} blocks")
+    host, info = _gpu_mul(B, ctx, ta, tb, 1.0, a, b)
+    _check(host, info, oracle.multiply(ta, tb, 1.0, a, b))
+
+
 @pytest.mark.parametrize("alpha,beta", [(1.0, 1.0), (-0.5, 2.0), (0.0, 1.5), (2.0, 0.0)])
 def test_uniform_23_alpha_beta(B, alpha, beta):
     rng = np.random.default_rng(713)
