@@ -706,7 +706,15 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
       if (xs[u] >= 0) kk[u] = upos[pr[u].x];
   };
   __syncthreads();
-  for (int32_t i0 = lane; i0 < tot; i0 += CH * 64) {
+  // the first chunk stays in registers for the pass that writes the steps
+  int2 pr0[CH];
+  int xs0[CH];
+  int32_t kk0[CH];
+  gather(lane, pr0, xs0, kk0);
+#pragma unroll
+  for (int u = 0; u < CH; u++)
+    if (xs0[u] >= 0) atomicOr(&bmx[xs0[u] * W + (kk0[u] >> 5)], 1u << (kk0[u] & 31));
+  for (int32_t i0 = lane + CH * 64; i0 < tot; i0 += CH * 64) {
     int2 pr[CH];
     int xs[CH];
     int32_t kk[CH];
@@ -770,11 +778,7 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
   }
   // the blocks the steps use (result blocks of one row or column write the
   // same offset)
-  for (int32_t i0 = lane; i0 < tot; i0 += CH * 64) {
-    int2 pr[CH];
-    int xs[CH];
-    int32_t kk[CH];
-    gather(i0, pr, xs, kk);
+  auto place = [&](const int2 (&pr)[CH], const int (&xs)[CH], const int32_t (&kk)[CH]) {
 #pragma unroll
     for (int u = 0; u < CH; u++) {
       if (xs[u] < 0) continue;
@@ -785,6 +789,14 @@ __global__ __launch_bounds__(64) void k_tile_steps(int4 *tiles, int64_t ntile, c
       rr[r] = a_area ? a_area * pr[u].x : a_off[pr[u].x];
       rr[TI + c] = b_area ? b_area * pr[u].y : b_off[pr[u].y];
     }
+  };
+  place(pr0, xs0, kk0);
+  for (int32_t i0 = lane + CH * 64; i0 < tot; i0 += CH * 64) {
+    int2 pr[CH];
+    int xs[CH];
+    int32_t kk[CH];
+    gather(i0, pr, xs, kk);
+    place(pr, xs, kk);
   }
 }
 
