@@ -173,6 +173,9 @@ __global__ __launch_bounds__(256) void k_block_norms(const int64_t *off, const d
     double s[U];
 #pragma unroll
     for (int u = 0; u < U; u++) s[u] = 0.0;
+    // unrolled: several iterations' loads in flight, the sums still taken in
+    // the order of d
+#pragma unroll 4
     for (int64_t d = lane; d < lmax; d += G) {
       double x[U];
 #pragma unroll
